@@ -1,0 +1,225 @@
+/*
+ * skm.h — exact sparse spherical k-means on AMD MI355X (gfx950).
+ *
+ * Implements the method of Knittel, Koch & Ertl, "Efficient Sparse Spherical
+ * k-Means for Document Clustering" (DocEng 2021):
+ *   - Sec. 2: rows are unit-length sparse vectors; a centroid is the sum of its
+ *     members divided by that sum's length; each row goes to the centroid with
+ *     the highest dot product; the loop alternates update and assignment and
+ *     stops when assignments no longer change or when the largest squared
+ *     centroid shift falls below a threshold (Sec. 4.1 uses 1e-4).
+ *   - Sec. 3.1 (NCC): a row whose previous centroid did not change only has to
+ *     be compared with the centroids that did change.
+ *   - Sec. 3.2 (INDEX): an index over the centroids' sorted entries that, given
+ *     a baseline similarity, returns a superset of the centroids that can reach
+ *     it (Lemma 3.1); several thresholds {0.1, 0.25, 0.4, 0.6}; the highest one
+ *     not above the baseline is used.
+ *
+ * Results are those of a plain FP64 run: ties in the argmax go to the lowest
+ * centroid index, an empty cluster keeps its centroid.  Scores may be computed
+ * from FP32, BF16 or FP8-E4M3 copies of the centroids with FP32 accumulation;
+ * every row whose best centroid is not certified by a bound derived from the
+ * format's rounding and the accumulation error is decided again in FP64 against
+ * the FP64 centroids.
+ *
+ * Conventions for every call:
+ *   - Returns an skm_status; no C++ exception crosses this interface.
+ *   - On SKM_E_INVALID / SKM_E_NOMEM / SKM_E_STATE nothing was modified.
+ *   - On SKM_E_DEVICE the context is unusable; only skm_destroy is valid.
+ *   - skm_last_error() returns a thread-local message for the last failure.
+ *   - A context is used by one thread at a time.  Work is enqueued on the
+ *     context's stream; every call below returns after its results are
+ *     complete (it synchronises that stream), except where stated.
+ *   - "device pointer" means HIP device memory of the context's device;
+ *     "host pointer" means ordinary process memory.
+ */
+#ifndef SKM_H
+#define SKM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct skm_ctx skm_ctx;
+
+typedef enum {
+  SKM_OK = 0,
+  SKM_E_INVALID = 1,     /* malformed arguments or input */
+  SKM_E_NOMEM = 2,       /* the HBM budget or the device is out of memory */
+  SKM_E_DEVICE = 3,      /* a HIP call failed; the context is poisoned */
+  SKM_E_STATE = 4,       /* call made in the wrong order */
+  SKM_E_UNSUPPORTED = 5  /* valid but outside what this build supports */
+} skm_status;
+
+typedef enum {
+  SKM_FP32 = 0,      /* centroids scored from float copies */
+  SKM_BF16 = 1,      /* bfloat16 copies, round to nearest even */
+  SKM_FP8_E4M3 = 2   /* OCP E4M3 copies times a power-of-two scale per centroid */
+} skm_precision;
+
+enum {
+  SKM_NCC = 1u << 0,       /* Sec. 3.1: skip centroids that did not change */
+  SKM_INDEX = 1u << 1,     /* Sec. 3.2: dot-product index on rows whose previous
+                              centroid changed */
+  SKM_NO_EXACT = 1u << 2   /* skip the exact tier: the argmax is taken on the
+                              low-precision scores alone (timing comparator only;
+                              results are then NOT those of an FP64 run) */
+};
+
+typedef enum {
+  SKM_STOP_PAPER = 0,  /* stop after an assignment that moved nothing (or fewer
+                          than min_moved_frac * n_rows rows), or after an update
+                          whose largest squared centroid shift is < max_shift_sq */
+  SKM_STOP_FIXED = 1   /* run exactly max_iter iterations */
+} skm_stop_rule;
+
+/*
+ * A CSR matrix of rows (documents).  Borrowed for the duration of the call.
+ *   indptr  [n_rows + 1], indptr[0] = 0, non-decreasing, indptr[n_rows] = nnz
+ *   indices [nnz], strictly ascending within a row, in [0, n_cols)
+ *   values  [nnz], finite and > 0; each row's L2 norm within 1e-5 of 1
+ * on_device = 1: the three arrays are device pointers; 0: host pointers.
+ */
+typedef struct {
+  int64_t n_rows;
+  int64_t n_cols;
+  int64_t nnz;
+  const int64_t *indptr;
+  const int32_t *indices;
+  const float *values;
+  int32_t on_device;
+} skm_csr;
+
+typedef struct {
+  int32_t k;                  /* number of clusters, 1 <= k <= 65535 */
+  int32_t precision;          /* skm_precision */
+  uint32_t flags;             /* SKM_NCC | SKM_INDEX | SKM_NO_EXACT */
+  int32_t n_lambda;           /* index thresholds, ascending, in (0, 1] */
+  double lambda[8];           /* default {0.1, 0.25, 0.4, 0.6} (Sec. 4.1) */
+  int32_t index_min_changed;  /* use the index only when more than this many
+                                 centroids changed (Sec. 4.3 suggests ~100);
+                                 0 = whenever SKM_INDEX is set */
+  int32_t stop_rule;          /* skm_stop_rule */
+  int32_t max_iter;           /* cap for skm_iterate */
+  double min_moved_frac;      /* SKM_STOP_PAPER: also stop when fewer than this
+                                 fraction of rows moved (0 = only when none) */
+  double max_shift_sq;        /* SKM_STOP_PAPER shift threshold (Sec. 4.1: 1e-4) */
+  const int32_t *init_rows;   /* host, k distinct row ids: c_j = x_r / ||x_r|| */
+  const double *init_centroids; /* host, k x n_cols row-major; used when
+                                   init_rows is NULL (rows must be unit length,
+                                   non-negative) */
+  size_t hbm_budget_bytes;    /* 0 = no limit; counts every device allocation
+                                 the context makes */
+  void *stream;               /* hipStream_t to enqueue on; NULL = own stream */
+  int32_t validate;           /* 1 = check the CSR conventions above at init */
+} skm_config;
+
+typedef struct {
+  int32_t iter;               /* index of this iteration (0-based) */
+  int32_t changed_centroids;  /* centroids that changed before this assignment
+                                 (all of them at iteration 0) */
+  int64_t moved;              /* rows whose assignment changed (n_rows at 0) */
+  int64_t flagged;            /* rows sent to the exact FP64 tier */
+  int64_t band_overflow;      /* flagged rows rescored against every candidate */
+  int64_t ncc_rows;           /* rows that only compared changed centroids */
+  int64_t index_rows;         /* rows whose candidates came from the index */
+  double mean_candidates;     /* centroids scored per row (low precision) */
+  double objective_assign;    /* J_A = sum_i x_i . c_{a_i} (after update) */
+  double objective_update;    /* J_U = sum_j ||S_j||       (after update) */
+  double max_shift_sq;        /* max_j ||c_j(new) - c_j(old)||^2 (after update) */
+  float ms_assign;            /* device time of the phases, milliseconds */
+  float ms_exact;
+  float ms_update;
+  float ms_index;
+} skm_iter_stats;
+
+/* Fills *cfg with defaults: k = 0 (must be set), FP32, no flags, the four
+ * thresholds of Sec. 4.1, paper stop rule, max_iter 100, shift 1e-4. */
+void skm_config_default(skm_config *cfg);
+
+/* Creates a context: copies the rows into HBM, seeds the centroids (FP64) and
+ * builds their scoring copies.  *out is owned by the caller and released with
+ * skm_destroy.  SKM_E_INVALID for a malformed CSR or config, SKM_E_NOMEM when
+ * the budget is exceeded. */
+skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out);
+
+/* One assignment step against the current centroids (Sec. 2, with Sec. 3.1 /
+ * 3.2 when enabled).  st may be NULL. */
+skm_status skm_assign(skm_ctx *c, skm_iter_stats *st);
+
+/* One update step from the last assignment: FP64 member sums in ascending row
+ * order for every cluster whose membership changed, renormalisation, the
+ * changed-centroid set for the next assignment, new scoring copies and, when
+ * enabled, the index.  SKM_E_STATE if no assignment preceded it. */
+skm_status skm_update(skm_ctx *c, skm_iter_stats *st);
+
+/* Repeats {assign; stop test; update; stop test} up to max_iter times (the
+ * config's cap when max_iter <= 0).  per_iter: host array of max_iter records
+ * or NULL.  *n_done = iterations started, *converged = 1 if a stop test (not the
+ * cap) ended the loop. */
+skm_status skm_iterate(skm_ctx *c, int32_t max_iter, skm_iter_stats *per_iter,
+                       int32_t *n_done, int32_t *converged);
+
+/* Assigns new rows to the current centroids without changing the context
+ * (exact, no NCC since the rows have no previous assignment).  out_assign
+ * [n_rows] and out_score [n_rows] (the FP64 dot product with the chosen
+ * centroid) are device pointers when docs->on_device, else host pointers.
+ * stream: hipStream_t for this call (NULL = the context's stream).  Calls with
+ * different streams may run concurrently with each other; they must not
+ * overlap skm_assign/skm_update/skm_iterate on the same context. */
+skm_status skm_assign_new(skm_ctx *c, const skm_csr *docs, int32_t *out_assign,
+                          double *out_score, void *stream);
+
+/* Current assignment (after skm_assign) into out[n_rows]. */
+skm_status skm_get_assignments(const skm_ctx *c, int32_t *out, int32_t on_device);
+
+/* Current FP64 centroids, k x n_cols row-major, into out. */
+skm_status skm_get_centroids(const skm_ctx *c, double *out, int32_t on_device);
+
+/* Replaces the centroids (host, k x n_cols, unit rows, non-negative), rebuilds
+ * the scoring copies and marks every centroid changed.  For checks that feed
+ * known centroids into one assignment step. */
+skm_status skm_set_centroids(skm_ctx *c, const double *centroids);
+
+/* Scoring copy of the centroids, term-major: codes[t * ld + j] for term t and
+ * centroid j (4, 2 or 1 bytes per code for FP32 / BF16 / FP8), and the FP8 scale
+ * per centroid (1.0 otherwise).  Host buffers: codes of n_cols * ld * bytes,
+ * scales of k floats.  *ld receives the row stride (>= k). */
+skm_status skm_get_tile(const skm_ctx *c, void *codes, size_t codes_bytes, float *scales,
+                        int64_t *ld);
+
+/* Changed-centroid flags (1 = changed since the previous assignment) into a
+ * host array of k bytes. */
+skm_status skm_get_changed(const skm_ctx *c, uint8_t *out);
+
+/* Low-precision scores of the rows in docs against every centroid, before any
+ * exact tier: out[i * k + j], host, n_rows * k floats.  Diagnostic for checking
+ * the error bound; small inputs only. */
+skm_status skm_score_dense(skm_ctx *c, const skm_csr *docs, float *out);
+
+/* The certified error bound the context applies to a low-precision score s of
+ * a row with nnz terms and L1 norm l1: |s - exact| <= bound. */
+double skm_error_bound(const skm_ctx *c, double s, int64_t nnz, double l1);
+
+/* Index of threshold level `level` (Sec. 3.2), after an update with SKM_INDEX:
+ * term-major lists.  offsets [n_cols + 1] (host int64), entries (host) of
+ * (centroid << 16 | m) uint32 with m the minimum overlap count; each term's
+ * list ascending by centroid.  Pass entries = NULL to get *n_entries only. */
+skm_status skm_get_index(const skm_ctx *c, int32_t level, int64_t *offsets, uint32_t *entries,
+                         int64_t *n_entries);
+
+/* Device memory the context currently holds, in bytes. */
+size_t skm_hbm_bytes(const skm_ctx *c);
+
+const char *skm_last_error(void);
+
+void skm_destroy(skm_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SKM_H */

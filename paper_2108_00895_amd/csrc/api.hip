@@ -1,0 +1,707 @@
+// The C ABI of libskm (declared in include/skm.h): context lifetime, HBM
+// accounting, the assignment / update / iterate state machine, and the
+// getters used by tests.  Every step of the method runs in the kernels of
+// kernels_score.hip and kernels_update.hip; this file only sequences them.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace skm;
+
+namespace {
+
+thread_local std::string g_err;
+
+skm_status fail(skm_status st, const std::string &msg) {
+  g_err = msg;
+  return st;
+}
+
+skm_status device_fail(skm_ctx *c, const char *what, hipError_t e) {
+  if (c) c->poisoned = true;
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return SKM_E_DEVICE;
+}
+
+#define HIP_TRY(c, expr)                                   \
+  do {                                                     \
+    hipError_t _e = (expr);                                \
+    if (_e != hipSuccess) return device_fail(c, #expr, _e); \
+  } while (0)
+
+#define ST_TRY(expr)                \
+  do {                              \
+    skm_status _s = (expr);         \
+    if (_s != SKM_OK) return _s;    \
+  } while (0)
+
+template <typename T>
+skm_status dalloc(skm_ctx *c, T **p, size_t count) {
+  size_t bytes = round_up((int64_t)std::max<size_t>(count * sizeof(T), 1), 256);
+  if (c->cfg.hbm_budget_bytes && c->hbm_bytes + bytes > c->cfg.hbm_budget_bytes)
+    return fail(SKM_E_NOMEM, "HBM budget exceeded: need " + std::to_string(c->hbm_bytes + bytes) +
+                                 " bytes, budget " + std::to_string(c->cfg.hbm_budget_bytes));
+  void *q = nullptr;
+  hipError_t e = hipMalloc(&q, bytes);
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+    (void)hipGetLastError();
+    return fail(SKM_E_NOMEM, "device out of memory allocating " + std::to_string(bytes) + " bytes");
+  }
+  if (e != hipSuccess) return device_fail(c, "hipMalloc", e);
+  c->allocations.push_back(q);
+  c->hbm_bytes += bytes;
+  *p = static_cast<T *>(q);
+  return SKM_OK;
+}
+
+double unit_roundoff(int prec) {
+  switch (prec) {
+    case SKM_FP32: return 0x1p-24;
+    case SKM_BF16: return 0x1p-8;
+    default: return 0x1p-4;
+  }
+}
+
+int code_bytes(int prec) { return prec == SKM_FP32 ? 4 : (prec == SKM_BF16 ? 2 : 1); }
+
+// Absolute error term of the encoding per unit of a row's L1 norm.  FP8 codes
+// below 2^-6 are subnormal with spacing 2^-9, so a value can be off by half of
+// that times the centroid's scale; scales are at most 2^-8 because centroid
+// entries are at most 1 (unit rows) and the scale is the least power of two
+// with max <= 448 * scale.  FP32 / BF16 only lose values below 2^-126.
+double abs_coefficient(int prec) {
+  const double uq = unit_roundoff(prec);
+  if (prec == SKM_FP8_E4M3) return 0x1p-8 * 0x1p-10 / (1.0 - uq) * (1.0 + 0x1p-20);
+  return 0x1p-120;
+}
+
+skm_status check_csr_header(const skm_csr *d, int64_t max_cols) {
+  if (!d) return fail(SKM_E_INVALID, "docs is NULL");
+  if (d->n_rows < 0 || d->n_cols < 1 || d->nnz < 0) return fail(SKM_E_INVALID, "bad CSR sizes");
+  if (max_cols > 0 && d->n_cols > max_cols)
+    return fail(SKM_E_INVALID, "n_cols exceeds the context's vocabulary");
+  if (d->n_cols > INT32_MAX || d->n_rows > INT32_MAX)
+    return fail(SKM_E_UNSUPPORTED, "n_rows and n_cols must fit int32");
+  if (d->n_rows > 0 && (!d->indptr || (d->nnz > 0 && (!d->indices || !d->values))))
+    return fail(SKM_E_INVALID, "CSR array pointer is NULL");
+  return SKM_OK;
+}
+
+// indptr must be checked before any kernel walks rows.
+skm_status check_indptr(const int64_t *ip, int64_t n, int64_t nnz) {
+  if (ip[0] != 0) return fail(SKM_E_INVALID, "indptr[0] != 0");
+  for (int64_t i = 0; i < n; ++i)
+    if (ip[i + 1] < ip[i]) return fail(SKM_E_INVALID, "indptr decreases at row " + std::to_string(i));
+  if (ip[n] != nnz) return fail(SKM_E_INVALID, "indptr[n_rows] != nnz");
+  return SKM_OK;
+}
+
+struct DevRows {
+  int64_t *indptr = nullptr;
+  int32_t *indices = nullptr;
+  float *values = nullptr;
+  double *xl1 = nullptr, *xl2 = nullptr;
+};
+
+// Copies (host or device) rows into context-owned or temporary device memory
+// and computes per-row norms; checks the CSR conventions on the device.
+template <typename Alloc>
+skm_status upload_rows(skm_ctx *c, const skm_csr *d, int64_t D, bool validate, hipStream_t s,
+                       Alloc alloc, DevRows *out) {
+  const int64_t n = d->n_rows, z = d->nnz;
+  std::vector<int64_t> ip_host;
+  const int64_t *ip = d->indptr;
+  if (d->on_device) {
+    ip_host.resize(n + 1);
+    HIP_TRY(c, hipMemcpyAsync(ip_host.data(), d->indptr, sizeof(int64_t) * (n + 1),
+                              hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    ip = ip_host.data();
+  }
+  ST_TRY(check_indptr(ip, n, z));
+  ST_TRY(alloc(&out->indptr, (size_t)(n + 1) * sizeof(int64_t)));
+  ST_TRY(alloc(&out->indices, (size_t)std::max<int64_t>(z, 1) * sizeof(int32_t)));
+  ST_TRY(alloc(&out->values, (size_t)std::max<int64_t>(z, 1) * sizeof(float)));
+  ST_TRY(alloc(&out->xl1, (size_t)std::max<int64_t>(n, 1) * sizeof(double)));
+  ST_TRY(alloc(&out->xl2, (size_t)std::max<int64_t>(n, 1) * sizeof(double)));
+  const hipMemcpyKind kind = d->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  HIP_TRY(c, hipMemcpyAsync(out->indptr, d->indptr, sizeof(int64_t) * (n + 1), kind, s));
+  if (z > 0) {
+    HIP_TRY(c, hipMemcpyAsync(out->indices, d->indices, sizeof(int32_t) * z, kind, s));
+    HIP_TRY(c, hipMemcpyAsync(out->values, d->values, sizeof(float) * z, kind, s));
+  }
+  int32_t *bad = nullptr;
+  ST_TRY(alloc(&bad, sizeof(int32_t)));
+  HIP_TRY(c, launch_fill_i32(bad, 0, 1, s));
+  HIP_TRY(c, launch_row_stats(out->indptr, out->indices, out->values, n, D, out->xl1, out->xl2, bad,
+                              s));
+  int32_t hbad = 0;
+  HIP_TRY(c, hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  if (hbad & 4) return fail(SKM_E_INVALID, "term index out of range [0, n_cols)");
+  if (validate) {
+    if (hbad & 2) return fail(SKM_E_INVALID, "values must be finite and > 0");
+    if (hbad & 8) return fail(SKM_E_INVALID, "indices must be strictly ascending within a row");
+    if (hbad & 32) return fail(SKM_E_INVALID, "empty row");
+    if (hbad & 16) return fail(SKM_E_INVALID, "row L2 norm differs from 1 by more than 1e-5");
+  }
+  return SKM_OK;
+}
+
+skm_status check_ctx(const skm_ctx *c) {
+  if (!c) return fail(SKM_E_INVALID, "context is NULL");
+  if (c->poisoned) return fail(SKM_E_DEVICE, "context is poisoned by an earlier device error");
+  return SKM_OK;
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0.f;
+  }
+  return ms;
+}
+
+// Scoring copies of the centroids flagged in `changed` (all when nullptr).
+skm_status rebuild_tiles(skm_ctx *c, const uint8_t *changed) {
+  if (c->prec == SKM_FP8_E4M3)
+    HIP_TRY(c, launch_fp8_scales(c->master, c->k, c->D, changed, c->scale, c->stream));
+  HIP_TRY(c, launch_quantize(c->master, c->k, c->D, changed, c->scale, c->prec, c->tile, c->ld,
+                             c->stream));
+  return SKM_OK;
+}
+
+ScoreArgs base_args(skm_ctx *c) {
+  ScoreArgs a{};
+  a.indptr = c->indptr;
+  a.indices = c->indices;
+  a.values = c->values;
+  a.xl1 = c->xl1;
+  a.n_rows = c->N;
+  a.tile = c->tile;
+  a.ld = c->ld;
+  a.k = c->k;
+  a.scale = c->prec == SKM_FP8_E4M3 ? c->scale : nullptr;
+  a.uq = c->uq;
+  a.abs_coef = c->abs_coef;
+  a.no_exact = (c->cfg.flags & SKM_NO_EXACT) ? 1 : 0;
+  a.a_out = c->a;
+  a.lo_out = c->lo;
+  a.hi_out = c->hi;
+  a.flag_rows = c->flag_rows;
+  a.flag_L = c->flag_L;
+  a.flag_mode = c->flag_mode;
+  a.counters = c->counters;
+  a.stat = c->stat;
+  return a;
+}
+
+int exact_waves() { return 4096; }
+
+}  // namespace
+
+extern "C" {
+
+void skm_config_default(skm_config *cfg) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->precision = SKM_FP32;
+  cfg->n_lambda = 4;
+  cfg->lambda[0] = 0.1;
+  cfg->lambda[1] = 0.25;
+  cfg->lambda[2] = 0.4;
+  cfg->lambda[3] = 0.6;
+  cfg->index_min_changed = 0;
+  cfg->stop_rule = SKM_STOP_PAPER;
+  cfg->max_iter = 100;
+  cfg->min_moved_frac = 0.0;
+  cfg->max_shift_sq = 1e-4;
+  cfg->validate = 1;
+}
+
+const char *skm_last_error(void) { return g_err.c_str(); }
+
+size_t skm_hbm_bytes(const skm_ctx *c) { return c ? c->hbm_bytes : 0; }
+
+void skm_destroy(skm_ctx *c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (void *p : c->allocations) (void)hipFree(p);
+  for (hipEvent_t &e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  (void)hipGetLastError();
+  delete c;
+}
+
+skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
+  if (!out) return fail(SKM_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!cfg) return fail(SKM_E_INVALID, "cfg is NULL");
+  ST_TRY(check_csr_header(docs, 0));
+  if (docs->n_rows < 1) return fail(SKM_E_INVALID, "need at least one row");
+  if (cfg->k < 1 || cfg->k > 65535) return fail(SKM_E_INVALID, "k must be in [1, 65535]");
+  if (cfg->precision < SKM_FP32 || cfg->precision > SKM_FP8_E4M3)
+    return fail(SKM_E_INVALID, "unknown precision");
+  if (!cfg->init_rows && !cfg->init_centroids)
+    return fail(SKM_E_INVALID, "init_rows or init_centroids is required");
+  if (cfg->init_rows) {
+    if (cfg->k > docs->n_rows) return fail(SKM_E_INVALID, "k exceeds n_rows");
+    for (int32_t j = 0; j < cfg->k; ++j)
+      if (cfg->init_rows[j] < 0 || cfg->init_rows[j] >= docs->n_rows)
+        return fail(SKM_E_INVALID, "init_rows entry out of range");
+  }
+  if (cfg->flags & SKM_INDEX) {
+    if (cfg->n_lambda < 1 || cfg->n_lambda > 8) return fail(SKM_E_INVALID, "n_lambda must be 1..8");
+    for (int i = 0; i < cfg->n_lambda; ++i)
+      if (!(cfg->lambda[i] > 0.0 && cfg->lambda[i] <= 1.0) ||
+          (i > 0 && !(cfg->lambda[i] > cfg->lambda[i - 1])))
+        return fail(SKM_E_INVALID, "lambda must be ascending in (0, 1]");
+  }
+  if (cfg->stop_rule != SKM_STOP_PAPER && cfg->stop_rule != SKM_STOP_FIXED)
+    return fail(SKM_E_INVALID, "unknown stop rule");
+
+  skm_ctx *c = new (std::nothrow) skm_ctx();
+  if (!c) return fail(SKM_E_NOMEM, "host allocation failed");
+  c->cfg = *cfg;
+  c->cfg.init_rows = nullptr;
+  c->cfg.init_centroids = nullptr;
+  c->N = docs->n_rows;
+  c->D = docs->n_cols;
+  c->Z = docs->nnz;
+  c->k = cfg->k;
+  c->prec = cfg->precision;
+  c->esize = code_bytes(c->prec);
+  c->uq = unit_roundoff(c->prec);
+  c->abs_coef = abs_coefficient(c->prec);
+  c->ld = round_up(c->k, kChunk);
+  c->nblk = (c->N + 8191) / 8192;
+
+  auto cleanup = [&](skm_status st) {
+    skm_destroy(c);
+    return st;
+  };
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) return cleanup(device_fail(nullptr, "hipGetDevice", e));
+  if (cfg->stream) {
+    c->stream = static_cast<hipStream_t>(cfg->stream);
+  } else {
+    e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return cleanup(device_fail(nullptr, "hipStreamCreate", e));
+    c->own_stream = true;
+  }
+  for (hipEvent_t &ev : c->ev) {
+    e = hipEventCreate(&ev);
+    if (e != hipSuccess) return cleanup(device_fail(nullptr, "hipEventCreate", e));
+  }
+  auto alloc = [c](auto **p, size_t bytes) {
+    using T = std::remove_pointer_t<std::remove_reference_t<decltype(p)>>;
+    return dalloc(c, reinterpret_cast<T **>(p), (bytes + sizeof(T) - 1) / sizeof(T));
+  };
+  DevRows rows;
+  skm_status st = upload_rows(c, docs, c->D, cfg->validate != 0, c->stream, alloc, &rows);
+  if (st != SKM_OK) return cleanup(st);
+  c->indptr = rows.indptr;
+  c->indices = rows.indices;
+  c->values = rows.values;
+  c->xl1 = rows.xl1;
+  c->xl2 = rows.xl2;
+
+  const int64_t kD = (int64_t)c->k * c->D;
+  const int64_t N = c->N, k = c->k;
+#define A_(p, n)                                  \
+  do {                                            \
+    skm_status _s = dalloc(c, &(p), (size_t)(n)); \
+    if (_s != SKM_OK) return cleanup(_s);         \
+  } while (0)
+  A_(c->master, kD);
+  A_(c->S, kD);
+  A_(c->tile, c->D * c->ld * c->esize);
+  A_(c->scale, c->ld);
+  A_(c->snorm, k);
+  A_(c->shift, k);
+  A_(c->dot_old, k);
+  A_(c->changed, k);
+  A_(c->ch_ids, k);
+  A_(c->a, N);
+  A_(c->a_prev, N);
+  A_(c->lo, N);
+  A_(c->hi, N);
+  A_(c->lo_prev, N);
+  A_(c->hi_prev, N);
+  A_(c->flag_rows, N);
+  A_(c->flag_L, N);
+  A_(c->flag_mode, N);
+  A_(c->counters, 8);
+  A_(c->stat, 8);
+  A_(c->hist, c->nblk * k);
+  A_(c->counts, k);
+  A_(c->offsets, k + 1);
+  A_(c->members, N);
+  A_(c->red, 8);
+  A_(c->ids_count, 1);
+  if (c->cfg.flags & SKM_NCC) A_(c->tile_ch, c->D * c->ld * c->esize);
+#undef A_
+
+  hipStream_t s = c->stream;
+  if (launch_fill_u8(c->tile, 0, c->D * c->ld * c->esize, s) != hipSuccess ||
+      launch_fill_f64(c->snorm, 0.0, k, s) != hipSuccess ||
+      launch_fill_u8(c->changed, 1, k, s) != hipSuccess)
+    return cleanup(device_fail(c, "fill", hipGetLastError()));
+  {
+    std::vector<float> ones(c->ld, 1.0f);
+    e = hipMemcpyAsync(c->scale, ones.data(), sizeof(float) * c->ld, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return cleanup(device_fail(c, "hipMemcpy scale", e));
+    if (cfg->init_rows) {
+      int32_t *drows = nullptr;
+      if ((st = dalloc(c, &drows, (size_t)k)) != SKM_OK) return cleanup(st);
+      e = hipMemcpyAsync(drows, cfg->init_rows, sizeof(int32_t) * k, hipMemcpyHostToDevice, s);
+      if (e == hipSuccess) e = launch_seed(c->indptr, c->indices, c->values, drows, c->k, c->D,
+                                           c->master, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return cleanup(device_fail(c, "seed", e));
+    } else {
+      e = hipMemcpyAsync(c->master, cfg->init_centroids, sizeof(double) * kD, hipMemcpyHostToDevice,
+                         s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return cleanup(device_fail(c, "init centroids", e));
+    }
+  }
+  if ((st = rebuild_tiles(c, nullptr)) != SKM_OK) return cleanup(st);
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return cleanup(device_fail(c, "init sync", e));
+  c->force_all = true;
+  c->have_prev = false;
+  c->last_changed = c->k;
+  *out = c;
+  return SKM_OK;
+}
+
+skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
+  ST_TRY(check_ctx(c));
+  hipStream_t s = c->stream;
+  ScoreArgs a = base_args(c);
+  const bool ncc = (c->cfg.flags & SKM_NCC) && c->have_prev;
+  int32_t n_ch = c->k;
+  HIP_TRY(c, hipEventRecord(c->ev[0], s));
+  if (ncc) {
+    HIP_TRY(c, launch_compact_changed(c->changed, c->k, c->ch_ids, c->ids_count, s));
+    HIP_TRY(c, hipMemcpyAsync(&n_ch, c->ids_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    c->ld_ch = round_up(std::max<int32_t>(n_ch, 1), kChunk);
+    HIP_TRY(c, launch_gather_tile(c->tile, c->ld, c->D, c->esize, c->ch_ids, n_ch, c->tile_ch,
+                                  c->ld_ch, s));
+    a.a_prev = c->a_prev;
+    a.changed = c->changed;
+    a.tile_ch = c->tile_ch;
+    a.ld_ch = c->ld_ch;
+    a.n_ch = n_ch;
+    a.ch_ids = c->ch_ids;
+    a.prev_lo = c->lo_prev;
+    a.prev_hi = c->hi_prev;
+  }
+  HIP_TRY(c, launch_fill_i32(c->counters, 0, 8, s));
+  HIP_TRY(c, launch_fill_i32(reinterpret_cast<int32_t *>(c->stat), 0, 16, s));
+  HIP_TRY(c, launch_score(a, c->prec, s));
+  HIP_TRY(c, hipEventRecord(c->ev[1], s));
+  if (!a.no_exact) {
+    ExactArgs x{a, c->master, c->D, exact_waves()};
+    HIP_TRY(c, launch_exact(x, c->prec, s));
+  }
+  HIP_TRY(c, hipEventRecord(c->ev[2], s));
+  if (c->have_prev) HIP_TRY(c, launch_count_moved(c->a, c->a_prev, c->N, c->stat + 4, s));
+  int32_t cnt[8];
+  unsigned long long stv[8];
+  HIP_TRY(c, hipMemcpyAsync(cnt, c->counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipMemcpyAsync(stv, c->stat, sizeof(stv), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  c->assigned = true;
+  c->last_moved = c->have_prev ? (int64_t)stv[4] : c->N;
+  if (st_out) {
+    std::memset(st_out, 0, sizeof(*st_out));
+    st_out->iter = c->iter;
+    st_out->changed_centroids = c->have_prev ? c->last_changed : c->k;
+    st_out->moved = c->last_moved;
+    st_out->flagged = cnt[0];
+    st_out->band_overflow = cnt[1];
+    st_out->ncc_rows = (int64_t)stv[1];
+    st_out->index_rows = (int64_t)stv[2];
+    st_out->mean_candidates = (double)stv[0] / (double)c->N;
+    st_out->ms_assign = elapsed(c->ev[0], c->ev[1]);
+    st_out->ms_exact = elapsed(c->ev[1], c->ev[2]);
+    st_out->objective_assign = st_out->objective_update = st_out->max_shift_sq = -1.0;
+  }
+  return SKM_OK;
+}
+
+skm_status skm_update(skm_ctx *c, skm_iter_stats *st_out) {
+  ST_TRY(check_ctx(c));
+  if (!c->assigned) return fail(SKM_E_STATE, "skm_update needs a preceding skm_assign");
+  hipStream_t s = c->stream;
+  HIP_TRY(c, hipEventRecord(c->ev[3], s));
+  if (c->force_all || !c->have_prev) {
+    HIP_TRY(c, launch_fill_u8(c->changed, 1, c->k, s));
+  } else {
+    HIP_TRY(c, launch_fill_u8(c->changed, 0, c->k, s));
+    HIP_TRY(c, launch_mark_changed(c->a, c->a_prev, c->N, c->changed, s));
+  }
+  int32_t n_ids = 0;
+  HIP_TRY(c, launch_compact_changed(c->changed, c->k, c->ch_ids, c->ids_count, s));
+  HIP_TRY(c, hipMemcpyAsync(&n_ids, c->ids_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, launch_bucket(c->a, c->N, c->k, c->nblk, c->hist, c->counts, c->offsets, c->members, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  HIP_TRY(c, launch_sum_members(c->indptr, c->indices, c->values, c->offsets, c->members, c->ch_ids,
+                                n_ids, c->D, c->S, s));
+  HIP_TRY(c, launch_renorm(c->S, c->counts, c->ch_ids, n_ids, c->D, c->master, c->snorm, c->shift,
+                           c->dot_old, s));
+  HIP_TRY(c, launch_reduce_stats(c->changed, c->snorm, c->shift, c->dot_old, c->k, c->red, s));
+  ST_TRY(rebuild_tiles(c, c->changed));
+  HIP_TRY(c, hipEventRecord(c->ev[4], s));
+  double red[3];
+  HIP_TRY(c, hipMemcpyAsync(red, c->red, sizeof(red), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  std::swap(c->a, c->a_prev);
+  std::swap(c->lo, c->lo_prev);
+  std::swap(c->hi, c->hi_prev);
+  c->have_prev = true;
+  c->force_all = false;
+  c->assigned = false;
+  c->last_changed = n_ids;
+  c->iter += 1;
+  if (st_out) {
+    st_out->objective_assign = red[0];
+    st_out->objective_update = red[1];
+    st_out->max_shift_sq = red[2];
+    st_out->ms_update = elapsed(c->ev[3], c->ev[4]);
+  }
+  return SKM_OK;
+}
+
+skm_status skm_iterate(skm_ctx *c, int32_t max_iter, skm_iter_stats *per_iter, int32_t *n_done,
+                       int32_t *converged) {
+  ST_TRY(check_ctx(c));
+  if (max_iter <= 0) max_iter = c->cfg.max_iter;
+  int32_t done = 0;
+  int32_t conv = 0;
+  for (int32_t t = 0; t < max_iter; ++t) {
+    skm_iter_stats st{};
+    ST_TRY(skm_assign(c, &st));
+    done += 1;
+    const bool paper = c->cfg.stop_rule == SKM_STOP_PAPER;
+    if (paper && c->iter >= 1 &&
+        (st.moved == 0 || (double)st.moved < c->cfg.min_moved_frac * (double)c->N)) {
+      conv = 1;
+      if (per_iter) per_iter[t] = st;
+      break;
+    }
+    ST_TRY(skm_update(c, &st));
+    if (per_iter) per_iter[t] = st;
+    if (paper && st.max_shift_sq < c->cfg.max_shift_sq) {
+      conv = 1;
+      break;
+    }
+  }
+  if (n_done) *n_done = done;
+  if (converged) *converged = conv;
+  return SKM_OK;
+}
+
+skm_status skm_assign_new(skm_ctx *c, const skm_csr *docs, int32_t *out_assign, double *out_score,
+                          void *stream) {
+  ST_TRY(check_ctx(c));
+  ST_TRY(check_csr_header(docs, c->D));
+  if (!out_assign || !out_score) return fail(SKM_E_INVALID, "output pointer is NULL");
+  const int64_t n = docs->n_rows;
+  if (n == 0) return SKM_OK;
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  std::vector<void *> tmp;
+  auto talloc = [&](auto **p, size_t bytes) -> skm_status {
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(bytes, 1));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SKM_E_NOMEM, "temporary device allocation failed");
+    }
+    tmp.push_back(q);
+    *p = static_cast<std::remove_reference_t<decltype(*p)>>(q);
+    return SKM_OK;
+  };
+  auto release = [&]() {
+    for (void *q : tmp) (void)hipFree(q);
+  };
+  DevRows r;
+  skm_status st = upload_rows(c, docs, c->D, false, s, talloc, &r);
+  if (st != SKM_OK) {
+    release();
+    return st;
+  }
+  int32_t *a = nullptr, *flag_rows = nullptr, *counters = nullptr;
+  double *lo = nullptr, *hi = nullptr, *flag_L = nullptr, *score = nullptr;
+  uint8_t *flag_mode = nullptr;
+  unsigned long long *stat = nullptr;
+  if ((st = talloc(&a, n * 4)) != SKM_OK || (st = talloc(&flag_rows, n * 4)) != SKM_OK ||
+      (st = talloc(&counters, 32)) != SKM_OK || (st = talloc(&lo, n * 8)) != SKM_OK ||
+      (st = talloc(&hi, n * 8)) != SKM_OK || (st = talloc(&flag_L, n * 8)) != SKM_OK ||
+      (st = talloc(&score, n * 8)) != SKM_OK || (st = talloc(&flag_mode, n)) != SKM_OK ||
+      (st = talloc(&stat, 64)) != SKM_OK) {
+    release();
+    return st;
+  }
+  ScoreArgs sa = base_args(c);
+  sa.indptr = r.indptr;
+  sa.indices = r.indices;
+  sa.values = r.values;
+  sa.xl1 = r.xl1;
+  sa.n_rows = n;
+  sa.a_out = a;
+  sa.lo_out = lo;
+  sa.hi_out = hi;
+  sa.flag_rows = flag_rows;
+  sa.flag_L = flag_L;
+  sa.flag_mode = flag_mode;
+  sa.counters = counters;
+  sa.stat = stat;
+  sa.no_exact = 0;
+  hipError_t e = launch_fill_i32(counters, 0, 8, s);
+  if (e == hipSuccess) e = launch_fill_i32(reinterpret_cast<int32_t *>(stat), 0, 16, s);
+  if (e == hipSuccess) e = launch_score(sa, c->prec, s);
+  if (e == hipSuccess) {
+    ExactArgs x{sa, c->master, c->D, exact_waves()};
+    e = launch_exact(x, c->prec, s);
+  }
+  if (e == hipSuccess)
+    e = launch_exact_scores(r.indptr, r.indices, r.values, n, a, c->master, c->D, score, s);
+  const hipMemcpyKind kind = docs->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (e == hipSuccess) e = hipMemcpyAsync(out_assign, a, n * 4, kind, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(out_score, score, n * 8, kind, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  release();
+  if (e != hipSuccess) return device_fail(c, "skm_assign_new", e);
+  return SKM_OK;
+}
+
+skm_status skm_get_assignments(const skm_ctx *c, int32_t *out, int32_t on_device) {
+  ST_TRY(check_ctx(c));
+  if (!out) return fail(SKM_E_INVALID, "out is NULL");
+  const int32_t *src = c->assigned ? c->a : c->a_prev;
+  if (!c->assigned && !c->have_prev) return fail(SKM_E_STATE, "no assignment yet");
+  hipError_t e = hipMemcpyAsync(out, src, sizeof(int32_t) * c->N,
+                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return device_fail(const_cast<skm_ctx *>(c), "get_assignments", e);
+  return SKM_OK;
+}
+
+skm_status skm_get_centroids(const skm_ctx *c, double *out, int32_t on_device) {
+  ST_TRY(check_ctx(c));
+  if (!out) return fail(SKM_E_INVALID, "out is NULL");
+  hipError_t e = hipMemcpyAsync(out, c->master, sizeof(double) * c->k * c->D,
+                                on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return device_fail(const_cast<skm_ctx *>(c), "get_centroids", e);
+  return SKM_OK;
+}
+
+skm_status skm_set_centroids(skm_ctx *c, const double *centroids) {
+  ST_TRY(check_ctx(c));
+  if (!centroids) return fail(SKM_E_INVALID, "centroids is NULL");
+  HIP_TRY(c, hipMemcpyAsync(c->master, centroids, sizeof(double) * c->k * c->D,
+                            hipMemcpyHostToDevice, c->stream));
+  ST_TRY(rebuild_tiles(c, nullptr));
+  HIP_TRY(c, launch_fill_u8(c->changed, 1, c->k, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->force_all = true;
+  c->have_prev = false;
+  c->assigned = false;
+  c->last_changed = c->k;
+  return SKM_OK;
+}
+
+skm_status skm_get_tile(const skm_ctx *c, void *codes, size_t codes_bytes, float *scales,
+                        int64_t *ld) {
+  ST_TRY(check_ctx(c));
+  const size_t need = (size_t)c->D * c->ld * c->esize;
+  if (ld) *ld = c->ld;
+  if (codes) {
+    if (codes_bytes < need) return fail(SKM_E_INVALID, "codes buffer too small");
+    HIP_TRY(const_cast<skm_ctx *>(c),
+            hipMemcpyAsync(codes, c->tile, need, hipMemcpyDeviceToHost, c->stream));
+  }
+  if (scales)
+    HIP_TRY(const_cast<skm_ctx *>(c),
+            hipMemcpyAsync(scales, c->scale, sizeof(float) * c->k, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(const_cast<skm_ctx *>(c), hipStreamSynchronize(c->stream));
+  return SKM_OK;
+}
+
+skm_status skm_get_changed(const skm_ctx *c, uint8_t *out) {
+  ST_TRY(check_ctx(c));
+  if (!out) return fail(SKM_E_INVALID, "out is NULL");
+  HIP_TRY(const_cast<skm_ctx *>(c),
+          hipMemcpyAsync(out, c->changed, c->k, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(const_cast<skm_ctx *>(c), hipStreamSynchronize(c->stream));
+  return SKM_OK;
+}
+
+skm_status skm_score_dense(skm_ctx *c, const skm_csr *docs, float *out) {
+  ST_TRY(check_ctx(c));
+  ST_TRY(check_csr_header(docs, c->D));
+  if (!out) return fail(SKM_E_INVALID, "out is NULL");
+  const int64_t n = docs->n_rows;
+  if (n == 0) return SKM_OK;
+  std::vector<void *> tmp;
+  auto talloc = [&](auto **p, size_t bytes) -> skm_status {
+    void *q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(bytes, 1)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SKM_E_NOMEM, "temporary device allocation failed");
+    }
+    tmp.push_back(q);
+    *p = static_cast<std::remove_reference_t<decltype(*p)>>(q);
+    return SKM_OK;
+  };
+  auto release = [&]() {
+    for (void *q : tmp) (void)hipFree(q);
+  };
+  DevRows r;
+  skm_status st = upload_rows(c, docs, c->D, false, c->stream, talloc, &r);
+  float *d_out = nullptr;
+  if (st == SKM_OK) st = talloc(&d_out, sizeof(float) * n * c->k);
+  if (st != SKM_OK) {
+    release();
+    return st;
+  }
+  hipError_t e = launch_score_dense(r.indptr, r.indices, r.values, n, c->tile, c->ld, c->k, c->scale,
+                                    c->prec, d_out, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, d_out, sizeof(float) * n * c->k, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  release();
+  if (e != hipSuccess) return device_fail(c, "score_dense", e);
+  return SKM_OK;
+}
+
+double skm_error_bound(const skm_ctx *c, double s, int64_t nnz, double l1) {
+  if (!c) return -1.0;
+  return bound_kappa(nnz, c->uq) * s + bound_abs(nnz, l1, c->abs_coef);
+}
+
+skm_status skm_get_index(const skm_ctx *c, int32_t level, int64_t *offsets, uint32_t *entries,
+                         int64_t *n_entries) {
+  (void)level;
+  (void)offsets;
+  (void)entries;
+  (void)n_entries;
+  ST_TRY(check_ctx(c));
+  return fail(SKM_E_UNSUPPORTED, "index not built");
+}
+
+}  // extern "C"

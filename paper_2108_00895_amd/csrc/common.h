@@ -1,0 +1,168 @@
+// Device helpers shared by the kernels of libskm: wavefront primitives, the
+// scoring-copy encodings and the certified error bound.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <math.h>
+
+#include "../../include/skm.h"
+
+namespace skm {
+
+constexpr int kWave = 64;
+constexpr int kColsPerLane = 8;
+constexpr int kChunk = kWave * kColsPerLane;  // centroid columns per wave pass
+constexpr int kBandCap = 256;                 // exact-tier band kept in LDS per row
+
+__host__ __device__ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// ---------------------------------------------------------------- wave helpers
+
+__device__ inline int lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ inline float readlane_f(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+__device__ inline uint64_t lanemask_lt() {
+  const int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ inline double shfl_xor_d(double v, int m) {
+  return __shfl_xor(v, m, kWave);
+}
+
+// Lexicographic "better": higher score, then lower index.
+__device__ inline bool better(float s, int j, float bs, int bj) {
+  return s > bs || (s == bs && j < bj);
+}
+__device__ inline bool better_d(double s, int j, double bs, int bj) {
+  return s > bs || (s == bs && j < bj);
+}
+
+// Merge (b1, j1, b2) top-two summaries across the wave; every lane ends with
+// the wave's result.  b2 is the best score among all candidates other than j1.
+__device__ inline void wave_top2(float &b1, int &j1, float &b2) {
+#pragma unroll
+  for (int m = 1; m < kWave; m <<= 1) {
+    float o1 = __shfl_xor(b1, m, kWave);
+    int oj = __shfl_xor(j1, m, kWave);
+    float o2 = __shfl_xor(b2, m, kWave);
+    if (better(o1, oj, b1, j1)) {
+      b2 = fmaxf(b1, o2);
+      b1 = o1;
+      j1 = oj;
+    } else {
+      b2 = fmaxf(b2, o1);
+    }
+  }
+}
+
+__device__ inline void wave_best_d(double &s, int &j) {
+#pragma unroll
+  for (int m = 1; m < kWave; m <<= 1) {
+    double os = shfl_xor_d(s, m);
+    int oj = __shfl_xor(j, m, kWave);
+    if (better_d(os, oj, s, j)) {
+      s = os;
+      j = oj;
+    }
+  }
+}
+
+__device__ inline double wave_sum_d(double v) {
+#pragma unroll
+  for (int m = 1; m < kWave; m <<= 1) v += shfl_xor_d(v, m);
+  return v;
+}
+
+__device__ inline int64_t wave_sum_i64(int64_t v) {
+#pragma unroll
+  for (int m = 1; m < kWave; m <<= 1) v += __shfl_xor(v, m, kWave);
+  return v;
+}
+
+// ------------------------------------------------------- scoring-copy encodings
+// All conversions start from the FP64 centroid value and round once, to nearest
+// with ties to even.  Centroid values are >= 0.
+
+// bfloat16: 8 significant bits, binary32's exponent range.
+__host__ __device__ inline uint16_t encode_bf16(double c) {
+  if (!(c > 0.0)) return 0;
+  if (c < 0x1p-126) {                       // subnormal: spacing 2^-133
+    double m = rint(ldexp(c, 133));
+    return (uint16_t)m;                     // m == 128 encodes 2^-126 correctly
+  }
+  int ex;
+  double m = frexp(c, &ex);                 // c = m * 2^ex, m in [0.5, 1)
+  double q = rint(m * 256.0);               // 8 significant bits
+  if (q == 256.0) {
+    q = 128.0;
+    ex += 1;
+  }
+  int e_field = ex - 1 + 127;
+  if (e_field >= 255) return 0x7F80;        // overflow to +inf (not reached: c <= 1)
+  return (uint16_t)((e_field << 7) | ((int)q - 128));
+}
+
+// FP8 E4M3 (OCP): bias 7, 3 mantissa bits, max 448, subnormal spacing 2^-9.
+// v must already be divided by the centroid's power-of-two scale.
+__host__ __device__ inline uint8_t encode_e4m3(double v) {
+  if (!(v > 0.0)) return 0;
+  if (v < 0x1p-6) {
+    double m = rint(v * 512.0);             // m == 8 encodes 2^-6 correctly
+    return (uint8_t)m;
+  }
+  int ex;
+  double m = frexp(v, &ex);
+  double q = rint(m * 16.0);                // 4 significant bits
+  if (q == 16.0) {
+    q = 8.0;
+    ex += 1;
+  }
+  int e_field = ex - 1 + 7;
+  int code = (e_field << 3) | ((int)q - 8);
+  return (uint8_t)(code > 0x7E ? 0x7E : code);   // saturate at 448
+}
+
+// Least e with cmax <= 448 * 2^e (0 for cmax == 0).
+__host__ __device__ inline int e4m3_scale_exp(double cmax) {
+  if (!(cmax > 0.0)) return 0;
+  int e;
+  frexp(cmax / 448.0, &e);
+  e += 1;
+  while (cmax <= ldexp(448.0, e - 1)) e -= 1;
+  while (cmax > ldexp(448.0, e)) e += 1;
+  return e;
+}
+
+// ------------------------------------------------------------- error bound
+// A low-precision score s^ = fl32(sum_t x_t * c^_t) of a row with n terms,
+// where |c^_t - c_t| <= u_q * c_t + a (a: absolute term of the encoding, scaled),
+// and the FP32 sum runs as n fused multiply-adds (one rounding each):
+//   |s^ - S^| <= g_n * S^,   g_n = n u / (1 - n u), u = 2^-24   (recursive sum)
+//   |S^ - s|  <= u_q * s + a * ||x||_1
+// which gives |s^ - s| <= kappa * s^ + A with
+//   kappa = (g_n + u_q / (1 - u_q)) / (1 - g_n),  A = a ||x||_1 / (1 - u_q).
+// Both are inflated slightly so the FP64 evaluation of the test stays safe.
+__host__ __device__ inline double bound_kappa(int64_t n, double uq) {
+  const double u = 0x1p-24;
+  double nn = (double)(n > 0 ? n : 1);
+  double g = nn * u / (1.0 - nn * u);
+  double k = (g + uq / (1.0 - uq)) / (1.0 - g);
+  return k * (1.0 + 0x1p-20) + 0x1p-60;
+}
+
+__host__ __device__ inline double bound_abs(int64_t n, double l1, double abs_coef) {
+  return abs_coef * l1 + (double)(n > 0 ? n : 1) * 0x1p-140;
+}
+
+// Bound on |fl64(sum_t x_t c_t) - s| for the FP64 rescoring (n products).
+__host__ __device__ inline double exact_err(int64_t n, double s) {
+  double nn = (double)(n > 0 ? n : 1) + 2.0;
+  return nn * 0x1p-52 * fabs(s) + 0x1p-1000;
+}
+
+}  // namespace skm

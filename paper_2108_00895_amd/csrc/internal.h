@@ -1,0 +1,185 @@
+// Internal declarations of libskm: the context, kernel argument blocks and the
+// launchers each kernel file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace skm {
+
+// ------------------------------------------------------------ argument blocks
+
+struct ScoreArgs {
+  // rows
+  const int64_t *indptr;
+  const int32_t *indices;
+  const float *values;
+  const double *xl1;          // per-row L1 norm (FP8 absolute error term)
+  int64_t n_rows;
+  // scoring copy, term-major [n_cols][ld]
+  const uint8_t *tile;
+  int64_t ld;
+  int32_t k;
+  const float *scale;         // per-centroid scale (FP8) or nullptr
+  // Sec. 3.1: rows whose previous centroid is unchanged score the compacted
+  // copy of the changed centroids and keep the previous one as a candidate
+  const int32_t *a_prev;      // nullptr: no NCC
+  const uint8_t *changed;
+  const uint8_t *tile_ch;
+  int64_t ld_ch;
+  int32_t n_ch;
+  const int32_t *ch_ids;
+  const double *prev_lo;
+  const double *prev_hi;
+  // Sec. 3.2: per-row candidate lists (nullptr: no index)
+  const int64_t *cand_off;    // [n_rows + 1]; a row with cand_off[i] < 0 marker uses the dense path
+  const int32_t *cand;
+  // bound
+  double uq;
+  double abs_coef;
+  int32_t no_exact;
+  // outputs
+  int32_t *a_out;
+  double *lo_out;
+  double *hi_out;
+  int32_t *flag_rows;
+  double *flag_L;
+  uint8_t *flag_mode;         // 0 dense all, 1 NCC, 2 candidate list
+  int32_t *counters;          // [0] flagged rows, [1] band overflows
+  unsigned long long *stat;   // [0] centroids scored, [1] NCC rows, [2] index rows
+};
+
+struct ExactArgs {
+  ScoreArgs s;
+  const double *master;       // k x D FP64 centroids
+  int64_t D;
+  int32_t max_waves;
+};
+
+struct Buf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace skm
+
+struct skm_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool poisoned = false;
+  skm_config cfg{};
+
+  int64_t N = 0, D = 0, Z = 0;
+  int32_t k = 0;
+  int64_t ld = 0;      // tile row stride (centroid columns, padded)
+  int prec = SKM_FP32;
+  int esize = 4;       // bytes per scoring code
+  double uq = 0, abs_coef = 0;
+
+  size_t hbm_bytes = 0;
+  std::vector<void *> allocations;
+
+  // rows (CSR) and per-row constants
+  int64_t *indptr = nullptr;
+  int32_t *indices = nullptr;
+  float *values = nullptr;
+  double *xl1 = nullptr;
+  double *xl2 = nullptr;
+
+  // centroids
+  double *master = nullptr;    // k x D FP64, unit rows
+  double *S = nullptr;         // k x D FP64 member sums (rows of changed clusters)
+  uint8_t *tile = nullptr;     // D x ld codes
+  float *scale = nullptr;      // [ld]
+  double *snorm = nullptr;     // ||S_j|| of the current membership
+  double *shift = nullptr;     // per-cluster ||dc||^2 of the last update
+  double *dot_old = nullptr;   // S_j . c_j(old) of the last update
+  uint8_t *changed = nullptr;  // k flags
+  int32_t *ch_ids = nullptr;   // compacted changed ids (ascending)
+  int32_t n_ch = 0;
+  uint8_t *tile_ch = nullptr;  // D x ld compacted copy
+  int64_t ld_ch = 0;
+
+  // assignment state
+  int32_t *a = nullptr;        // current assignment
+  int32_t *a_prev = nullptr;   // assignment that produced the current centroids
+  double *lo = nullptr, *hi = nullptr;   // certified interval of x_i . c_{a_i}
+  double *lo_prev = nullptr, *hi_prev = nullptr;  // the same for a_prev
+
+  // scratch
+  int32_t *flag_rows = nullptr;
+  double *flag_L = nullptr;
+  uint8_t *flag_mode = nullptr;
+  int32_t *counters = nullptr;
+  unsigned long long *stat = nullptr;
+  int32_t *hist = nullptr;     // [nblk][k]
+  int32_t *counts = nullptr;   // [k]
+  int64_t *offsets = nullptr;  // [k + 1]
+  int32_t *members = nullptr;  // [N]
+  double *red = nullptr;       // reduction outputs
+  int32_t *ids_count = nullptr;
+  int64_t nblk = 0;
+
+  // state
+  int32_t iter = 0;            // completed updates
+  bool assigned = false;       // an assignment is pending an update
+  bool have_prev = false;      // a_prev / changed are meaningful for NCC
+  bool force_all = true;       // next update recomputes every cluster
+  int32_t last_changed = 0;    // changed centroids before the last assignment
+  int64_t last_moved = 0;
+
+  hipEvent_t ev[8] = {};
+};
+
+namespace skm {
+
+// kernels_score.hip
+hipError_t launch_score(const ScoreArgs &a, int prec, hipStream_t s);
+hipError_t launch_exact(const ExactArgs &a, int prec, hipStream_t s);
+hipError_t launch_score_dense(const int64_t *indptr, const int32_t *indices, const float *values,
+                              int64_t n_rows, const uint8_t *tile, int64_t ld, int32_t k,
+                              const float *scale, int prec, float *out, hipStream_t s);
+hipError_t launch_exact_scores(const int64_t *indptr, const int32_t *indices, const float *values,
+                               int64_t n_rows, const int32_t *a, const double *master, int64_t D,
+                               double *out, hipStream_t s);
+
+// kernels_update.hip
+hipError_t launch_row_stats(const int64_t *indptr, const int32_t *indices, const float *values,
+                            int64_t n_rows, int64_t D, double *xl1, double *xl2, int32_t *bad,
+                            hipStream_t s);
+hipError_t launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
+hipError_t launch_seed(const int64_t *indptr, const int32_t *indices, const float *values,
+                       const int32_t *rows, int32_t k, int64_t D, double *master, hipStream_t s);
+hipError_t launch_fp8_scales(const double *master, int32_t k, int64_t D, const uint8_t *changed,
+                             float *scale, hipStream_t s);
+hipError_t launch_quantize(const double *master, int32_t k, int64_t D, const uint8_t *changed,
+                           const float *scale, int prec, uint8_t *tile, int64_t ld, hipStream_t s);
+hipError_t launch_count_moved(const int32_t *a, const int32_t *a_prev, int64_t n,
+                              unsigned long long *out, hipStream_t s);
+hipError_t launch_mark_changed(const int32_t *a, const int32_t *a_prev, int64_t n, uint8_t *changed,
+                               hipStream_t s);
+hipError_t launch_compact_changed(const uint8_t *changed, int32_t k, int32_t *ids, int32_t *count,
+                                  hipStream_t s);
+hipError_t launch_gather_tile(const uint8_t *tile, int64_t ld, int64_t D, int esize,
+                              const int32_t *ids, int32_t n, uint8_t *out, int64_t ld_out,
+                              hipStream_t s);
+hipError_t launch_bucket(const int32_t *a, int64_t n, int32_t k, int64_t nblk, int32_t *hist,
+                         int32_t *counts, int64_t *offsets, int32_t *members, hipStream_t s);
+hipError_t launch_sum_members(const int64_t *indptr, const int32_t *indices, const float *values,
+                              const int64_t *offsets, const int32_t *members, const int32_t *ids,
+                              int32_t n_ids, int64_t D, double *S, hipStream_t s);
+hipError_t launch_renorm(const double *S, const int32_t *counts, const int32_t *ids, int32_t n_ids,
+                         int64_t D, double *master, double *snorm, double *shift, double *dot_old,
+                         hipStream_t s);
+hipError_t launch_reduce_stats(const uint8_t *changed, const double *snorm, const double *shift,
+                               const double *dot_old, int32_t k, double *out, hipStream_t s);
+
+}  // namespace skm

@@ -1,0 +1,455 @@
+// Assignment kernels: low-precision gather-FMA scoring with a fused top-two
+// argmax and certification (paper Sec. 2, Sec. 3.1), and the exact FP64 tier.
+//
+// Layout: the scoring copy of the centroids is term-major, codes[t * ld + j],
+// so one term's codes for 512 consecutive centroids are contiguous: a wavefront
+// scores one row against a 512-centroid chunk, lane l holding centroids
+// [8l, 8l + 8) of the chunk, and walks the row's terms; each step is one
+// coalesced 16 B (BF16), 32 B (FP32) or 8 B (FP8) load per lane plus eight FMAs.
+// Row terms are broadcast with v_readlane from a 64-term register batch.
+#include "internal.h"
+
+namespace skm {
+namespace {
+
+template <int P>
+struct Codes;
+
+template <>
+struct Codes<SKM_FP32> {
+  static constexpr int kBytes = 4;
+  struct raw_t {
+    float4 a, b;
+  };
+  __device__ static raw_t load(const uint8_t *p) {
+    const float4 *q = reinterpret_cast<const float4 *>(p);
+    return raw_t{q[0], q[1]};
+  }
+  __device__ static void fma8(const raw_t &r, float x, float acc[8]) {
+    acc[0] = fmaf(x, r.a.x, acc[0]);
+    acc[1] = fmaf(x, r.a.y, acc[1]);
+    acc[2] = fmaf(x, r.a.z, acc[2]);
+    acc[3] = fmaf(x, r.a.w, acc[3]);
+    acc[4] = fmaf(x, r.b.x, acc[4]);
+    acc[5] = fmaf(x, r.b.y, acc[5]);
+    acc[6] = fmaf(x, r.b.z, acc[6]);
+    acc[7] = fmaf(x, r.b.w, acc[7]);
+  }
+};
+
+template <>
+struct Codes<SKM_BF16> {
+  static constexpr int kBytes = 2;
+  using raw_t = uint4;
+  __device__ static raw_t load(const uint8_t *p) { return *reinterpret_cast<const uint4 *>(p); }
+  __device__ static void fma8(const raw_t &r, float x, float acc[8]) {
+    // little-endian: the lower half-word is the lower column
+    acc[0] = fmaf(x, __uint_as_float(r.x << 16), acc[0]);
+    acc[1] = fmaf(x, __uint_as_float(r.x & 0xFFFF0000u), acc[1]);
+    acc[2] = fmaf(x, __uint_as_float(r.y << 16), acc[2]);
+    acc[3] = fmaf(x, __uint_as_float(r.y & 0xFFFF0000u), acc[3]);
+    acc[4] = fmaf(x, __uint_as_float(r.z << 16), acc[4]);
+    acc[5] = fmaf(x, __uint_as_float(r.z & 0xFFFF0000u), acc[5]);
+    acc[6] = fmaf(x, __uint_as_float(r.w << 16), acc[6]);
+    acc[7] = fmaf(x, __uint_as_float(r.w & 0xFFFF0000u), acc[7]);
+  }
+};
+
+template <>
+struct Codes<SKM_FP8_E4M3> {
+  static constexpr int kBytes = 1;
+  using raw_t = uint2;
+  __device__ static raw_t load(const uint8_t *p) { return *reinterpret_cast<const uint2 *>(p); }
+  __device__ static void fma8(const raw_t &r, float x, float acc[8]) {
+    // v_cvt_pk_f32_fp8 decodes two OCP E4M3 bytes (word_sel picks bytes 2,3)
+    auto p0 = __builtin_amdgcn_cvt_pk_f32_fp8((int)r.x, false);
+    auto p1 = __builtin_amdgcn_cvt_pk_f32_fp8((int)r.x, true);
+    auto p2 = __builtin_amdgcn_cvt_pk_f32_fp8((int)r.y, false);
+    auto p3 = __builtin_amdgcn_cvt_pk_f32_fp8((int)r.y, true);
+    acc[0] = fmaf(x, p0[0], acc[0]);
+    acc[1] = fmaf(x, p0[1], acc[1]);
+    acc[2] = fmaf(x, p1[0], acc[2]);
+    acc[3] = fmaf(x, p1[1], acc[3]);
+    acc[4] = fmaf(x, p2[0], acc[4]);
+    acc[5] = fmaf(x, p2[1], acc[5]);
+    acc[6] = fmaf(x, p3[0], acc[6]);
+    acc[7] = fmaf(x, p3[1], acc[7]);
+  }
+};
+
+__device__ inline int64_t uniform64(int64_t v) {
+  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+  uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ inline int32_t uniform32(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// acc[c] += sum over the row's terms of x_t * code[t][c0 + 8*lane + c], in
+// ascending term order, one FMA per term (the order the error bound assumes).
+template <int P>
+__device__ inline void score_chunk(int64_t b, int64_t e, const int32_t *__restrict__ indices,
+                                   const float *__restrict__ values, const uint8_t *__restrict__ tile,
+                                   int64_t ld, int64_t c0, float acc[8]) {
+  using C = Codes<P>;
+  const int lane = lane_id();
+  const uint8_t *base = tile + (c0 + (int64_t)lane * kColsPerLane) * C::kBytes;
+  const int64_t rowbytes = ld * C::kBytes;
+  for (int64_t q0 = b; q0 < e; q0 += kWave) {
+    const int cnt = (int)((e - q0) < kWave ? (e - q0) : kWave);
+    int my_t = 0;
+    float my_x = 0.f;
+    if (lane < cnt) {
+      my_t = indices[q0 + lane];
+      my_x = values[q0 + lane];
+    }
+    int u = 0;
+    for (; u + 4 <= cnt; u += 4) {
+      const int t0 = __builtin_amdgcn_readlane(my_t, u);
+      const int t1 = __builtin_amdgcn_readlane(my_t, u + 1);
+      const int t2 = __builtin_amdgcn_readlane(my_t, u + 2);
+      const int t3 = __builtin_amdgcn_readlane(my_t, u + 3);
+      typename C::raw_t r0 = C::load(base + (int64_t)t0 * rowbytes);
+      typename C::raw_t r1 = C::load(base + (int64_t)t1 * rowbytes);
+      typename C::raw_t r2 = C::load(base + (int64_t)t2 * rowbytes);
+      typename C::raw_t r3 = C::load(base + (int64_t)t3 * rowbytes);
+      C::fma8(r0, readlane_f(my_x, u), acc);
+      C::fma8(r1, readlane_f(my_x, u + 1), acc);
+      C::fma8(r2, readlane_f(my_x, u + 2), acc);
+      C::fma8(r3, readlane_f(my_x, u + 3), acc);
+    }
+    for (; u < cnt; ++u) {
+      const int t0 = __builtin_amdgcn_readlane(my_t, u);
+      typename C::raw_t r0 = C::load(base + (int64_t)t0 * rowbytes);
+      C::fma8(r0, readlane_f(my_x, u), acc);
+    }
+  }
+}
+
+struct RowPlan {
+  const uint8_t *tile;
+  int64_t ld;
+  int32_t ncols;
+  const int32_t *colmap;   // column -> centroid id, nullptr = identity
+  bool ncc;
+  int32_t ap;
+};
+
+__device__ inline RowPlan plan_row(const ScoreArgs &a, int64_t row, bool allow_ncc) {
+  RowPlan p{a.tile, a.ld, a.k, nullptr, false, -1};
+  if (allow_ncc && a.a_prev) {
+    const int32_t ap = a.a_prev[row];
+    if (!a.changed[ap]) {
+      p.tile = a.tile_ch;
+      p.ld = a.ld_ch;
+      p.ncols = a.n_ch;
+      p.colmap = a.ch_ids;
+      p.ncc = true;
+      p.ap = ap;
+    }
+  }
+  return p;
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_score(ScoreArgs a) {
+  const int wave = uniform32(threadIdx.x >> 6);
+  const int64_t rix = (int64_t)blockIdx.x * 4 + wave;
+  if (rix >= a.n_rows) return;
+  const int lane = lane_id();
+  const int64_t row = rix;
+  const int64_t b = uniform64(a.indptr[row]);
+  const int64_t e = uniform64(a.indptr[row + 1]);
+  const RowPlan pl = plan_row(a, row, true);
+
+  float b1 = -INFINITY, b2 = -INFINITY;
+  int j1 = 0x7FFFFFFF;
+  for (int64_t c0 = 0; c0 < pl.ncols; c0 += kChunk) {
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    score_chunk<P>(b, e, a.indices, a.values, pl.tile, pl.ld, c0, acc);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int64_t col = c0 + lane * kColsPerLane + c;
+      if (col < pl.ncols) {
+        const int j = pl.colmap ? pl.colmap[col] : (int)col;
+        float s = acc[c];
+        if (a.scale) s *= a.scale[j];
+        if (better(s, j, b1, j1)) {
+          b2 = b1;
+          b1 = s;
+          j1 = j;
+        } else if (s > b2) {
+          b2 = s;
+        }
+      }
+    }
+  }
+  wave_top2(b1, j1, b2);
+  if (lane != 0) return;
+
+  const int64_t n = e - b;
+  const double kap = bound_kappa(n, a.uq);
+  const double A = bound_abs(n, a.xl1[row], a.abs_coef);
+  auto lo_of = [&](float s) { return s == -INFINITY ? -INFINITY : (double)s - (kap * (double)s + A); };
+  auto hi_of = [&](float s) { return s == -INFINITY ? -INFINITY : (double)s + (kap * (double)s + A); };
+
+  int win;
+  double wlo, whi, L;
+  bool certain;
+  if (!pl.ncc) {
+    win = j1;
+    wlo = lo_of(b1);
+    whi = hi_of(b1);
+    certain = wlo > hi_of(b2);
+    L = wlo;
+  } else {
+    const double plo = a.prev_lo[row], phi = a.prev_hi[row];
+    if (b1 == -INFINITY) {
+      win = pl.ap;
+      wlo = plo;
+      whi = phi;
+      certain = true;
+      L = plo;
+    } else if (plo >= lo_of(b1)) {
+      win = pl.ap;
+      wlo = plo;
+      whi = phi;
+      certain = plo > hi_of(b1);
+      L = plo;
+    } else {
+      win = j1;
+      wlo = lo_of(b1);
+      whi = hi_of(b1);
+      certain = wlo > fmax(phi, hi_of(b2));
+      L = wlo;
+    }
+  }
+  atomicAdd(&a.stat[0], (unsigned long long)pl.ncols);
+  if (pl.ncc) atomicAdd(&a.stat[1], 1ull);
+  if (certain || a.no_exact) {
+    a.a_out[row] = win;
+    a.lo_out[row] = wlo;
+    a.hi_out[row] = whi;
+  } else {
+    const int f = atomicAdd(&a.counters[0], 1);
+    a.flag_rows[f] = (int32_t)row;
+    a.flag_L[f] = L;
+    a.flag_mode[f] = pl.ncc ? 1 : 0;
+  }
+}
+
+__device__ inline double dot64(int64_t b, int64_t e, const int32_t *__restrict__ indices,
+                               const float *__restrict__ values, const double *__restrict__ crow) {
+  double s = 0.0;
+  for (int64_t q = b; q < e; ++q) s = fma((double)values[q], crow[indices[q]], s);
+  return s;
+}
+
+// Exact tier.  For each flagged row: recompute the low-precision scores, keep
+// the band of candidates whose upper bound reaches the row's certified lower
+// bound L (every centroid that can be the true maximum), and decide among them
+// in FP64 against the FP64 centroids (lowest index on ties).  When the band
+// exceeds kBandCap every candidate is rescored in FP64.
+template <int P>
+__global__ __launch_bounds__(256) void k_exact(ExactArgs x) {
+  __shared__ int32_t band_all[4][kBandCap];
+  const ScoreArgs &a = x.s;
+  const int wave = uniform32(threadIdx.x >> 6);
+  const int lane = lane_id();
+  int32_t *band = band_all[wave];
+  const int32_t n_flag = uniform32(*(volatile int32_t *)&a.counters[0]);
+  for (int64_t f = (int64_t)blockIdx.x * 4 + wave; f < n_flag; f += (int64_t)gridDim.x * 4) {
+    const int64_t row = uniform64(a.flag_rows[f]);
+    const double L = a.flag_L[f];
+    const bool ncc_row = a.flag_mode[f] == 1;
+    const int64_t b = uniform64(a.indptr[row]);
+    const int64_t e = uniform64(a.indptr[row + 1]);
+    const int64_t n = e - b;
+    RowPlan pl{a.tile, a.ld, a.k, nullptr, false, -1};
+    if (ncc_row) {
+      pl.tile = a.tile_ch;
+      pl.ld = a.ld_ch;
+      pl.ncols = a.n_ch;
+      pl.colmap = a.ch_ids;
+      pl.ncc = true;
+      pl.ap = a.a_prev[row];
+    }
+    const double kap = bound_kappa(n, a.uq);
+    const double A = bound_abs(n, a.xl1[row], a.abs_coef);
+    int nb = 0;
+    for (int64_t c0 = 0; c0 < pl.ncols; c0 += kChunk) {
+      float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      score_chunk<P>(b, e, a.indices, a.values, pl.tile, pl.ld, c0, acc);
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int64_t col = c0 + lane * kColsPerLane + c;
+        bool in = false;
+        int j = 0;
+        if (col < pl.ncols) {
+          j = pl.colmap ? pl.colmap[col] : (int)col;
+          double s = acc[c];
+          if (a.scale) s *= (double)a.scale[j];
+          in = s + (kap * s + A) >= L;
+        }
+        const uint64_t m = __ballot(in);
+        if (in) {
+          const int pos = nb + __popcll(m & lanemask_lt());
+          if (pos < kBandCap) band[pos] = j;
+        }
+        nb += __popcll(m);
+      }
+    }
+    if (pl.ncc) {
+      if (lane == 0 && nb < kBandCap) band[nb] = pl.ap;
+      nb += 1;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    double bs = -INFINITY;
+    int bj = 0x7FFFFFFF;
+    if (nb <= kBandCap) {
+      for (int i = lane; i < nb; i += kWave) {
+        const int j = band[i];
+        const double s = dot64(b, e, a.indices, a.values, x.master + (int64_t)j * x.D);
+        if (better_d(s, j, bs, bj)) {
+          bs = s;
+          bj = j;
+        }
+      }
+    } else {
+      for (int64_t col = lane; col < pl.ncols; col += kWave) {
+        const int j = pl.colmap ? pl.colmap[col] : (int)col;
+        const double s = dot64(b, e, a.indices, a.values, x.master + (int64_t)j * x.D);
+        if (better_d(s, j, bs, bj)) {
+          bs = s;
+          bj = j;
+        }
+      }
+      if (pl.ncc && lane == 0) {
+        const double s = dot64(b, e, a.indices, a.values, x.master + (int64_t)pl.ap * x.D);
+        if (better_d(s, pl.ap, bs, bj)) {
+          bs = s;
+          bj = pl.ap;
+        }
+      }
+    }
+    wave_best_d(bs, bj);
+    if (lane == 0) {
+      const double err = exact_err(n, bs);
+      a.a_out[row] = bj;
+      a.lo_out[row] = bs - err;
+      a.hi_out[row] = bs + err;
+      if (nb > kBandCap) atomicAdd(&a.counters[1], 1);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// Dense low-precision score matrix (diagnostic): one wave per row.
+template <int P>
+__global__ __launch_bounds__(256) void k_score_dense(const int64_t *indptr, const int32_t *indices,
+                                                     const float *values, int64_t n_rows,
+                                                     const uint8_t *tile, int64_t ld, int32_t k,
+                                                     const float *scale, float *out) {
+  const int wave = uniform32(threadIdx.x >> 6);
+  const int64_t row = (int64_t)blockIdx.x * 4 + wave;
+  if (row >= n_rows) return;
+  const int lane = lane_id();
+  const int64_t b = uniform64(indptr[row]);
+  const int64_t e = uniform64(indptr[row + 1]);
+  for (int64_t c0 = 0; c0 < k; c0 += kChunk) {
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    score_chunk<P>(b, e, indices, values, tile, ld, c0, acc);
+    for (int c = 0; c < 8; ++c) {
+      const int64_t col = c0 + lane * kColsPerLane + c;
+      if (col < k) out[row * k + col] = scale ? acc[c] * scale[col] : acc[c];
+    }
+  }
+}
+
+// FP64 dot product of each row with its assigned centroid: one wave per row,
+// lanes over terms, fixed-shape wave sum.
+__global__ __launch_bounds__(256) void k_exact_scores(const int64_t *indptr, const int32_t *indices,
+                                                      const float *values, int64_t n_rows,
+                                                      const int32_t *asg, const double *master,
+                                                      int64_t D, double *out) {
+  const int wave = uniform32(threadIdx.x >> 6);
+  const int64_t row = (int64_t)blockIdx.x * 4 + wave;
+  if (row >= n_rows) return;
+  const int lane = lane_id();
+  const int64_t b = indptr[row], e = indptr[row + 1];
+  const double *c = master + (int64_t)asg[row] * D;
+  double s = 0.0;
+  for (int64_t q = b + lane; q < e; q += kWave) s = fma((double)values[q], c[indices[q]], s);
+  s = wave_sum_d(s);
+  if (lane == 0) out[row] = s;
+}
+
+template <int P>
+hipError_t launch_score_t(const ScoreArgs &a, hipStream_t s) {
+  if (a.n_rows <= 0) return hipSuccess;
+  const int64_t blocks = (a.n_rows + 3) / 4;
+  hipLaunchKernelGGL(k_score<P>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_exact_t(const ExactArgs &x, hipStream_t s) {
+  hipLaunchKernelGGL(k_exact<P>, dim3((unsigned)x.max_waves / 4), dim3(256), 0, s, x);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_score(const ScoreArgs &a, int prec, hipStream_t s) {
+  switch (prec) {
+    case SKM_FP32: return launch_score_t<SKM_FP32>(a, s);
+    case SKM_BF16: return launch_score_t<SKM_BF16>(a, s);
+    case SKM_FP8_E4M3: return launch_score_t<SKM_FP8_E4M3>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_exact(const ExactArgs &x, int prec, hipStream_t s) {
+  switch (prec) {
+    case SKM_FP32: return launch_exact_t<SKM_FP32>(x, s);
+    case SKM_BF16: return launch_exact_t<SKM_BF16>(x, s);
+    case SKM_FP8_E4M3: return launch_exact_t<SKM_FP8_E4M3>(x, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_score_dense(const int64_t *indptr, const int32_t *indices, const float *values,
+                              int64_t n_rows, const uint8_t *tile, int64_t ld, int32_t k,
+                              const float *scale, int prec, float *out, hipStream_t s) {
+  if (n_rows <= 0) return hipSuccess;
+  const dim3 g((unsigned)((n_rows + 3) / 4)), blk(256);
+  switch (prec) {
+    case SKM_FP32:
+      hipLaunchKernelGGL(k_score_dense<SKM_FP32>, g, blk, 0, s, indptr, indices, values, n_rows, tile,
+                         ld, k, nullptr, out);
+      break;
+    case SKM_BF16:
+      hipLaunchKernelGGL(k_score_dense<SKM_BF16>, g, blk, 0, s, indptr, indices, values, n_rows, tile,
+                         ld, k, nullptr, out);
+      break;
+    case SKM_FP8_E4M3:
+      hipLaunchKernelGGL(k_score_dense<SKM_FP8_E4M3>, g, blk, 0, s, indptr, indices, values, n_rows,
+                         tile, ld, k, scale, out);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_exact_scores(const int64_t *indptr, const int32_t *indices, const float *values,
+                               int64_t n_rows, const int32_t *asg, const double *master, int64_t D,
+                               double *out, hipStream_t s) {
+  if (n_rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_exact_scores, dim3((unsigned)((n_rows + 3) / 4)), dim3(256), 0, s, indptr,
+                     indices, values, n_rows, asg, master, D, out);
+  return hipGetLastError();
+}
+
+}  // namespace skm

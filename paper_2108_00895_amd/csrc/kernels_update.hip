@@ -1,0 +1,509 @@
+// Update-side kernels (paper Sec. 2: a centroid is its members' sum divided by
+// the sum's length) and the small helpers around them.
+//
+// The centroid update is atomic-free in its floating point: rows are bucketed
+// by cluster with a stable counting sort (integer atomics only for counts), and
+// one workgroup owns one cluster's FP64 sum, adding member rows in ascending
+// row order.  Unchanged membership therefore reproduces a centroid bit for bit,
+// which is what lets Sec. 3.1 skip unchanged centroids exactly.
+#include "internal.h"
+
+namespace skm {
+namespace {
+
+constexpr int64_t kBucketBlock = 8192;   // rows per counting-sort block
+
+__device__ inline int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+__device__ inline int64_t gstride() { return (int64_t)gridDim.x * blockDim.x; }
+
+unsigned grid_for(int64_t n, int threads, int64_t cap = 65536) {
+  int64_t g = (n + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+// Block-wide fixed-shape sum over 256 threads (deterministic order).
+__device__ inline double block_sum_256(double v, double *sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ void k_row_stats(const int64_t *indptr, const int32_t *indices, const float *values,
+                            int64_t n_rows, int64_t D, double *xl1, double *xl2, int32_t *bad) {
+  const int lane = lane_id();
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n_rows) return;
+  const int64_t b = indptr[row], e = indptr[row + 1];
+  int flags = 0;
+  if (e < b) flags |= 1;
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t q = b + lane; q < e; q += kWave) {
+    const float v = values[q];
+    const int32_t t = indices[q];
+    if (!(v > 0.f) || !isfinite(v)) flags |= 2;
+    if (t < 0 || t >= D) flags |= 4;
+    if (q > b && indices[q - 1] >= t) flags |= 8;
+    s1 += (double)v;
+    s2 += (double)v * (double)v;
+  }
+  s1 = wave_sum_d(s1);
+  s2 = wave_sum_d(s2);
+  for (int m = 1; m < kWave; m <<= 1) flags |= __shfl_xor(flags, m, kWave);
+  if (lane == 0) {
+    xl1[row] = s1;
+    xl2[row] = sqrt(s2);
+    if (e > b && fabs(sqrt(s2) - 1.0) > 1e-5) flags |= 16;
+    if (e == b) flags |= 32;
+    if (flags) atomicOr(bad, flags);
+  }
+}
+
+template <typename T>
+__global__ void k_fill(T *p, T v, int64_t n) {
+  for (int64_t i = gtid(); i < n; i += gstride()) p[i] = v;
+}
+
+// c_j = x_r / ||x_r|| for r = rows[j]; the master rows are zero beforehand.
+__global__ void k_seed(const int64_t *indptr, const int32_t *indices, const float *values,
+                       const int32_t *rows, int64_t D, double *master) {
+  __shared__ double sh[256];
+  const int j = blockIdx.x;
+  const int64_t r = rows[j];
+  const int64_t b = indptr[r], e = indptr[r + 1];
+  double ss = 0.0;
+  for (int64_t q = b + threadIdx.x; q < e; q += 256) ss += (double)values[q] * (double)values[q];
+  const double nrm = sqrt(block_sum_256(ss, sh));
+  for (int64_t q = b + threadIdx.x; q < e; q += 256)
+    master[(int64_t)j * D + indices[q]] = (double)values[q] / nrm;
+}
+
+__global__ void k_fp8_scales(const double *master, int64_t D, const uint8_t *changed, float *scale) {
+  __shared__ double sh[256];
+  const int j = blockIdx.x;
+  if (changed && !changed[j]) return;
+  double m = 0.0;
+  for (int64_t t = threadIdx.x; t < D; t += 256) m = fmax(m, master[(int64_t)j * D + t]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) scale[j] = ldexpf(1.0f, e4m3_scale_exp(sh[0]));
+}
+
+// Scoring copy: transpose 64 centroids x 64 terms of the FP64 master through
+// LDS and encode (term-major output, 64 consecutive codes per term row).
+template <int P>
+__global__ __launch_bounds__(256) void k_quantize(const double *master, int32_t k, int64_t D,
+                                                  const uint8_t *changed, const float *scale,
+                                                  uint8_t *tile, int64_t ld) {
+  __shared__ double buf[64][65];
+  const int64_t j0 = (int64_t)blockIdx.x * 64;
+  const int64_t t0 = (int64_t)blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  int any = 0;
+  if (threadIdx.x < 64) {
+    const int64_t j = j0 + threadIdx.x;
+    any = (j < k) && (changed == nullptr || changed[j]);
+  }
+  if (!__syncthreads_or(any)) return;
+  for (int jj = ty; jj < 64; jj += 4) {
+    const int64_t j = j0 + jj, t = t0 + tx;
+    buf[jj][tx] = (j < k && t < D) ? master[j * D + t] : 0.0;
+  }
+  __syncthreads();
+  for (int tt = ty; tt < 64; tt += 4) {
+    const int64_t t = t0 + tt, j = j0 + tx;
+    if (t >= D || j >= k) continue;
+    const double c = buf[tx][tt];
+    if (P == SKM_FP32) {
+      reinterpret_cast<float *>(tile)[t * ld + j] = (float)c;
+    } else if (P == SKM_BF16) {
+      reinterpret_cast<uint16_t *>(tile)[t * ld + j] = encode_bf16(c);
+    } else {
+      const int e = ilogbf(scale[j]);
+      tile[t * ld + j] = encode_e4m3(ldexp(c, -e));
+    }
+  }
+}
+
+__global__ void k_count_moved(const int32_t *a, const int32_t *a_prev, int64_t n,
+                              unsigned long long *out) {
+  int64_t c = 0;
+  for (int64_t i = gtid(); i < n; i += gstride()) c += (a[i] != a_prev[i]);
+  c = wave_sum_i64(c);
+  if (lane_id() == 0 && c) atomicAdd(out, (unsigned long long)c);
+}
+
+__global__ void k_mark_changed(const int32_t *a, const int32_t *a_prev, int64_t n, uint8_t *changed) {
+  for (int64_t i = gtid(); i < n; i += gstride()) {
+    const int32_t x = a[i], y = a_prev[i];
+    if (x != y) {
+      changed[x] = 1;
+      changed[y] = 1;
+    }
+  }
+}
+
+// Ascending list of changed ids: one workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_compact_changed(const uint8_t *changed, int32_t k,
+                                                          int32_t *ids, int32_t *count) {
+  __shared__ int32_t sh[1024];
+  const int t = threadIdx.x;
+  const int per = (k + 1023) / 1024;
+  const int lo = t * per, hi = min(k, lo + per);
+  int c = 0;
+  for (int j = lo; j < hi; ++j) c += changed[j] ? 1 : 0;
+  sh[t] = c;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {   // Hillis-Steele inclusive scan
+    int v = (t >= off) ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += v;
+    __syncthreads();
+  }
+  int pos = sh[t] - c;
+  for (int j = lo; j < hi; ++j)
+    if (changed[j]) ids[pos++] = j;
+  if (t == 1023) *count = sh[1023];
+}
+
+template <typename T>
+__global__ void k_gather_tile(const T *tile, int64_t ld, const int32_t *ids, int32_t n, T *out,
+                              int64_t ld_out) {
+  const int64_t t = blockIdx.x;
+  for (int o = threadIdx.x; o < n; o += blockDim.x) out[t * ld_out + o] = tile[t * ld + ids[o]];
+}
+
+// ---- stable counting sort of rows by cluster
+
+__global__ void k_block_hist(const int32_t *a, int64_t n, int32_t k, int32_t *hist) {
+  const int64_t b = blockIdx.x;
+  const int64_t lo = b * kBucketBlock, hi = min(n, lo + kBucketBlock);
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) atomicAdd(&hist[b * k + a[i]], 1);
+}
+
+// For each cluster: exclusive prefix over blocks in place, total into counts.
+__global__ void k_block_scan(int32_t *hist, int64_t nblk, int32_t k, int32_t *counts) {
+  const int64_t j = gtid();
+  if (j >= k) return;
+  int32_t run = 0;
+  for (int64_t b = 0; b < nblk; ++b) {
+    const int32_t v = hist[b * k + j];
+    hist[b * k + j] = run;
+    run += v;
+  }
+  counts[j] = run;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_counts(const int32_t *counts, int32_t k,
+                                                      int64_t *offsets) {
+  __shared__ int64_t sh[1024];
+  const int t = threadIdx.x;
+  const int per = (k + 1023) / 1024;
+  const int lo = t * per, hi = min(k, lo + per);
+  int64_t c = 0;
+  for (int j = lo; j < hi; ++j) c += counts[j];
+  sh[t] = c;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int64_t v = (t >= off) ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += v;
+    __syncthreads();
+  }
+  int64_t pos = sh[t] - c;
+  for (int j = lo; j < hi; ++j) {
+    offsets[j] = pos;
+    pos += counts[j];
+  }
+  if (t == 1023) offsets[k] = sh[1023];
+}
+
+// One wavefront per block of rows, in row order: rank among equal clusters in
+// the 64-row batch by ballots, running per-(block, cluster) counter by atomics
+// that only this wavefront touches.
+__global__ __launch_bounds__(64) void k_block_scatter(const int32_t *a, int64_t n, int32_t k,
+                                                      int32_t *hist, const int64_t *offsets,
+                                                      int32_t *members) {
+  const int64_t b = blockIdx.x;
+  const int64_t lo = b * kBucketBlock, hi = min(n, lo + kBucketBlock);
+  const int lane = lane_id();
+  for (int64_t base = lo; base < hi; base += kWave) {
+    const int64_t i = base + lane;
+    const bool valid = i < hi;
+    const int32_t cl = valid ? a[i] : -1;
+    uint64_t remaining = __ballot(valid);
+    uint64_t peers = 0;
+    while (remaining) {
+      const int leader = __ffsll((unsigned long long)remaining) - 1;
+      const int32_t lc = __shfl(cl, leader, kWave);
+      const uint64_t m = __ballot(valid && cl == lc);
+      if (valid && cl == lc) peers = m;
+      remaining &= ~m;
+    }
+    const int leader = valid ? __ffsll((unsigned long long)peers) - 1 : 0;
+    int32_t old = 0;
+    if (valid && leader == lane) old = atomicAdd(&hist[b * k + cl], __popcll(peers));
+    old = __shfl(old, leader, kWave);
+    if (valid) {
+      const int rank = __popcll(peers & lanemask_lt());
+      members[offsets[cl] + old + rank] = (int32_t)i;
+    }
+  }
+}
+
+// S_j = sum of member rows in ascending row order (member lists are sorted),
+// FP64, for each listed cluster.  One workgroup per cluster, so no atomics:
+// entries of one row have distinct terms, and rows are separated by barriers.
+__global__ __launch_bounds__(256) void k_sum_members(const int64_t *indptr, const int32_t *indices,
+                                                     const float *values, const int64_t *offsets,
+                                                     const int32_t *members, const int32_t *ids,
+                                                     int64_t D, double *S) {
+  const int32_t j = ids[blockIdx.x];
+  double *Sj = S + (int64_t)j * D;
+  for (int64_t t = threadIdx.x; t < D; t += 256) Sj[t] = 0.0;
+  __syncthreads();
+  const int64_t r0 = offsets[j], r1 = offsets[j + 1];
+  for (int64_t r = r0; r < r1; ++r) {
+    const int64_t i = members[r];
+    const int64_t b = indptr[i], e = indptr[i + 1];
+    for (int64_t q = b + threadIdx.x; q < e; q += 256) Sj[indices[q]] += (double)values[q];
+    __syncthreads();
+  }
+}
+
+// c_j = S_j / ||S_j|| (empty clusters keep c_j), with the per-cluster shift
+// ||c_j(new) - c_j(old)||^2 and S_j . c_j(old).
+__global__ __launch_bounds__(256) void k_renorm(const double *S, const int32_t *counts,
+                                                const int32_t *ids, int64_t D, double *master,
+                                                double *snorm, double *shift, double *dot_old) {
+  __shared__ double sh[256];
+  const int32_t j = ids[blockIdx.x];
+  const double *Sj = S + (int64_t)j * D;
+  double *Mj = master + (int64_t)j * D;
+  if (counts[j] == 0) {
+    if (threadIdx.x == 0) {
+      snorm[j] = 0.0;
+      shift[j] = 0.0;
+      dot_old[j] = 0.0;
+    }
+    return;
+  }
+  double ss = 0.0;
+  for (int64_t t = threadIdx.x; t < D; t += 256) ss += Sj[t] * Sj[t];
+  const double nrm = sqrt(block_sum_256(ss, sh));
+  double sh2 = 0.0, dot = 0.0;
+  for (int64_t t = threadIdx.x; t < D; t += 256) {
+    const double s = Sj[t];
+    const double o = Mj[t];
+    const double c = s / nrm;
+    const double d = c - o;
+    sh2 += d * d;
+    dot += s * o;
+    Mj[t] = c;
+  }
+  sh2 = block_sum_256(sh2, sh);
+  dot = block_sum_256(dot, sh);
+  if (threadIdx.x == 0) {
+    snorm[j] = nrm;
+    shift[j] = sh2;
+    dot_old[j] = dot;
+  }
+}
+
+// out[0] = J_A = sum_j S_j . c_j(old), out[1] = J_U = sum_j ||S_j||,
+// out[2] = max_j shift_j, all over one workgroup in a fixed order.
+__global__ __launch_bounds__(1024) void k_reduce_stats(const uint8_t *changed, const double *snorm,
+                                                       const double *shift, const double *dot_old,
+                                                       int32_t k, double *out) {
+  __shared__ double sa[1024], su[1024], sm[1024];
+  const int t = threadIdx.x;
+  double ja = 0.0, ju = 0.0, mx = 0.0;
+  for (int j = t; j < k; j += 1024) {
+    const bool ch = changed[j] != 0;
+    ja += ch ? dot_old[j] : snorm[j];
+    ju += snorm[j];
+    if (ch) mx = fmax(mx, shift[j]);
+  }
+  sa[t] = ja;
+  su[t] = ju;
+  sm[t] = mx;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (t < w) {
+      sa[t] += sa[t + w];
+      su[t] += su[t + w];
+      sm[t] = fmax(sm[t], sm[t + w]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    out[0] = sa[0];
+    out[1] = su[0];
+    out[2] = sm[0];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_row_stats(const int64_t *indptr, const int32_t *indices, const float *values,
+                            int64_t n_rows, int64_t D, double *xl1, double *xl2, int32_t *bad,
+                            hipStream_t s) {
+  if (n_rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_row_stats, dim3((unsigned)((n_rows + 3) / 4)), dim3(256), 0, s, indptr,
+                     indices, values, n_rows, D, xl1, xl2, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill<uint8_t>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed(const int64_t *indptr, const int32_t *indices, const float *values,
+                       const int32_t *rows, int32_t k, int64_t D, double *master, hipStream_t s) {
+  hipError_t err = launch_fill_f64(master, 0.0, (int64_t)k * D, s);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_seed, dim3((unsigned)k), dim3(256), 0, s, indptr, indices, values, rows, D,
+                     master);
+  return hipGetLastError();
+}
+
+hipError_t launch_fp8_scales(const double *master, int32_t k, int64_t D, const uint8_t *changed,
+                             float *scale, hipStream_t s) {
+  hipLaunchKernelGGL(k_fp8_scales, dim3((unsigned)k), dim3(256), 0, s, master, D, changed, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_quantize(const double *master, int32_t k, int64_t D, const uint8_t *changed,
+                           const float *scale, int prec, uint8_t *tile, int64_t ld, hipStream_t s) {
+  const dim3 g((unsigned)((k + 63) / 64), (unsigned)((D + 63) / 64)), b(256);
+  switch (prec) {
+    case SKM_FP32:
+      hipLaunchKernelGGL(k_quantize<SKM_FP32>, g, b, 0, s, master, k, D, changed, scale, tile, ld);
+      break;
+    case SKM_BF16:
+      hipLaunchKernelGGL(k_quantize<SKM_BF16>, g, b, 0, s, master, k, D, changed, scale, tile, ld);
+      break;
+    case SKM_FP8_E4M3:
+      hipLaunchKernelGGL(k_quantize<SKM_FP8_E4M3>, g, b, 0, s, master, k, D, changed, scale, tile,
+                         ld);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_count_moved(const int32_t *a, const int32_t *a_prev, int64_t n,
+                              unsigned long long *out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_count_moved, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, a, a_prev, n,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mark_changed(const int32_t *a, const int32_t *a_prev, int64_t n, uint8_t *changed,
+                               hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mark_changed, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, a, a_prev, n,
+                     changed);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_changed(const uint8_t *changed, int32_t k, int32_t *ids, int32_t *count,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(k_compact_changed, dim3(1), dim3(1024), 0, s, changed, k, ids, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_tile(const uint8_t *tile, int64_t ld, int64_t D, int esize,
+                              const int32_t *ids, int32_t n, uint8_t *out, int64_t ld_out,
+                              hipStream_t s) {
+  if (n <= 0 || D <= 0) return hipSuccess;
+  const dim3 g((unsigned)D), b(256);
+  switch (esize) {
+    case 4:
+      hipLaunchKernelGGL(k_gather_tile<uint32_t>, g, b, 0, s, (const uint32_t *)tile, ld, ids, n,
+                         (uint32_t *)out, ld_out);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_gather_tile<uint16_t>, g, b, 0, s, (const uint16_t *)tile, ld, ids, n,
+                         (uint16_t *)out, ld_out);
+      break;
+    case 1:
+      hipLaunchKernelGGL(k_gather_tile<uint8_t>, g, b, 0, s, tile, ld, ids, n, out, ld_out);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_bucket(const int32_t *a, int64_t n, int32_t k, int64_t nblk, int32_t *hist,
+                         int32_t *counts, int64_t *offsets, int32_t *members, hipStream_t s) {
+  hipError_t err = launch_fill_i32(hist, 0, nblk * k, s);
+  if (err != hipSuccess) return err;
+  if (n > 0) {
+    hipLaunchKernelGGL(k_block_hist, dim3((unsigned)nblk), dim3(256), 0, s, a, n, k, hist);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+  }
+  hipLaunchKernelGGL(k_block_scan, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, s, hist, nblk, k,
+                     counts);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, counts, k, offsets);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+  if (n > 0) {
+    hipLaunchKernelGGL(k_block_scatter, dim3((unsigned)nblk), dim3(64), 0, s, a, n, k, hist, offsets,
+                       members);
+    err = hipGetLastError();
+  }
+  return err;
+}
+
+hipError_t launch_sum_members(const int64_t *indptr, const int32_t *indices, const float *values,
+                              const int64_t *offsets, const int32_t *members, const int32_t *ids,
+                              int32_t n_ids, int64_t D, double *S, hipStream_t s) {
+  if (n_ids <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sum_members, dim3((unsigned)n_ids), dim3(256), 0, s, indptr, indices, values,
+                     offsets, members, ids, D, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_renorm(const double *S, const int32_t *counts, const int32_t *ids, int32_t n_ids,
+                         int64_t D, double *master, double *snorm, double *shift, double *dot_old,
+                         hipStream_t s) {
+  if (n_ids <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_renorm, dim3((unsigned)n_ids), dim3(256), 0, s, S, counts, ids, D, master,
+                     snorm, shift, dot_old);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_stats(const uint8_t *changed, const double *snorm, const double *shift,
+                               const double *dot_old, int32_t k, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_stats, dim3(1), dim3(1024), 0, s, changed, snorm, shift, dot_old, k,
+                     out);
+  return hipGetLastError();
+}
+
+}  // namespace skm

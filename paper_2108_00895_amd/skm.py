@@ -1,0 +1,318 @@
+"""ctypes binding of libskm (include/skm.h): argument marshalling only.
+
+Every step of the clustering runs in the HIP kernels behind the C ABI; this
+module converts Python arguments (numpy arrays for host data, torch CUDA
+tensors for device data) into the C structs and back.  It has no fallback: if
+libskm.so is missing or cannot be loaded, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libskm.so")
+
+SKM_OK, SKM_E_INVALID, SKM_E_NOMEM, SKM_E_DEVICE, SKM_E_STATE, SKM_E_UNSUPPORTED = range(6)
+FP32, BF16, FP8_E4M3 = 0, 1, 2
+NCC, INDEX, NO_EXACT = 1, 2, 4
+STOP_PAPER, STOP_FIXED = 0, 1
+PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3}
+CODE_BYTES = {FP32: 4, BF16: 2, FP8_E4M3: 1}
+
+EXPORTED = [
+    "skm_config_default", "skm_init", "skm_assign", "skm_update", "skm_iterate",
+    "skm_assign_new", "skm_get_assignments", "skm_get_centroids", "skm_set_centroids",
+    "skm_get_tile", "skm_get_changed", "skm_score_dense", "skm_error_bound", "skm_get_index",
+    "skm_hbm_bytes", "skm_last_error", "skm_destroy",
+]
+
+
+class SkmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"skm status {status}: {msg}")
+        self.status = status
+
+
+class Csr(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("n_cols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("indptr", ctypes.c_void_p), ("indices", ctypes.c_void_p),
+                ("values", ctypes.c_void_p), ("on_device", ctypes.c_int32)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("n_lambda", ctypes.c_int32), ("lambda_", ctypes.c_double * 8),
+                ("index_min_changed", ctypes.c_int32), ("stop_rule", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("min_moved_frac", ctypes.c_double),
+                ("max_shift_sq", ctypes.c_double), ("init_rows", ctypes.c_void_p),
+                ("init_centroids", ctypes.c_void_p), ("hbm_budget_bytes", ctypes.c_size_t),
+                ("stream", ctypes.c_void_p), ("validate", ctypes.c_int32)]
+
+
+class IterStats(ctypes.Structure):
+    _fields_ = [("iter", ctypes.c_int32), ("changed_centroids", ctypes.c_int32),
+                ("moved", ctypes.c_int64), ("flagged", ctypes.c_int64),
+                ("band_overflow", ctypes.c_int64), ("ncc_rows", ctypes.c_int64),
+                ("index_rows", ctypes.c_int64), ("mean_candidates", ctypes.c_double),
+                ("objective_assign", ctypes.c_double), ("objective_update", ctypes.c_double),
+                ("max_shift_sq", ctypes.c_double), ("ms_assign", ctypes.c_float),
+                ("ms_exact", ctypes.c_float), ("ms_update", ctypes.c_float),
+                ("ms_index", ctypes.c_float)]
+
+    def asdict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load():
+    """Load libskm.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    # One HIP runtime per process: when PyTorch is present its libamdhip64 is
+    # loaded first, and libskm's dependency on the same soname binds to it.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, st = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int
+    P = ctypes.POINTER
+    lib.skm_config_default.argtypes = [P(Config)]
+    lib.skm_config_default.restype = None
+    lib.skm_init.argtypes = [P(Csr), P(Config), P(vp)]
+    lib.skm_init.restype = st
+    lib.skm_assign.argtypes = [vp, P(IterStats)]
+    lib.skm_assign.restype = st
+    lib.skm_update.argtypes = [vp, P(IterStats)]
+    lib.skm_update.restype = st
+    lib.skm_iterate.argtypes = [vp, i32, vp, P(i32), P(i32)]
+    lib.skm_iterate.restype = st
+    lib.skm_assign_new.argtypes = [vp, P(Csr), vp, vp, vp]
+    lib.skm_assign_new.restype = st
+    lib.skm_get_assignments.argtypes = [vp, vp, i32]
+    lib.skm_get_assignments.restype = st
+    lib.skm_get_centroids.argtypes = [vp, vp, i32]
+    lib.skm_get_centroids.restype = st
+    lib.skm_set_centroids.argtypes = [vp, vp]
+    lib.skm_set_centroids.restype = st
+    lib.skm_get_tile.argtypes = [vp, vp, ctypes.c_size_t, vp, P(i64)]
+    lib.skm_get_tile.restype = st
+    lib.skm_get_changed.argtypes = [vp, vp]
+    lib.skm_get_changed.restype = st
+    lib.skm_score_dense.argtypes = [vp, P(Csr), vp]
+    lib.skm_score_dense.restype = st
+    lib.skm_error_bound.argtypes = [vp, ctypes.c_double, i64, ctypes.c_double]
+    lib.skm_error_bound.restype = ctypes.c_double
+    lib.skm_get_index.argtypes = [vp, i32, vp, vp, P(i64)]
+    lib.skm_get_index.restype = st
+    lib.skm_hbm_bytes.argtypes = [vp]
+    lib.skm_hbm_bytes.restype = ctypes.c_size_t
+    lib.skm_last_error.argtypes = []
+    lib.skm_last_error.restype = ctypes.c_char_p
+    lib.skm_destroy.argtypes = [vp]
+    lib.skm_destroy.restype = None
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != SKM_OK:
+        raise SkmError(status, load().skm_last_error().decode(errors="replace"))
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def make_csr(indptr, indices, values, n_cols):
+    """Csr struct + keep-alive tuple.  numpy arrays -> host; torch CUDA tensors -> device."""
+    if _is_torch(indptr):
+        import torch
+
+        assert indptr.dtype == torch.int64 and indices.dtype == torch.int32
+        assert values.dtype == torch.float32
+        assert indptr.is_cuda and indices.is_cuda and values.is_cuda
+        indptr, indices, values = indptr.contiguous(), indices.contiguous(), values.contiguous()
+        c = Csr(indptr.numel() - 1, n_cols, indices.numel(), indptr.data_ptr(),
+                indices.data_ptr(), values.data_ptr(), 1)
+        return c, (indptr, indices, values)
+    indptr = np.ascontiguousarray(indptr, dtype=np.int64)
+    indices = np.ascontiguousarray(indices, dtype=np.int32)
+    values = np.ascontiguousarray(values, dtype=np.float32)
+    c = Csr(len(indptr) - 1, n_cols, len(indices), indptr.ctypes.data, indices.ctypes.data,
+            values.ctypes.data, 0)
+    return c, (indptr, indices, values)
+
+
+@dataclass
+class Options:
+    precision: str = "fp32"
+    ncc: bool = False
+    index: bool = False
+    no_exact: bool = False
+    lambdas: tuple = (0.1, 0.25, 0.4, 0.6)
+    index_min_changed: int = 0
+    stop_rule: str = "paper"
+    max_iter: int = 100
+    min_moved_frac: float = 0.0
+    max_shift_sq: float = 1e-4
+    hbm_budget_bytes: int = 0
+    validate: bool = True
+
+
+class Context:
+    """One clustering problem resident on the GPU (wraps skm_ctx)."""
+
+    def __init__(self, csr, n_cols, k, init_rows=None, init_centroids=None, stream=None,
+                 **opts):
+        lib = load()
+        o = Options(**opts)
+        cfg = Config()
+        lib.skm_config_default(ctypes.byref(cfg))
+        cfg.k = k
+        cfg.precision = PRECISIONS[o.precision]
+        cfg.flags = (NCC if o.ncc else 0) | (INDEX if o.index else 0) | (NO_EXACT if o.no_exact else 0)
+        cfg.n_lambda = len(o.lambdas)
+        for i, lam in enumerate(o.lambdas):
+            cfg.lambda_[i] = lam
+        cfg.index_min_changed = o.index_min_changed
+        cfg.stop_rule = STOP_PAPER if o.stop_rule == "paper" else STOP_FIXED
+        cfg.max_iter = o.max_iter
+        cfg.min_moved_frac = o.min_moved_frac
+        cfg.max_shift_sq = o.max_shift_sq
+        cfg.hbm_budget_bytes = o.hbm_budget_bytes
+        cfg.validate = 1 if o.validate else 0
+        keep = []
+        if init_rows is not None:
+            r = np.ascontiguousarray(init_rows, dtype=np.int32)
+            keep.append(r)
+            cfg.init_rows = r.ctypes.data
+        if init_centroids is not None:
+            C = np.ascontiguousarray(init_centroids, dtype=np.float64)
+            keep.append(C)
+            cfg.init_centroids = C.ctypes.data
+        if stream is not None:
+            cfg.stream = stream
+        c, hold = make_csr(*csr, n_cols)
+        h = ctypes.c_void_p()
+        _check(lib.skm_init(ctypes.byref(c), ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self.k, self.n_cols, self.n_rows = k, n_cols, c.n_rows
+        self.precision = cfg.precision
+        self.opts = o
+
+    # -- lifecycle
+    def close(self):
+        if getattr(self, "_h", None):
+            load().skm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- steps
+    def assign(self):
+        st = IterStats()
+        _check(load().skm_assign(self._h, ctypes.byref(st)))
+        return st.asdict()
+
+    def update(self):
+        st = IterStats()
+        _check(load().skm_update(self._h, ctypes.byref(st)))
+        return st.asdict()
+
+    def iterate(self, max_iter=0):
+        n = max_iter if max_iter > 0 else self.opts.max_iter
+        arr = (IterStats * n)()
+        done, conv = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().skm_iterate(self._h, max_iter, arr, ctypes.byref(done), ctypes.byref(conv)))
+        return [arr[i].asdict() for i in range(done.value)], bool(conv.value)
+
+    def assign_new(self, csr, stream=None):
+        c, hold = make_csr(*csr, self.n_cols)
+        n = c.n_rows
+        if c.on_device:
+            import torch
+
+            dev = hold[0].device
+            a = torch.empty(n, dtype=torch.int32, device=dev)
+            s = torch.empty(n, dtype=torch.float64, device=dev)
+            _check(load().skm_assign_new(self._h, ctypes.byref(c), a.data_ptr(), s.data_ptr(),
+                                         stream))
+            return a, s
+        a = np.empty(n, dtype=np.int32)
+        s = np.empty(n, dtype=np.float64)
+        _check(load().skm_assign_new(self._h, ctypes.byref(c), a.ctypes.data, s.ctypes.data,
+                                     stream))
+        return a, s
+
+    # -- getters
+    def assignments(self):
+        out = np.empty(self.n_rows, dtype=np.int32)
+        _check(load().skm_get_assignments(self._h, out.ctypes.data, 0))
+        return out
+
+    def centroids(self):
+        out = np.empty((self.k, self.n_cols), dtype=np.float64)
+        _check(load().skm_get_centroids(self._h, out.ctypes.data, 0))
+        return out
+
+    def set_centroids(self, C):
+        C = np.ascontiguousarray(C, dtype=np.float64)
+        assert C.shape == (self.k, self.n_cols)
+        _check(load().skm_set_centroids(self._h, C.ctypes.data))
+
+    def tile(self):
+        """(codes [n_cols, k] as uint32/uint16/uint8, scales [k])."""
+        ld = ctypes.c_int64()
+        _check(load().skm_get_tile(self._h, None, 0, None, ctypes.byref(ld)))
+        dt = {FP32: np.uint32, BF16: np.uint16, FP8_E4M3: np.uint8}[self.precision]
+        buf = np.empty((self.n_cols, ld.value), dtype=dt)
+        sc = np.empty(self.k, dtype=np.float32)
+        _check(load().skm_get_tile(self._h, buf.ctypes.data, buf.nbytes, sc.ctypes.data,
+                                   ctypes.byref(ld)))
+        return buf[:, :self.k], sc
+
+    def changed(self):
+        out = np.empty(self.k, dtype=np.uint8)
+        _check(load().skm_get_changed(self._h, out.ctypes.data))
+        return out
+
+    def score_dense(self, csr):
+        c, hold = make_csr(*csr, self.n_cols)
+        out = np.empty((c.n_rows, self.k), dtype=np.float32)
+        _check(load().skm_score_dense(self._h, ctypes.byref(c), out.ctypes.data))
+        return out
+
+    def error_bound(self, s, nnz, l1):
+        return load().skm_error_bound(self._h, float(s), int(nnz), float(l1))
+
+    def index_level(self, level):
+        lib = load()
+        n = ctypes.c_int64()
+        off = np.empty(self.n_cols + 1, dtype=np.int64)
+        _check(lib.skm_get_index(self._h, level, off.ctypes.data, None, ctypes.byref(n)))
+        ent = np.empty(n.value, dtype=np.uint32)
+        _check(lib.skm_get_index(self._h, level, off.ctypes.data, ent.ctypes.data, ctypes.byref(n)))
+        return off, ent
+
+    def hbm_bytes(self):
+        return load().skm_hbm_bytes(self._h)

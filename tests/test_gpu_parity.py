@@ -1,0 +1,295 @@
+"""GPU path vs the CPU FP64 oracle, through the C ABI (needs an MI355X).
+
+Assignments must equal the oracle's bit for bit except rows whose FP64 top-two
+gap is below 1e-12; centroids and objectives must agree within relative 1e-5.
+Sizes span several 512-centroid chunks with a ragged tail.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import quant
+from paper_2108_00895_amd import Context, SkmError, skm
+
+from gpu_common import (assert_assign_equal, corpus, dense, rel_centroid_err, say, to_device)
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ["fp32", "bf16", "fp8"]
+
+
+@pytest.fixture(scope="module")
+def mid():
+    # 3000 rows, 9000 terms, k = 700: two 512-wide chunks, the second ragged
+    csr, c = corpus(3000, 9000, nnz_mean=60.0, nnz_max=400, seed=31)
+    rows = synth.seed_rows(c.n_docs, 700, 5)
+    return csr, c, rows
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_fp8_bf16_fp32_codes_decode_exactly(prec):
+    """One-term rows of value 1 read single codes back through the scoring
+    kernel: score == scale * decode(code), with codes from the format definitions."""
+    say("case: decode", prec)
+    D = 127
+    if prec == "fp8":
+        vals = np.array([quant.fp8_from_bits(b) for b in range(127)]) * 2.0 ** -9
+    else:
+        rng = np.random.default_rng(3)
+        vals = rng.random(D) ** 3
+    C = vals[None, :]
+    ip = np.arange(D + 1, dtype=np.int64)
+    ix = np.arange(D, dtype=np.int32)
+    v = np.ones(D, dtype=np.float32)
+    ctx = Context((ip, ix, v), D, 1, init_centroids=C, precision=prec)
+    codes, sc = ctx.tile()
+    S = ctx.score_dense((ip, ix, v))[:, 0]
+    if prec == "fp8":
+        assert sc[0] == 2.0 ** -9
+        assert np.array_equal(codes[:, 0], np.arange(127, dtype=np.uint8))
+        want = np.array([quant.fp8_from_bits(b) for b in range(127)]) * 2.0 ** -9
+    elif prec == "bf16":
+        assert np.array_equal(codes[:, 0], [quant.bf16_bits(x) for x in vals])
+        want = np.array([quant.bf16_round(x) for x in vals])
+    else:
+        want = vals.astype(np.float32).astype(np.float64)
+    np.testing.assert_array_equal(S.astype(np.float64), want)
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_tile_codes_match_format_definitions(prec, mid):
+    csr, c, rows = mid
+    say("case: tile codes", prec)
+    C = oracle.seed(csr, c.n_terms, rows[:40])
+    ctx = Context(csr, c.n_terms, 40, init_centroids=C, precision=prec)
+    codes, sc = ctx.tile()
+    for j in range(0, 40, 7):
+        want, s = quant.quantize_row(C[j], prec)
+        assert np.array_equal(codes[:, j], want), j
+        assert sc[j] == np.float32(s)
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_error_bound_holds_for_every_pair(prec, mid):
+    csr, c, rows = mid
+    say("case: bound", prec)
+    C = oracle.seed(csr, c.n_terms, rows[:300])
+    sub = synth.subset(*csr, np.arange(400))
+    ctx = Context(csr, c.n_terms, 300, init_centroids=C, precision=prec)
+    Sg = ctx.score_dense(sub).astype(np.float64)
+    Sr = oracle.scores(sub, C)
+    ip = sub[0]
+    nnz = np.diff(ip)
+    l1 = np.add.reduceat(sub[2].astype(np.float64), ip[:-1])
+    worst = 0.0
+    for i in range(Sg.shape[0]):
+        E = np.array([ctx.error_bound(s, nnz[i], l1[i]) for s in Sg[i]])
+        ratio = np.abs(Sg[i] - Sr[i]) / E
+        worst = max(worst, ratio.max())
+    assert worst <= 1.0, worst
+    say("  max |s^-s|/E =", worst)
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_first_assignment_equals_oracle(prec, mid):
+    csr, c, rows = mid
+    say("case: assign0", prec)
+    C0 = oracle.seed(csr, c.n_terms, rows)
+    a_ref, s1, s2 = oracle.assign(csr, C0)
+    ctx = Context(to_device(csr), c.n_terms, len(rows), init_rows=rows, precision=prec)
+    st = ctx.assign()
+    a = ctx.assignments()
+    n_tie = assert_assign_equal(a, a_ref, s1, s2, f"assign {prec}")
+    say(f"  flagged {st['flagged']} ties {n_tie}")
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_teacher_forced_step(prec, mid):
+    """Oracle centroids after three oracle iterations, fed to the GPU: one
+    assignment step must equal the oracle's."""
+    csr, c, rows = mid
+    say("case: teacher forced", prec)
+    ref = oracle.run(csr, c.n_terms, len(rows), rows, max_iter=3, stop_rule="fixed")
+    a_ref, s1, s2 = oracle.assign(csr, ref.C)
+    ctx = Context(csr, c.n_terms, len(rows), init_rows=rows, precision=prec)
+    ctx.set_centroids(ref.C)
+    ctx.assign()
+    assert_assign_equal(ctx.assignments(), a_ref, s1, s2, f"teacher forced {prec}")
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec,ncc", [("fp32", False), ("bf16", True), ("fp8", True),
+                                      ("fp32", True)])
+def test_trajectory_equals_oracle(prec, ncc, mid):
+    """Whole runs under the paper's stopping rule: every iteration's moved
+    count and assignment, the objectives and the final centroids."""
+    csr, c, rows = mid
+    say("case: trajectory", prec, ncc)
+    ref = oracle.run(csr, c.n_terms, len(rows), rows, max_iter=25)
+    ctx = Context(to_device(csr), c.n_terms, len(rows), init_rows=rows, precision=prec, ncc=ncc,
+                  max_iter=25)
+    stats, conv = ctx.iterate()
+    assert conv == ref.converged and len(stats) == len(ref.records)
+    for st, rec in zip(stats, ref.records):
+        assert st["moved"] == rec.moved, (st["iter"], st["moved"], rec.moved)
+        if rec.updated:
+            assert math.isclose(st["objective_assign"], rec.J_A, rel_tol=1e-9)
+            assert math.isclose(st["objective_update"], rec.J_U, rel_tol=1e-9)
+            assert math.isclose(st["max_shift_sq"], rec.max_shift_sq, rel_tol=1e-6, abs_tol=1e-14)
+    assert np.array_equal(ctx.assignments(), ref.a)
+    assert rel_centroid_err(ctx.centroids(), ref.C) < 1e-9
+    if ncc and len(stats) > 3:
+        assert stats[-1]["ncc_rows"] > 0
+    ctx.close()
+
+
+def test_small_workload_ten_iterations():
+    w = synth.SMALL
+    say("case: small workload", w.name)
+    csr = synth.generate(w.corpus)
+    rows = synth.seed_rows(w.corpus.n_docs, w.k, w.corpus.seed)
+    ref = oracle.run(csr, w.corpus.n_terms, w.k, rows, max_iter=10, stop_rule="fixed")
+    ctx = Context(csr, w.corpus.n_terms, w.k, init_rows=rows, precision="fp32",
+                  stop_rule="fixed", max_iter=10)
+    stats, conv = ctx.iterate()
+    assert len(stats) == 10 and not conv
+    for st, rec in zip(stats, ref.records):
+        assert st["moved"] == rec.moved
+        assert math.isclose(st["objective_update"], rec.J_U, rel_tol=1e-5)
+    assert np.array_equal(ctx.assignments(), ref.a)
+    assert rel_centroid_err(ctx.centroids(), ref.C) < 1e-5
+    ctx.close()
+
+
+def test_update_equals_oracle_update(mid):
+    csr, c, rows = mid
+    say("case: update")
+    ctx = Context(csr, c.n_terms, len(rows), init_rows=rows, precision="bf16")
+    ctx.assign()
+    a = ctx.assignments()
+    C0 = oracle.seed(csr, c.n_terms, rows)
+    st = ctx.update()
+    u = oracle.update(csr, a, C0)
+    assert rel_centroid_err(ctx.centroids(), u.C) < 1e-12
+    assert math.isclose(st["objective_update"], float(u.snorm.sum()), rel_tol=1e-12)
+    assert math.isclose(st["objective_assign"], float(u.dot_old.sum()), rel_tol=1e-12)
+    assert math.isclose(st["max_shift_sq"], float(u.shift_sq.max()), rel_tol=1e-9)
+    ctx.close()
+
+
+def test_assign_new_equals_oracle(mid):
+    csr, c, rows = mid
+    say("case: assign_new")
+    ref = oracle.run(csr, c.n_terms, len(rows), rows, max_iter=2, stop_rule="fixed")
+    new, _ = corpus(777, c.n_terms, nnz_mean=60.0, nnz_max=400, seed=99)
+    a_ref, s1, s2 = oracle.assign(new, ref.C)
+    for prec in PRECS:
+        ctx = Context(csr, c.n_terms, len(rows), init_rows=rows, precision=prec)
+        ctx.set_centroids(ref.C)
+        a, s = ctx.assign_new(new)
+        assert_assign_equal(a, a_ref, s1, s2, "assign_new " + prec)
+        np.testing.assert_allclose(s, s1, rtol=1e-12)
+        ad, sd = ctx.assign_new(to_device(new))
+        assert np.array_equal(ad.cpu().numpy(), a)
+        # empty request
+        e = (np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.float32))
+        a0, s0 = ctx.assign_new(e)
+        assert len(a0) == 0
+        ctx.close()
+
+
+def test_edge_cases():
+    say("case: edges")
+    csr, c = corpus(200, 500, nnz_mean=12.0, nnz_max=40, seed=8)
+    # k = 1
+    ctx = Context(csr, c.n_terms, 1, init_rows=[3], max_iter=5)
+    stats, conv = ctx.iterate()
+    ref = oracle.run(csr, c.n_terms, 1, [3], max_iter=5)
+    assert conv and len(stats) == len(ref.records)
+    assert rel_centroid_err(ctx.centroids(), ref.C) < 1e-12
+    ctx.close()
+    # duplicate seeds: the higher duplicate stays empty and keeps its centroid
+    ctx = Context(csr, c.n_terms, 3, init_rows=[5, 5, 17], stop_rule="fixed", max_iter=1)
+    ctx.iterate()
+    ref = oracle.run(csr, c.n_terms, 3, [5, 5, 17], max_iter=1, stop_rule="fixed")
+    assert np.array_equal(ctx.assignments(), ref.a)
+    assert np.array_equal(ctx.centroids()[1], ref.C[1])
+    ctx.close()
+    # a row sharing no term with any centroid goes to centroid 0
+    ip = np.array([0, 1, 2, 3], np.int64)
+    ix = np.array([0, 1, 2], np.int32)
+    v = np.ones(3, np.float32)
+    C = np.zeros((2, 4))
+    C[0, 3] = 1.0
+    C[1, 1] = 1.0
+    ctx = Context((ip, ix, v), 4, 2, init_centroids=C, precision="bf16")
+    ctx.assign()
+    assert ctx.assignments().tolist() == [0, 1, 0]
+    ctx.close()
+    # one row; k = n
+    one = synth.subset(*csr, [7])
+    ctx = Context(one, c.n_terms, 1, init_rows=[0])
+    ctx.assign()
+    assert ctx.assignments().tolist() == [0]
+    ctx.close()
+
+
+def test_long_rows_max_nnz():
+    say("case: long rows")
+    cc = synth.Corpus(300, 30000, 1500.0, 0.3, 1000, 2000, 1.05, seed=12)
+    csr = synth.generate(cc)
+    rows = synth.seed_rows(300, 37, 2)
+    ref = oracle.run(csr, cc.n_terms, 37, rows, max_iter=4, stop_rule="fixed")
+    for prec in ("bf16", "fp8"):
+        ctx = Context(csr, cc.n_terms, 37, init_rows=rows, precision=prec, ncc=True,
+                      stop_rule="fixed", max_iter=4)
+        ctx.iterate()
+        assert np.array_equal(ctx.assignments(), ref.a)
+        ctx.close()
+
+
+def test_deterministic_runs(mid):
+    csr, c, rows = mid
+    say("case: determinism")
+    out = []
+    for _ in range(2):
+        ctx = Context(to_device(csr), c.n_terms, len(rows), init_rows=rows, precision="bf16",
+                      ncc=True, stop_rule="fixed", max_iter=4)
+        ctx.iterate()
+        out.append((ctx.assignments(), ctx.centroids()))
+        ctx.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1].view(np.uint64), out[1][1].view(np.uint64))
+
+
+def test_error_paths():
+    say("case: errors")
+    csr, c = corpus(100, 300, nnz_mean=10.0, nnz_max=30, seed=4)
+    ip, ix, v = csr
+    bad = ix.copy()
+    bad[5] = 300
+    with pytest.raises(SkmError) as e:
+        Context((ip, bad, v), c.n_terms, 3, init_rows=[0, 1, 2])
+    assert e.value.status == skm.SKM_E_INVALID
+    with pytest.raises(SkmError) as e:
+        Context(csr, c.n_terms, 3, init_rows=[0, 1, 2], hbm_budget_bytes=1000)
+    assert e.value.status == skm.SKM_E_NOMEM
+    ctx = Context(csr, c.n_terms, 3, init_rows=[0, 1, 2])
+    with pytest.raises(SkmError) as e:
+        ctx.update()
+    assert e.value.status == skm.SKM_E_STATE
+    ctx.assign()
+    ctx.update()   # still usable after the refused call
+    ctx.close()
+    nonunit = v.copy()
+    nonunit[0] *= 2
+    with pytest.raises(SkmError) as e:
+        Context((ip, ix, nonunit), c.n_terms, 3, init_rows=[0, 1, 2])
+    assert e.value.status == skm.SKM_E_INVALID

@@ -1,0 +1,44 @@
+"""The C-ABI library loads and exports every entry point declared in
+include/skm.h (CPU only: no compute call is made)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2108_00895_amd import skm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "skm.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(skm_\w+)\s*\(", text, re.M)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = skm.load()
+    names = _declared()
+    assert "skm_init" in names and "skm_assign_new" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(names) == sorted(skm.EXPORTED)
+
+
+def test_struct_layouts_match_header():
+    # sizes follow the header's field order on x86-64
+    assert ctypes.sizeof(skm.Csr) == 7 * 8
+    assert ctypes.sizeof(skm.IterStats) == 4 + 4 + 5 * 8 + 4 * 8 + 4 * 4
+    cfg = skm.Config()
+    skm.load().skm_config_default(ctypes.byref(cfg))
+    assert cfg.n_lambda == 4 and list(cfg.lambda_[:4]) == [0.1, 0.25, 0.4, 0.6]
+    assert cfg.max_shift_sq == 1e-4 and cfg.validate == 1
+
+
+def test_null_arguments_rejected_without_device():
+    lib = skm.load()
+    h = ctypes.c_void_p()
+    assert lib.skm_init(None, None, ctypes.byref(h)) == skm.SKM_E_INVALID
+    assert b"NULL" in lib.skm_last_error()
+    assert lib.skm_assign(None, None) == skm.SKM_E_INVALID
+    lib.skm_destroy(None)
