@@ -127,10 +127,14 @@ typedef struct {
   int64_t ncc_rows;           /* rows that only compared changed centroids */
   int64_t index_rows;         /* rows whose candidates came from the index */
   double mean_candidates;     /* centroids scored per row (low precision) */
+  double scored_products;     /* sum over rows of nnz_i * (centroids scored):
+                                 the multiply-adds of the scoring kernel */
   double objective_assign;    /* J_A = sum_i x_i . c_{a_i} (after update) */
   double objective_update;    /* J_U = sum_j ||S_j||       (after update) */
   double max_shift_sq;        /* max_j ||c_j(new) - c_j(old)||^2 (after update) */
-  float ms_assign;            /* device time of the phases, milliseconds */
+  float ms_assign;            /* device time of the phases, milliseconds:
+                                 whole assignment step (all of the below) */
+  float ms_score;             /* the low-precision scoring kernel alone */
   float ms_exact;
   float ms_update;
   float ms_index;

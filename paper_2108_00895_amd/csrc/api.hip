@@ -172,7 +172,7 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 skm_status rebuild_tiles(skm_ctx *c, const uint8_t *changed) {
   if (c->prec == SKM_FP8_E4M3)
     HIP_TRY(c, launch_fp8_scales(c->master, c->k, c->D, changed, c->scale, c->stream));
-  HIP_TRY(c, launch_quantize(c->master, c->k, c->D, changed, c->scale, c->prec, c->tile, c->ld,
+  HIP_TRY(c, launch_quantize(c->master, c->k, c->D, changed, c->scale, c->prec, c->tile,
                              c->stream));
   return SKM_OK;
 }
@@ -185,7 +185,7 @@ ScoreArgs base_args(skm_ctx *c) {
   a.xl1 = c->xl1;
   a.n_rows = c->N;
   a.tile = c->tile;
-  a.ld = c->ld;
+  a.D = c->D;
   a.k = c->k;
   a.scale = c->prec == SKM_FP8_E4M3 ? c->scale : nullptr;
   a.uq = c->uq;
@@ -264,6 +264,9 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
           (i > 0 && !(cfg->lambda[i] > cfg->lambda[i - 1])))
         return fail(SKM_E_INVALID, "lambda must be ascending in (0, 1]");
   }
+  if (docs->n_cols * kChunk * code_bytes(cfg->precision) > INT32_MAX)
+    return fail(SKM_E_UNSUPPORTED, "n_cols too large: one 512-centroid slab of codes must stay "
+                                   "below 2 GiB");
   if (cfg->stop_rule != SKM_STOP_PAPER && cfg->stop_rule != SKM_STOP_FIXED)
     return fail(SKM_E_INVALID, "unknown stop rule");
 
@@ -295,6 +298,13 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
     e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     if (e != hipSuccess) return cleanup(device_fail(nullptr, "hipStreamCreate", e));
     c->own_stream = true;
+  }
+  {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess &&
+        cus > 0)
+      c->score_blocks = cus * 8;
+    (void)hipGetLastError();
   }
   for (hipEvent_t &ev : c->ev) {
     e = hipEventCreate(&ev);
@@ -346,6 +356,7 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
   A_(c->members, N);
   A_(c->red, 8);
   A_(c->ids_count, 1);
+  A_(c->part, ((int64_t)c->k + kChunk - 1) / kChunk * N);
   if (c->cfg.flags & SKM_NCC) A_(c->tile_ch, c->D * c->ld * c->esize);
 #undef A_
 
@@ -394,13 +405,10 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
     HIP_TRY(c, launch_compact_changed(c->changed, c->k, c->ch_ids, c->ids_count, s));
     HIP_TRY(c, hipMemcpyAsync(&n_ch, c->ids_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
-    c->ld_ch = round_up(std::max<int32_t>(n_ch, 1), kChunk);
-    HIP_TRY(c, launch_gather_tile(c->tile, c->ld, c->D, c->esize, c->ch_ids, n_ch, c->tile_ch,
-                                  c->ld_ch, s));
+    HIP_TRY(c, launch_gather_tile(c->tile, c->D, c->esize, c->ch_ids, n_ch, c->tile_ch, s));
     a.a_prev = c->a_prev;
     a.changed = c->changed;
     a.tile_ch = c->tile_ch;
-    a.ld_ch = c->ld_ch;
     a.n_ch = n_ch;
     a.ch_ids = c->ch_ids;
     a.prev_lo = c->lo_prev;
@@ -408,10 +416,11 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
   }
   HIP_TRY(c, launch_fill_i32(c->counters, 0, 8, s));
   HIP_TRY(c, launch_fill_i32(reinterpret_cast<int32_t *>(c->stat), 0, 16, s));
-  HIP_TRY(c, launch_score(a, c->prec, s));
+  HIP_TRY(c, hipEventRecord(c->ev[5], s));
+  HIP_TRY(c, launch_score(a, c->part, c->score_blocks, c->prec, s));
   HIP_TRY(c, hipEventRecord(c->ev[1], s));
   if (!a.no_exact) {
-    ExactArgs x{a, c->master, c->D, exact_waves()};
+    ExactArgs x{a, c->part, c->master, c->D, exact_waves()};
     HIP_TRY(c, launch_exact(x, c->prec, s));
   }
   HIP_TRY(c, hipEventRecord(c->ev[2], s));
@@ -433,7 +442,9 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
     st_out->ncc_rows = (int64_t)stv[1];
     st_out->index_rows = (int64_t)stv[2];
     st_out->mean_candidates = (double)stv[0] / (double)c->N;
-    st_out->ms_assign = elapsed(c->ev[0], c->ev[1]);
+    st_out->scored_products = (double)stv[3];
+    st_out->ms_assign = elapsed(c->ev[0], c->ev[2]);
+    st_out->ms_score = elapsed(c->ev[5], c->ev[1]);
     st_out->ms_exact = elapsed(c->ev[1], c->ev[2]);
     st_out->objective_assign = st_out->objective_update = st_out->max_shift_sq = -1.0;
   }
@@ -541,6 +552,12 @@ skm_status skm_assign_new(skm_ctx *c, const skm_csr *docs, int32_t *out_assign, 
     release();
     return st;
   }
+  skm::Partial *part = nullptr;
+  if ((st = talloc(&part, sizeof(skm::Partial) * (((int64_t)c->k + kChunk - 1) / kChunk) * n)) !=
+      SKM_OK) {
+    release();
+    return st;
+  }
   int32_t *a = nullptr, *flag_rows = nullptr, *counters = nullptr;
   double *lo = nullptr, *hi = nullptr, *flag_L = nullptr, *score = nullptr;
   uint8_t *flag_mode = nullptr;
@@ -570,9 +587,9 @@ skm_status skm_assign_new(skm_ctx *c, const skm_csr *docs, int32_t *out_assign, 
   sa.no_exact = 0;
   hipError_t e = launch_fill_i32(counters, 0, 8, s);
   if (e == hipSuccess) e = launch_fill_i32(reinterpret_cast<int32_t *>(stat), 0, 16, s);
-  if (e == hipSuccess) e = launch_score(sa, c->prec, s);
+  if (e == hipSuccess) e = launch_score(sa, part, c->score_blocks, c->prec, s);
   if (e == hipSuccess) {
-    ExactArgs x{sa, c->master, c->D, exact_waves()};
+    ExactArgs x{sa, part, c->master, c->D, exact_waves()};
     e = launch_exact(x, c->prec, s);
   }
   if (e == hipSuccess)
@@ -630,15 +647,21 @@ skm_status skm_get_tile(const skm_ctx *c, void *codes, size_t codes_bytes, float
   ST_TRY(check_ctx(c));
   const size_t need = (size_t)c->D * c->ld * c->esize;
   if (ld) *ld = c->ld;
+  skm_ctx *m = const_cast<skm_ctx *>(c);
   if (codes) {
     if (codes_bytes < need) return fail(SKM_E_INVALID, "codes buffer too small");
-    HIP_TRY(const_cast<skm_ctx *>(c),
-            hipMemcpyAsync(codes, c->tile, need, hipMemcpyDeviceToHost, c->stream));
+    std::vector<uint8_t> blocked(need);
+    HIP_TRY(m, hipMemcpyAsync(blocked.data(), c->tile, need, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(m, hipStreamSynchronize(c->stream));
+    uint8_t *dst = static_cast<uint8_t *>(codes);
+    for (int64_t t = 0; t < c->D; ++t)
+      for (int64_t j0 = 0; j0 < c->ld; j0 += kChunk)
+        std::memcpy(dst + (t * c->ld + j0) * c->esize, blocked.data() + tile_index(t, j0, c->D) * c->esize,
+                    (size_t)kChunk * c->esize);
   }
   if (scales)
-    HIP_TRY(const_cast<skm_ctx *>(c),
-            hipMemcpyAsync(scales, c->scale, sizeof(float) * c->k, hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(const_cast<skm_ctx *>(c), hipStreamSynchronize(c->stream));
+    HIP_TRY(m, hipMemcpyAsync(scales, c->scale, sizeof(float) * c->k, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(m, hipStreamSynchronize(c->stream));
   return SKM_OK;
 }
 
@@ -679,7 +702,7 @@ skm_status skm_score_dense(skm_ctx *c, const skm_csr *docs, float *out) {
     release();
     return st;
   }
-  hipError_t e = launch_score_dense(r.indptr, r.indices, r.values, n, c->tile, c->ld, c->k, c->scale,
+  hipError_t e = launch_score_dense(r.indptr, r.indices, r.values, n, c->tile, c->D, c->k, c->scale,
                                     c->prec, d_out, c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(out, d_out, sizeof(float) * n * c->k, hipMemcpyDeviceToHost, c->stream);

@@ -17,6 +17,15 @@ constexpr int kBandCap = 256;                 // exact-tier band kept in LDS per
 
 __host__ __device__ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// Scoring copies are blocked by 512-centroid chunks: chunk c is a contiguous
+// [D][512] slab, so one chunk's term rows are consecutive 512-code pieces.  A
+// plain [D][k] layout would put a chunk's pieces at a stride of k codes, which
+// for the k of interest is a multiple of 4 KiB and folds every piece of a
+// chunk onto the same few L2 channels and sets.
+__host__ __device__ inline int64_t tile_index(int64_t t, int64_t j, int64_t D) {
+  return ((j / kChunk) * D + t) * kChunk + (j % kChunk);
+}
+
 // ---------------------------------------------------------------- wave helpers
 
 __device__ inline int lane_id() { return threadIdx.x & (kWave - 1); }

@@ -21,9 +21,9 @@ struct ScoreArgs {
   const float *values;
   const double *xl1;          // per-row L1 norm (FP8 absolute error term)
   int64_t n_rows;
-  // scoring copy, term-major [n_cols][ld]
+  // scoring copy, chunk-blocked term-major (see tile_index)
   const uint8_t *tile;
-  int64_t ld;
+  int64_t D;
   int32_t k;
   const float *scale;         // per-centroid scale (FP8) or nullptr
   // Sec. 3.1: rows whose previous centroid is unchanged score the compacted
@@ -31,7 +31,6 @@ struct ScoreArgs {
   const int32_t *a_prev;      // nullptr: no NCC
   const uint8_t *changed;
   const uint8_t *tile_ch;
-  int64_t ld_ch;
   int32_t n_ch;
   const int32_t *ch_ids;
   const double *prev_lo;
@@ -54,8 +53,17 @@ struct ScoreArgs {
   unsigned long long *stat;   // [0] centroids scored, [1] NCC rows, [2] index rows
 };
 
+// Top two of one row against one 512-centroid chunk.
+struct Partial {
+  float b1;
+  int32_t j1;
+  float b2;
+  int32_t pad;
+};
+
 struct ExactArgs {
   ScoreArgs s;
+  const Partial *part;        // [chunk][row] partials of the scoring pass
   const double *master;       // k x D FP64 centroids
   int64_t D;
   int32_t max_waves;
@@ -95,7 +103,7 @@ struct skm_ctx {
   // centroids
   double *master = nullptr;    // k x D FP64, unit rows
   double *S = nullptr;         // k x D FP64 member sums (rows of changed clusters)
-  uint8_t *tile = nullptr;     // D x ld codes
+  uint8_t *tile = nullptr;     // ld / 512 chunks of D x 512 codes (tile_index)
   float *scale = nullptr;      // [ld]
   double *snorm = nullptr;     // ||S_j|| of the current membership
   double *shift = nullptr;     // per-cluster ||dc||^2 of the last update
@@ -103,8 +111,7 @@ struct skm_ctx {
   uint8_t *changed = nullptr;  // k flags
   int32_t *ch_ids = nullptr;   // compacted changed ids (ascending)
   int32_t n_ch = 0;
-  uint8_t *tile_ch = nullptr;  // D x ld compacted copy
-  int64_t ld_ch = 0;
+  uint8_t *tile_ch = nullptr;  // compacted copy of the changed centroids, same layout
 
   // assignment state
   int32_t *a = nullptr;        // current assignment
@@ -124,6 +131,8 @@ struct skm_ctx {
   int32_t *members = nullptr;  // [N]
   double *red = nullptr;       // reduction outputs
   int32_t *ids_count = nullptr;
+  skm::Partial *part = nullptr;  // [ceil(k / 512)][N] scoring partials
+  int score_blocks = 2048;       // persistent scoring grid
   int64_t nblk = 0;
 
   // state
@@ -140,10 +149,10 @@ struct skm_ctx {
 namespace skm {
 
 // kernels_score.hip
-hipError_t launch_score(const ScoreArgs &a, int prec, hipStream_t s);
+hipError_t launch_score(const ScoreArgs &a, Partial *part, int blocks, int prec, hipStream_t s);
 hipError_t launch_exact(const ExactArgs &a, int prec, hipStream_t s);
 hipError_t launch_score_dense(const int64_t *indptr, const int32_t *indices, const float *values,
-                              int64_t n_rows, const uint8_t *tile, int64_t ld, int32_t k,
+                              int64_t n_rows, const uint8_t *tile, int64_t D, int32_t k,
                               const float *scale, int prec, float *out, hipStream_t s);
 hipError_t launch_exact_scores(const int64_t *indptr, const int32_t *indices, const float *values,
                                int64_t n_rows, const int32_t *a, const double *master, int64_t D,
@@ -161,16 +170,15 @@ hipError_t launch_seed(const int64_t *indptr, const int32_t *indices, const floa
 hipError_t launch_fp8_scales(const double *master, int32_t k, int64_t D, const uint8_t *changed,
                              float *scale, hipStream_t s);
 hipError_t launch_quantize(const double *master, int32_t k, int64_t D, const uint8_t *changed,
-                           const float *scale, int prec, uint8_t *tile, int64_t ld, hipStream_t s);
+                           const float *scale, int prec, uint8_t *tile, hipStream_t s);
 hipError_t launch_count_moved(const int32_t *a, const int32_t *a_prev, int64_t n,
                               unsigned long long *out, hipStream_t s);
 hipError_t launch_mark_changed(const int32_t *a, const int32_t *a_prev, int64_t n, uint8_t *changed,
                                hipStream_t s);
 hipError_t launch_compact_changed(const uint8_t *changed, int32_t k, int32_t *ids, int32_t *count,
                                   hipStream_t s);
-hipError_t launch_gather_tile(const uint8_t *tile, int64_t ld, int64_t D, int esize,
-                              const int32_t *ids, int32_t n, uint8_t *out, int64_t ld_out,
-                              hipStream_t s);
+hipError_t launch_gather_tile(const uint8_t *tile, int64_t D, int esize, const int32_t *ids,
+                              int32_t n, uint8_t *out, hipStream_t s);
 hipError_t launch_bucket(const int32_t *a, int64_t n, int32_t k, int64_t nblk, int32_t *hist,
                          int32_t *counts, int64_t *offsets, int32_t *members, hipStream_t s);
 hipError_t launch_sum_members(const int64_t *indptr, const int32_t *indices, const float *values,

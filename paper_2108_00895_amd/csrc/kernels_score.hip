@@ -7,6 +7,8 @@
 // [8l, 8l + 8) of the chunk, and walks the row's terms; each step is one
 // coalesced 16 B (BF16), 32 B (FP32) or 8 B (FP8) load per lane plus eight FMAs.
 // Row terms are broadcast with v_readlane from a 64-term register batch.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace skm {
@@ -15,15 +17,25 @@ namespace {
 template <int P>
 struct Codes;
 
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v2i __attribute__((ext_vector_type(2)));
+
+// Raw buffer loads: the resource (slab base and size) lives in scalar
+// registers, the term row's byte offset is a scalar offset and the lane's
+// column offset a 32-bit vector offset.  Reads past the slab return zero.
 template <>
 struct Codes<SKM_FP32> {
   static constexpr int kBytes = 4;
   struct raw_t {
     float4 a, b;
   };
-  __device__ static raw_t load(const uint8_t *p) {
-    const float4 *q = reinterpret_cast<const float4 *>(p);
-    return raw_t{q[0], q[1]};
+  __device__ static raw_t load(__amdgpu_buffer_rsrc_t rs, int voff, int soff) {
+    const v4i x = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0);
+    const v4i y = __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 16, soff, 0);
+    return raw_t{make_float4(__int_as_float(x[0]), __int_as_float(x[1]), __int_as_float(x[2]),
+                             __int_as_float(x[3])),
+                 make_float4(__int_as_float(y[0]), __int_as_float(y[1]), __int_as_float(y[2]),
+                             __int_as_float(y[3]))};
   }
   __device__ static void fma8(const raw_t &r, float x, float acc[8]) {
     acc[0] = fmaf(x, r.a.x, acc[0]);
@@ -41,7 +53,10 @@ template <>
 struct Codes<SKM_BF16> {
   static constexpr int kBytes = 2;
   using raw_t = uint4;
-  __device__ static raw_t load(const uint8_t *p) { return *reinterpret_cast<const uint4 *>(p); }
+  __device__ static raw_t load(__amdgpu_buffer_rsrc_t rs, int voff, int soff) {
+    const v4i x = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0);
+    return make_uint4((uint32_t)x[0], (uint32_t)x[1], (uint32_t)x[2], (uint32_t)x[3]);
+  }
   __device__ static void fma8(const raw_t &r, float x, float acc[8]) {
     // little-endian: the lower half-word is the lower column
     acc[0] = fmaf(x, __uint_as_float(r.x << 16), acc[0]);
@@ -59,7 +74,10 @@ template <>
 struct Codes<SKM_FP8_E4M3> {
   static constexpr int kBytes = 1;
   using raw_t = uint2;
-  __device__ static raw_t load(const uint8_t *p) { return *reinterpret_cast<const uint2 *>(p); }
+  __device__ static raw_t load(__amdgpu_buffer_rsrc_t rs, int voff, int soff) {
+    const v2i x = __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0);
+    return make_uint2((uint32_t)x[0], (uint32_t)x[1]);
+  }
   __device__ static void fma8(const raw_t &r, float x, float acc[8]) {
     // v_cvt_pk_f32_fp8 decodes two OCP E4M3 bytes (word_sel picks bytes 2,3)
     auto p0 = __builtin_amdgcn_cvt_pk_f32_fp8((int)r.x, false);
@@ -84,16 +102,22 @@ __device__ inline int64_t uniform64(int64_t v) {
 }
 __device__ inline int32_t uniform32(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// acc[c] += sum over the row's terms of x_t * code[t][c0 + 8*lane + c], in
+// acc[c] += sum over the row's terms of x_t * code(t, c0 + 8*lane + c), in
 // ascending term order, one FMA per term (the order the error bound assumes).
+// Eight code loads are kept in flight per lane.
 template <int P>
 __device__ inline void score_chunk(int64_t b, int64_t e, const int32_t *__restrict__ indices,
                                    const float *__restrict__ values, const uint8_t *__restrict__ tile,
-                                   int64_t ld, int64_t c0, float acc[8]) {
+                                   int64_t D, int64_t c0, float acc[8]) {
   using C = Codes<P>;
   const int lane = lane_id();
-  const uint8_t *base = tile + (c0 + (int64_t)lane * kColsPerLane) * C::kBytes;
-  const int64_t rowbytes = ld * C::kBytes;
+  // chunk slab [D][512] as a buffer resource in scalar registers
+  const uint8_t *slab = reinterpret_cast<const uint8_t *>(
+      uniform64(reinterpret_cast<int64_t>(tile + tile_index(0, c0, D) * C::kBytes)));
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint8_t *>(slab), 0, (int)(D * kChunk * C::kBytes), 0x00020000);
+  const int voff = lane * kColsPerLane * C::kBytes;
+  constexpr int rowbytes = kChunk * C::kBytes;
   for (int64_t q0 = b; q0 < e; q0 += kWave) {
     const int cnt = (int)((e - q0) < kWave ? (e - q0) : kWave);
     int my_t = 0;
@@ -103,23 +127,17 @@ __device__ inline void score_chunk(int64_t b, int64_t e, const int32_t *__restri
       my_x = values[q0 + lane];
     }
     int u = 0;
-    for (; u + 4 <= cnt; u += 4) {
-      const int t0 = __builtin_amdgcn_readlane(my_t, u);
-      const int t1 = __builtin_amdgcn_readlane(my_t, u + 1);
-      const int t2 = __builtin_amdgcn_readlane(my_t, u + 2);
-      const int t3 = __builtin_amdgcn_readlane(my_t, u + 3);
-      typename C::raw_t r0 = C::load(base + (int64_t)t0 * rowbytes);
-      typename C::raw_t r1 = C::load(base + (int64_t)t1 * rowbytes);
-      typename C::raw_t r2 = C::load(base + (int64_t)t2 * rowbytes);
-      typename C::raw_t r3 = C::load(base + (int64_t)t3 * rowbytes);
-      C::fma8(r0, readlane_f(my_x, u), acc);
-      C::fma8(r1, readlane_f(my_x, u + 1), acc);
-      C::fma8(r2, readlane_f(my_x, u + 2), acc);
-      C::fma8(r3, readlane_f(my_x, u + 3), acc);
+    for (; u + 8 <= cnt; u += 8) {
+      typename C::raw_t r[8];
+#pragma unroll
+      for (int v = 0; v < 8; ++v)
+        r[v] = C::load(rs, voff, __builtin_amdgcn_readlane(my_t, u + v) * rowbytes);
+#pragma unroll
+      for (int v = 0; v < 8; ++v) C::fma8(r[v], readlane_f(my_x, u + v), acc);
     }
     for (; u < cnt; ++u) {
       const int t0 = __builtin_amdgcn_readlane(my_t, u);
-      typename C::raw_t r0 = C::load(base + (int64_t)t0 * rowbytes);
+      typename C::raw_t r0 = C::load(rs, voff, t0 * rowbytes);
       C::fma8(r0, readlane_f(my_x, u), acc);
     }
   }
@@ -127,7 +145,6 @@ __device__ inline void score_chunk(int64_t b, int64_t e, const int32_t *__restri
 
 struct RowPlan {
   const uint8_t *tile;
-  int64_t ld;
   int32_t ncols;
   const int32_t *colmap;   // column -> centroid id, nullptr = identity
   bool ncc;
@@ -135,12 +152,11 @@ struct RowPlan {
 };
 
 __device__ inline RowPlan plan_row(const ScoreArgs &a, int64_t row, bool allow_ncc) {
-  RowPlan p{a.tile, a.ld, a.k, nullptr, false, -1};
+  RowPlan p{a.tile, a.k, nullptr, false, -1};
   if (allow_ncc && a.a_prev) {
     const int32_t ap = a.a_prev[row];
     if (!a.changed[ap]) {
       p.tile = a.tile_ch;
-      p.ld = a.ld_ch;
       p.ncols = a.n_ch;
       p.colmap = a.ch_ids;
       p.ncc = true;
@@ -150,28 +166,35 @@ __device__ inline RowPlan plan_row(const ScoreArgs &a, int64_t row, bool allow_n
   return p;
 }
 
+// Per-(row, chunk) top-two of the low-precision scores.  The grid is
+// persistent and walks items chunk-major (item = chunk * n_rows + row), so all
+// wavefronts sweep the same 512-centroid slice of the codes at the same time
+// and its hot term rows stay in L2 / the Infinity Cache instead of being
+// re-fetched from HBM for every row.
 template <int P>
-__global__ __launch_bounds__(256) void k_score(ScoreArgs a) {
+__global__ __launch_bounds__(256) void k_score_part(ScoreArgs a, Partial *__restrict__ part,
+                                                    int64_t n_items) {
   const int wave = uniform32(threadIdx.x >> 6);
-  const int64_t rix = (int64_t)blockIdx.x * 4 + wave;
-  if (rix >= a.n_rows) return;
   const int lane = lane_id();
-  const int64_t row = rix;
-  const int64_t b = uniform64(a.indptr[row]);
-  const int64_t e = uniform64(a.indptr[row + 1]);
-  const RowPlan pl = plan_row(a, row, true);
-
-  float b1 = -INFINITY, b2 = -INFINITY;
-  int j1 = 0x7FFFFFFF;
-  for (int64_t c0 = 0; c0 < pl.ncols; c0 += kChunk) {
+  const int64_t stride = (int64_t)gridDim.x * 4;
+  for (int64_t it = (int64_t)blockIdx.x * 4 + wave; it < n_items; it += stride) {
+    const int64_t c = uniform64(it / a.n_rows);
+    const int64_t row = uniform64(it - c * a.n_rows);
+    const RowPlan pl = plan_row(a, row, true);
+    const int64_t c0 = c * kChunk;
+    if (c0 >= pl.ncols) continue;
+    const int64_t b = uniform64(a.indptr[row]);
+    const int64_t e = uniform64(a.indptr[row + 1]);
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    score_chunk<P>(b, e, a.indices, a.values, pl.tile, pl.ld, c0, acc);
+    score_chunk<P>(b, e, a.indices, a.values, pl.tile, a.D, c0, acc);
+    float b1 = -INFINITY, b2 = -INFINITY;
+    int j1 = 0x7FFFFFFF;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int64_t col = c0 + lane * kColsPerLane + c;
+    for (int q = 0; q < 8; ++q) {
+      const int64_t col = c0 + lane * kColsPerLane + q;
       if (col < pl.ncols) {
         const int j = pl.colmap ? pl.colmap[col] : (int)col;
-        float s = acc[c];
+        float s = acc[q];
         if (a.scale) s *= a.scale[j];
         if (better(s, j, b1, j1)) {
           b2 = b1;
@@ -182,58 +205,101 @@ __global__ __launch_bounds__(256) void k_score(ScoreArgs a) {
         }
       }
     }
+    wave_top2(b1, j1, b2);
+    if (lane == 0) part[c * a.n_rows + row] = Partial{b1, j1, b2, 0};
   }
-  wave_top2(b1, j1, b2);
-  if (lane != 0) return;
+}
 
-  const int64_t n = e - b;
-  const double kap = bound_kappa(n, a.uq);
-  const double A = bound_abs(n, a.xl1[row], a.abs_coef);
-  auto lo_of = [&](float s) { return s == -INFINITY ? -INFINITY : (double)s - (kap * (double)s + A); };
-  auto hi_of = [&](float s) { return s == -INFINITY ? -INFINITY : (double)s + (kap * (double)s + A); };
-
-  int win;
-  double wlo, whi, L;
-  bool certain;
-  if (!pl.ncc) {
-    win = j1;
-    wlo = lo_of(b1);
-    whi = hi_of(b1);
-    certain = wlo > hi_of(b2);
-    L = wlo;
-  } else {
-    const double plo = a.prev_lo[row], phi = a.prev_hi[row];
-    if (b1 == -INFINITY) {
-      win = pl.ap;
-      wlo = plo;
-      whi = phi;
-      certain = true;
-      L = plo;
-    } else if (plo >= lo_of(b1)) {
-      win = pl.ap;
-      wlo = plo;
-      whi = phi;
-      certain = plo > hi_of(b1);
-      L = plo;
-    } else {
+// Merges a row's chunk partials in chunk order and certifies the winner:
+// certain when the winner's lower bound exceeds every other candidate's upper
+// bound; otherwise the row goes to the exact tier with L = the certified lower
+// bound of the maximum.  One thread per row.
+__global__ __launch_bounds__(256) void k_finalize(ScoreArgs a, const Partial *__restrict__ part) {
+  __shared__ unsigned long long sh[3][256];
+  const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  unsigned long long n_cols = 0, n_prod = 0, n_ncc = 0;
+  if (row < a.n_rows) {
+    const int64_t b = a.indptr[row], e = a.indptr[row + 1];
+    const RowPlan pl = plan_row(a, row, true);
+    float b1 = -INFINITY, b2 = -INFINITY;
+    int j1 = 0x7FFFFFFF;
+    const int64_t nch = (pl.ncols + kChunk - 1) / kChunk;
+    for (int64_t c = 0; c < nch; ++c) {
+      const Partial p = part[c * a.n_rows + row];
+      if (better(p.b1, p.j1, b1, j1)) {
+        b2 = fmaxf(b1, p.b2);
+        b1 = p.b1;
+        j1 = p.j1;
+      } else {
+        b2 = fmaxf(b2, p.b1);
+      }
+    }
+    const int64_t n = e - b;
+    const double kap = bound_kappa(n, a.uq);
+    const double A = bound_abs(n, a.xl1[row], a.abs_coef);
+    auto lo_of = [&](float s) { return s == -INFINITY ? -INFINITY : (double)s - (kap * (double)s + A); };
+    auto hi_of = [&](float s) { return s == -INFINITY ? -INFINITY : (double)s + (kap * (double)s + A); };
+    int win;
+    double wlo, whi, L;
+    bool certain;
+    if (!pl.ncc) {
       win = j1;
       wlo = lo_of(b1);
       whi = hi_of(b1);
-      certain = wlo > fmax(phi, hi_of(b2));
+      certain = wlo > hi_of(b2);
       L = wlo;
+    } else {
+      const double plo = a.prev_lo[row], phi = a.prev_hi[row];
+      if (b1 == -INFINITY) {
+        win = pl.ap;
+        wlo = plo;
+        whi = phi;
+        certain = true;
+        L = plo;
+      } else if (plo >= lo_of(b1)) {
+        win = pl.ap;
+        wlo = plo;
+        whi = phi;
+        certain = plo > hi_of(b1);
+        L = plo;
+      } else {
+        win = j1;
+        wlo = lo_of(b1);
+        whi = hi_of(b1);
+        certain = wlo > fmax(phi, hi_of(b2));
+        L = wlo;
+      }
+    }
+    n_cols = (unsigned long long)pl.ncols;
+    n_prod = (unsigned long long)pl.ncols * (unsigned long long)n;
+    n_ncc = pl.ncc ? 1ull : 0ull;
+    if (certain || a.no_exact) {
+      a.a_out[row] = win;
+      a.lo_out[row] = wlo;
+      a.hi_out[row] = whi;
+    } else {
+      const int f = atomicAdd(&a.counters[0], 1);
+      a.flag_rows[f] = (int32_t)row;
+      a.flag_L[f] = L;
+      a.flag_mode[f] = pl.ncc ? 1 : 0;
     }
   }
-  atomicAdd(&a.stat[0], (unsigned long long)pl.ncols);
-  if (pl.ncc) atomicAdd(&a.stat[1], 1ull);
-  if (certain || a.no_exact) {
-    a.a_out[row] = win;
-    a.lo_out[row] = wlo;
-    a.hi_out[row] = whi;
-  } else {
-    const int f = atomicAdd(&a.counters[0], 1);
-    a.flag_rows[f] = (int32_t)row;
-    a.flag_L[f] = L;
-    a.flag_mode[f] = pl.ncc ? 1 : 0;
+  sh[0][threadIdx.x] = n_cols;
+  sh[1][threadIdx.x] = n_prod;
+  sh[2][threadIdx.x] = n_ncc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+      sh[2][threadIdx.x] += sh[2][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(&a.stat[0], sh[0][0]);
+    atomicAdd(&a.stat[3], sh[1][0]);
+    if (sh[2][0]) atomicAdd(&a.stat[1], sh[2][0]);
   }
 }
 
@@ -264,10 +330,9 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs x) {
     const int64_t b = uniform64(a.indptr[row]);
     const int64_t e = uniform64(a.indptr[row + 1]);
     const int64_t n = e - b;
-    RowPlan pl{a.tile, a.ld, a.k, nullptr, false, -1};
+    RowPlan pl{a.tile, a.k, nullptr, false, -1};
     if (ncc_row) {
       pl.tile = a.tile_ch;
-      pl.ld = a.ld_ch;
       pl.ncols = a.n_ch;
       pl.colmap = a.ch_ids;
       pl.ncc = true;
@@ -275,10 +340,21 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs x) {
     }
     const double kap = bound_kappa(n, a.uq);
     const double A = bound_abs(n, a.xl1[row], a.abs_coef);
+    auto hi_of = [&](float s) { return s == -INFINITY ? -INFINITY : (double)s + (kap * (double)s + A); };
     int nb = 0;
     for (int64_t c0 = 0; c0 < pl.ncols; c0 += kChunk) {
+      // A chunk whose second-best upper bound is below L can only contribute
+      // its best centroid: skip rescoring it.
+      const Partial p = x.part[(c0 / kChunk) * a.n_rows + row];
+      if (hi_of(p.b2) < L) {
+        if (hi_of(p.b1) >= L) {
+          if (lane == 0 && nb < kBandCap) band[nb] = p.j1;
+          nb += 1;
+        }
+        continue;
+      }
       float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      score_chunk<P>(b, e, a.indices, a.values, pl.tile, pl.ld, c0, acc);
+      score_chunk<P>(b, e, a.indices, a.values, pl.tile, a.D, c0, acc);
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         const int64_t col = c0 + lane * kColsPerLane + c;
@@ -350,7 +426,7 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs x) {
 template <int P>
 __global__ __launch_bounds__(256) void k_score_dense(const int64_t *indptr, const int32_t *indices,
                                                      const float *values, int64_t n_rows,
-                                                     const uint8_t *tile, int64_t ld, int32_t k,
+                                                     const uint8_t *tile, int64_t D, int32_t k,
                                                      const float *scale, float *out) {
   const int wave = uniform32(threadIdx.x >> 6);
   const int64_t row = (int64_t)blockIdx.x * 4 + wave;
@@ -360,7 +436,7 @@ __global__ __launch_bounds__(256) void k_score_dense(const int64_t *indptr, cons
   const int64_t e = uniform64(indptr[row + 1]);
   for (int64_t c0 = 0; c0 < k; c0 += kChunk) {
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    score_chunk<P>(b, e, indices, values, tile, ld, c0, acc);
+    score_chunk<P>(b, e, indices, values, tile, D, c0, acc);
     for (int c = 0; c < 8; ++c) {
       const int64_t col = c0 + lane * kColsPerLane + c;
       if (col < k) out[row * k + col] = scale ? acc[c] * scale[col] : acc[c];
@@ -387,10 +463,17 @@ __global__ __launch_bounds__(256) void k_exact_scores(const int64_t *indptr, con
 }
 
 template <int P>
-hipError_t launch_score_t(const ScoreArgs &a, hipStream_t s) {
+hipError_t launch_score_t(const ScoreArgs &a, Partial *part, int blocks, hipStream_t s) {
   if (a.n_rows <= 0) return hipSuccess;
-  const int64_t blocks = (a.n_rows + 3) / 4;
-  hipLaunchKernelGGL(k_score<P>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  const int64_t nchunks = (a.k + kChunk - 1) / kChunk;
+  const int64_t n_items = nchunks * a.n_rows;
+  const int64_t need = (n_items + 3) / 4;
+  const int g = (int)std::min<int64_t>(blocks, need);
+  hipLaunchKernelGGL(k_score_part<P>, dim3((unsigned)g), dim3(256), 0, s, a, part, n_items);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)((a.n_rows + 255) / 256)), dim3(256), 0, s, a,
+                     (const Partial *)part);
   return hipGetLastError();
 }
 
@@ -402,11 +485,11 @@ hipError_t launch_exact_t(const ExactArgs &x, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_score(const ScoreArgs &a, int prec, hipStream_t s) {
+hipError_t launch_score(const ScoreArgs &a, Partial *part, int blocks, int prec, hipStream_t s) {
   switch (prec) {
-    case SKM_FP32: return launch_score_t<SKM_FP32>(a, s);
-    case SKM_BF16: return launch_score_t<SKM_BF16>(a, s);
-    case SKM_FP8_E4M3: return launch_score_t<SKM_FP8_E4M3>(a, s);
+    case SKM_FP32: return launch_score_t<SKM_FP32>(a, part, blocks, s);
+    case SKM_BF16: return launch_score_t<SKM_BF16>(a, part, blocks, s);
+    case SKM_FP8_E4M3: return launch_score_t<SKM_FP8_E4M3>(a, part, blocks, s);
   }
   return hipErrorInvalidValue;
 }
@@ -421,22 +504,22 @@ hipError_t launch_exact(const ExactArgs &x, int prec, hipStream_t s) {
 }
 
 hipError_t launch_score_dense(const int64_t *indptr, const int32_t *indices, const float *values,
-                              int64_t n_rows, const uint8_t *tile, int64_t ld, int32_t k,
+                              int64_t n_rows, const uint8_t *tile, int64_t D, int32_t k,
                               const float *scale, int prec, float *out, hipStream_t s) {
   if (n_rows <= 0) return hipSuccess;
   const dim3 g((unsigned)((n_rows + 3) / 4)), blk(256);
   switch (prec) {
     case SKM_FP32:
       hipLaunchKernelGGL(k_score_dense<SKM_FP32>, g, blk, 0, s, indptr, indices, values, n_rows, tile,
-                         ld, k, nullptr, out);
+                         D, k, nullptr, out);
       break;
     case SKM_BF16:
       hipLaunchKernelGGL(k_score_dense<SKM_BF16>, g, blk, 0, s, indptr, indices, values, n_rows, tile,
-                         ld, k, nullptr, out);
+                         D, k, nullptr, out);
       break;
     case SKM_FP8_E4M3:
       hipLaunchKernelGGL(k_score_dense<SKM_FP8_E4M3>, g, blk, 0, s, indptr, indices, values, n_rows,
-                         tile, ld, k, scale, out);
+                         tile, D, k, scale, out);
       break;
     default: return hipErrorInvalidValue;
   }

@@ -106,7 +106,7 @@ __global__ void k_fp8_scales(const double *master, int64_t D, const uint8_t *cha
 template <int P>
 __global__ __launch_bounds__(256) void k_quantize(const double *master, int32_t k, int64_t D,
                                                   const uint8_t *changed, const float *scale,
-                                                  uint8_t *tile, int64_t ld) {
+                                                  uint8_t *tile) {
   __shared__ double buf[64][65];
   const int64_t j0 = (int64_t)blockIdx.x * 64;
   const int64_t t0 = (int64_t)blockIdx.y * 64;
@@ -126,13 +126,14 @@ __global__ __launch_bounds__(256) void k_quantize(const double *master, int32_t 
     const int64_t t = t0 + tt, j = j0 + tx;
     if (t >= D || j >= k) continue;
     const double c = buf[tx][tt];
+    const int64_t o = tile_index(t, j, D);
     if (P == SKM_FP32) {
-      reinterpret_cast<float *>(tile)[t * ld + j] = (float)c;
+      reinterpret_cast<float *>(tile)[o] = (float)c;
     } else if (P == SKM_BF16) {
-      reinterpret_cast<uint16_t *>(tile)[t * ld + j] = encode_bf16(c);
+      reinterpret_cast<uint16_t *>(tile)[o] = encode_bf16(c);
     } else {
       const int e = ilogbf(scale[j]);
-      tile[t * ld + j] = encode_e4m3(ldexp(c, -e));
+      tile[o] = encode_e4m3(ldexp(c, -e));
     }
   }
 }
@@ -179,10 +180,10 @@ __global__ __launch_bounds__(1024) void k_compact_changed(const uint8_t *changed
 }
 
 template <typename T>
-__global__ void k_gather_tile(const T *tile, int64_t ld, const int32_t *ids, int32_t n, T *out,
-                              int64_t ld_out) {
+__global__ void k_gather_tile(const T *tile, int64_t D, const int32_t *ids, int32_t n, T *out) {
   const int64_t t = blockIdx.x;
-  for (int o = threadIdx.x; o < n; o += blockDim.x) out[t * ld_out + o] = tile[t * ld + ids[o]];
+  for (int o = threadIdx.x; o < n; o += blockDim.x)
+    out[tile_index(t, o, D)] = tile[tile_index(t, ids[o], D)];
 }
 
 // ---- stable counting sort of rows by cluster
@@ -398,18 +399,17 @@ hipError_t launch_fp8_scales(const double *master, int32_t k, int64_t D, const u
 }
 
 hipError_t launch_quantize(const double *master, int32_t k, int64_t D, const uint8_t *changed,
-                           const float *scale, int prec, uint8_t *tile, int64_t ld, hipStream_t s) {
+                           const float *scale, int prec, uint8_t *tile, hipStream_t s) {
   const dim3 g((unsigned)((k + 63) / 64), (unsigned)((D + 63) / 64)), b(256);
   switch (prec) {
     case SKM_FP32:
-      hipLaunchKernelGGL(k_quantize<SKM_FP32>, g, b, 0, s, master, k, D, changed, scale, tile, ld);
+      hipLaunchKernelGGL(k_quantize<SKM_FP32>, g, b, 0, s, master, k, D, changed, scale, tile);
       break;
     case SKM_BF16:
-      hipLaunchKernelGGL(k_quantize<SKM_BF16>, g, b, 0, s, master, k, D, changed, scale, tile, ld);
+      hipLaunchKernelGGL(k_quantize<SKM_BF16>, g, b, 0, s, master, k, D, changed, scale, tile);
       break;
     case SKM_FP8_E4M3:
-      hipLaunchKernelGGL(k_quantize<SKM_FP8_E4M3>, g, b, 0, s, master, k, D, changed, scale, tile,
-                         ld);
+      hipLaunchKernelGGL(k_quantize<SKM_FP8_E4M3>, g, b, 0, s, master, k, D, changed, scale, tile);
       break;
     default: return hipErrorInvalidValue;
   }
@@ -438,22 +438,21 @@ hipError_t launch_compact_changed(const uint8_t *changed, int32_t k, int32_t *id
   return hipGetLastError();
 }
 
-hipError_t launch_gather_tile(const uint8_t *tile, int64_t ld, int64_t D, int esize,
-                              const int32_t *ids, int32_t n, uint8_t *out, int64_t ld_out,
-                              hipStream_t s) {
+hipError_t launch_gather_tile(const uint8_t *tile, int64_t D, int esize, const int32_t *ids,
+                              int32_t n, uint8_t *out, hipStream_t s) {
   if (n <= 0 || D <= 0) return hipSuccess;
   const dim3 g((unsigned)D), b(256);
   switch (esize) {
     case 4:
-      hipLaunchKernelGGL(k_gather_tile<uint32_t>, g, b, 0, s, (const uint32_t *)tile, ld, ids, n,
-                         (uint32_t *)out, ld_out);
+      hipLaunchKernelGGL(k_gather_tile<uint32_t>, g, b, 0, s, (const uint32_t *)tile, D, ids, n,
+                         (uint32_t *)out);
       break;
     case 2:
-      hipLaunchKernelGGL(k_gather_tile<uint16_t>, g, b, 0, s, (const uint16_t *)tile, ld, ids, n,
-                         (uint16_t *)out, ld_out);
+      hipLaunchKernelGGL(k_gather_tile<uint16_t>, g, b, 0, s, (const uint16_t *)tile, D, ids, n,
+                         (uint16_t *)out);
       break;
     case 1:
-      hipLaunchKernelGGL(k_gather_tile<uint8_t>, g, b, 0, s, tile, ld, ids, n, out, ld_out);
+      hipLaunchKernelGGL(k_gather_tile<uint8_t>, g, b, 0, s, tile, D, ids, n, out);
       break;
     default: return hipErrorInvalidValue;
   }

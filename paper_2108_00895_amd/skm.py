@@ -58,9 +58,10 @@ class IterStats(ctypes.Structure):
                 ("moved", ctypes.c_int64), ("flagged", ctypes.c_int64),
                 ("band_overflow", ctypes.c_int64), ("ncc_rows", ctypes.c_int64),
                 ("index_rows", ctypes.c_int64), ("mean_candidates", ctypes.c_double),
+                ("scored_products", ctypes.c_double),
                 ("objective_assign", ctypes.c_double), ("objective_update", ctypes.c_double),
                 ("max_shift_sq", ctypes.c_double), ("ms_assign", ctypes.c_float),
-                ("ms_exact", ctypes.c_float), ("ms_update", ctypes.c_float),
+                ("ms_score", ctypes.c_float), ("ms_exact", ctypes.c_float), ("ms_update", ctypes.c_float),
                 ("ms_index", ctypes.c_float)]
 
     def asdict(self):
