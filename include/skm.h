@@ -126,6 +126,12 @@ typedef struct {
   int64_t band_overflow;      /* flagged rows rescored against every candidate */
   int64_t ncc_rows;           /* rows that only compared changed centroids */
   int64_t index_rows;         /* rows whose candidates came from the index */
+  int64_t index_no_level;     /* index-eligible rows whose baseline reached no
+                                 threshold (scored densely) */
+  int64_t index_guarded;      /* rows whose index query would read more entries
+                                 than a quarter of a dense scan (scored densely) */
+  int64_t index_over_cap;     /* rows with more candidates than the per-row list
+                                 holds (scored densely) */
   double mean_candidates;     /* centroids scored per row (low precision) */
   double scored_products;     /* sum over rows of nnz_i * (centroids scored):
                                  the multiply-adds of the scoring kernel */
@@ -137,7 +143,8 @@ typedef struct {
   float ms_score;             /* the low-precision scoring kernel alone */
   float ms_exact;
   float ms_update;
-  float ms_index;
+  float ms_index;             /* index query + exact candidate scoring (assign),
+                                 index build (update) */
 } skm_iter_stats;
 
 /* Fills *cfg with defaults: k = 0 (must be set), FP32, no flags, the four
@@ -214,6 +221,13 @@ double skm_error_bound(const skm_ctx *c, double s, int64_t nnz, double l1);
  * list ascending by centroid.  Pass entries = NULL to get *n_entries only. */
 skm_status skm_get_index(const skm_ctx *c, int32_t level, int64_t *offsets, uint32_t *entries,
                          int64_t *n_entries);
+
+/* Candidate sets of the Sec. 3.2 index at threshold level `level` for the rows
+ * of docs (host CSR), without baselines: offsets [n_rows + 1] and cand
+ * [cap] (host), each row's candidates ascending.  SKM_E_INVALID if cap is too
+ * small (offsets[n_rows] then holds the size needed). */
+skm_status skm_index_query(skm_ctx *c, const skm_csr *docs, int32_t level, int64_t *offsets,
+                           int32_t *cand, int64_t cap);
 
 /* Device memory the context currently holds, in bytes. */
 size_t skm_hbm_bytes(const skm_ctx *c);

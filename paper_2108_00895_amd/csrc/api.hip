@@ -204,6 +204,87 @@ ScoreArgs base_args(skm_ctx *c) {
 
 int exact_waves() { return 4096; }
 
+// Frees one allocation made by dalloc.
+void dfree(skm_ctx *c, void *p, size_t count_bytes) {
+  if (!p) return;
+  auto it = std::find(c->allocations.begin(), c->allocations.end(), p);
+  if (it != c->allocations.end()) c->allocations.erase(it);
+  (void)hipFree(p);
+  c->hbm_bytes -= round_up((int64_t)std::max<size_t>(count_bytes, 1), 256);
+}
+
+// Sec. 3.2 index from the current master: entries per centroid, sorted, prefix
+// sums of squares, term-major G.  Entry-sized buffers grow on demand.
+skm_status build_index(skm_ctx *c) {
+  hipStream_t s = c->stream;
+  HIP_TRY(c, hipEventRecord(c->ev[6], s));
+  HIP_TRY(c, index_build_counts(c->master, c->k, c->D, c->idx_cnt, c->idx_eoff, s));
+  int64_t total = 0;
+  HIP_TRY(c, hipMemcpyAsync(&total, c->idx_eoff + c->k, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  if (total > c->idx_cap_entries) {
+    const int64_t cap = std::max<int64_t>(total + total / 4, 1024);
+    const int64_t old = c->idx_cap_entries;
+    dfree(c, c->idx_key0, old * 8);
+    dfree(c, c->idx_key1, old * 8);
+    dfree(c, c->idx_term0, old * 4);
+    dfree(c, c->idx_term1, old * 4);
+    dfree(c, c->idx_Q, (old + c->k) * 8);
+    dfree(c, c->idx_G, old * 8);
+    c->idx_key0 = c->idx_key1 = nullptr;
+    c->idx_term0 = c->idx_term1 = nullptr;
+    c->idx_Q = nullptr;
+    c->idx_G = nullptr;
+    c->idx_cap_entries = 0;
+    c->index_ready = false;
+    ST_TRY(dalloc(c, &c->idx_key0, (size_t)cap));
+    ST_TRY(dalloc(c, &c->idx_key1, (size_t)cap));
+    ST_TRY(dalloc(c, &c->idx_term0, (size_t)cap));
+    ST_TRY(dalloc(c, &c->idx_term1, (size_t)cap));
+    ST_TRY(dalloc(c, &c->idx_Q, (size_t)(cap + c->k)));
+    ST_TRY(dalloc(c, &c->idx_G, (size_t)cap));
+    c->idx_cap_entries = cap;
+  }
+  IndexBuild ib{c->master, c->k, c->D, c->idx_eoff, c->idx_key0, c->idx_key1, c->idx_term0,
+                c->idx_term1, c->idx_Q, c->idx_mask, c->idx_blkpre, c->idx_tcnt, c->idx_toff,
+                c->idx_G};
+  HIP_TRY(c, index_build_rest(ib, s));
+  HIP_TRY(c, hipEventRecord(c->ev[7], s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  c->idx_entries = total;
+  c->index_ready = true;
+  c->ms_index_build = elapsed(c->ev[6], c->ev[7]);
+  return SKM_OK;
+}
+
+IndexArgs index_args(skm_ctx *c) {
+  IndexArgs x{};
+  x.indptr = c->indptr;
+  x.indices = c->indices;
+  x.values = c->values;
+  x.xl2 = c->xl2;
+  x.master = c->master;
+  x.D = c->D;
+  x.k = c->k;
+  x.rows = c->idx_rows;
+  x.a_prev = c->a_prev;
+  x.toff = c->idx_toff;
+  x.G = c->idx_G;
+  x.eoff = c->idx_eoff;
+  x.Q = c->idx_Q;
+  for (int i = 0; i < 8; ++i) x.lambda[i] = c->cfg.lambda[i];
+  x.n_lambda = c->cfg.n_lambda;
+  x.forced_level = -1;
+  x.guard = c->idx_guard;
+  x.cap = c->idx_cap;
+  x.cand = c->idx_cand;
+  x.ncand = c->idx_ncand;
+  x.level = c->idx_level;
+  x.mode = c->mode;
+  x.stat = c->stat;
+  return x;
+}
+
 }  // namespace
 
 extern "C" {
@@ -358,6 +439,28 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
   A_(c->ids_count, 1);
   A_(c->part, ((int64_t)c->k + kChunk - 1) / kChunk * N);
   if (c->cfg.flags & SKM_NCC) A_(c->tile_ch, c->D * c->ld * c->esize);
+  if (c->cfg.flags & SKM_INDEX) {
+    int max_lds = 0;
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) !=
+        hipSuccess)
+      max_lds = 65536;
+    (void)hipGetLastError();
+    if (index_lds_bytes(c->k) + 4096 > (size_t)max_lds)
+      return cleanup(fail(SKM_E_UNSUPPORTED, "k too large for the index query's LDS (" +
+                                                 std::to_string(max_lds) + " bytes per workgroup)"));
+    const int64_t nb = (k + 63) / 64;
+    A_(c->mode, N);
+    A_(c->idx_cnt, k);
+    A_(c->idx_eoff, k + 1);
+    A_(c->idx_mask, c->D * nb);
+    A_(c->idx_blkpre, c->D * nb);
+    A_(c->idx_tcnt, c->D);
+    A_(c->idx_toff, c->D + 1);
+    A_(c->idx_rows, N);
+    A_(c->idx_cand, N * (int64_t)c->idx_cap);
+    A_(c->idx_ncand, N);
+    A_(c->idx_level, N);
+  }
 #undef A_
 
   hipStream_t s = c->stream;
@@ -385,6 +488,7 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
     }
   }
   if ((st = rebuild_tiles(c, nullptr)) != SKM_OK) return cleanup(st);
+  if ((c->cfg.flags & SKM_INDEX) && (st = build_index(c)) != SKM_OK) return cleanup(st);
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return cleanup(device_fail(c, "init sync", e));
   c->force_all = true;
@@ -416,6 +520,22 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
   }
   HIP_TRY(c, launch_fill_i32(c->counters, 0, 8, s));
   HIP_TRY(c, launch_fill_i32(reinterpret_cast<int32_t *>(c->stat), 0, 16, s));
+  const bool use_index = (c->cfg.flags & SKM_INDEX) && c->have_prev && c->index_ready &&
+                         (c->cfg.index_min_changed <= 0 || c->last_changed > c->cfg.index_min_changed);
+  if (use_index) {
+    HIP_TRY(c, hipEventRecord(c->ev[6], s));
+    HIP_TRY(c, launch_fill_u8(c->mode, 0, c->N, s));
+    HIP_TRY(c, index_rows(c->a_prev, (c->cfg.flags & SKM_NCC) ? c->changed : nullptr, c->N,
+                          c->idx_rows, c->ids_count, s));
+    int32_t n_rows_idx = 0;
+    HIP_TRY(c, hipMemcpyAsync(&n_rows_idx, c->ids_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    IndexArgs x = index_args(c);
+    HIP_TRY(c, index_query(x, n_rows_idx, s));
+    HIP_TRY(c, index_score(x, n_rows_idx, c->a, c->lo, c->hi, s));
+    HIP_TRY(c, hipEventRecord(c->ev[7], s));
+    a.mode = c->mode;
+  }
   HIP_TRY(c, hipEventRecord(c->ev[5], s));
   HIP_TRY(c, launch_score(a, c->part, c->score_blocks, c->prec, s));
   HIP_TRY(c, hipEventRecord(c->ev[1], s));
@@ -441,11 +561,15 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
     st_out->band_overflow = cnt[1];
     st_out->ncc_rows = (int64_t)stv[1];
     st_out->index_rows = (int64_t)stv[2];
+    st_out->index_no_level = (int64_t)stv[5];
+    st_out->index_guarded = (int64_t)stv[6];
+    st_out->index_over_cap = (int64_t)stv[7];
     st_out->mean_candidates = (double)stv[0] / (double)c->N;
     st_out->scored_products = (double)stv[3];
     st_out->ms_assign = elapsed(c->ev[0], c->ev[2]);
     st_out->ms_score = elapsed(c->ev[5], c->ev[1]);
     st_out->ms_exact = elapsed(c->ev[1], c->ev[2]);
+    st_out->ms_index = use_index ? elapsed(c->ev[6], c->ev[7]) : 0.f;
     st_out->objective_assign = st_out->objective_update = st_out->max_shift_sq = -1.0;
   }
   return SKM_OK;
@@ -474,6 +598,7 @@ skm_status skm_update(skm_ctx *c, skm_iter_stats *st_out) {
   HIP_TRY(c, launch_reduce_stats(c->changed, c->snorm, c->shift, c->dot_old, c->k, c->red, s));
   ST_TRY(rebuild_tiles(c, c->changed));
   HIP_TRY(c, hipEventRecord(c->ev[4], s));
+  if (c->cfg.flags & SKM_INDEX) ST_TRY(build_index(c));
   double red[3];
   HIP_TRY(c, hipMemcpyAsync(red, c->red, sizeof(red), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
@@ -490,6 +615,7 @@ skm_status skm_update(skm_ctx *c, skm_iter_stats *st_out) {
     st_out->objective_update = red[1];
     st_out->max_shift_sq = red[2];
     st_out->ms_update = elapsed(c->ev[3], c->ev[4]);
+    if (c->cfg.flags & SKM_INDEX) st_out->ms_index += c->ms_index_build;
   }
   return SKM_OK;
 }
@@ -633,6 +759,7 @@ skm_status skm_set_centroids(skm_ctx *c, const double *centroids) {
   HIP_TRY(c, hipMemcpyAsync(c->master, centroids, sizeof(double) * c->k * c->D,
                             hipMemcpyHostToDevice, c->stream));
   ST_TRY(rebuild_tiles(c, nullptr));
+  if (c->cfg.flags & SKM_INDEX) ST_TRY(build_index(c));
   HIP_TRY(c, launch_fill_u8(c->changed, 1, c->k, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->force_all = true;
@@ -719,12 +846,126 @@ double skm_error_bound(const skm_ctx *c, double s, int64_t nnz, double l1) {
 
 skm_status skm_get_index(const skm_ctx *c, int32_t level, int64_t *offsets, uint32_t *entries,
                          int64_t *n_entries) {
-  (void)level;
-  (void)offsets;
-  (void)entries;
-  (void)n_entries;
   ST_TRY(check_ctx(c));
-  return fail(SKM_E_UNSUPPORTED, "index not built");
+  if (!(c->cfg.flags & SKM_INDEX) || !c->index_ready)
+    return fail(SKM_E_STATE, "the index is not built (SKM_INDEX not set)");
+  if (level < 0 || level >= c->cfg.n_lambda) return fail(SKM_E_INVALID, "level out of range");
+  if (!offsets || !n_entries) return fail(SKM_E_INVALID, "offsets / n_entries is NULL");
+  skm_ctx *m = const_cast<skm_ctx *>(c);
+  const int64_t E = c->idx_entries, D = c->D, k = c->k;
+  std::vector<int64_t> toff(D + 1), eoff(k + 1);
+  std::vector<uint2> G(std::max<int64_t>(E, 1));
+  std::vector<double> Q(E + k);
+  HIP_TRY(m, hipMemcpyAsync(toff.data(), c->idx_toff, 8 * (D + 1), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(m, hipMemcpyAsync(eoff.data(), c->idx_eoff, 8 * (k + 1), hipMemcpyDeviceToHost, c->stream));
+  if (E > 0) {
+    HIP_TRY(m, hipMemcpyAsync(G.data(), c->idx_G, 8 * E, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(m, hipMemcpyAsync(Q.data(), c->idx_Q, 8 * (E + k), hipMemcpyDeviceToHost, c->stream));
+  }
+  HIP_TRY(m, hipStreamSynchronize(c->stream));
+  const double lam = c->cfg.lambda[level];
+  const double thr = lam * lam * (1.0 - 0x1p-40);
+  // m_p = least m with Q_j[min(p + m, n_j)] - Q_j[p] >= thr; no P entry when none
+  int64_t n = 0;
+  offsets[0] = 0;
+  for (int64_t t = 0; t < D; ++t) {
+    for (int64_t g = toff[t]; g < toff[t + 1]; ++g) {
+      const int64_t j = G[g].x, p = G[g].y, nj = eoff[j + 1] - eoff[j];
+      const double *q = Q.data() + eoff[j] + j;
+      if (q[nj] - q[p] < thr) continue;
+      int64_t lo = 1, hi = nj - p;
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if (q[p + mid] - q[p] >= thr) hi = mid;
+        else lo = mid + 1;
+      }
+      if (entries) entries[n] = (uint32_t)(j << 16) | (uint32_t)std::min<int64_t>(lo, 0xFFFF);
+      ++n;
+    }
+    offsets[t + 1] = n;
+  }
+  *n_entries = n;
+  return SKM_OK;
+}
+
+skm_status skm_index_query(skm_ctx *c, const skm_csr *docs, int32_t level, int64_t *offsets,
+                           int32_t *cand, int64_t cap) {
+  ST_TRY(check_ctx(c));
+  ST_TRY(check_csr_header(docs, c->D));
+  if (!(c->cfg.flags & SKM_INDEX) || !c->index_ready)
+    return fail(SKM_E_STATE, "the index is not built (SKM_INDEX not set)");
+  if (level < 0 || level >= c->cfg.n_lambda) return fail(SKM_E_INVALID, "level out of range");
+  if (!offsets || (!cand && cap > 0)) return fail(SKM_E_INVALID, "output pointer is NULL");
+  const int64_t n = docs->n_rows;
+  offsets[0] = 0;
+  if (n == 0) return SKM_OK;
+  std::vector<void *> tmp;
+  auto talloc = [&](auto **p, size_t bytes) -> skm_status {
+    void *q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(bytes, 1)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SKM_E_NOMEM, "temporary device allocation failed");
+    }
+    tmp.push_back(q);
+    *p = static_cast<std::remove_reference_t<decltype(*p)>>(q);
+    return SKM_OK;
+  };
+  auto release = [&]() {
+    for (void *q : tmp) (void)hipFree(q);
+  };
+  DevRows r;
+  skm_status st = upload_rows(c, docs, c->D, false, c->stream, talloc, &r);
+  int32_t *rows = nullptr, *dcand = nullptr, *ncand = nullptr, *lvl = nullptr;
+  unsigned long long *stat = nullptr;
+  if (st == SKM_OK) st = talloc(&rows, 4 * n);
+  if (st == SKM_OK) st = talloc(&dcand, 4 * n * (int64_t)c->k);
+  if (st == SKM_OK) st = talloc(&ncand, 4 * n);
+  if (st == SKM_OK) st = talloc(&lvl, 4 * n);
+  if (st == SKM_OK) st = talloc(&stat, 128);
+  if (st != SKM_OK) {
+    release();
+    return st;
+  }
+  std::vector<int32_t> hrows(n);
+  for (int64_t i = 0; i < n; ++i) hrows[i] = (int32_t)i;
+  IndexArgs x = index_args(c);
+  x.indptr = r.indptr;
+  x.indices = r.indices;
+  x.values = r.values;
+  x.xl2 = r.xl2;
+  x.rows = rows;
+  x.a_prev = nullptr;
+  x.forced_level = level;
+  x.guard = 1e300;
+  x.cap = c->k;
+  x.cand = dcand;
+  x.ncand = ncand;
+  x.level = lvl;
+  x.mode = nullptr;
+  x.stat = stat;
+  std::vector<int32_t> hn(n);
+  hipError_t e = hipMemcpyAsync(rows, hrows.data(), 4 * n, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = launch_fill_i32(reinterpret_cast<int32_t *>(stat), 0, 32, c->stream);
+  if (e == hipSuccess) e = index_query(x, n, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(hn.data(), ncand, 4 * n, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    release();
+    return device_fail(c, "skm_index_query", e);
+  }
+  for (int64_t i = 0; i < n; ++i) offsets[i + 1] = offsets[i] + hn[i];
+  if (offsets[n] > cap) {
+    release();
+    return fail(SKM_E_INVALID, "cand buffer too small");
+  }
+  for (int64_t i = 0; i < n && e == hipSuccess; ++i)
+    if (hn[i] > 0)
+      e = hipMemcpyAsync(cand + offsets[i], dcand + i * (int64_t)c->k, 4 * hn[i],
+                         hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  release();
+  if (e != hipSuccess) return device_fail(c, "skm_index_query copy", e);
+  return SKM_OK;
 }
 
 }  // extern "C"

@@ -38,6 +38,7 @@ struct ScoreArgs {
   // Sec. 3.2: per-row candidate lists (nullptr: no index)
   const int64_t *cand_off;    // [n_rows + 1]; a row with cand_off[i] < 0 marker uses the dense path
   const int32_t *cand;
+  const uint8_t *mode;        // 2 = row finished by the index path (skip), or nullptr
   // bound
   double uq;
   double abs_coef;
@@ -69,10 +70,53 @@ struct ExactArgs {
   int32_t max_waves;
 };
 
-struct Buf {
-  void *p = nullptr;
-  size_t bytes = 0;
+// Device pieces of the Sec. 3.2 index.
+struct IndexBuild {
+  const double *master;
+  int32_t k;
+  int64_t D;
+  const int64_t *eoff;   // [k + 1] entry offsets per centroid
+  uint64_t *key0, *key1; // sort keys (~bits of the value), ping-pong
+  int32_t *term0, *term1;
+  double *Q;             // prefix sums of squares, centroid j at eoff[j] + j
+  uint64_t *mask;        // [D][ceil(k/64)] non-zero masks
+  int32_t *blkpre;       // [D][ceil(k/64)] per-term prefix of mask popcounts
+  int32_t *tcnt;         // [D] centroids per term
+  int64_t *toff;         // [D + 1] G offsets
+  uint2 *G;              // (centroid, position) per (term, centroid)
 };
+
+struct IndexArgs {
+  const int64_t *indptr;
+  const int32_t *indices;
+  const float *values;
+  const double *xl2;
+  const double *master;
+  int64_t D;
+  int32_t k;
+  const int32_t *rows;      // rows handled, one workgroup each
+  const int32_t *a_prev;    // previous assignment (baseline), or nullptr
+  const int64_t *toff;
+  const uint2 *G;
+  const int64_t *eoff;
+  const double *Q;
+  double lambda[8];
+  int32_t n_lambda;
+  int32_t forced_level;     // >= 0: use this level, no baseline, no cost guard
+  double guard;             // max query reads as a fraction of nnz * k
+  int32_t cap;              // candidate slots per row
+  int32_t *cand;            // [slots][cap]
+  int32_t *ncand;           // [slots], -1 = dense path
+  int32_t *level;           // [slots]
+  uint8_t *mode;            // [n_rows] 2 = finished by the index path, or nullptr
+  unsigned long long *stat; // [0] scored, [2] index rows, [3] products, [5] no level,
+                            // [6] guard, [7] over cap
+};
+
+// LDS of the index query: k positions (4 B) and k 16-bit counts.
+__host__ __device__ inline size_t index_lds_bytes(int32_t k) {
+  return sizeof(uint32_t) * ((size_t)k + ((size_t)k + 1) / 2);
+}
 
 }  // namespace skm
 
@@ -132,6 +176,24 @@ struct skm_ctx {
   double *red = nullptr;       // reduction outputs
   int32_t *ids_count = nullptr;
   skm::Partial *part = nullptr;  // [ceil(k / 512)][N] scoring partials
+  uint8_t *mode = nullptr;       // [N] 2 = row finished by the index path
+  // Sec. 3.2 index (built when SKM_INDEX is set)
+  bool index_ready = false;
+  int64_t idx_cap_entries = 0;   // capacity of the entry-sized buffers
+  int64_t idx_entries = 0;       // entries of the current build
+  int32_t *idx_cnt = nullptr;
+  int64_t *idx_eoff = nullptr;
+  uint64_t *idx_key0 = nullptr, *idx_key1 = nullptr;
+  int32_t *idx_term0 = nullptr, *idx_term1 = nullptr;
+  double *idx_Q = nullptr;
+  uint2 *idx_G = nullptr;
+  uint64_t *idx_mask = nullptr;
+  int32_t *idx_blkpre = nullptr, *idx_tcnt = nullptr;
+  int64_t *idx_toff = nullptr;
+  int32_t *idx_rows = nullptr, *idx_cand = nullptr, *idx_ncand = nullptr, *idx_level = nullptr;
+  int32_t idx_cap = 128;
+  double idx_guard = 0.25;
+  float ms_index_build = 0.f;
   int score_blocks = 2048;       // persistent scoring grid
   int64_t nblk = 0;
 
@@ -157,6 +219,16 @@ hipError_t launch_score_dense(const int64_t *indptr, const int32_t *indices, con
 hipError_t launch_exact_scores(const int64_t *indptr, const int32_t *indices, const float *values,
                                int64_t n_rows, const int32_t *a, const double *master, int64_t D,
                                double *out, hipStream_t s);
+
+// kernels_index.hip
+hipError_t index_build_counts(const double *master, int32_t k, int64_t D, int32_t *cnt,
+                              int64_t *eoff, hipStream_t s);
+hipError_t index_build_rest(const IndexBuild &ib, hipStream_t s);
+hipError_t index_rows(const int32_t *a_prev, const uint8_t *changed, int64_t n, int32_t *rows,
+                      int32_t *count, hipStream_t s);
+hipError_t index_query(const IndexArgs &x, int64_t n_slots, hipStream_t s);
+hipError_t index_score(const IndexArgs &x, int64_t n_slots, int32_t *a_out, double *lo_out,
+                       double *hi_out, hipStream_t s);
 
 // kernels_update.hip
 hipError_t launch_row_stats(const int64_t *indptr, const int32_t *indices, const float *values,

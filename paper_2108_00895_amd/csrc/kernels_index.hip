@@ -1,0 +1,510 @@
+// The dot-product index of paper Sec. 3.2 on the GPU.
+//
+// Build (from the FP64 master):
+//   - every centroid's non-zero entries, sorted by value descending (equal
+//     values: ascending term), with the FP64 prefix sums Q_j of their squares;
+//   - G: for every term t, the centroids with a non-zero at t, ascending, each
+//     with the term's position p in that centroid's sorted order.
+// The paper's minimum overlap count of position p for threshold lam is
+//   m_p = least m with Q_j[min(p + m, n_j)] - Q_j[p] >= lam^2,
+// and the positions entering P are those where such an m exists.  m_p is
+// non-decreasing in p, so "some overlapping term t of x has (j, m_p) in P with
+// count_j >= m_p" holds exactly when it holds at the highest-valued overlapping
+// position p*: the query computes count_j and p*_j from G and tests
+//   Q_j[min(p*_j + count_j, n_j)] - Q_j[p*_j] >= lam^2,
+// which returns the same set as the paper's two-map query.  Sums are compared
+// against lam^2 (1 - 2^-40) so FP64 rounding of the prefix differences can only
+// enlarge the candidate set.
+#include <algorithm>
+
+#include "internal.h"
+
+namespace skm {
+namespace {
+
+constexpr int kRun = 2048;   // LDS sort run
+
+__device__ inline bool key_less(uint64_t ka, int32_t ta, uint64_t kb, int32_t tb) {
+  return ka < kb || (ka == kb && ta < tb);
+}
+
+// Non-zeros per centroid.
+__global__ __launch_bounds__(256) void k_centroid_nnz(const double *master, int64_t D, int32_t *cnt) {
+  __shared__ int32_t sh[256];
+  const int j = blockIdx.x;
+  int c = 0;
+  for (int64_t t = threadIdx.x; t < D; t += 256) c += master[(int64_t)j * D + t] != 0.0;
+  sh[threadIdx.x] = c;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) cnt[j] = sh[0];
+}
+
+// Entries of centroid j in term order: key = ~bits(value) (ascending key =
+// descending value, values are positive), term.
+__global__ __launch_bounds__(256) void k_extract(const double *master, int64_t D, const int64_t *eoff,
+                                                 uint64_t *key, int32_t *term) {
+  __shared__ int32_t sh[256];
+  const int j = blockIdx.x;
+  const double *row = master + (int64_t)j * D;
+  int64_t base = eoff[j];
+  const int64_t per = (D + 255) / 256;
+  const int64_t lo = threadIdx.x * per, hi = min(D, lo + per);
+  int c = 0;
+  for (int64_t t = lo; t < hi; ++t) c += row[t] != 0.0;
+  sh[threadIdx.x] = c;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    int v = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int64_t pos = base + sh[threadIdx.x] - c;
+  for (int64_t t = lo; t < hi; ++t) {
+    const double v = row[t];
+    if (v != 0.0) {
+      key[pos] = ~(uint64_t)__double_as_longlong(v);
+      term[pos] = (int32_t)t;
+      ++pos;
+    }
+  }
+}
+
+// Merge-path co-rank: number of elements of A among the first o outputs of
+// merge(A, B) (keys are unique within a centroid).
+__device__ inline int64_t corank(int64_t o, const uint64_t *ka, const int32_t *ta, int64_t na,
+                                 const uint64_t *kb, const int32_t *tb, int64_t nb) {
+  int64_t lo = o > nb ? o - nb : 0, hi = o < na ? o : na;
+  while (lo < hi) {
+    const int64_t i = (lo + hi) / 2, j = o - i;
+    const bool too_small = i < na && j > 0 && !key_less(kb[j - 1], tb[j - 1], ka[i], ta[i]);
+    if (too_small) lo = i + 1;
+    else hi = i;
+  }
+  return lo;
+}
+
+// Sorts each centroid's segment ascending by (key, term): bitonic runs of
+// 2048 in LDS, then merge passes between the two buffers.  The result ends in
+// (key0, term0).
+__global__ __launch_bounds__(256) void k_sort_segments(const int64_t *eoff, uint64_t *key0,
+                                                       int32_t *term0, uint64_t *key1,
+                                                       int32_t *term1) {
+  __shared__ uint64_t sk[kRun];
+  __shared__ int32_t st[kRun];
+  const int j = blockIdx.x;
+  const int64_t s0 = eoff[j], s1 = eoff[j + 1], n = s1 - s0;
+  if (n <= 1) return;
+  for (int64_t r0 = 0; r0 < n; r0 += kRun) {
+    const int64_t m = min<int64_t>(kRun, n - r0);
+    for (int i = threadIdx.x; i < kRun; i += 256) {
+      sk[i] = i < m ? key0[s0 + r0 + i] : ~0ull;
+      st[i] = i < m ? term0[s0 + r0 + i] : 0x7FFFFFFF;
+    }
+    __syncthreads();
+    for (int size = 2; size <= kRun; size <<= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int i = threadIdx.x; i < kRun / 2; i += 256) {
+          const int lo = 2 * i - (i & (stride - 1));
+          const int hi = lo + stride;
+          const bool up = (lo & size) == 0;
+          const bool gt = key_less(sk[hi], st[hi], sk[lo], st[lo]);
+          if (gt == up) {
+            const uint64_t k2 = sk[lo];
+            sk[lo] = sk[hi];
+            sk[hi] = k2;
+            const int32_t t2 = st[lo];
+            st[lo] = st[hi];
+            st[hi] = t2;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int i = threadIdx.x; i < m; i += 256) {
+      key0[s0 + r0 + i] = sk[i];
+      term0[s0 + r0 + i] = st[i];
+    }
+    __syncthreads();
+  }
+  uint64_t *ka = key0 + s0, *kb = key1 + s0;
+  int32_t *ta = term0 + s0, *tb = term1 + s0;
+  int passes = 0;
+  for (int64_t w = kRun; w < n; w <<= 1) {
+    for (int64_t a = 0; a < n; a += 2 * w) {
+      const int64_t na = min(w, n - a);
+      const int64_t nb = max<int64_t>(0, min(w, n - a - w));
+      const int64_t len = na + nb;
+      const int64_t per = (len + 255) / 256;
+      const int64_t o0 = min<int64_t>((int64_t)threadIdx.x * per, len);
+      const int64_t o1 = min<int64_t>(o0 + per, len);
+      const uint64_t *KA = ka + a, *KB = ka + a + na;
+      const int32_t *TA = ta + a, *TB = ta + a + na;
+      int64_t i = corank(o0, KA, TA, na, KB, TB, nb);
+      int64_t jj = o0 - i;
+      for (int64_t o = o0; o < o1; ++o) {
+        const bool takeB = jj < nb && (i >= na || key_less(KB[jj], TB[jj], KA[i], TA[i]));
+        if (takeB) {
+          kb[a + o] = KB[jj];
+          tb[a + o] = TB[jj];
+          ++jj;
+        } else {
+          kb[a + o] = KA[i];
+          tb[a + o] = TA[i];
+          ++i;
+        }
+      }
+    }
+    __syncthreads();
+    uint64_t *kt = ka;
+    ka = kb;
+    kb = kt;
+    int32_t *tt = ta;
+    ta = tb;
+    tb = tt;
+    ++passes;
+  }
+  if (passes & 1) {   // result is in the second buffer: copy back
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+      key0[s0 + i] = ka[i];
+      term0[s0 + i] = ta[i];
+    }
+  }
+}
+
+// Q_j[0] = 0, Q_j[p + 1] = Q_j[p] + v_p^2 over the sorted entries (fixed
+// per-thread pieces + block scan: deterministic).  Q_j starts at qoff = eoff[j] + j.
+__global__ __launch_bounds__(256) void k_prefix_sq(const int64_t *eoff, const uint64_t *key,
+                                                   double *Q) {
+  __shared__ double sh[256];
+  const int j = blockIdx.x;
+  const int64_t s0 = eoff[j], n = eoff[j + 1] - s0;
+  double *q = Q + s0 + j;
+  const int64_t per = (n + 255) / 256;
+  const int64_t lo = min<int64_t>((int64_t)threadIdx.x * per, n), hi = min(n, lo + per);
+  double c = 0.0;
+  for (int64_t p = lo; p < hi; ++p) {
+    const double v = __longlong_as_double((long long)~key[s0 + p]);
+    c += v * v;
+  }
+  sh[threadIdx.x] = c;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    double v = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0.0;
+    __syncthreads();
+    sh[threadIdx.x] += v;
+    __syncthreads();
+  }
+  double run = sh[threadIdx.x] - c;
+  if (threadIdx.x == 0) q[0] = 0.0;
+  for (int64_t p = lo; p < hi; ++p) {
+    const double v = __longlong_as_double((long long)~key[s0 + p]);
+    run += v * v;
+    q[p + 1] = run;
+  }
+}
+
+// Non-zero masks, term-major: mask[t * nb + b] bit i = (c_{64b+i, t} != 0).
+__global__ __launch_bounds__(256) void k_term_masks(const double *master, int32_t k, int64_t D,
+                                                    int64_t nb, uint64_t *mask) {
+  __shared__ uint8_t nz[64][65];
+  const int64_t j0 = (int64_t)blockIdx.x * 64, t0 = (int64_t)blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int jj = ty; jj < 64; jj += 4) {
+    const int64_t j = j0 + jj, t = t0 + tx;
+    nz[jj][tx] = (j < k && t < D) ? (master[j * D + t] != 0.0) : 0;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int64_t t = t0 + threadIdx.x;
+    if (t < D) {
+      uint64_t m = 0;
+      for (int jj = 0; jj < 64; ++jj) m |= (uint64_t)nz[jj][threadIdx.x] << jj;
+      mask[t * nb + blockIdx.x] = m;
+    }
+  }
+}
+
+// Per term: exclusive prefix of mask popcounts over its blocks, total count.
+__global__ void k_term_prefix(const uint64_t *mask, int64_t D, int64_t nb, int32_t *blkpre,
+                              int32_t *tcnt) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= D) return;
+  int32_t run = 0;
+  for (int64_t b = 0; b < nb; ++b) {
+    blkpre[t * nb + b] = run;
+    run += __popcll(mask[t * nb + b]);
+  }
+  tcnt[t] = run;
+}
+
+// G entries: (centroid, position) at term t's slot ordered by centroid.
+__global__ __launch_bounds__(256) void k_fill_G(const int64_t *eoff, const int32_t *term,
+                                                const uint64_t *mask, const int32_t *blkpre,
+                                                const int64_t *toff, int64_t nb, uint2 *G) {
+  const int j = blockIdx.x;
+  const int64_t s0 = eoff[j], n = eoff[j + 1] - s0;
+  const int64_t b = j >> 6;
+  const uint64_t below = (j & 63) ? (~0ull >> (64 - (j & 63))) : 0ull;
+  for (int64_t p = threadIdx.x; p < n; p += 256) {
+    const int64_t t = term[s0 + p];
+    const int64_t pos = toff[t] + blkpre[t * nb + b] + __popcll(mask[t * nb + b] & below);
+    G[pos] = make_uint2((uint32_t)j, (uint32_t)p);
+  }
+}
+
+__global__ void k_scan_i32_to_i64(const int32_t *cnt, int64_t n, int64_t *off) {
+  // single workgroup of 1024 threads, chunked exclusive scan
+  __shared__ int64_t sh[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t lo = min<int64_t>(t * per, n), hi = min(n, lo + per);
+  int64_t c = 0;
+  for (int64_t i = lo; i < hi; ++i) c += cnt[i];
+  sh[t] = c;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    int64_t v = t >= o ? sh[t - o] : 0;
+    __syncthreads();
+    sh[t] += v;
+    __syncthreads();
+  }
+  int64_t pos = sh[t] - c;
+  for (int64_t i = lo; i < hi; ++i) {
+    off[i] = pos;
+    pos += cnt[i];
+  }
+  if (t == 1023) off[n] = sh[1023];
+}
+
+// ---------------------------------------------------------------- query
+
+__device__ inline double index_threshold(double lam) { return lam * lam * (1.0 - 0x1p-40); }
+
+// Index path for the rows in `rows` (their previous centroid changed).  One
+// workgroup per row:
+//   1. baseline b = x . c_{a_prev} in FP64 (the current centroid of the previous
+//      assignment), b_lo = b - err; level = highest lam with lam * ||x|| <= b_lo;
+//   2. cost guard: the query reads sum_t |G[t]| entries; when that exceeds
+//      guard * nnz * k the dense scan is cheaper and the row stays dense;
+//   3. overlap counts and highest-valued positions in LDS, the candidate test
+//      above, candidates ascending into cand[slot * cap ...] (dense fallback
+//      when more than cap survive).
+// mode[row] = 2 marks rows finished here (scored by k_index_score).
+__global__ __launch_bounds__(256) void k_index_query(IndexArgs x) {
+  extern __shared__ uint32_t lds[];
+  uint32_t *pmin = lds;                        // k positions
+  uint32_t *cnt = lds + x.k;                   // k counts, two 16-bit counts per word
+  __shared__ double red[256];
+  __shared__ int32_t sh_i[256];
+  __shared__ int s_level;
+  const int64_t slot = blockIdx.x;
+  const int64_t row = x.rows[slot];
+  const int64_t b = x.indptr[row], e = x.indptr[row + 1], n = e - b;
+  const int32_t ap = x.a_prev ? x.a_prev[row] : 0;
+  // 1. baseline
+  double part = 0.0;
+  if (x.a_prev)
+    for (int64_t q = b + threadIdx.x; q < e; q += 256)
+      part = fma((double)x.values[q], x.master[(int64_t)ap * x.D + x.indices[q]], part);
+  red[threadIdx.x] = part;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double base = red[0];
+  const double blo = base - exact_err(n, base);
+  const double xn = x.xl2[row] * (1.0 + 0x1p-40);
+  // 2. cost guard
+  double gsum = 0.0;
+  for (int64_t q = b + threadIdx.x; q < e; q += 256) {
+    const int32_t t = x.indices[q];
+    gsum += (double)(x.toff[t + 1] - x.toff[t]);
+  }
+  __syncthreads();
+  red[threadIdx.x] = gsum;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    int lv = -1;
+    for (int l = 0; l < x.n_lambda; ++l)
+      if (x.lambda[l] * xn <= blo) lv = l;
+    if (x.forced_level >= 0) lv = x.forced_level;
+    else if (lv >= 0 && red[0] > x.guard * (double)n * (double)x.k) lv = -2;
+    s_level = lv;
+  }
+  __syncthreads();
+  const int level = s_level;
+  if (level < 0) {
+    if (threadIdx.x == 0) {
+      x.ncand[slot] = -1;
+      atomicAdd(&x.stat[level == -1 ? 5 : 6], 1ull);
+    }
+    return;
+  }
+  // 3. counts and best positions
+  for (int j = threadIdx.x; j < x.k; j += 256) pmin[j] = 0xFFFFFFFFu;
+  for (int j = threadIdx.x; j < (x.k + 1) / 2; j += 256) cnt[j] = 0;
+  __syncthreads();
+  for (int64_t q = b; q < e; ++q) {
+    const int32_t t = x.indices[q];
+    for (int64_t g = x.toff[t] + threadIdx.x; g < x.toff[t + 1]; g += 256) {
+      const uint2 ent = x.G[g];
+      atomicAdd(&cnt[ent.x >> 1], 1u << (16 * (ent.x & 1)));
+      atomicMin(&pmin[ent.x], ent.y);
+    }
+  }
+  __syncthreads();
+  const double thr = index_threshold(x.lambda[level]);
+  int total = 0;
+  for (int j0 = 0; j0 < x.k; j0 += 256) {
+    const int j = j0 + threadIdx.x;
+    int in = 0;
+    const uint32_t cj = j < x.k ? (cnt[j >> 1] >> (16 * (j & 1))) & 0xFFFFu : 0u;
+    if (cj > 0) {
+      const int64_t nj = x.eoff[j + 1] - x.eoff[j];
+      const int64_t p = pmin[j];
+      const int64_t h = min<int64_t>(p + cj, nj);
+      const double *Qj = x.Q + x.eoff[j] + j;
+      in = (Qj[h] - Qj[p] >= thr) ? 1 : 0;
+    }
+    sh_i[threadIdx.x] = in;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      int v = (int)threadIdx.x >= off ? sh_i[threadIdx.x - off] : 0;
+      __syncthreads();
+      sh_i[threadIdx.x] += v;
+      __syncthreads();
+    }
+    const int pos = total + sh_i[threadIdx.x] - in;
+    if (in && pos < x.cap) x.cand[slot * x.cap + pos] = j;
+    total += sh_i[255];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    x.ncand[slot] = total <= x.cap ? total : -1;
+    x.level[slot] = level;
+    if (total <= x.cap) {
+      if (x.mode) x.mode[row] = 2;
+      atomicAdd(&x.stat[2], 1ull);
+      atomicAdd(&x.stat[0], (unsigned long long)total + 1ull);
+      atomicAdd(&x.stat[3], (unsigned long long)(total + 1) * (unsigned long long)n);
+    } else {
+      atomicAdd(&x.stat[7], 1ull);
+    }
+  }
+}
+
+// FP64 exact scores of an index row's candidates plus its previous centroid;
+// lowest index among the maxima.  One wavefront per row.
+__global__ __launch_bounds__(256) void k_index_score(IndexArgs x, int64_t n_slots, int32_t *a_out,
+                                                     double *lo_out, double *hi_out) {
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int64_t slot = (int64_t)blockIdx.x * 4 + wave;
+  if (slot >= n_slots) return;
+  const int32_t nc = x.ncand[slot];
+  if (nc < 0) return;
+  const int64_t row = x.rows[slot];
+  const int64_t b = x.indptr[row], e = x.indptr[row + 1];
+  const int32_t ap = x.a_prev[row];
+  double bs = -INFINITY;
+  int bj = 0x7FFFFFFF;
+  for (int i = lane; i <= nc; i += kWave) {
+    const int j = i < nc ? x.cand[slot * x.cap + i] : ap;
+    const double *c = x.master + (int64_t)j * x.D;
+    double s = 0.0;
+    for (int64_t q = b; q < e; ++q) s = fma((double)x.values[q], c[x.indices[q]], s);
+    if (better_d(s, j, bs, bj)) {
+      bs = s;
+      bj = j;
+    }
+  }
+  wave_best_d(bs, bj);
+  if (lane == 0) {
+    const double err = exact_err(e - b, bs);
+    a_out[row] = bj;
+    lo_out[row] = bs - err;
+    hi_out[row] = bs + err;
+  }
+}
+
+// Rows whose previous centroid changed, in ascending order (index path).
+__global__ __launch_bounds__(1024) void k_index_rows(const int32_t *a_prev, const uint8_t *changed,
+                                                     int64_t n, int32_t *rows, int32_t *count) {
+  __shared__ int32_t sh[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t lo = min<int64_t>(t * per, n), hi = min(n, lo + per);
+  int c = 0;
+  for (int64_t i = lo; i < hi; ++i) c += (!changed || changed[a_prev[i]]) ? 1 : 0;
+  sh[t] = c;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    int v = t >= o ? sh[t - o] : 0;
+    __syncthreads();
+    sh[t] += v;
+    __syncthreads();
+  }
+  int pos = sh[t] - c;
+  for (int64_t i = lo; i < hi; ++i)
+    if (!changed || changed[a_prev[i]]) rows[pos++] = (int32_t)i;
+  if (t == 1023) *count = sh[1023];
+}
+
+}  // namespace
+
+hipError_t index_build_counts(const double *master, int32_t k, int64_t D, int32_t *cnt,
+                              int64_t *eoff, hipStream_t s) {
+  hipLaunchKernelGGL(k_centroid_nnz, dim3((unsigned)k), dim3(256), 0, s, master, D, cnt);
+  hipLaunchKernelGGL(k_scan_i32_to_i64, dim3(1), dim3(1024), 0, s, cnt, (int64_t)k, eoff);
+  return hipGetLastError();
+}
+
+hipError_t index_build_rest(const IndexBuild &ib, hipStream_t s) {
+  const int32_t k = ib.k;
+  const int64_t D = ib.D, nb = (k + 63) / 64;
+  hipLaunchKernelGGL(k_extract, dim3((unsigned)k), dim3(256), 0, s, ib.master, D, ib.eoff, ib.key0,
+                     ib.term0);
+  hipLaunchKernelGGL(k_sort_segments, dim3((unsigned)k), dim3(256), 0, s, ib.eoff, ib.key0,
+                     ib.term0, ib.key1, ib.term1);
+  hipLaunchKernelGGL(k_prefix_sq, dim3((unsigned)k), dim3(256), 0, s, ib.eoff, ib.key0, ib.Q);
+  hipLaunchKernelGGL(k_term_masks, dim3((unsigned)nb, (unsigned)((D + 63) / 64)), dim3(256), 0, s,
+                     ib.master, k, D, nb, ib.mask);
+  hipLaunchKernelGGL(k_term_prefix, dim3((unsigned)((D + 255) / 256)), dim3(256), 0, s, ib.mask, D,
+                     nb, ib.blkpre, ib.tcnt);
+  hipLaunchKernelGGL(k_scan_i32_to_i64, dim3(1), dim3(1024), 0, s, ib.tcnt, D, ib.toff);
+  hipLaunchKernelGGL(k_fill_G, dim3((unsigned)k), dim3(256), 0, s, ib.eoff, ib.term0, ib.mask,
+                     ib.blkpre, ib.toff, nb, ib.G);
+  return hipGetLastError();
+}
+
+hipError_t index_rows(const int32_t *a_prev, const uint8_t *changed, int64_t n, int32_t *rows,
+                      int32_t *count, hipStream_t s) {
+  hipLaunchKernelGGL(k_index_rows, dim3(1), dim3(1024), 0, s, a_prev, changed, n, rows, count);
+  return hipGetLastError();
+}
+
+hipError_t index_query(const IndexArgs &x, int64_t n_slots, hipStream_t s) {
+  if (n_slots <= 0) return hipSuccess;
+  const size_t lds = index_lds_bytes(x.k);
+  hipLaunchKernelGGL(k_index_query, dim3((unsigned)n_slots), dim3(256), lds, s, x);
+  return hipGetLastError();
+}
+
+hipError_t index_score(const IndexArgs &x, int64_t n_slots, int32_t *a_out, double *lo_out,
+                       double *hi_out, hipStream_t s) {
+  if (n_slots <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_index_score, dim3((unsigned)((n_slots + 3) / 4)), dim3(256), 0, s, x, n_slots,
+                     a_out, lo_out, hi_out);
+  return hipGetLastError();
+}
+
+}  // namespace skm

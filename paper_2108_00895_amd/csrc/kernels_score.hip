@@ -149,10 +149,16 @@ struct RowPlan {
   const int32_t *colmap;   // column -> centroid id, nullptr = identity
   bool ncc;
   int32_t ap;
+  bool done;               // finished by the index path
 };
 
 __device__ inline RowPlan plan_row(const ScoreArgs &a, int64_t row, bool allow_ncc) {
-  RowPlan p{a.tile, a.k, nullptr, false, -1};
+  RowPlan p{a.tile, a.k, nullptr, false, -1, false};
+  if (a.mode && a.mode[row] == 2) {
+    p.ncols = 0;
+    p.done = true;
+    return p;
+  }
   if (allow_ncc && a.a_prev) {
     const int32_t ap = a.a_prev[row];
     if (!a.changed[ap]) {
@@ -218,9 +224,9 @@ __global__ __launch_bounds__(256) void k_finalize(ScoreArgs a, const Partial *__
   __shared__ unsigned long long sh[3][256];
   const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
   unsigned long long n_cols = 0, n_prod = 0, n_ncc = 0;
-  if (row < a.n_rows) {
+  const RowPlan pl = row < a.n_rows ? plan_row(a, row, true) : RowPlan{};
+  if (row < a.n_rows && !pl.done) {
     const int64_t b = a.indptr[row], e = a.indptr[row + 1];
-    const RowPlan pl = plan_row(a, row, true);
     float b1 = -INFINITY, b2 = -INFINITY;
     int j1 = 0x7FFFFFFF;
     const int64_t nch = (pl.ncols + kChunk - 1) / kChunk;
@@ -330,7 +336,7 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs x) {
     const int64_t b = uniform64(a.indptr[row]);
     const int64_t e = uniform64(a.indptr[row + 1]);
     const int64_t n = e - b;
-    RowPlan pl{a.tile, a.k, nullptr, false, -1};
+    RowPlan pl{a.tile, a.k, nullptr, false, -1, false};
     if (ncc_row) {
       pl.tile = a.tile_ch;
       pl.ncols = a.n_ch;

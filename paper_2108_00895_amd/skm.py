@@ -27,6 +27,7 @@ EXPORTED = [
     "skm_config_default", "skm_init", "skm_assign", "skm_update", "skm_iterate",
     "skm_assign_new", "skm_get_assignments", "skm_get_centroids", "skm_set_centroids",
     "skm_get_tile", "skm_get_changed", "skm_score_dense", "skm_error_bound", "skm_get_index",
+    "skm_index_query",
     "skm_hbm_bytes", "skm_last_error", "skm_destroy",
 ]
 
@@ -57,7 +58,9 @@ class IterStats(ctypes.Structure):
     _fields_ = [("iter", ctypes.c_int32), ("changed_centroids", ctypes.c_int32),
                 ("moved", ctypes.c_int64), ("flagged", ctypes.c_int64),
                 ("band_overflow", ctypes.c_int64), ("ncc_rows", ctypes.c_int64),
-                ("index_rows", ctypes.c_int64), ("mean_candidates", ctypes.c_double),
+                ("index_rows", ctypes.c_int64), ("index_no_level", ctypes.c_int64),
+                ("index_guarded", ctypes.c_int64), ("index_over_cap", ctypes.c_int64),
+                ("mean_candidates", ctypes.c_double),
                 ("scored_products", ctypes.c_double),
                 ("objective_assign", ctypes.c_double), ("objective_update", ctypes.c_double),
                 ("max_shift_sq", ctypes.c_double), ("ms_assign", ctypes.c_float),
@@ -115,6 +118,8 @@ def load():
     lib.skm_error_bound.restype = ctypes.c_double
     lib.skm_get_index.argtypes = [vp, i32, vp, vp, P(i64)]
     lib.skm_get_index.restype = st
+    lib.skm_index_query.argtypes = [vp, P(Csr), i32, vp, vp, i64]
+    lib.skm_index_query.restype = st
     lib.skm_hbm_bytes.argtypes = [vp]
     lib.skm_hbm_bytes.restype = ctypes.c_size_t
     lib.skm_last_error.argtypes = []
@@ -314,6 +319,16 @@ class Context:
         ent = np.empty(n.value, dtype=np.uint32)
         _check(lib.skm_get_index(self._h, level, off.ctypes.data, ent.ctypes.data, ctypes.byref(n)))
         return off, ent
+
+    def index_query(self, csr, level):
+        """Candidate lists (list of int arrays) of the index at `level`."""
+        c, hold = make_csr(*csr, self.n_cols)
+        off = np.empty(c.n_rows + 1, dtype=np.int64)
+        cap = max(1, c.n_rows * self.k)
+        cand = np.empty(cap, dtype=np.int32)
+        _check(load().skm_index_query(self._h, ctypes.byref(c), level, off.ctypes.data,
+                                      cand.ctypes.data, cap))
+        return [cand[off[i]:off[i + 1]].copy() for i in range(c.n_rows)]
 
     def hbm_bytes(self):
         return load().skm_hbm_bytes(self._h)

@@ -50,6 +50,8 @@ def _load():
     lib.synth_indptr.argtypes = [i64, i32, dbl, dbl, i64, i64, u64, vp, i32]
     lib.synth_fill.restype = ctypes.c_int
     lib.synth_fill.argtypes = [i64, i32, dbl, dbl, u64, vp, vp, vp, i32]
+    lib.synth_topic_fill.restype = ctypes.c_int
+    lib.synth_topic_fill.argtypes = [i64, i32, i32, i32, dbl, dbl, dbl, u64, vp, vp, vp, i32]
     lib.synth_seed_rows.restype = ctypes.c_int
     lib.synth_seed_rows.argtypes = [i64, i32, u64, vp]
     lib.synth_stream_u64.restype = None
@@ -104,6 +106,43 @@ def generate(c: Corpus, nthreads: int = 0):
                         indices.ctypes.data, values.ctypes.data, nthreads)
     if rc != 0:
         raise RuntimeError(f"synth_fill failed ({rc})")
+    return indptr, indices, values
+
+
+@dataclass(frozen=True)
+class TopicCorpus:
+    """Topic-structured corpus: shared Zipf vocabulary plus one block per topic."""
+
+    n_docs: int
+    n_terms: int
+    n_topics: int
+    n_shared: int
+    shared_frac: float
+    nnz_mean: float
+    nnz_sigma: float
+    nnz_min: int
+    nnz_max: int
+    zipf_s: float
+    seed: int
+    tf_p: float = 0.6
+
+
+def generate_topics(c: TopicCorpus, nthreads: int = 0):
+    lib = _load()
+    block = (c.n_terms - c.n_shared) // c.n_topics
+    indptr = np.empty(c.n_docs + 1, dtype=np.int64)
+    nmax = min(c.nnz_max, c.n_shared + block)
+    nnz = lib.synth_indptr(c.n_docs, c.n_terms, c.nnz_mean, c.nnz_sigma, c.nnz_min, nmax, c.seed,
+                           indptr.ctypes.data, nthreads)
+    if nnz < 0:
+        raise ValueError(f"invalid corpus parameters {c}")
+    indices = np.empty(nnz, dtype=np.int32)
+    values = np.empty(nnz, dtype=np.float32)
+    rc = lib.synth_topic_fill(c.n_docs, c.n_terms, c.n_topics, c.n_shared, c.shared_frac, c.zipf_s,
+                              c.tf_p, c.seed, indptr.ctypes.data, indices.ctypes.data,
+                              values.ctypes.data, nthreads)
+    if rc != 0:
+        raise RuntimeError(f"synth_topic_fill failed ({rc})")
     return indptr, indices, values
 
 

@@ -183,6 +183,101 @@ int synth_fill(int64_t n_docs, int32_t n_terms, double zipf_s, double tf_p, uint
   return 0;
 }
 
+/*
+ * Topic-structured variant (the paper's collections have topical structure that
+ * iid Zipf draws lack).  Terms [0, n_shared) are a shared vocabulary; the rest
+ * is split into n_topics equal blocks.  Row d picks a topic uniformly; each of
+ * its terms is drawn, with probability shared_frac, from Zipf(s) over the
+ * shared vocabulary, otherwise from Zipf(s) over its topic's block.  Weights,
+ * idf and normalisation as in synth_fill.
+ */
+int synth_topic_fill(int64_t n_docs, int32_t n_terms, int32_t n_topics, int32_t n_shared,
+                     double shared_frac, double zipf_s, double tf_p, uint64_t seed,
+                     const int64_t *indptr, int32_t *indices, float *values, int32_t nthreads) {
+  if (n_docs < 0 || n_topics < 1 || n_shared < 1 || n_shared >= n_terms) return -1;
+  const int32_t block = (n_terms - n_shared) / n_topics;
+  if (block < 1) return -1;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+  const int32_t nmax = n_shared > block ? n_shared : block;
+  double *cdf = (double *)malloc(sizeof(double) * (size_t)nmax);
+  if (!cdf) return -2;
+  double acc = 0.0;
+  for (int32_t r = 0; r < nmax; ++r) {
+    acc += pow((double)(r + 1), -zipf_s);
+    cdf[r] = acc;
+  }
+  const double log_q = log(1.0 - tf_p);
+  int err = 0;
+#pragma omp parallel
+  {
+    uint8_t *seen = (uint8_t *)calloc((size_t)n_terms, 1);
+    if (!seen) {
+#pragma omp atomic write
+      err = 1;
+    }
+#pragma omp for schedule(dynamic, 256)
+    for (int64_t d = 0; d < n_docs; ++d) {
+      if (!seen) continue;
+      int64_t b = indptr[d], n = indptr[d + 1] - b;
+      stream_t st = stream_for(seed, PURPOSE_TERMS, (uint64_t)d);
+      const int32_t topic = (int32_t)(next_u01(&st) * n_topics) % n_topics;
+      int64_t got = 0, tries = 0;
+      while (got < n) {
+        const double us = next_u01(&st);
+        /* after many rejections alternate between the two pools so both can fill */
+        const int shared = tries > 64 * n ? (int)(tries & 1) : us < shared_frac;
+        const int32_t size = shared ? n_shared : block;
+        const double u = next_u01(&st) * cdf[size - 1];
+        int32_t lo = 0, hi = size - 1;
+        while (lo < hi) {
+          int32_t mid = lo + (hi - lo) / 2;
+          if (cdf[mid] >= u) hi = mid; else lo = mid + 1;
+        }
+        const int32_t t = shared ? lo : n_shared + topic * block + lo;
+        ++tries;
+        if (seen[t]) continue;
+        seen[t] = 1;
+        indices[b + got] = t;
+        ++got;
+      }
+      qsort(indices + b, (size_t)n, sizeof(int32_t), cmp_i32);
+      stream_t tfs = stream_for(seed, PURPOSE_TF, (uint64_t)d);
+      for (int64_t q = 0; q < n; ++q) {
+        seen[indices[b + q]] = 0;
+        double u = next_u01(&tfs);
+        double tf = 1.0 + floor(log(u) / log_q);
+        values[b + q] = (float)log1p(tf);
+      }
+    }
+    free(seen);
+  }
+  free(cdf);
+  if (err) return -2;
+  int64_t nnz = indptr[n_docs];
+  int64_t *df = (int64_t *)calloc((size_t)n_terms, sizeof(int64_t));
+  double *idf = (double *)malloc(sizeof(double) * (size_t)n_terms);
+  if (!df || !idf) { free(df); free(idf); return -2; }
+  for (int64_t q = 0; q < nnz; ++q) df[indices[q]] += 1;
+  for (int32_t t = 0; t < n_terms; ++t)
+    idf[t] = log((1.0 + (double)n_docs) / (1.0 + (double)df[t])) + 1.0;
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t d = 0; d < n_docs; ++d) {
+    int64_t b = indptr[d], e = indptr[d + 1];
+    double ss = 0.0;
+    for (int64_t q = b; q < e; ++q) {
+      double v = (double)values[q] * idf[indices[q]];
+      ss += v * v;
+    }
+    double inv = 1.0 / sqrt(ss);
+    for (int64_t q = b; q < e; ++q) values[q] = (float)((double)values[q] * idf[indices[q]] * inv);
+  }
+  free(df);
+  free(idf);
+  return 0;
+}
+
 /* k distinct document ids, uniform, in draw order. */
 int synth_seed_rows(int64_t n_docs, int32_t k, uint64_t seed, int32_t *out) {
   if (k < 0 || (int64_t)k > n_docs) return -1;

@@ -173,10 +173,11 @@ def test_update_equals_oracle_update(mid):
     say("case: update")
     ctx = Context(csr, c.n_terms, len(rows), init_rows=rows, precision="bf16")
     ctx.assign()
-    a = ctx.assignments()
     C0 = oracle.seed(csr, c.n_terms, rows)
+    a_ref, s1, s2 = oracle.assign(csr, C0)
+    assert np.array_equal(ctx.assignments(), a_ref)   # no ties on this corpus
     st = ctx.update()
-    u = oracle.update(csr, a, C0)
+    u = oracle.update(csr, a_ref, C0)
     assert rel_centroid_err(ctx.centroids(), u.C) < 1e-12
     assert math.isclose(st["objective_update"], float(u.snorm.sum()), rel_tol=1e-12)
     assert math.isclose(st["objective_assign"], float(u.dot_old.sum()), rel_tol=1e-12)
@@ -293,3 +294,105 @@ def test_error_paths():
     with pytest.raises(SkmError) as e:
         Context((ip, ix, nonunit), c.n_terms, 3, init_rows=[0, 1, 2])
     assert e.value.status == skm.SKM_E_INVALID
+
+
+# ------------------------------------------------------------------ index (Sec. 3.2)
+
+def _sparse_rows(C):
+    return [(np.nonzero(r)[0], r[np.nonzero(r)[0]]) for r in C]
+
+
+def _topic(n=3000, seed=5):
+    tc = synth.TopicCorpus(n, 6000, 12, 400, 0.3, 40.0, 0.5, 5, 200, 1.1, seed=seed)
+    return synth.generate_topics(tc), tc
+
+
+@pytest.mark.parametrize("src", ["seeds", "centroids"])
+def test_index_build_equals_oracle(src):
+    """P_lambda per term ((centroid, minimum overlap count) lists) equals the
+    oracle's exact-arithmetic build of the same centroids, for all four levels."""
+    from oracle import index as oix
+
+    say("case: index build", src)
+    csr, tc = _topic(1500, seed=9)
+    rows = synth.seed_rows(tc.n_docs, 60, 3)
+    if src == "seeds":
+        C = oracle.seed(csr, tc.n_terms, rows)
+    else:
+        C = oracle.run(csr, tc.n_terms, 60, rows, max_iter=3, stop_rule="fixed").C
+    ctx = Context(csr, tc.n_terms, 60, init_centroids=C, index=True)
+    cents = _sparse_rows(C)
+    for level, lam in enumerate((0.1, 0.25, 0.4, 0.6)):
+        off, ent = ctx.index_level(level)
+        G, P = oix.build(cents, lam)
+        got = {}
+        for t in range(tc.n_terms):
+            e = ent[off[t]:off[t + 1]]
+            if len(e):
+                got[t] = [(int(x >> 16), int(x & 0xFFFF)) for x in e]
+        want = {t: sorted(v) for t, v in P.items()}
+        assert got == want, level
+    ctx.close()
+
+
+def test_index_query_equals_oracle():
+    from oracle import index as oix
+
+    say("case: index query")
+    csr, tc = _topic(1500, seed=11)
+    rows = synth.seed_rows(tc.n_docs, 50, 4)
+    C = oracle.run(csr, tc.n_terms, 50, rows, max_iter=3, stop_rule="fixed").C
+    ctx = Context(csr, tc.n_terms, 50, init_centroids=C, index=True)
+    cents = _sparse_rows(C)
+    q = synth.subset(*csr, np.arange(0, 1500, 7))
+    n_pruned = 0
+    for level, lam in enumerate((0.1, 0.25, 0.4, 0.6)):
+        got = ctx.index_query(q, level)
+        G, P = oix.build(cents, lam)
+        S = oracle.scores(q, C)
+        for i in range(len(got)):
+            terms = q[1][q[0][i]:q[0][i + 1]]
+            want = oix.query(G, P, terms)
+            assert got[i].tolist() == want, (level, i)
+            # every centroid reaching lam * ||x|| is a candidate (Lemma 3.1)
+            reach = np.nonzero(S[i] >= lam * 1.000001)[0]
+            assert set(reach.tolist()) <= set(want)
+            n_pruned += 50 - len(want)
+    assert n_pruned > 0
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_index_trajectory_equals_oracle(prec):
+    """NCC + INDEX on topic-structured rows: identical trajectory to the oracle,
+    and the index really decides rows in later iterations."""
+    say("case: index trajectory", prec)
+    csr, tc = _topic(4000, seed=13)
+    k = 48
+    rows = synth.seed_rows(tc.n_docs, k, 6)
+    ref = oracle.run(csr, tc.n_terms, k, rows, max_iter=20)
+    ctx = Context(to_device(csr), tc.n_terms, k, init_rows=rows, precision=prec, ncc=True,
+                  index=True, max_iter=20)
+    stats, conv = ctx.iterate()
+    assert conv == ref.converged and len(stats) == len(ref.records)
+    for st, rec in zip(stats, ref.records):
+        assert st["moved"] == rec.moved, (st["iter"], st["moved"], rec.moved)
+    assert np.array_equal(ctx.assignments(), ref.a)
+    assert rel_centroid_err(ctx.centroids(), ref.C) < 1e-9
+    assert sum(s["index_rows"] for s in stats) > 0
+    say("  index rows per iteration:", [s["index_rows"] for s in stats])
+    ctx.close()
+
+
+def test_index_only_without_ncc():
+    say("case: index without ncc")
+    csr, tc = _topic(2500, seed=17)
+    k = 30
+    rows = synth.seed_rows(tc.n_docs, k, 8)
+    ref = oracle.run(csr, tc.n_terms, k, rows, max_iter=8, stop_rule="fixed")
+    ctx = Context(csr, tc.n_terms, k, init_rows=rows, precision="fp8", index=True,
+                  stop_rule="fixed", max_iter=8)
+    stats, _ = ctx.iterate()
+    assert np.array_equal(ctx.assignments(), ref.a)
+    assert sum(s["index_rows"] for s in stats) > 0
+    ctx.close()
