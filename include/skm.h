@@ -51,7 +51,9 @@ typedef enum {
   SKM_E_NOMEM = 2,       /* the HBM budget or the device is out of memory */
   SKM_E_DEVICE = 3,      /* a HIP call failed; the context is poisoned */
   SKM_E_STATE = 4,       /* call made in the wrong order */
-  SKM_E_UNSUPPORTED = 5  /* valid but outside what this build supports */
+  SKM_E_UNSUPPORTED = 5, /* valid but outside what this build supports */
+  SKM_E_BUSY = 6,        /* a request server is attached to the context */
+  SKM_E_TIMEOUT = 7      /* skm_server_wait ran out of time (request still queued) */
 } skm_status;
 
 typedef enum {
@@ -228,6 +230,63 @@ skm_status skm_get_index(const skm_ctx *c, int32_t level, int64_t *offsets, uint
  * small (offsets[n_rows] then holds the size needed). */
 skm_status skm_index_query(skm_ctx *c, const skm_csr *docs, int32_t level, int64_t *offsets,
                            int32_t *cand, int64_t cap);
+
+/* ---------------------------------------------------------------- serving
+ * A request server keeps one context's centroids resident and answers
+ * assign-new-rows requests (the exact assignment of skm_assign_new) from many
+ * client threads.  A worker thread batches queued requests continuously: as
+ * soon as one of its n_slots batch slots (each with its own stream and
+ * preallocated device buffers) is free, it packs the requests at the head of
+ * the queue that fit the slot's row and non-zero capacity and launches them;
+ * requests that arrive while batches run join the next free slot, so
+ * transfers and kernels of different batches overlap.  Admission is by memory:
+ * the slots are sized up front and their total is held within
+ * hbm_budget_bytes.  While a server is attached, calls that change the
+ * context (assign, update, iterate, set_centroids) return SKM_E_BUSY. */
+typedef struct skm_server skm_server;
+
+typedef struct {
+  int32_t n_slots;          /* batches in flight, default 4 */
+  int32_t slot_rows;        /* rows per batch, default 16384 */
+  int64_t slot_nnz;         /* non-zeros per batch, default 4 Mi */
+  size_t hbm_budget_bytes;  /* device memory cap for the slots; n_slots shrinks to fit (0 = none) */
+  int32_t max_wait_us;      /* a partly filled batch waits at most this long for more rows
+                               when no batch is running, default 100 */
+} skm_server_config;
+
+typedef struct {
+  int64_t requests_done;
+  int64_t rows_done;
+  int64_t batches;
+  double p50_ms, p99_ms, mean_ms, max_ms;  /* latency, submit to outputs written */
+  double rows_per_s;        /* rows_done over first submit .. last completion */
+  int32_t slots;            /* slots actually allocated */
+  int32_t max_queue_depth;
+  size_t hbm_bytes;         /* device memory held by the server */
+} skm_server_stats;
+
+void skm_server_config_default(skm_server_config *cfg);
+
+/* Starts a server on context c (which must outlive it). */
+skm_status skm_server_start(skm_ctx *c, const skm_server_config *cfg, skm_server **out);
+
+/* Queues the rows of docs (host CSR, copied before return) for assignment;
+ * out_assign [n_rows] and out_score [n_rows] are host buffers the server fills
+ * before skm_server_wait(ticket) returns SKM_OK.  Thread-safe.  SKM_E_INVALID
+ * for a malformed CSR or one larger than a slot. */
+skm_status skm_server_submit(skm_server *s, const skm_csr *docs, int32_t *out_assign,
+                             double *out_score, int64_t *ticket);
+
+/* Blocks until the request is answered (SKM_OK, or the request's error), or
+ * timeout_s seconds pass (SKM_E_TIMEOUT; the request stays queued; timeout_s
+ * < 0 waits forever).  Each ticket is waited for at most once successfully. */
+skm_status skm_server_wait(skm_server *s, int64_t ticket, double timeout_s);
+
+/* Latency and throughput counters since start. */
+skm_status skm_server_get_stats(skm_server *s, skm_server_stats *out);
+
+/* Answers every queued request, stops the worker and frees the server. */
+skm_status skm_server_stop(skm_server *s);
 
 /* Device memory the context currently holds, in bytes. */
 size_t skm_hbm_bytes(const skm_ctx *c);

@@ -159,6 +159,13 @@ skm_status check_ctx(const skm_ctx *c) {
   return SKM_OK;
 }
 
+// Calls that change the clustering state are refused while a server reads it.
+skm_status check_ctx_writable(const skm_ctx *c) {
+  ST_TRY(check_ctx(c));
+  if (c->server_attached) return fail(SKM_E_BUSY, "a request server is attached to this context");
+  return SKM_OK;
+}
+
 float elapsed(hipEvent_t a, hipEvent_t b) {
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
@@ -286,6 +293,44 @@ IndexArgs index_args(skm_ctx *c) {
 }
 
 }  // namespace
+
+namespace skm {
+
+skm_status set_error(skm_status st, const std::string &msg) { return fail(st, msg); }
+
+// Exact assignment of rows that are not part of the clustering (no NCC, no
+// index): low-precision scoring with certification, the FP64 exact tier for
+// uncertain rows, and the FP64 score of the chosen centroid.  Enqueues only.
+hipError_t launch_new_rows(skm_ctx *c, const NewRows &b, int64_t n, hipStream_t s) {
+  ScoreArgs sa = base_args(c);
+  sa.indptr = b.indptr;
+  sa.indices = b.indices;
+  sa.values = b.values;
+  sa.xl1 = b.xl1;
+  sa.n_rows = n;
+  sa.a_out = b.a;
+  sa.lo_out = b.lo;
+  sa.hi_out = b.hi;
+  sa.flag_rows = b.flag_rows;
+  sa.flag_L = b.flag_L;
+  sa.flag_mode = b.flag_mode;
+  sa.counters = b.counters;
+  sa.stat = b.stat;
+  sa.no_exact = 0;
+  sa.mode = nullptr;
+  hipError_t e = launch_fill_i32(b.counters, 0, 8, s);
+  if (e == hipSuccess) e = launch_fill_i32(reinterpret_cast<int32_t *>(b.stat), 0, 16, s);
+  if (e == hipSuccess) e = launch_score(sa, b.part, c->score_blocks, c->prec, s);
+  if (e == hipSuccess) {
+    ExactArgs x{sa, b.part, c->master, c->D, exact_waves()};
+    e = launch_exact(x, c->prec, s);
+  }
+  if (e == hipSuccess)
+    e = launch_exact_scores(b.indptr, b.indices, b.values, n, b.a, c->master, c->D, b.score, s);
+  return e;
+}
+
+}  // namespace skm
 
 extern "C" {
 
@@ -499,7 +544,7 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
 }
 
 skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
-  ST_TRY(check_ctx(c));
+  ST_TRY(check_ctx_writable(c));
   hipStream_t s = c->stream;
   ScoreArgs a = base_args(c);
   const bool ncc = (c->cfg.flags & SKM_NCC) && c->have_prev;
@@ -535,6 +580,7 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
     HIP_TRY(c, index_score(x, n_rows_idx, c->a, c->lo, c->hi, s));
     HIP_TRY(c, hipEventRecord(c->ev[7], s));
     a.mode = c->mode;
+    c->idx_eligible = n_rows_idx;
   }
   HIP_TRY(c, hipEventRecord(c->ev[5], s));
   HIP_TRY(c, launch_score(a, c->part, c->score_blocks, c->prec, s));
@@ -552,6 +598,15 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
   HIP_TRY(c, hipStreamSynchronize(s));
   c->assigned = true;
   c->last_moved = c->have_prev ? (int64_t)stv[4] : c->N;
+  if (use_index) {
+    // Sec. 4.3: the index only pays when it decides rows; back off otherwise
+    if ((double)stv[2] < 0.05 * (double)std::max<int64_t>(c->idx_eligible, 1)) {
+      c->idx_skip = c->idx_backoff;
+      c->idx_backoff = std::min(2 * c->idx_backoff, 64);
+    } else {
+      c->idx_backoff = 8;
+    }
+  }
   if (st_out) {
     std::memset(st_out, 0, sizeof(*st_out));
     st_out->iter = c->iter;
@@ -576,7 +631,7 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
 }
 
 skm_status skm_update(skm_ctx *c, skm_iter_stats *st_out) {
-  ST_TRY(check_ctx(c));
+  ST_TRY(check_ctx_writable(c));
   if (!c->assigned) return fail(SKM_E_STATE, "skm_update needs a preceding skm_assign");
   hipStream_t s = c->stream;
   HIP_TRY(c, hipEventRecord(c->ev[3], s));
@@ -598,7 +653,15 @@ skm_status skm_update(skm_ctx *c, skm_iter_stats *st_out) {
   HIP_TRY(c, launch_reduce_stats(c->changed, c->snorm, c->shift, c->dot_old, c->k, c->red, s));
   ST_TRY(rebuild_tiles(c, c->changed));
   HIP_TRY(c, hipEventRecord(c->ev[4], s));
-  if (c->cfg.flags & SKM_INDEX) ST_TRY(build_index(c));
+  c->ms_index_build = 0.f;
+  c->index_ready = false;
+  if (c->cfg.flags & SKM_INDEX) {
+    if (c->idx_skip > 0) {
+      c->idx_skip -= 1;   // index off for this iteration: no rebuild
+    } else {
+      ST_TRY(build_index(c));
+    }
+  }
   double red[3];
   HIP_TRY(c, hipMemcpyAsync(red, c->red, sizeof(red), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
@@ -622,7 +685,7 @@ skm_status skm_update(skm_ctx *c, skm_iter_stats *st_out) {
 
 skm_status skm_iterate(skm_ctx *c, int32_t max_iter, skm_iter_stats *per_iter, int32_t *n_done,
                        int32_t *converged) {
-  ST_TRY(check_ctx(c));
+  ST_TRY(check_ctx_writable(c));
   if (max_iter <= 0) max_iter = c->cfg.max_iter;
   int32_t done = 0;
   int32_t conv = 0;
@@ -696,30 +759,9 @@ skm_status skm_assign_new(skm_ctx *c, const skm_csr *docs, int32_t *out_assign, 
     release();
     return st;
   }
-  ScoreArgs sa = base_args(c);
-  sa.indptr = r.indptr;
-  sa.indices = r.indices;
-  sa.values = r.values;
-  sa.xl1 = r.xl1;
-  sa.n_rows = n;
-  sa.a_out = a;
-  sa.lo_out = lo;
-  sa.hi_out = hi;
-  sa.flag_rows = flag_rows;
-  sa.flag_L = flag_L;
-  sa.flag_mode = flag_mode;
-  sa.counters = counters;
-  sa.stat = stat;
-  sa.no_exact = 0;
-  hipError_t e = launch_fill_i32(counters, 0, 8, s);
-  if (e == hipSuccess) e = launch_fill_i32(reinterpret_cast<int32_t *>(stat), 0, 16, s);
-  if (e == hipSuccess) e = launch_score(sa, part, c->score_blocks, c->prec, s);
-  if (e == hipSuccess) {
-    ExactArgs x{sa, part, c->master, c->D, exact_waves()};
-    e = launch_exact(x, c->prec, s);
-  }
-  if (e == hipSuccess)
-    e = launch_exact_scores(r.indptr, r.indices, r.values, n, a, c->master, c->D, score, s);
+  NewRows nr{r.indptr, r.indices, r.values, r.xl1, part, a, lo, hi, flag_rows, flag_L, flag_mode,
+             counters, stat, score};
+  hipError_t e = launch_new_rows(c, nr, n, s);
   const hipMemcpyKind kind = docs->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   if (e == hipSuccess) e = hipMemcpyAsync(out_assign, a, n * 4, kind, s);
   if (e == hipSuccess) e = hipMemcpyAsync(out_score, score, n * 8, kind, s);
@@ -754,7 +796,7 @@ skm_status skm_get_centroids(const skm_ctx *c, double *out, int32_t on_device) {
 }
 
 skm_status skm_set_centroids(skm_ctx *c, const double *centroids) {
-  ST_TRY(check_ctx(c));
+  ST_TRY(check_ctx_writable(c));
   if (!centroids) return fail(SKM_E_INVALID, "centroids is NULL");
   HIP_TRY(c, hipMemcpyAsync(c->master, centroids, sizeof(double) * c->k * c->D,
                             hipMemcpyHostToDevice, c->stream));

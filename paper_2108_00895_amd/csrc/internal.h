@@ -70,6 +70,23 @@ struct ExactArgs {
   int32_t max_waves;
 };
 
+// Device buffers of one batch of new rows (assignment without clustering).
+struct NewRows {
+  const int64_t *indptr;
+  const int32_t *indices;
+  const float *values;
+  const double *xl1;
+  Partial *part;
+  int32_t *a;
+  double *lo, *hi;
+  int32_t *flag_rows;
+  double *flag_L;
+  uint8_t *flag_mode;
+  int32_t *counters;
+  unsigned long long *stat;
+  double *score;
+};
+
 // Device pieces of the Sec. 3.2 index.
 struct IndexBuild {
   const double *master;
@@ -193,7 +210,13 @@ struct skm_ctx {
   int32_t *idx_rows = nullptr, *idx_cand = nullptr, *idx_ncand = nullptr, *idx_level = nullptr;
   int32_t idx_cap = 128;
   double idx_guard = 0.25;
+  // dynamic enabling: a probe that decides fewer than 5 % of the eligible rows
+  // turns the index off for idx_backoff iterations (doubling up to 64)
+  int32_t idx_skip = 0;
+  int32_t idx_backoff = 8;
   float ms_index_build = 0.f;
+  int64_t idx_eligible = 0;
+  int server_attached = 0;     // a request server reads this context
   int score_blocks = 2048;       // persistent scoring grid
   int64_t nblk = 0;
 
@@ -220,6 +243,10 @@ hipError_t launch_exact_scores(const int64_t *indptr, const int32_t *indices, co
                                int64_t n_rows, const int32_t *a, const double *master, int64_t D,
                                double *out, hipStream_t s);
 
+// api.hip
+hipError_t launch_new_rows(skm_ctx *c, const NewRows &b, int64_t n, hipStream_t s);
+skm_status set_error(skm_status st, const std::string &msg);  // thread-local last error
+
 // kernels_index.hip
 hipError_t index_build_counts(const double *master, int32_t k, int64_t D, int32_t *cnt,
                               int64_t *eoff, hipStream_t s);
@@ -231,6 +258,8 @@ hipError_t index_score(const IndexArgs &x, int64_t n_slots, int32_t *a_out, doub
                        double *hi_out, hipStream_t s);
 
 // kernels_update.hip
+hipError_t launch_row_stats_only(const int64_t *indptr, const int32_t *indices, const float *values,
+                                 int64_t n_rows, double *xl1, hipStream_t s);
 hipError_t launch_row_stats(const int64_t *indptr, const int32_t *indices, const float *values,
                             int64_t n_rows, int64_t D, double *xl1, double *xl2, int32_t *bad,
                             hipStream_t s);

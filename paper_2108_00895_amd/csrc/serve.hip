@@ -1,0 +1,419 @@
+// Request server of libskm: continuous batching of assign-new-rows requests
+// against one resident context (declared in include/skm.h).
+//
+// Client threads submit host CSR requests; a worker thread owns n_slots batch
+// slots, each a HIP stream with pinned staging buffers and device buffers
+// sized for slot_rows rows and slot_nnz non-zeros.  Whenever a slot is free
+// the worker packs the requests at the head of the queue into it (in arrival
+// order, as many as fit), copies them in on the slot's stream, runs the exact
+// new-row pipeline (low-precision scoring + certification + FP64 tier + FP64
+// scores) and copies the answers back; a completed slot's answers are
+// scattered to the requests' output buffers and their waiters are woken.
+// Different slots run on different streams, so batches overlap on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.h"
+
+using namespace skm;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+  int64_t id = 0;
+  int64_t n_rows = 0, nnz = 0;
+  std::vector<int64_t> indptr;
+  std::vector<int32_t> indices;
+  std::vector<float> values;
+  int32_t *out_a = nullptr;
+  double *out_s = nullptr;
+  Clock::time_point t_submit;
+  bool done = false;
+  skm_status status = SKM_OK;
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done_ev = nullptr;
+  int64_t *h_indptr = nullptr;
+  int32_t *h_indices = nullptr;
+  float *h_values = nullptr;
+  int32_t *h_a = nullptr;
+  double *h_s = nullptr;
+  NewRows d{};
+  int64_t *d_indptr = nullptr;
+  int32_t *d_indices = nullptr;
+  float *d_values = nullptr;
+  double *d_xl1 = nullptr;
+  std::vector<std::shared_ptr<Request>> reqs;
+  int64_t rows = 0;
+  bool busy = false;
+};
+
+size_t slot_device_bytes(const skm_ctx *c, int64_t rows, int64_t nnz) {
+  const int64_t nch = (c->k + kChunk - 1) / kChunk;
+  return (size_t)(rows + 1) * 8 + (size_t)nnz * 8 + (size_t)rows * 8 /*xl1*/ +
+         (size_t)nch * rows * sizeof(Partial) + (size_t)rows * (4 + 8 + 8 + 4 + 8 + 1 + 8) + 32 + 128;
+}
+
+}  // namespace
+
+struct skm_server {
+  skm_ctx *c = nullptr;
+  skm_server_config cfg{};
+  std::vector<Slot> slots;
+  std::vector<void *> dev_allocs, host_allocs;
+  size_t hbm = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::shared_ptr<Request>> queue;
+  std::unordered_map<int64_t, std::shared_ptr<Request>> live;
+  int64_t next_id = 1;
+  bool stopping = false;
+  std::thread worker;
+  // statistics
+  std::vector<double> lat_ms;
+  int64_t rows_done = 0, batches = 0;
+  int32_t max_depth = 0;
+  bool any_submit = false;
+  Clock::time_point t_first, t_last;
+  hipError_t dev_error = hipSuccess;
+};
+
+namespace {
+
+template <typename T>
+bool dev_alloc(skm_server *s, T **p, size_t count) {
+  void *q = nullptr;
+  const size_t bytes = std::max<size_t>(count * sizeof(T), 1);
+  if (hipMalloc(&q, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  s->dev_allocs.push_back(q);
+  s->hbm += bytes;
+  *p = static_cast<T *>(q);
+  return true;
+}
+
+template <typename T>
+bool host_alloc(skm_server *s, T **p, size_t count) {
+  void *q = nullptr;
+  if (hipHostMalloc(&q, std::max<size_t>(count * sizeof(T), 1), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  s->host_allocs.push_back(q);
+  *p = static_cast<T *>(q);
+  return true;
+}
+
+void release(skm_server *s) {
+  for (Slot &sl : s->slots) {
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    if (sl.done_ev) (void)hipEventDestroy(sl.done_ev);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+  }
+  for (void *p : s->dev_allocs) (void)hipFree(p);
+  for (void *p : s->host_allocs) (void)hipHostFree(p);
+  (void)hipGetLastError();
+}
+
+bool make_slot(skm_server *s, Slot &sl) {
+  const int64_t R = s->cfg.slot_rows, Z = s->cfg.slot_nnz;
+  const int64_t nch = (s->c->k + kChunk - 1) / kChunk;
+  if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess) return false;
+  if (hipEventCreateWithFlags(&sl.done_ev, hipEventDisableTiming) != hipSuccess) return false;
+  bool ok = host_alloc(s, &sl.h_indptr, R + 1) && host_alloc(s, &sl.h_indices, Z) &&
+            host_alloc(s, &sl.h_values, Z) && host_alloc(s, &sl.h_a, R) && host_alloc(s, &sl.h_s, R);
+  ok = ok && dev_alloc(s, &sl.d_indptr, R + 1) && dev_alloc(s, &sl.d_indices, Z) &&
+       dev_alloc(s, &sl.d_values, Z) && dev_alloc(s, &sl.d_xl1, R) &&
+       dev_alloc(s, &sl.d.part, (size_t)(nch * R)) && dev_alloc(s, &sl.d.a, R) &&
+       dev_alloc(s, &sl.d.lo, R) && dev_alloc(s, &sl.d.hi, R) && dev_alloc(s, &sl.d.flag_rows, R) &&
+       dev_alloc(s, &sl.d.flag_L, R) && dev_alloc(s, &sl.d.flag_mode, R) &&
+       dev_alloc(s, &sl.d.counters, 8) && dev_alloc(s, &sl.d.stat, 16) &&
+       dev_alloc(s, &sl.d.score, R);
+  sl.d.indptr = sl.d_indptr;
+  sl.d.indices = sl.d_indices;
+  sl.d.values = sl.d_values;
+  sl.d.xl1 = sl.d_xl1;
+  return ok;
+}
+
+// Packs the requests at the head of the queue into a free slot and launches
+// it.  Called with the lock held; the host copies are made under the lock
+// (they are memcpys of already-validated host arrays).
+void launch_slot(skm_server *s, Slot &sl) {
+  int64_t rows = 0, nnz = 0;
+  sl.reqs.clear();
+  sl.h_indptr[0] = 0;
+  while (!s->queue.empty()) {
+    const auto &r = s->queue.front();
+    if (rows + r->n_rows > s->cfg.slot_rows || nnz + r->nnz > s->cfg.slot_nnz) break;
+    std::memcpy(sl.h_indices + nnz, r->indices.data(), sizeof(int32_t) * r->nnz);
+    std::memcpy(sl.h_values + nnz, r->values.data(), sizeof(float) * r->nnz);
+    for (int64_t i = 0; i < r->n_rows; ++i) sl.h_indptr[rows + i + 1] = nnz + r->indptr[i + 1];
+    rows += r->n_rows;
+    nnz += r->nnz;
+    sl.reqs.push_back(r);
+    s->queue.pop_front();
+  }
+  sl.rows = rows;
+  hipStream_t st = sl.stream;
+  hipError_t e = hipMemcpyAsync(sl.d_indptr, sl.h_indptr, 8 * (rows + 1), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && nnz > 0)
+    e = hipMemcpyAsync(sl.d_indices, sl.h_indices, 4 * nnz, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && nnz > 0)
+    e = hipMemcpyAsync(sl.d_values, sl.h_values, 4 * nnz, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_row_stats_only(sl.d_indptr, sl.d_indices, sl.d_values, rows, sl.d_xl1, st);
+  if (e == hipSuccess) e = launch_new_rows(s->c, sl.d, rows, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(sl.h_a, sl.d.a, 4 * rows, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(sl.h_s, sl.d.score, 8 * rows, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipEventRecord(sl.done_ev, st);
+  if (e != hipSuccess) s->dev_error = e;
+  sl.busy = true;
+  s->batches += 1;
+}
+
+// Scatters a finished slot's answers to its requests (lock held).
+void finish_slot(skm_server *s, Slot &sl, hipError_t e) {
+  int64_t row = 0;
+  const auto now = Clock::now();
+  for (auto &r : sl.reqs) {
+    if (e == hipSuccess) {
+      std::memcpy(r->out_a, sl.h_a + row, sizeof(int32_t) * r->n_rows);
+      std::memcpy(r->out_s, sl.h_s + row, sizeof(double) * r->n_rows);
+      r->status = SKM_OK;
+    } else {
+      r->status = SKM_E_DEVICE;
+    }
+    row += r->n_rows;
+    r->done = true;
+    s->lat_ms.push_back(std::chrono::duration<double, std::milli>(now - r->t_submit).count());
+    s->rows_done += r->n_rows;
+  }
+  s->t_last = now;
+  sl.reqs.clear();
+  sl.busy = false;
+}
+
+void worker_loop(skm_server *s) {
+  (void)hipSetDevice(s->c->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  Clock::time_point partial_since{};
+  bool partial_waiting = false;
+  for (;;) {
+    bool progressed = false;
+    // completions
+    for (Slot &sl : s->slots) {
+      if (!sl.busy) continue;
+      const hipError_t q = hipEventQuery(sl.done_ev);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) s->dev_error = q;
+      finish_slot(s, sl, s->dev_error);
+      progressed = true;
+    }
+    if (progressed) s->cv_done.notify_all();
+    // launches: fill free slots from the queue head
+    int busy = 0;
+    for (Slot &sl : s->slots) busy += sl.busy;
+    for (Slot &sl : s->slots) {
+      if (sl.busy || s->queue.empty()) continue;
+      // a partly filled batch waits a little for more rows, but only while
+      // nothing is running (otherwise running batches already hide the wait)
+      int64_t queued_rows = 0;
+      for (auto &r : s->queue) queued_rows += r->n_rows;
+      const bool full = queued_rows >= s->cfg.slot_rows;
+      if (!full && busy == 0 && !s->stopping && s->cfg.max_wait_us > 0) {
+        if (!partial_waiting) {
+          partial_waiting = true;
+          partial_since = Clock::now();
+        }
+        if (Clock::now() - partial_since < std::chrono::microseconds(s->cfg.max_wait_us)) break;
+      }
+      partial_waiting = false;
+      launch_slot(s, sl);
+      busy += 1;
+      progressed = true;
+    }
+    if (s->stopping && s->queue.empty() && busy == 0) break;
+    if (!progressed) {
+      // nothing finished and nothing launched: sleep briefly (new requests or
+      // a shorter deadline wake us), then poll the running slots again
+      s->cv_work.wait_for(lk, std::chrono::microseconds(busy ? 20 : 200));
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void skm_server_config_default(skm_server_config *cfg) {
+  if (!cfg) return;
+  cfg->n_slots = 4;
+  cfg->slot_rows = 16384;
+  cfg->slot_nnz = 4 * 1024 * 1024;
+  cfg->hbm_budget_bytes = 0;
+  cfg->max_wait_us = 100;
+}
+
+skm_status skm_server_start(skm_ctx *c, const skm_server_config *cfg, skm_server **out) {
+  if (!c || !out) return set_error(SKM_E_INVALID, "context or out is NULL");
+  *out = nullptr;
+  if (c->poisoned) return set_error(SKM_E_DEVICE, "context is poisoned");
+  if (c->server_attached) return set_error(SKM_E_BUSY, "a server is already attached");
+  skm_server_config cf;
+  skm_server_config_default(&cf);
+  if (cfg) cf = *cfg;
+  if (cf.n_slots < 1 || cf.slot_rows < 1 || cf.slot_nnz < 1 || cf.max_wait_us < 0)
+    return set_error(SKM_E_INVALID, "bad server config");
+  const size_t per = slot_device_bytes(c, cf.slot_rows, cf.slot_nnz);
+  if (cf.hbm_budget_bytes) {
+    const int64_t fit = (int64_t)(cf.hbm_budget_bytes / per);
+    if (fit < 1) return set_error(SKM_E_NOMEM, "HBM budget below one batch slot");
+    cf.n_slots = (int32_t)std::min<int64_t>(cf.n_slots, fit);
+  }
+  auto *s = new (std::nothrow) skm_server();
+  if (!s) return set_error(SKM_E_NOMEM, "host allocation failed");
+  s->c = c;
+  s->cfg = cf;
+  s->slots.resize(cf.n_slots);
+  for (Slot &sl : s->slots) {
+    if (!make_slot(s, sl)) {
+      release(s);
+      delete s;
+      return set_error(SKM_E_NOMEM, "allocating a batch slot failed");
+    }
+  }
+  c->server_attached = 1;
+  s->worker = std::thread(worker_loop, s);
+  *out = s;
+  return SKM_OK;
+}
+
+skm_status skm_server_submit(skm_server *s, const skm_csr *docs, int32_t *out_assign,
+                             double *out_score, int64_t *ticket) {
+  if (!s || !docs || !ticket) return set_error(SKM_E_INVALID, "NULL argument");
+  if (docs->on_device) return set_error(SKM_E_INVALID, "server requests are host CSR");
+  const int64_t n = docs->n_rows, z = docs->nnz;
+  if (n < 0 || z < 0 || docs->n_cols > s->c->D || docs->n_cols < 1)
+    return set_error(SKM_E_INVALID, "bad CSR sizes");
+  if (n > 0 && (!out_assign || !out_score || !docs->indptr || (z > 0 && (!docs->indices || !docs->values))))
+    return set_error(SKM_E_INVALID, "NULL array");
+  if (n > s->cfg.slot_rows || z > s->cfg.slot_nnz)
+    return set_error(SKM_E_INVALID, "request larger than a batch slot");
+  auto r = std::make_shared<Request>();
+  r->n_rows = n;
+  r->nnz = z;
+  if (n > 0) {
+    r->indptr.assign(docs->indptr, docs->indptr + n + 1);
+    if (r->indptr[0] != 0 || r->indptr[n] != z) return set_error(SKM_E_INVALID, "bad indptr");
+    for (int64_t i = 0; i < n; ++i)
+      if (r->indptr[i + 1] < r->indptr[i]) return set_error(SKM_E_INVALID, "indptr decreases");
+    r->indices.assign(docs->indices, docs->indices + z);
+    r->values.assign(docs->values, docs->values + z);
+    for (int64_t q = 0; q < z; ++q)
+      if (r->indices[q] < 0 || r->indices[q] >= s->c->D)
+        return set_error(SKM_E_INVALID, "term index out of range");
+  }
+  r->out_a = out_assign;
+  r->out_s = out_score;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stopping) return set_error(SKM_E_STATE, "server is stopping");
+    r->id = s->next_id++;
+    r->t_submit = Clock::now();
+    if (!s->any_submit) {
+      s->any_submit = true;
+      s->t_first = r->t_submit;
+    }
+    if (n == 0) {
+      r->done = true;
+    } else {
+      s->queue.push_back(r);
+      s->max_depth = std::max<int32_t>(s->max_depth, (int32_t)s->queue.size());
+    }
+    s->live[r->id] = r;
+    *ticket = r->id;
+  }
+  s->cv_work.notify_one();
+  return SKM_OK;
+}
+
+skm_status skm_server_wait(skm_server *s, int64_t ticket, double timeout_s) {
+  if (!s) return set_error(SKM_E_INVALID, "server is NULL");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->live.find(ticket);
+  if (it == s->live.end()) return set_error(SKM_E_INVALID, "unknown ticket");
+  auto r = it->second;
+  auto ready = [&] { return r->done; };
+  if (timeout_s < 0) {
+    s->cv_done.wait(lk, ready);
+  } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready)) {
+    return set_error(SKM_E_TIMEOUT, "request not answered yet");
+  }
+  s->live.erase(ticket);
+  if (r->status != SKM_OK) return set_error(r->status, "device error while serving");
+  return SKM_OK;
+}
+
+skm_status skm_server_get_stats(skm_server *s, skm_server_stats *out) {
+  if (!s || !out) return set_error(SKM_E_INVALID, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  std::memset(out, 0, sizeof(*out));
+  out->requests_done = (int64_t)s->lat_ms.size();
+  out->rows_done = s->rows_done;
+  out->batches = s->batches;
+  out->slots = (int32_t)s->slots.size();
+  out->max_queue_depth = s->max_depth;
+  out->hbm_bytes = s->hbm;
+  if (!s->lat_ms.empty()) {
+    std::vector<double> v = s->lat_ms;
+    std::sort(v.begin(), v.end());
+    auto pct = [&](double p) {
+      const size_t i = (size_t)std::min<double>(v.size() - 1, std::floor(p * (double)(v.size() - 1) + 0.5));
+      return v[i];
+    };
+    out->p50_ms = pct(0.50);
+    out->p99_ms = pct(0.99);
+    out->max_ms = v.back();
+    double sum = 0;
+    for (double x : v) sum += x;
+    out->mean_ms = sum / (double)v.size();
+    const double span = std::chrono::duration<double>(s->t_last - s->t_first).count();
+    out->rows_per_s = span > 0 ? (double)s->rows_done / span : 0.0;
+  }
+  return SKM_OK;
+}
+
+skm_status skm_server_stop(skm_server *s) {
+  if (!s) return set_error(SKM_E_INVALID, "server is NULL");
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stopping = true;
+  }
+  s->cv_work.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  const bool dev_err = s->dev_error != hipSuccess;
+  s->c->server_attached = 0;
+  if (dev_err) s->c->poisoned = true;
+  release(s);
+  delete s;
+  return dev_err ? set_error(SKM_E_DEVICE, "device error while serving") : SKM_OK;
+}
+
+}  // extern "C"

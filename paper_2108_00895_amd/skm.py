@@ -16,7 +16,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libskm.so")
 
-SKM_OK, SKM_E_INVALID, SKM_E_NOMEM, SKM_E_DEVICE, SKM_E_STATE, SKM_E_UNSUPPORTED = range(6)
+(SKM_OK, SKM_E_INVALID, SKM_E_NOMEM, SKM_E_DEVICE, SKM_E_STATE, SKM_E_UNSUPPORTED, SKM_E_BUSY,
+ SKM_E_TIMEOUT) = range(8)
 FP32, BF16, FP8_E4M3 = 0, 1, 2
 NCC, INDEX, NO_EXACT = 1, 2, 4
 STOP_PAPER, STOP_FIXED = 0, 1
@@ -27,7 +28,8 @@ EXPORTED = [
     "skm_config_default", "skm_init", "skm_assign", "skm_update", "skm_iterate",
     "skm_assign_new", "skm_get_assignments", "skm_get_centroids", "skm_set_centroids",
     "skm_get_tile", "skm_get_changed", "skm_score_dense", "skm_error_bound", "skm_get_index",
-    "skm_index_query",
+    "skm_index_query", "skm_server_config_default", "skm_server_start", "skm_server_submit",
+    "skm_server_wait", "skm_server_get_stats", "skm_server_stop",
     "skm_hbm_bytes", "skm_last_error", "skm_destroy",
 ]
 
@@ -66,6 +68,24 @@ class IterStats(ctypes.Structure):
                 ("max_shift_sq", ctypes.c_double), ("ms_assign", ctypes.c_float),
                 ("ms_score", ctypes.c_float), ("ms_exact", ctypes.c_float), ("ms_update", ctypes.c_float),
                 ("ms_index", ctypes.c_float)]
+
+    def asdict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("n_slots", ctypes.c_int32), ("slot_rows", ctypes.c_int32),
+                ("slot_nnz", ctypes.c_int64), ("hbm_budget_bytes", ctypes.c_size_t),
+                ("max_wait_us", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("requests_done", ctypes.c_int64), ("rows_done", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("rows_per_s", ctypes.c_double),
+                ("slots", ctypes.c_int32), ("max_queue_depth", ctypes.c_int32),
+                ("hbm_bytes", ctypes.c_size_t)]
 
     def asdict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -120,6 +140,18 @@ def load():
     lib.skm_get_index.restype = st
     lib.skm_index_query.argtypes = [vp, P(Csr), i32, vp, vp, i64]
     lib.skm_index_query.restype = st
+    lib.skm_server_config_default.argtypes = [P(ServerConfig)]
+    lib.skm_server_config_default.restype = None
+    lib.skm_server_start.argtypes = [vp, P(ServerConfig), P(vp)]
+    lib.skm_server_start.restype = st
+    lib.skm_server_submit.argtypes = [vp, P(Csr), vp, vp, P(i64)]
+    lib.skm_server_submit.restype = st
+    lib.skm_server_wait.argtypes = [vp, i64, ctypes.c_double]
+    lib.skm_server_wait.restype = st
+    lib.skm_server_get_stats.argtypes = [vp, P(ServerStats)]
+    lib.skm_server_get_stats.restype = st
+    lib.skm_server_stop.argtypes = [vp]
+    lib.skm_server_stop.restype = st
     lib.skm_hbm_bytes.argtypes = [vp]
     lib.skm_hbm_bytes.restype = ctypes.c_size_t
     lib.skm_last_error.argtypes = []
@@ -332,3 +364,57 @@ class Context:
 
     def hbm_bytes(self):
         return load().skm_hbm_bytes(self._h)
+
+
+class Server:
+    """Request server on a context (wraps skm_server): continuous batching of
+    assign-new-rows requests.  submit() is thread-safe and returns a ticket;
+    wait(ticket) returns (assignments, scores)."""
+
+    def __init__(self, ctx: Context, n_slots=4, slot_rows=16384, slot_nnz=4 * 1024 * 1024,
+                 hbm_budget_bytes=0, max_wait_us=100):
+        lib = load()
+        cfg = ServerConfig()
+        lib.skm_server_config_default(ctypes.byref(cfg))
+        cfg.n_slots, cfg.slot_rows, cfg.slot_nnz = n_slots, slot_rows, slot_nnz
+        cfg.hbm_budget_bytes, cfg.max_wait_us = hbm_budget_bytes, max_wait_us
+        h = ctypes.c_void_p()
+        _check(lib.skm_server_start(ctx._h, ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._ctx = ctx
+        self._out = {}
+        import threading
+
+        self._lock = threading.Lock()
+
+    def submit(self, csr):
+        c, hold = make_csr(*csr, self._ctx.n_cols)
+        a = np.empty(c.n_rows, dtype=np.int32)
+        s = np.empty(c.n_rows, dtype=np.float64)
+        t = ctypes.c_int64()
+        _check(load().skm_server_submit(self._h, ctypes.byref(c), a.ctypes.data, s.ctypes.data,
+                                        ctypes.byref(t)))
+        with self._lock:
+            self._out[t.value] = (a, s)
+        return t.value
+
+    def wait(self, ticket, timeout_s=-1.0):
+        _check(load().skm_server_wait(self._h, ticket, float(timeout_s)))
+        with self._lock:
+            return self._out.pop(ticket)
+
+    def stats(self):
+        st = ServerStats()
+        _check(load().skm_server_get_stats(self._h, ctypes.byref(st)))
+        return st.asdict()
+
+    def stop(self):
+        if getattr(self, "_h", None):
+            h, self._h = self._h, None
+            _check(load().skm_server_stop(h))
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.stop()

@@ -1,0 +1,99 @@
+"""Serving: continuous batching of assign-new-rows requests (needs an MI355X).
+
+Every request's answer must be the same alone (skm_assign_new) and in the mix
+(batched with other requests by the server), and equal to the FP64 oracle.
+"""
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2108_00895_amd import Context, SkmError, skm
+from paper_2108_00895_amd.skm import Server
+
+from gpu_common import assert_assign_equal, corpus, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def resident():
+    csr, c = corpus(3000, 9000, nnz_mean=60.0, nnz_max=400, seed=41)
+    rows = synth.seed_rows(c.n_docs, 600, 2)
+    ref = oracle.run(csr, c.n_terms, 600, rows, max_iter=2, stop_rule="fixed")
+    return csr, c, ref.C
+
+
+def _requests(D, n_req, seed):
+    new, _ = corpus(5000, D, nnz_mean=60.0, nnz_max=400, seed=seed)
+    rng = np.random.default_rng(seed)
+    sizes = np.clip(np.round(rng.lognormal(np.log(16), 1.2, n_req)), 1, 300).astype(int)
+    out, start = [], 0
+    for sz in sizes:
+        if start + sz > 5000:
+            start = 0
+        out.append(synth.subset(*new, np.arange(start, start + sz)))
+        start += sz
+    return out
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_mix_equals_alone_and_oracle(prec, resident):
+    csr, c, C = resident
+    say("case: serving mix", prec)
+    ctx = Context(csr, c.n_terms, 600, init_centroids=C, precision=prec)
+    reqs = _requests(c.n_terms, 150, seed=7)
+    alone = [ctx.assign_new(r) for r in reqs]
+    got = [None] * len(reqs)
+    with Server(ctx, n_slots=3, slot_rows=512, slot_nnz=512 * 400, max_wait_us=200) as srv:
+        def client(ids):
+            tickets = [(i, srv.submit(reqs[i])) for i in ids]
+            for i, t in tickets:
+                got[i] = srv.wait(t, 60.0)
+
+        threads = [threading.Thread(target=client, args=(list(range(w, len(reqs), 4)),))
+                   for w in range(4)]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join()
+        st = srv.stats()
+        # the context is read-only while served
+        with pytest.raises(SkmError) as e:
+            ctx.assign()
+        assert e.value.status == skm.SKM_E_BUSY
+    say("  stats", {k: round(v, 3) if isinstance(v, float) else v for k, v in st.items()})
+    assert st["requests_done"] == len(reqs) and st["batches"] < len(reqs)
+    for r, (a1, s1), (a2, s2) in zip(reqs, alone, got):
+        assert np.array_equal(a1, a2)
+        assert np.array_equal(s1, s2)
+        ar, r1, r2 = oracle.assign(r, C)
+        assert_assign_equal(a2, ar, r1, r2, "served")
+        np.testing.assert_allclose(s2, r1, rtol=1e-12)
+    ctx.assign()   # writable again after stop
+    ctx.close()
+
+
+def test_server_admission_and_errors(resident):
+    csr, c, C = resident
+    say("case: serving errors")
+    ctx = Context(csr, c.n_terms, 600, init_centroids=C, precision="bf16")
+    with pytest.raises(SkmError) as e:
+        Server(ctx, slot_rows=1024, slot_nnz=1 << 20, hbm_budget_bytes=1000)
+    assert e.value.status == skm.SKM_E_NOMEM
+    srv = Server(ctx, n_slots=8, slot_rows=64, slot_nnz=64 * 400, hbm_budget_bytes=700_000)
+    assert 1 <= srv.stats()["slots"] < 8          # the budget limits the slots
+    big = synth.subset(*csr, np.arange(100))
+    with pytest.raises(SkmError) as e:
+        srv.submit(big)                            # larger than a slot
+    assert e.value.status == skm.SKM_E_INVALID
+    t = srv.submit(synth.subset(*csr, np.arange(10)))
+    a, s = srv.wait(t, 30.0)
+    assert len(a) == 10
+    empty = (np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    a0, _ = srv.wait(srv.submit(empty), 5.0)
+    assert len(a0) == 0
+    srv.stop()
+    ctx.close()

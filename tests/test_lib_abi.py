@@ -35,6 +35,14 @@ def test_struct_layouts_match_header():
     assert cfg.max_shift_sq == 1e-4 and cfg.validate == 1
 
 
+def test_server_structs():
+    assert ctypes.sizeof(skm.ServerConfig) == 4 + 4 + 8 + 8 + 8
+    cfg = skm.ServerConfig()
+    skm.load().skm_server_config_default(ctypes.byref(cfg))
+    assert cfg.n_slots == 4 and cfg.slot_rows == 16384 and cfg.max_wait_us == 100
+    assert skm.load().skm_server_start(None, None, ctypes.byref(ctypes.c_void_p())) == skm.SKM_E_INVALID
+
+
 def test_null_arguments_rejected_without_device():
     lib = skm.load()
     h = ctypes.c_void_p()
