@@ -66,9 +66,11 @@ enum {
   SKM_NCC = 1u << 0,       /* Sec. 3.1: skip centroids that did not change */
   SKM_INDEX = 1u << 1,     /* Sec. 3.2: dot-product index on rows whose previous
                               centroid changed */
-  SKM_NO_EXACT = 1u << 2   /* skip the exact tier: the argmax is taken on the
+  SKM_NO_EXACT = 1u << 2,  /* skip the exact tier: the argmax is taken on the
                               low-precision scores alone (timing comparator only;
                               results are then NOT those of an FP64 run) */
+  SKM_DENSE_ONLY = 1u << 3 /* score every term from the dense code slabs (no
+                              per-term lists of non-zero codes) */
 };
 
 typedef enum {

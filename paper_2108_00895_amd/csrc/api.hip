@@ -59,6 +59,15 @@ skm_status dalloc(skm_ctx *c, T **p, size_t count) {
   return SKM_OK;
 }
 
+// Frees one allocation made by dalloc.
+void dfree(skm_ctx *c, void *p, size_t count_bytes) {
+  if (!p) return;
+  auto it = std::find(c->allocations.begin(), c->allocations.end(), p);
+  if (it != c->allocations.end()) c->allocations.erase(it);
+  (void)hipFree(p);
+  c->hbm_bytes -= round_up((int64_t)std::max<size_t>(count_bytes, 1), 256);
+}
+
 double unit_roundoff(int prec) {
   switch (prec) {
     case SKM_FP32: return 0x1p-24;
@@ -175,12 +184,56 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
   return ms;
 }
 
-// Scoring copies of the centroids flagged in `changed` (all when nullptr).
+int ent_words(int prec) { return prec == SKM_FP32 ? 2 : 1; }
+
+// Tail lists (kernels_tail.hip) of copy `which` (0 full, 1 compacted) with
+// ncols columns; the entry buffer grows on demand.
+skm_status build_tail(skm_ctx *c, int which, const uint8_t *tile, int32_t ncols) {
+  skm_ctx::Tail &T = c->tails[which];
+  T.ready = false;
+  if (!c->use_tail || ncols <= 0) return SKM_OK;
+  hipStream_t s = c->stream;
+  const int nch = (ncols + kChunk - 1) / kChunk;
+  const int64_t dense_max = c->D;   // no cap on the dense set
+  HIP_TRY(c, tail_count(tile, c->D, ncols, c->prec, dense_max, T.cnt, T.cf, T.hist, T.tail, T.off,
+                        T.base, s));
+  uint64_t total = 0;
+  HIP_TRY(c, hipMemcpyAsync(&total, T.base + nch, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  const int64_t words = (int64_t)total * ent_words(c->prec);
+  if (words > T.cap_entries) {
+    // free the old list and allocate 25 % headroom
+    if (T.ent) {
+      auto it = std::find(c->allocations.begin(), c->allocations.end(), (void *)T.ent);
+      if (it != c->allocations.end()) c->allocations.erase(it);
+      (void)hipFree(T.ent);
+      c->hbm_bytes -= round_up(std::max<int64_t>(T.cap_entries * 4, 1), 256);
+      T.ent = nullptr;
+      T.cap_entries = 0;
+    }
+    const int64_t cap = std::max<int64_t>(words + words / 4, 1024);
+    ST_TRY(dalloc(c, &T.ent, (size_t)cap));
+    T.cap_entries = cap;
+  }
+  HIP_TRY(c, tail_fill(tile, c->D, ncols, c->prec, T.tail, T.off, T.base, T.ent, s));
+  T.ready = true;
+  return SKM_OK;
+}
+
+TailView tail_view(const skm_ctx *c, int which) {
+  const skm_ctx::Tail &T = c->tails[which];
+  if (!T.ready) return TailView{nullptr, nullptr, nullptr, nullptr};
+  return TailView{T.tail, T.off, T.base, T.ent};
+}
+
+// Scoring copies of the centroids flagged in `changed` (all when nullptr),
+// and the full copy's tail lists.
 skm_status rebuild_tiles(skm_ctx *c, const uint8_t *changed) {
   if (c->prec == SKM_FP8_E4M3)
     HIP_TRY(c, launch_fp8_scales(c->master, c->k, c->D, changed, c->scale, c->stream));
   HIP_TRY(c, launch_quantize(c->master, c->k, c->D, changed, c->scale, c->prec, c->tile,
                              c->stream));
+  ST_TRY(build_tail(c, 0, c->tile, c->k));
   return SKM_OK;
 }
 
@@ -198,6 +251,8 @@ ScoreArgs base_args(skm_ctx *c) {
   a.uq = c->uq;
   a.abs_coef = c->abs_coef;
   a.no_exact = (c->cfg.flags & SKM_NO_EXACT) ? 1 : 0;
+  a.tv = tail_view(c, 0);
+  a.tv_ch = TailView{nullptr, nullptr, nullptr, nullptr};
   a.a_out = c->a;
   a.lo_out = c->lo;
   a.hi_out = c->hi;
@@ -211,13 +266,84 @@ ScoreArgs base_args(skm_ctx *c) {
 
 int exact_waves() { return 4096; }
 
-// Frees one allocation made by dalloc.
-void dfree(skm_ctx *c, void *p, size_t count_bytes) {
-  if (!p) return;
-  auto it = std::find(c->allocations.begin(), c->allocations.end(), p);
-  if (it != c->allocations.end()) c->allocations.erase(it);
-  (void)hipFree(p);
-  c->hbm_bytes -= round_up((int64_t)std::max<size_t>(count_bytes, 1), 256);
+constexpr int64_t kSegRows = 256;       // members per summation segment
+constexpr int64_t kWorkBytes = 2ll << 30;  // partial-row workspace cap
+
+// FP64 member sums of the n_ids changed clusters (ids in c->ch_ids): clusters
+// with at most kSegRows members are summed by one workgroup each; larger ones
+// are split into segments summed in parallel into workspace rows and combined
+// in segment order.  Rounds keep the workspace within kWorkBytes.
+skm_status sum_changed(skm_ctx *c, int32_t n_ids) {
+  if (n_ids <= 0) return SKM_OK;
+  hipStream_t s = c->stream;
+  std::vector<int32_t> ids(n_ids), counts(c->k);
+  std::vector<int64_t> offs(c->k + 1);
+  HIP_TRY(c, hipMemcpyAsync(ids.data(), c->ch_ids, 4 * n_ids, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipMemcpyAsync(counts.data(), c->counts, 4 * c->k, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipMemcpyAsync(offs.data(), c->offsets, 8 * (c->k + 1), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  const int64_t max_slots = std::max<int64_t>(1, kWorkBytes / (8 * c->D));
+  size_t pos = 0;
+  std::vector<int4> tasks, groups;
+  std::vector<int64_t> r0s;
+  while (pos < ids.size()) {
+    tasks.clear();
+    groups.clear();
+    r0s.clear();
+    int64_t slots = 0;
+    for (; pos < ids.size(); ++pos) {
+      const int32_t j = ids[pos];
+      const int64_t cnt = counts[j];
+      const int64_t nseg =
+          std::min<int64_t>(max_slots, std::max<int64_t>(1, (cnt + kSegRows - 1) / kSegRows));
+      const int64_t seg = nseg > 0 ? (cnt + nseg - 1) / nseg : cnt;
+      if (nseg == 1) {
+        tasks.push_back(make_int4(j, (int)cnt, -1, 0));
+        r0s.push_back(offs[j]);
+        continue;
+      }
+      if (slots + nseg > max_slots && slots > 0) break;   // next round
+      groups.push_back(make_int4(j, (int)slots, (int)nseg, 0));
+      for (int64_t g = 0; g < nseg; ++g) {
+        const int64_t r0 = offs[j] + g * seg;
+        const int64_t len = std::max<int64_t>(0, std::min<int64_t>(seg, offs[j] + cnt - r0));
+        tasks.push_back(make_int4(j, (int)len, (int)(slots + g), 0));
+        r0s.push_back(r0);
+      }
+      slots += nseg;
+    }
+    if ((int64_t)tasks.size() > c->task_cap) {
+      const int64_t cap = std::max<int64_t>((int64_t)tasks.size() * 2, 1024);
+      if (c->tasks) dfree(c, c->tasks, c->task_cap * sizeof(int4));
+      if (c->task_r0) dfree(c, c->task_r0, c->task_cap * sizeof(int64_t));
+      c->tasks = nullptr;
+      c->task_r0 = nullptr;
+      c->task_cap = 0;
+      ST_TRY(dalloc(c, &c->tasks, (size_t)cap));
+      ST_TRY(dalloc(c, &c->task_r0, (size_t)cap));
+      c->task_cap = cap;
+    }
+    if (slots > c->work_slots) {
+      if (c->work) dfree(c, c->work, c->work_slots * 8 * c->D);
+      c->work = nullptr;
+      c->work_slots = 0;
+      ST_TRY(dalloc(c, &c->work, (size_t)(slots * c->D)));
+      c->work_slots = slots;
+    }
+    if (!c->groups) ST_TRY(dalloc(c, &c->groups, (size_t)c->k));
+    HIP_TRY(c, hipMemcpyAsync(c->tasks, tasks.data(), sizeof(int4) * tasks.size(),
+                              hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipMemcpyAsync(c->task_r0, r0s.data(), 8 * r0s.size(), hipMemcpyHostToDevice, s));
+    if (!groups.empty())
+      HIP_TRY(c, hipMemcpyAsync(c->groups, groups.data(), sizeof(int4) * groups.size(),
+                                hipMemcpyHostToDevice, s));
+    HIP_TRY(c, launch_sum_tasks(c->indptr, c->indices, c->values, c->members, c->tasks, c->task_r0,
+                                (int32_t)tasks.size(), c->D, c->S, c->work, s));
+    HIP_TRY(c, launch_combine(c->groups, (int32_t)groups.size(), c->D, c->work, c->S, s));
+    // the host vectors are reused next round: wait for the copies to finish
+    HIP_TRY(c, hipStreamSynchronize(s));
+  }
+  return SKM_OK;
 }
 
 // Sec. 3.2 index from the current master: entries per centroid, sorted, prefix
@@ -483,6 +609,16 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
   A_(c->red, 8);
   A_(c->ids_count, 1);
   A_(c->part, ((int64_t)c->k + kChunk - 1) / kChunk * N);
+  c->use_tail = !(c->cfg.flags & SKM_DENSE_ONLY);
+  for (int w = 0; w < ((c->cfg.flags & SKM_NCC) ? 2 : 1) && c->use_tail; ++w) {
+    const int64_t nch = ((int64_t)c->k + kChunk - 1) / kChunk;
+    A_(c->tails[w].tail, c->D);
+    A_(c->tails[w].cnt, nch * c->D);
+    A_(c->tails[w].off, nch * (c->D + 1));
+    A_(c->tails[w].base, nch + 1);
+    A_(c->tails[w].cf, c->D);
+    A_(c->tails[w].hist, (int64_t)c->k + 2);
+  }
   if (c->cfg.flags & SKM_NCC) A_(c->tile_ch, c->D * c->ld * c->esize);
   if (c->cfg.flags & SKM_INDEX) {
     int max_lds = 0;
@@ -555,11 +691,13 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
     HIP_TRY(c, hipMemcpyAsync(&n_ch, c->ids_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
     HIP_TRY(c, launch_gather_tile(c->tile, c->D, c->esize, c->ch_ids, n_ch, c->tile_ch, s));
+    ST_TRY(build_tail(c, 1, c->tile_ch, n_ch));
     a.a_prev = c->a_prev;
     a.changed = c->changed;
     a.tile_ch = c->tile_ch;
     a.n_ch = n_ch;
     a.ch_ids = c->ch_ids;
+    a.tv_ch = tail_view(c, 1);
     a.prev_lo = c->lo_prev;
     a.prev_hi = c->hi_prev;
   }
@@ -646,8 +784,7 @@ skm_status skm_update(skm_ctx *c, skm_iter_stats *st_out) {
   HIP_TRY(c, hipMemcpyAsync(&n_ids, c->ids_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, launch_bucket(c->a, c->N, c->k, c->nblk, c->hist, c->counts, c->offsets, c->members, s));
   HIP_TRY(c, hipStreamSynchronize(s));
-  HIP_TRY(c, launch_sum_members(c->indptr, c->indices, c->values, c->offsets, c->members, c->ch_ids,
-                                n_ids, c->D, c->S, s));
+  ST_TRY(sum_changed(c, n_ids));
   HIP_TRY(c, launch_renorm(c->S, c->counts, c->ch_ids, n_ids, c->D, c->master, c->snorm, c->shift,
                            c->dot_old, s));
   HIP_TRY(c, launch_reduce_stats(c->changed, c->snorm, c->shift, c->dot_old, c->k, c->red, s));
@@ -872,7 +1009,7 @@ skm_status skm_score_dense(skm_ctx *c, const skm_csr *docs, float *out) {
     return st;
   }
   hipError_t e = launch_score_dense(r.indptr, r.indices, r.values, n, c->tile, c->D, c->k, c->scale,
-                                    c->prec, d_out, c->stream);
+                                    tail_view(c, 0), c->prec, d_out, c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(out, d_out, sizeof(float) * n * c->k, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

@@ -150,15 +150,18 @@ __host__ __device__ inline int e4m3_scale_exp(double cmax) {
 // ------------------------------------------------------------- error bound
 // A low-precision score s^ = fl32(sum_t x_t * c^_t) of a row with n terms,
 // where |c^_t - c_t| <= u_q * c_t + a (a: absolute term of the encoding, scaled),
-// and the FP32 sum runs as n fused multiply-adds (one rounding each):
-//   |s^ - S^| <= g_n * S^,   g_n = n u / (1 - n u), u = 2^-24   (recursive sum)
+// and the FP32 sum runs in at most 2n + 2 roundings (fused multiply-adds on the
+// dense path, a rounded product plus an add on the list path, one final merge):
+//   |s^ - S^| <= g_m * S^,   g_m = m u / (1 - m u), m = 2n + 2, u = 2^-24
 //   |S^ - s|  <= u_q * s + a * ||x||_1
 // which gives |s^ - s| <= kappa * s^ + A with
-//   kappa = (g_n + u_q / (1 - u_q)) / (1 - g_n),  A = a ||x||_1 / (1 - u_q).
+//   kappa = (g_m + u_q / (1 - u_q)) / (1 - g_m),  A = a ||x||_1 / (1 - u_q).
 // Both are inflated slightly so the FP64 evaluation of the test stays safe.
 __host__ __device__ inline double bound_kappa(int64_t n, double uq) {
   const double u = 0x1p-24;
-  double nn = (double)(n > 0 ? n : 1);
+  // each term costs at most two roundings (a product rounded before an LDS
+  // add on the list path), plus the final merge of the two partial sums
+  double nn = 2.0 * (double)(n > 0 ? n : 1) + 2.0;
   double g = nn * u / (1.0 - nn * u);
   double k = (g + uq / (1.0 - uq)) / (1.0 - g);
   return k * (1.0 + 0x1p-20) + 0x1p-60;

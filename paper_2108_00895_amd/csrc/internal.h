@@ -14,6 +14,15 @@ namespace skm {
 
 // ------------------------------------------------------------ argument blocks
 
+// Lists of non-zero codes of the tail terms of one scoring copy (see
+// kernels_tail.hip).  tail == nullptr: every term takes the dense path.
+struct TailView {
+  const uint8_t *tail;    // [D] 1 = tail term
+  const uint32_t *off;    // [nch][D + 1] entry offsets within chunk cc's entries
+  const uint64_t *base;   // [nch + 1] first entry of chunk cc
+  const uint32_t *ent;    // entries (BF16 / FP8: (col << 16) | code; FP32: (col, bits))
+};
+
 struct ScoreArgs {
   // rows
   const int64_t *indptr;
@@ -33,6 +42,8 @@ struct ScoreArgs {
   const uint8_t *tile_ch;
   int32_t n_ch;
   const int32_t *ch_ids;
+  TailView tv;                // tail lists of the full copy
+  TailView tv_ch;             // tail lists of the compacted copy
   const double *prev_lo;
   const double *prev_hi;
   // Sec. 3.2: per-row candidate lists (nullptr: no index)
@@ -193,6 +204,15 @@ struct skm_ctx {
   double *red = nullptr;       // reduction outputs
   int32_t *ids_count = nullptr;
   skm::Partial *part = nullptr;  // [ceil(k / 512)][N] scoring partials
+  // tail lists: [0] of the full copy, [1] of the compacted (NCC) copy
+  struct Tail {
+    uint8_t *tail = nullptr;
+    uint32_t *cnt = nullptr, *off = nullptr, *ent = nullptr, *cf = nullptr, *hist = nullptr;
+    uint64_t *base = nullptr;
+    int64_t cap_entries = 0;
+    bool ready = false;
+  } tails[2];
+  bool use_tail = true;
   uint8_t *mode = nullptr;       // [N] 2 = row finished by the index path
   // Sec. 3.2 index (built when SKM_INDEX is set)
   bool index_ready = false;
@@ -217,6 +237,13 @@ struct skm_ctx {
   float ms_index_build = 0.f;
   int64_t idx_eligible = 0;
   int server_attached = 0;     // a request server reads this context
+  // segmented member sums of large clusters
+  int4 *tasks = nullptr;         // [task cap]
+  int64_t *task_r0 = nullptr;    // [task cap]
+  int4 *groups = nullptr;        // [k]
+  int64_t task_cap = 0;
+  double *work = nullptr;        // [work_slots][D] partial sums
+  int64_t work_slots = 0;
   int score_blocks = 2048;       // persistent scoring grid
   int64_t nblk = 0;
 
@@ -238,7 +265,8 @@ hipError_t launch_score(const ScoreArgs &a, Partial *part, int blocks, int prec,
 hipError_t launch_exact(const ExactArgs &a, int prec, hipStream_t s);
 hipError_t launch_score_dense(const int64_t *indptr, const int32_t *indices, const float *values,
                               int64_t n_rows, const uint8_t *tile, int64_t D, int32_t k,
-                              const float *scale, int prec, float *out, hipStream_t s);
+                              const float *scale, const TailView &tv, int prec, float *out,
+                              hipStream_t s);
 hipError_t launch_exact_scores(const int64_t *indptr, const int32_t *indices, const float *values,
                                int64_t n_rows, const int32_t *a, const double *master, int64_t D,
                                double *out, hipStream_t s);
@@ -246,6 +274,13 @@ hipError_t launch_exact_scores(const int64_t *indptr, const int32_t *indices, co
 // api.hip
 hipError_t launch_new_rows(skm_ctx *c, const NewRows &b, int64_t n, hipStream_t s);
 skm_status set_error(skm_status st, const std::string &msg);  // thread-local last error
+
+// kernels_tail.hip
+hipError_t tail_count(const uint8_t *tile, int64_t D, int32_t ncols, int prec, int64_t dense_max,
+                      uint32_t *cnt, uint32_t *cf, uint32_t *hist, uint8_t *tail, uint32_t *off,
+                      uint64_t *base, hipStream_t s);
+hipError_t tail_fill(const uint8_t *tile, int64_t D, int32_t ncols, int prec, const uint8_t *tail,
+                     const uint32_t *off, const uint64_t *base, uint32_t *ent, hipStream_t s);
 
 // kernels_index.hip
 hipError_t index_build_counts(const double *master, int32_t k, int64_t D, int32_t *cnt,
@@ -285,6 +320,11 @@ hipError_t launch_bucket(const int32_t *a, int64_t n, int32_t k, int64_t nblk, i
 hipError_t launch_sum_members(const int64_t *indptr, const int32_t *indices, const float *values,
                               const int64_t *offsets, const int32_t *members, const int32_t *ids,
                               int32_t n_ids, int64_t D, double *S, hipStream_t s);
+hipError_t launch_sum_tasks(const int64_t *indptr, const int32_t *indices, const float *values,
+                            const int32_t *members, const int4 *tasks, const int64_t *task_r0,
+                            int32_t n_tasks, int64_t D, double *S, double *work, hipStream_t s);
+hipError_t launch_combine(const int4 *groups, int32_t n_groups, int64_t D, const double *work,
+                          double *S, hipStream_t s);
 hipError_t launch_renorm(const double *S, const int32_t *counts, const int32_t *ids, int32_t n_ids,
                          int64_t D, double *master, double *snorm, double *shift, double *dot_old,
                          hipStream_t s);

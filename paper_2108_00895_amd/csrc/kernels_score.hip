@@ -26,6 +26,11 @@ typedef int v2i __attribute__((ext_vector_type(2)));
 template <>
 struct Codes<SKM_FP32> {
   static constexpr int kBytes = 4;
+  static constexpr int kEntWords = 2;
+  __device__ static void entry(const uint32_t *e, int &col, float &v) {
+    col = (int)e[0];
+    v = __uint_as_float(e[1]);
+  }
   struct raw_t {
     float4 a, b;
   };
@@ -52,6 +57,11 @@ struct Codes<SKM_FP32> {
 template <>
 struct Codes<SKM_BF16> {
   static constexpr int kBytes = 2;
+  static constexpr int kEntWords = 1;
+  __device__ static void entry(const uint32_t *e, int &col, float &v) {
+    col = (int)(e[0] >> 16);
+    v = __uint_as_float(e[0] << 16);
+  }
   using raw_t = uint4;
   __device__ static raw_t load(__amdgpu_buffer_rsrc_t rs, int voff, int soff) {
     const v4i x = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0);
@@ -73,6 +83,11 @@ struct Codes<SKM_BF16> {
 template <>
 struct Codes<SKM_FP8_E4M3> {
   static constexpr int kBytes = 1;
+  static constexpr int kEntWords = 1;
+  __device__ static void entry(const uint32_t *e, int &col, float &v) {
+    col = (int)(e[0] >> 16);
+    v = __builtin_amdgcn_cvt_pk_f32_fp8((int)(e[0] & 0xFFu), false)[0];
+  }
   using raw_t = uint2;
   __device__ static raw_t load(__amdgpu_buffer_rsrc_t rs, int voff, int soff) {
     const v2i x = __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0);
@@ -102,15 +117,21 @@ __device__ inline int64_t uniform64(int64_t v) {
 }
 __device__ inline int32_t uniform32(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// acc[c] += sum over the row's terms of x_t * code(t, c0 + 8*lane + c), in
-// ascending term order, one FMA per term (the order the error bound assumes).
-// Eight code loads are kept in flight per lane.
+// acc[c] += sum over the row's terms of x_t * code(t, c0 + 8*lane + c).
+// Head terms: one slab-row load per term (8 loads in flight per lane) and
+// eight FMAs into registers.  Tail terms (tv.tail[t] != 0): the term's list of
+// non-zero codes in this chunk, lanes over entries, products added into the
+// wave's 512-float LDS accumulator lacc, folded into acc at the end.  The
+// order of the sum differs from the term order; the error bound allows any
+// order (at most two roundings per term plus the final merge).
 template <int P>
 __device__ inline void score_chunk(int64_t b, int64_t e, const int32_t *__restrict__ indices,
                                    const float *__restrict__ values, const uint8_t *__restrict__ tile,
-                                   int64_t D, int64_t c0, float acc[8]) {
+                                   int64_t D, int64_t c0, float acc[8], const TailView &tv,
+                                   float *lacc) {
   using C = Codes<P>;
   const int lane = lane_id();
+  const int64_t cc = c0 / kChunk;
   // chunk slab [D][512] as a buffer resource in scalar registers
   const uint8_t *slab = reinterpret_cast<const uint8_t *>(
       uniform64(reinterpret_cast<int64_t>(tile + tile_index(0, c0, D) * C::kBytes)));
@@ -118,29 +139,104 @@ __device__ inline void score_chunk(int64_t b, int64_t e, const int32_t *__restri
       const_cast<uint8_t *>(slab), 0, (int)(D * kChunk * C::kBytes), 0x00020000);
   const int voff = lane * kColsPerLane * C::kBytes;
   constexpr int rowbytes = kChunk * C::kBytes;
+  const uint32_t *toff = tv.tail ? tv.off + cc * (D + 1) : nullptr;
+  const uint32_t *tent = tv.tail ? tv.ent + (int64_t)tv.base[cc] * C::kEntWords : nullptr;
+  bool used_lds = false;
   for (int64_t q0 = b; q0 < e; q0 += kWave) {
     const int cnt = (int)((e - q0) < kWave ? (e - q0) : kWave);
     int my_t = 0;
     float my_x = 0.f;
+    bool my_tail = false;
     if (lane < cnt) {
       my_t = indices[q0 + lane];
       my_x = values[q0 + lane];
+      my_tail = tv.tail && tv.tail[my_t];
     }
-    int u = 0;
-    for (; u + 8 <= cnt; u += 8) {
+    uint64_t dmask = __ballot(lane < cnt && !my_tail);
+    uint64_t tmask = __ballot(my_tail);
+    while (__popcll(dmask) >= 8) {
+      int u[8];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        u[v] = __builtin_ctzll(dmask);
+        dmask &= dmask - 1;
+      }
       typename C::raw_t r[8];
 #pragma unroll
       for (int v = 0; v < 8; ++v)
-        r[v] = C::load(rs, voff, __builtin_amdgcn_readlane(my_t, u + v) * rowbytes);
+        r[v] = C::load(rs, voff, __builtin_amdgcn_readlane(my_t, u[v]) * rowbytes);
 #pragma unroll
-      for (int v = 0; v < 8; ++v) C::fma8(r[v], readlane_f(my_x, u + v), acc);
+      for (int v = 0; v < 8; ++v) C::fma8(r[v], readlane_f(my_x, u[v]), acc);
     }
-    for (; u < cnt; ++u) {
-      const int t0 = __builtin_amdgcn_readlane(my_t, u);
-      typename C::raw_t r0 = C::load(rs, voff, t0 * rowbytes);
+    while (dmask) {
+      const int u = __builtin_ctzll(dmask);
+      dmask &= dmask - 1;
+      typename C::raw_t r0 = C::load(rs, voff, __builtin_amdgcn_readlane(my_t, u) * rowbytes);
       C::fma8(r0, readlane_f(my_x, u), acc);
     }
+    if (tmask) {
+      // All tail terms of the batch at once: lane l owns list [o0, o0 + len)
+      // of its term; the lists are flattened and each lane takes one entry
+      // per step, finding its owner by a binary search over the prefix sums.
+      used_lds = true;
+      uint32_t o0 = 0, len = 0;
+      if (my_tail) {
+        o0 = toff[my_t];
+        len = toff[my_t + 1] - o0;
+      }
+      uint32_t incl = len;
+#pragma unroll
+      for (int m = 1; m < kWave; m <<= 1) {
+        const uint32_t y = __shfl_up(incl, m, kWave);
+        if (lane >= m) incl += y;
+      }
+      const uint32_t excl = incl - len;
+      const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+      for (uint32_t f0 = 0; f0 < total; f0 += 2 * kWave) {
+        int col[2];
+        float v[2], x[2];
+        bool ok[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const uint32_t f = f0 + h * kWave + lane;
+          ok[h] = f < total;
+          int own = 0;
+#pragma unroll
+          for (int step = 32; step > 0; step >>= 1) {
+            const uint32_t pv = __shfl(incl, own + step - 1, kWave);
+            if (pv <= f) own += step;
+          }
+          own = own > kWave - 1 ? kWave - 1 : own;
+          const uint32_t ou = __shfl(o0, own, kWave);
+          const uint32_t eu = __shfl(excl, own, kWave);
+          x[h] = __shfl(my_x, own, kWave);
+          col[h] = 0;
+          v[h] = 0.f;
+          if (ok[h]) C::entry(tent + (int64_t)(ou + (f - eu)) * C::kEntWords, col[h], v[h]);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          if (ok[h]) atomicAdd(&lacc[col[h]], x[h] * v[h]);
+      }
+    }
   }
+  if (used_lds) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      acc[v] += lacc[lane * kColsPerLane + v];
+      lacc[lane * kColsPerLane + v] = 0.f;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+__device__ inline void zero_lacc(float *lacc) {
+  for (int i = lane_id(); i < kChunk; i += kWave) lacc[i] = 0.f;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
 struct RowPlan {
@@ -150,10 +246,11 @@ struct RowPlan {
   bool ncc;
   int32_t ap;
   bool done;               // finished by the index path
+  const TailView *tv;
 };
 
 __device__ inline RowPlan plan_row(const ScoreArgs &a, int64_t row, bool allow_ncc) {
-  RowPlan p{a.tile, a.k, nullptr, false, -1, false};
+  RowPlan p{a.tile, a.k, nullptr, false, -1, false, &a.tv};
   if (a.mode && a.mode[row] == 2) {
     p.ncols = 0;
     p.done = true;
@@ -167,6 +264,7 @@ __device__ inline RowPlan plan_row(const ScoreArgs &a, int64_t row, bool allow_n
       p.colmap = a.ch_ids;
       p.ncc = true;
       p.ap = ap;
+      p.tv = &a.tv_ch;
     }
   }
   return p;
@@ -180,8 +278,11 @@ __device__ inline RowPlan plan_row(const ScoreArgs &a, int64_t row, bool allow_n
 template <int P>
 __global__ __launch_bounds__(256) void k_score_part(ScoreArgs a, Partial *__restrict__ part,
                                                     int64_t n_items) {
+  __shared__ float lacc_all[4][kChunk];
   const int wave = uniform32(threadIdx.x >> 6);
   const int lane = lane_id();
+  float *lacc = lacc_all[wave];
+  zero_lacc(lacc);
   const int64_t stride = (int64_t)gridDim.x * 4;
   for (int64_t it = (int64_t)blockIdx.x * 4 + wave; it < n_items; it += stride) {
     const int64_t c = uniform64(it / a.n_rows);
@@ -192,7 +293,7 @@ __global__ __launch_bounds__(256) void k_score_part(ScoreArgs a, Partial *__rest
     const int64_t b = uniform64(a.indptr[row]);
     const int64_t e = uniform64(a.indptr[row + 1]);
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    score_chunk<P>(b, e, a.indices, a.values, pl.tile, a.D, c0, acc);
+    score_chunk<P>(b, e, a.indices, a.values, pl.tile, a.D, c0, acc, *pl.tv, lacc);
     float b1 = -INFINITY, b2 = -INFINITY;
     int j1 = 0x7FFFFFFF;
 #pragma unroll
@@ -324,10 +425,13 @@ __device__ inline double dot64(int64_t b, int64_t e, const int32_t *__restrict__
 template <int P>
 __global__ __launch_bounds__(256) void k_exact(ExactArgs x) {
   __shared__ int32_t band_all[4][kBandCap];
+  __shared__ float lacc_all[4][kChunk];
   const ScoreArgs &a = x.s;
   const int wave = uniform32(threadIdx.x >> 6);
   const int lane = lane_id();
   int32_t *band = band_all[wave];
+  float *lacc = lacc_all[wave];
+  zero_lacc(lacc);
   const int32_t n_flag = uniform32(*(volatile int32_t *)&a.counters[0]);
   for (int64_t f = (int64_t)blockIdx.x * 4 + wave; f < n_flag; f += (int64_t)gridDim.x * 4) {
     const int64_t row = uniform64(a.flag_rows[f]);
@@ -336,8 +440,9 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs x) {
     const int64_t b = uniform64(a.indptr[row]);
     const int64_t e = uniform64(a.indptr[row + 1]);
     const int64_t n = e - b;
-    RowPlan pl{a.tile, a.k, nullptr, false, -1, false};
+    RowPlan pl{a.tile, a.k, nullptr, false, -1, false, &a.tv};
     if (ncc_row) {
+      pl.tv = &a.tv_ch;
       pl.tile = a.tile_ch;
       pl.ncols = a.n_ch;
       pl.colmap = a.ch_ids;
@@ -360,7 +465,7 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs x) {
         continue;
       }
       float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      score_chunk<P>(b, e, a.indices, a.values, pl.tile, a.D, c0, acc);
+      score_chunk<P>(b, e, a.indices, a.values, pl.tile, a.D, c0, acc, *pl.tv, lacc);
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         const int64_t col = c0 + lane * kColsPerLane + c;
@@ -433,16 +538,19 @@ template <int P>
 __global__ __launch_bounds__(256) void k_score_dense(const int64_t *indptr, const int32_t *indices,
                                                      const float *values, int64_t n_rows,
                                                      const uint8_t *tile, int64_t D, int32_t k,
-                                                     const float *scale, float *out) {
+                                                     const float *scale, TailView tv, float *out) {
+  __shared__ float lacc_all[4][kChunk];
   const int wave = uniform32(threadIdx.x >> 6);
   const int64_t row = (int64_t)blockIdx.x * 4 + wave;
   if (row >= n_rows) return;
   const int lane = lane_id();
+  float *lacc = lacc_all[wave];
+  zero_lacc(lacc);
   const int64_t b = uniform64(indptr[row]);
   const int64_t e = uniform64(indptr[row + 1]);
   for (int64_t c0 = 0; c0 < k; c0 += kChunk) {
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    score_chunk<P>(b, e, indices, values, tile, D, c0, acc);
+    score_chunk<P>(b, e, indices, values, tile, D, c0, acc, tv, lacc);
     for (int c = 0; c < 8; ++c) {
       const int64_t col = c0 + lane * kColsPerLane + c;
       if (col < k) out[row * k + col] = scale ? acc[c] * scale[col] : acc[c];
@@ -511,21 +619,22 @@ hipError_t launch_exact(const ExactArgs &x, int prec, hipStream_t s) {
 
 hipError_t launch_score_dense(const int64_t *indptr, const int32_t *indices, const float *values,
                               int64_t n_rows, const uint8_t *tile, int64_t D, int32_t k,
-                              const float *scale, int prec, float *out, hipStream_t s) {
+                              const float *scale, const TailView &tv, int prec, float *out,
+                              hipStream_t s) {
   if (n_rows <= 0) return hipSuccess;
   const dim3 g((unsigned)((n_rows + 3) / 4)), blk(256);
   switch (prec) {
     case SKM_FP32:
       hipLaunchKernelGGL(k_score_dense<SKM_FP32>, g, blk, 0, s, indptr, indices, values, n_rows, tile,
-                         D, k, nullptr, out);
+                         D, k, nullptr, tv, out);
       break;
     case SKM_BF16:
       hipLaunchKernelGGL(k_score_dense<SKM_BF16>, g, blk, 0, s, indptr, indices, values, n_rows, tile,
-                         D, k, nullptr, out);
+                         D, k, nullptr, tv, out);
       break;
     case SKM_FP8_E4M3:
       hipLaunchKernelGGL(k_score_dense<SKM_FP8_E4M3>, g, blk, 0, s, indptr, indices, values, n_rows,
-                         tile, D, k, scale, out);
+                         tile, D, k, scale, tv, out);
       break;
     default: return hipErrorInvalidValue;
   }

@@ -295,6 +295,40 @@ __global__ __launch_bounds__(256) void k_sum_members(const int64_t *indptr, cons
   }
 }
 
+// Segmented variant: task = (cluster, member range [r0, r1), destination).  A
+// cluster with more members than one segment is split into fixed segments
+// whose sums go to partial rows of a workspace (dest >= 0) and are added in
+// segment order by k_combine; small clusters sum straight into S_j (dest < 0).
+// Every sum still runs in a fixed order, so results are reproducible.
+__global__ __launch_bounds__(256) void k_sum_tasks(const int64_t *indptr, const int32_t *indices,
+                                                   const float *values, const int32_t *members,
+                                                   const int4 *tasks, const int64_t *task_r0,
+                                                   int64_t D, double *S, double *work) {
+  const int4 tk = tasks[blockIdx.x];   // x = cluster, y = count, z = dest slot (-1: S_j)
+  double *dst = tk.z < 0 ? S + (int64_t)tk.x * D : work + (int64_t)tk.z * D;
+  for (int64_t t = threadIdx.x; t < D; t += 256) dst[t] = 0.0;
+  __syncthreads();
+  const int64_t r0 = task_r0[blockIdx.x], r1 = r0 + tk.y;
+  for (int64_t r = r0; r < r1; ++r) {
+    const int64_t i = members[r];
+    const int64_t b = indptr[i], e = indptr[i + 1];
+    for (int64_t q = b + threadIdx.x; q < e; q += 256) dst[indices[q]] += (double)values[q];
+    __syncthreads();
+  }
+}
+
+// S_j = sum of its segment partials, in segment order.  Block (group, term block).
+__global__ __launch_bounds__(256) void k_combine(const int4 *groups, int64_t D, int64_t tblk,
+                                                 const double *work, double *S) {
+  const int4 g = groups[blockIdx.x / tblk];   // x = cluster, y = first slot, z = segments
+  const int64_t t0 = (blockIdx.x % tblk) * 4096;
+  for (int64_t t = t0 + threadIdx.x; t < min(D, t0 + 4096); t += 256) {
+    double s = 0.0;
+    for (int p = 0; p < g.z; ++p) s += work[(int64_t)(g.y + p) * D + t];
+    S[(int64_t)g.x * D + t] = s;
+  }
+}
+
 // c_j = S_j / ||S_j|| (empty clusters keep c_j), with the per-cluster shift
 // ||c_j(new) - c_j(old)||^2 and S_j . c_j(old).
 __global__ __launch_bounds__(256) void k_renorm(const double *S, const int32_t *counts,
@@ -506,6 +540,24 @@ hipError_t launch_sum_members(const int64_t *indptr, const int32_t *indices, con
   if (n_ids <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_sum_members, dim3((unsigned)n_ids), dim3(256), 0, s, indptr, indices, values,
                      offsets, members, ids, D, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_tasks(const int64_t *indptr, const int32_t *indices, const float *values,
+                            const int32_t *members, const int4 *tasks, const int64_t *task_r0,
+                            int32_t n_tasks, int64_t D, double *S, double *work, hipStream_t s) {
+  if (n_tasks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sum_tasks, dim3((unsigned)n_tasks), dim3(256), 0, s, indptr, indices, values,
+                     members, tasks, task_r0, D, S, work);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(const int4 *groups, int32_t n_groups, int64_t D, const double *work,
+                          double *S, hipStream_t s) {
+  if (n_groups <= 0) return hipSuccess;
+  const int64_t tblk = (D + 4095) / 4096;
+  hipLaunchKernelGGL(k_combine, dim3((unsigned)(n_groups * tblk)), dim3(256), 0, s, groups, D, tblk,
+                     work, S);
   return hipGetLastError();
 }
 

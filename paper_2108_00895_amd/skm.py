@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libskm.so")
 (SKM_OK, SKM_E_INVALID, SKM_E_NOMEM, SKM_E_DEVICE, SKM_E_STATE, SKM_E_UNSUPPORTED, SKM_E_BUSY,
  SKM_E_TIMEOUT) = range(8)
 FP32, BF16, FP8_E4M3 = 0, 1, 2
-NCC, INDEX, NO_EXACT = 1, 2, 4
+NCC, INDEX, NO_EXACT, DENSE_ONLY = 1, 2, 4, 8
 STOP_PAPER, STOP_FIXED = 0, 1
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3}
 CODE_BYTES = {FP32: 4, BF16: 2, FP8_E4M3: 1}
@@ -197,6 +197,7 @@ class Options:
     ncc: bool = False
     index: bool = False
     no_exact: bool = False
+    dense_only: bool = False
     lambdas: tuple = (0.1, 0.25, 0.4, 0.6)
     index_min_changed: int = 0
     stop_rule: str = "paper"
@@ -218,7 +219,8 @@ class Context:
         lib.skm_config_default(ctypes.byref(cfg))
         cfg.k = k
         cfg.precision = PRECISIONS[o.precision]
-        cfg.flags = (NCC if o.ncc else 0) | (INDEX if o.index else 0) | (NO_EXACT if o.no_exact else 0)
+        cfg.flags = ((NCC if o.ncc else 0) | (INDEX if o.index else 0) |
+                     (NO_EXACT if o.no_exact else 0) | (DENSE_ONLY if o.dense_only else 0))
         cfg.n_lambda = len(o.lambdas)
         for i, lam in enumerate(o.lambdas):
             cfg.lambda_[i] = lam
