@@ -55,6 +55,8 @@ def _load():
     lib.orc_seed.argtypes = [i64, i32, vp, vp, vp, i32, vp, vp]
     lib.orc_assign.restype = ctypes.c_int
     lib.orc_assign.argtypes = [i64, i32, vp, vp, vp, i32, vp, vp, i64, vp, vp, vp, i32]
+    lib.orc_assign_seeds.restype = ctypes.c_int
+    lib.orc_assign_seeds.argtypes = [i64, i32, vp, vp, vp, i32, vp, vp, i64, vp, vp, vp, i32]
     lib.orc_scores.restype = ctypes.c_int
     lib.orc_scores.argtypes = [i64, i32, vp, vp, vp, i32, vp, vp, i64, vp]
     lib.orc_update.restype = ctypes.c_int
@@ -104,6 +106,24 @@ def assign(csr, C: np.ndarray, docs=None, nthreads: int = 0):
     rc = _load().orc_assign(len(ip) - 1, D, ip.ctypes.data, ix.ctypes.data, v.ctypes.data, k,
                             C.ctypes.data, dp, n, a.ctypes.data, s1.ctypes.data, s2.ctypes.data,
                             nthreads)
+    if rc != 0:
+        raise ValueError("row index out of range")
+    return a, s1, s2
+
+
+def assign_seeds(csr, n_terms: int, rows, docs, nthreads: int = 0):
+    """assign() against the initial centroids x_r/||x_r|| of the given seed rows,
+    computed from the rows directly (no dense k x D array), for listed rows."""
+    ip, ix, v = _csr(csr)
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    docs = np.ascontiguousarray(docs, dtype=np.int64)
+    n = len(docs)
+    a = np.empty(n, dtype=np.int32)
+    s1 = np.empty(n)
+    s2 = np.empty(n)
+    rc = _load().orc_assign_seeds(len(ip) - 1, n_terms, ip.ctypes.data, ix.ctypes.data,
+                                  v.ctypes.data, len(rows), rows.ctypes.data, docs.ctypes.data, n,
+                                  a.ctypes.data, s1.ctypes.data, s2.ctypes.data, nthreads)
     if rc != 0:
         raise ValueError("row index out of range")
     return a, s1, s2

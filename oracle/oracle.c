@@ -89,6 +89,67 @@ int orc_assign(int64_t n_docs, int32_t D, const int64_t *indptr, const int32_t *
   return bad ? -1 : 0;
 }
 
+/* Dot product of two rows of the CSR by merging their ascending term lists. */
+static double dot_rows(const int64_t *indptr, const int32_t *indices, const float *values,
+                       int64_t i, int64_t r) {
+  int64_t p = indptr[i], pe = indptr[i + 1], q = indptr[r], qe = indptr[r + 1];
+  double s = 0.0;
+  while (p < pe && q < qe) {
+    if (indices[p] < indices[q]) ++p;
+    else if (indices[p] > indices[q]) ++q;
+    else {
+      s += (double)values[p] * (double)values[q];
+      ++p;
+      ++q;
+    }
+  }
+  return s;
+}
+
+/*
+ * Assignment against the initial centroids c_j = x_{rows[j]} / ||x_{rows[j]}||
+ * without forming them densely (for sampled checks at full size):
+ * s_ij = (x_i . x_{rows[j]}) / ||x_{rows[j]}||.  Same outputs as orc_assign.
+ */
+int orc_assign_seeds(int64_t n_docs, int32_t D, const int64_t *indptr, const int32_t *indices,
+                     const float *values, int32_t k, const int32_t *rows, const int64_t *docs,
+                     int64_t n_list, int32_t *a, double *s1, double *s2, int32_t nthreads) {
+  (void)D;
+  if (k < 1) return -1;
+  double *nrm = (double *)malloc(sizeof(double) * (size_t)k);
+  if (!nrm) return -2;
+  for (int32_t j = 0; j < k; ++j) {
+    if (rows[j] < 0 || rows[j] >= n_docs) { free(nrm); return -1; }
+    nrm[j] = sqrt(dot_rows(indptr, indices, values, rows[j], rows[j]));
+  }
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t o = 0; o < n_list; ++o) {
+    int64_t i = docs[o];
+    if (i < 0 || i >= n_docs) { bad = 1; continue; }
+    int32_t best = 0;
+    double b1 = -INFINITY, b2 = -INFINITY;
+    for (int32_t j = 0; j < k; ++j) {
+      double s = dot_rows(indptr, indices, values, i, rows[j]) / nrm[j];
+      if (s > b1) {
+        b2 = b1;
+        b1 = s;
+        best = j;
+      } else if (s > b2) {
+        b2 = s;
+      }
+    }
+    a[o] = best;
+    s1[o] = b1;
+    s2[o] = b2;
+  }
+  free(nrm);
+  return bad ? -1 : 0;
+}
+
 /* Dense similarity matrix S[o][j] for listed rows (small inputs only). */
 int orc_scores(int64_t n_docs, int32_t D, const int64_t *indptr, const int32_t *indices,
                const float *values, int32_t k, const double *C, const int64_t *docs,

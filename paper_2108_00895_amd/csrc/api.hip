@@ -683,7 +683,10 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
   ST_TRY(check_ctx_writable(c));
   hipStream_t s = c->stream;
   ScoreArgs a = base_args(c);
-  const bool ncc = (c->cfg.flags & SKM_NCC) && c->have_prev;
+  // Sec. 3.1 only pays when a good share of centroids is unchanged: with more
+  // than half changed, building the compacted copy costs more than the
+  // columns it saves, and every row scores the full copy instead.
+  const bool ncc = (c->cfg.flags & SKM_NCC) && c->have_prev && 2 * c->last_changed <= c->k;
   int32_t n_ch = c->k;
   HIP_TRY(c, hipEventRecord(c->ev[0], s));
   if (ncc) {

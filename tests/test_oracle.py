@@ -209,3 +209,16 @@ def test_centroid_rows_subset_matches_update():
     rows, sn = oracle.centroid_rows(csr, c.n_terms, 7, a, [6, 1])
     np.testing.assert_array_equal(rows, u.C[[6, 1]])
     np.testing.assert_array_equal(sn, u.snorm[[6, 1]])
+
+
+def test_assign_seeds_matches_dense_seeds():
+    csr, c = _tiny()
+    rows = [3, 77, 150, 151, 299, 12]
+    docs = np.arange(0, c.n_docs, 3)
+    C = oracle.seed(csr, c.n_terms, rows)
+    a, s1, s2 = oracle.assign(csr, C, docs=docs)
+    b, t1, t2 = oracle.assign_seeds(csr, c.n_terms, rows, docs)
+    gap = s1 - s2
+    assert np.all((a == b) | (gap < 1e-12))
+    np.testing.assert_allclose(t1, s1, rtol=1e-14, atol=1e-16)
+    np.testing.assert_allclose(t2, s2, rtol=1e-14, atol=1e-16)
