@@ -446,7 +446,7 @@ hipError_t launch_new_rows(skm_ctx *c, const NewRows &b, int64_t n, hipStream_t 
   sa.mode = nullptr;
   hipError_t e = launch_fill_i32(b.counters, 0, 8, s);
   if (e == hipSuccess) e = launch_fill_i32(reinterpret_cast<int32_t *>(b.stat), 0, 16, s);
-  if (e == hipSuccess) e = launch_score(sa, b.part, c->score_blocks, c->prec, s);
+  if (e == hipSuccess) e = launch_score(sa, b.part, c->n_cu, c->prec, s);
   if (e == hipSuccess) {
     ExactArgs x{sa, b.part, c->master, c->D, exact_waves()};
     e = launch_exact(x, c->prec, s);
@@ -555,7 +555,7 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess &&
         cus > 0)
-      c->score_blocks = cus * 8;
+      c->n_cu = cus;
     (void)hipGetLastError();
   }
   for (hipEvent_t &ev : c->ev) {
@@ -724,7 +724,7 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
     c->idx_eligible = n_rows_idx;
   }
   HIP_TRY(c, hipEventRecord(c->ev[5], s));
-  HIP_TRY(c, launch_score(a, c->part, c->score_blocks, c->prec, s));
+  HIP_TRY(c, launch_score(a, c->part, c->n_cu, c->prec, s));
   HIP_TRY(c, hipEventRecord(c->ev[1], s));
   if (!a.no_exact) {
     ExactArgs x{a, c->part, c->master, c->D, exact_waves()};

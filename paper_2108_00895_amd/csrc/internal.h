@@ -244,7 +244,7 @@ struct skm_ctx {
   int64_t task_cap = 0;
   double *work = nullptr;        // [work_slots][D] partial sums
   int64_t work_slots = 0;
-  int score_blocks = 2048;       // persistent scoring grid
+  int n_cu = 256;                // compute units (the persistent scoring grid is sized from it)
   int64_t nblk = 0;
 
   // state
@@ -261,7 +261,9 @@ struct skm_ctx {
 namespace skm {
 
 // kernels_score.hip
-hipError_t launch_score(const ScoreArgs &a, Partial *part, int blocks, int prec, hipStream_t s);
+// n_cu: compute units of the device; the grid holds as many workgroups as fit
+// on them at once.
+hipError_t launch_score(const ScoreArgs &a, Partial *part, int n_cu, int prec, hipStream_t s);
 hipError_t launch_exact(const ExactArgs &a, int prec, hipStream_t s);
 hipError_t launch_score_dense(const int64_t *indptr, const int32_t *indices, const float *values,
                               int64_t n_rows, const uint8_t *tile, int64_t D, int32_t k,

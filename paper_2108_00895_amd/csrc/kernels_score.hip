@@ -577,12 +577,23 @@ __global__ __launch_bounds__(256) void k_exact_scores(const int64_t *indptr, con
 }
 
 template <int P>
-hipError_t launch_score_t(const ScoreArgs &a, Partial *part, int blocks, hipStream_t s) {
+hipError_t launch_score_t(const ScoreArgs &a, Partial *part, int n_cu, hipStream_t s) {
   if (a.n_rows <= 0) return hipSuccess;
+  // Workgroups resident per CU at this kernel's register and LDS use: the
+  // persistent grid is exactly one wave of them, so no workgroup starts late
+  // and sweeps the chunks out of step with the rest.
+  static const int per_cu = [] {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_score_part<P>, 256, 0) != hipSuccess ||
+        n <= 0)
+      n = 4;
+    (void)hipGetLastError();
+    return n;
+  }();
   const int64_t nchunks = (a.k + kChunk - 1) / kChunk;
   const int64_t n_items = nchunks * a.n_rows;
   const int64_t need = (n_items + 3) / 4;
-  const int g = (int)std::min<int64_t>(blocks, need);
+  const int g = (int)std::min<int64_t>((int64_t)n_cu * per_cu, need);
   hipLaunchKernelGGL(k_score_part<P>, dim3((unsigned)g), dim3(256), 0, s, a, part, n_items);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -599,11 +610,11 @@ hipError_t launch_exact_t(const ExactArgs &x, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_score(const ScoreArgs &a, Partial *part, int blocks, int prec, hipStream_t s) {
+hipError_t launch_score(const ScoreArgs &a, Partial *part, int n_cu, int prec, hipStream_t s) {
   switch (prec) {
-    case SKM_FP32: return launch_score_t<SKM_FP32>(a, part, blocks, s);
-    case SKM_BF16: return launch_score_t<SKM_BF16>(a, part, blocks, s);
-    case SKM_FP8_E4M3: return launch_score_t<SKM_FP8_E4M3>(a, part, blocks, s);
+    case SKM_FP32: return launch_score_t<SKM_FP32>(a, part, n_cu, s);
+    case SKM_BF16: return launch_score_t<SKM_BF16>(a, part, n_cu, s);
+    case SKM_FP8_E4M3: return launch_score_t<SKM_FP8_E4M3>(a, part, n_cu, s);
   }
   return hipErrorInvalidValue;
 }
