@@ -119,6 +119,12 @@ typedef struct {
                                  the context makes */
   void *stream;               /* hipStream_t to enqueue on; NULL = own stream */
   int32_t validate;           /* 1 = check the CSR conventions above at init */
+  int32_t head_max_terms;     /* BF16 / FP8 scoring: at most this many of the most
+                                 frequent terms are scored as a dense BF16 block on
+                                 the matrix cores (rounded to a multiple of 64);
+                                 below 64 = off.  Default 4096. */
+  double head_min_df;         /* a term joins that head when at least this fraction
+                                 of the rows contain it.  Default 1/128. */
 } skm_config;
 
 typedef struct {
@@ -149,10 +155,17 @@ typedef struct {
   float ms_update;
   float ms_index;             /* index query + exact candidate scoring (assign),
                                  index build (update) */
+  int32_t head_terms;         /* terms this assignment scored on the matrix cores
+                                 (0 = none; the head is not used for NCC rows) */
+  float ms_head;              /* device time of the head products (part of ms_score) */
+  int32_t score_launches;     /* launches of the sparse scoring kernel */
+  double sparse_products;     /* scored_products restricted to the terms scored on
+                                 the sparse path (all of them when head_terms = 0) */
 } skm_iter_stats;
 
 /* Fills *cfg with defaults: k = 0 (must be set), FP32, no flags, the four
- * thresholds of Sec. 4.1, paper stop rule, max_iter 100, shift 1e-4. */
+ * thresholds of Sec. 4.1, paper stop rule, max_iter 100, shift 1e-4, head of
+ * at most 4096 terms with document frequency >= 1/128. */
 void skm_config_default(skm_config *cfg);
 
 /* Creates a context: copies the rows into HBM, seeds the centroids (FP64) and
@@ -218,6 +231,22 @@ skm_status skm_score_dense(skm_ctx *c, const skm_csr *docs, float *out);
 /* The certified error bound the context applies to a low-precision score s of
  * a row with nnz terms and L1 norm l1: |s - exact| <= bound. */
 double skm_error_bound(const skm_ctx *c, double s, int64_t nnz, double l1);
+
+/* Number of head terms (the most frequent terms, scored as a dense BF16 block
+ * on the matrix cores; see head_max_terms), 0 when the head is off. */
+int32_t skm_head_terms(const skm_ctx *c);
+
+/* Diagnostic: the low-precision scores of the context's own rows
+ * [row0, row0 + n_rows) as an assignment step with the head computes them
+ * (head product plus the rows' other terms), before any exact tier:
+ * out[i * k + j], host, n_rows * k floats.  SKM_E_STATE when the head is off;
+ * SKM_E_INVALID for a range outside the rows or above one head batch. */
+skm_status skm_score_head(skm_ctx *c, int64_t row0, int64_t n_rows, float *out);
+
+/* The certified bound for such head scores (Sec. 2 scores with the row values
+ * of head terms rounded to BF16 and matrix-core accumulation); -1 when the
+ * head is off. */
+double skm_error_bound_head(const skm_ctx *c, double s, int64_t nnz, double l1);
 
 /* Index of threshold level `level` (Sec. 3.2), after an update with SKM_INDEX:
  * term-major lists.  offsets [n_cols + 1] (host int64), entries (host) of

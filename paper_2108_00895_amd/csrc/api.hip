@@ -4,6 +4,7 @@
 // kernels_score.hip and kernels_update.hip; this file only sequences them.
 #include <algorithm>
 #include <cstdio>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -234,6 +235,101 @@ skm_status rebuild_tiles(skm_ctx *c, const uint8_t *changed) {
   HIP_TRY(c, launch_quantize(c->master, c->k, c->D, changed, c->scale, c->prec, c->tile,
                              c->stream));
   ST_TRY(build_tail(c, 0, c->tile, c->k));
+  if (c->head_H > 0)
+    HIP_TRY(c, launch_head_codes(c->tile, c->D, c->k, c->prec, c->head_terms, c->head_H, c->k_pad,
+                                 c->ch_head, c->stream));
+  return SKM_OK;
+}
+
+// The dense head (kernels_head.hip): the terms contained in at least
+// head_min_df of the rows, most frequent first, at most head_max_terms, padded
+// to a multiple of 64 with the next most frequent terms.  Builds the rows'
+// BF16 head block and the remainder CSR once (the rows never change).  The
+// head stays off for FP32 scoring, when fewer than 64 terms qualify, or when
+// its buffers would not fit the HBM budget.
+skm_status setup_head(skm_ctx *c) {
+  c->head_H = 0;
+  if (c->prec == SKM_FP32 || c->cfg.head_max_terms < 64 || c->Z == 0) return SKM_OK;
+  hipStream_t s = c->stream;
+  uint32_t *d_df = nullptr;
+  ST_TRY(dalloc(c, &d_df, (size_t)c->D));
+  std::vector<uint32_t> df(c->D);
+  hipError_t e = launch_df(c->indices, c->Z, d_df, c->D, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(df.data(), d_df, sizeof(uint32_t) * c->D, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  dfree(c, d_df, sizeof(uint32_t) * c->D);
+  if (e != hipSuccess) return device_fail(c, "head df", e);
+
+  const double thr = std::max(1.0, std::ceil(c->cfg.head_min_df * (double)c->N));
+  std::vector<int32_t> order;
+  int64_t n_pos = 0, n_qual = 0;
+  for (int64_t t = 0; t < c->D; ++t) {
+    if (df[t] == 0) continue;
+    ++n_pos;
+    if ((double)df[t] >= thr) ++n_qual;
+  }
+  int64_t H = round_up(n_qual, 64);
+  H = std::min<int64_t>(H, (c->cfg.head_max_terms / 64) * 64);
+  H = std::min<int64_t>(H, (n_pos / 64) * 64);
+  if (H < 64) return SKM_OK;
+  order.reserve(n_pos);
+  for (int64_t t = 0; t < c->D; ++t)
+    if (df[t] > 0) order.push_back((int32_t)t);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return df[x] > df[y]; });
+  order.resize(H);
+  std::sort(order.begin(), order.end());
+  std::vector<int32_t> slot(c->D, -1);
+  int64_t head_nnz = 0;
+  for (int64_t h = 0; h < H; ++h) {
+    slot[order[h]] = (int32_t)h;
+    head_nnz += df[order[h]];
+  }
+  const int64_t rest_nnz = c->Z - head_nnz;
+  const int32_t k_pad = (int32_t)round_up(c->k, kChunk);
+  // head scores of one batch: up to 4 chunks (2048 centroids) of up to 2^20
+  // rows, 8 GiB at most
+  const int32_t chunks = (int32_t)std::min<int64_t>(4, k_pad / kChunk);
+  const int64_t rows = std::min<int64_t>(1ll << 20, round_up(c->N, 256));
+  const int64_t nscan = head_split_scan_blocks(c->N);
+  const size_t need = 4 * (size_t)H + 4 * (size_t)c->D + 2 * (size_t)c->N * H +
+                      2 * (size_t)k_pad * H + 4 * (size_t)rows * chunks * kChunk +
+                      8 * (size_t)(c->N + 1) +
+                      8 * (size_t)rest_nnz + 8 * (size_t)c->N + 8 * (size_t)nscan + 16 * 256;
+  if (c->cfg.hbm_budget_bytes && c->hbm_bytes + need > c->cfg.hbm_budget_bytes) return SKM_OK;
+
+  ST_TRY(dalloc(c, &c->head_terms, (size_t)H));
+  ST_TRY(dalloc(c, &c->head_slot, (size_t)c->D));
+  ST_TRY(dalloc(c, &c->xh, (size_t)c->N * H));
+  ST_TRY(dalloc(c, &c->ch_head, (size_t)k_pad * H));
+  ST_TRY(dalloc(c, &c->hs, (size_t)rows * chunks * kChunk));
+  ST_TRY(dalloc(c, &c->r_indptr, (size_t)c->N + 1));
+  ST_TRY(dalloc(c, &c->r_indices, (size_t)std::max<int64_t>(rest_nnz, 1)));
+  ST_TRY(dalloc(c, &c->r_values, (size_t)std::max<int64_t>(rest_nnz, 1)));
+  int64_t *cnt = nullptr, *work = nullptr;
+  ST_TRY(dalloc(c, &cnt, (size_t)c->N));
+  ST_TRY(dalloc(c, &work, (size_t)nscan));
+  e = hipMemcpyAsync(c->head_terms, order.data(), sizeof(int32_t) * H, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->head_slot, slot.data(), sizeof(int32_t) * c->D, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = launch_head_split(c->indptr, c->indices, c->values, c->N, c->head_slot, (int32_t)H, cnt,
+                          work, c->r_indptr, c->r_indices, c->r_values, c->xh, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  dfree(c, cnt, sizeof(int64_t) * c->N);
+  dfree(c, work, sizeof(int64_t) * nscan);
+  if (e != hipSuccess) return device_fail(c, "head split", e);
+  const int64_t launches = ((c->N + rows - 1) / rows) * ((k_pad / kChunk + chunks - 1) / chunks);
+  c->head_ev.assign(2 * launches, nullptr);
+  for (hipEvent_t &x : c->head_ev) {
+    e = hipEventCreate(&x);
+    if (e != hipSuccess) return device_fail(c, "hipEventCreate", e);
+  }
+  c->head_H = (int32_t)H;
+  c->k_pad = k_pad;
+  c->head_rows = rows;
+  c->head_chunks = chunks;
   return SKM_OK;
 }
 
@@ -244,6 +340,16 @@ ScoreArgs base_args(skm_ctx *c) {
   a.values = c->values;
   a.xl1 = c->xl1;
   a.n_rows = c->N;
+  a.sc_indptr = c->indptr;
+  a.sc_indices = c->indices;
+  a.sc_values = c->values;
+  a.hs = nullptr;
+  a.hs_ld = 0;
+  a.row0 = 0;
+  a.nb = c->N;
+  a.c_first = 0;
+  a.c_count = (int32_t)((c->k + kChunk - 1) / kChunk);
+  a.head_H = 0;
   a.tile = c->tile;
   a.D = c->D;
   a.k = c->k;
@@ -434,6 +540,12 @@ hipError_t launch_new_rows(skm_ctx *c, const NewRows &b, int64_t n, hipStream_t 
   sa.values = b.values;
   sa.xl1 = b.xl1;
   sa.n_rows = n;
+  sa.sc_indptr = b.indptr;
+  sa.sc_indices = b.indices;
+  sa.sc_values = b.values;
+  sa.nb = n;
+  sa.c_first = 0;
+  sa.c_count = (int32_t)((c->k + kChunk - 1) / kChunk);
   sa.a_out = b.a;
   sa.lo_out = b.lo;
   sa.hi_out = b.hi;
@@ -464,6 +576,8 @@ void skm_config_default(skm_config *cfg) {
   if (!cfg) return;
   std::memset(cfg, 0, sizeof(*cfg));
   cfg->precision = SKM_FP32;
+  cfg->head_max_terms = 4096;
+  cfg->head_min_df = 1.0 / 128.0;
   cfg->n_lambda = 4;
   cfg->lambda[0] = 0.1;
   cfg->lambda[1] = 0.25;
@@ -486,6 +600,8 @@ void skm_destroy(skm_ctx *c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (void *p : c->allocations) (void)hipFree(p);
   for (hipEvent_t &e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t &e : c->head_ev)
     if (e) (void)hipEventDestroy(e);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   (void)hipGetLastError();
@@ -601,7 +717,7 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
   A_(c->flag_L, N);
   A_(c->flag_mode, N);
   A_(c->counters, 8);
-  A_(c->stat, 8);
+  A_(c->stat, 16);
   A_(c->hist, c->nblk * k);
   A_(c->counts, k);
   A_(c->offsets, k + 1);
@@ -668,6 +784,7 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
       if (e != hipSuccess) return cleanup(device_fail(c, "init centroids", e));
     }
   }
+  if ((st = setup_head(c)) != SKM_OK) return cleanup(st);
   if ((st = rebuild_tiles(c, nullptr)) != SKM_OK) return cleanup(st);
   if ((c->cfg.flags & SKM_INDEX) && (st = build_index(c)) != SKM_OK) return cleanup(st);
   e = hipStreamSynchronize(s);
@@ -705,7 +822,7 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
     a.prev_hi = c->hi_prev;
   }
   HIP_TRY(c, launch_fill_i32(c->counters, 0, 8, s));
-  HIP_TRY(c, launch_fill_i32(reinterpret_cast<int32_t *>(c->stat), 0, 16, s));
+  HIP_TRY(c, launch_fill_i32(reinterpret_cast<int32_t *>(c->stat), 0, 32, s));
   const bool use_index = (c->cfg.flags & SKM_INDEX) && c->have_prev && c->index_ready &&
                          (c->cfg.index_min_changed <= 0 || c->last_changed > c->cfg.index_min_changed);
   if (use_index) {
@@ -724,7 +841,45 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
     c->idx_eligible = n_rows_idx;
   }
   HIP_TRY(c, hipEventRecord(c->ev[5], s));
-  HIP_TRY(c, launch_score(a, c->part, c->n_cu, c->prec, s));
+  const bool head = c->head_H > 0 && !ncc;
+  if (head) {
+    // batches of rows: head product on the matrix cores, then the sparse
+    // kernel adds the remaining terms to it; one merge over all rows at the end
+    a.sc_indptr = c->r_indptr;
+    a.sc_indices = c->r_indices;
+    a.sc_values = c->r_values;
+    a.hs = c->hs;
+    a.hs_ld = c->k_pad;
+    a.head_H = c->head_H;
+    // Batches are large (up to a million rows) so that the sparse kernel still
+    // sweeps each chunk of codes over many rows while its term rows are cached.
+    const int32_t nch = (int32_t)((c->k + kChunk - 1) / kChunk);
+    a.hs_ld = (int64_t)c->head_chunks * kChunk;
+    size_t ev = 0;
+    for (int64_t r0 = 0; r0 < c->N; r0 += c->head_rows) {
+      const int64_t nb = std::min<int64_t>(c->head_rows, c->N - r0);
+      for (int32_t g0 = 0; g0 < nch; g0 += c->head_chunks) {
+        const int32_t gc = std::min<int32_t>(c->head_chunks, nch - g0);
+        HIP_TRY(c, hipEventRecord(c->head_ev[ev], s));
+        HIP_TRY(c, launch_head_gemm(c->xh, c->head_H, r0, nb, c->ch_head, (int64_t)g0 * kChunk,
+                                    (int64_t)gc * kChunk, c->hs, a.hs_ld, s));
+        HIP_TRY(c, hipEventRecord(c->head_ev[ev + 1], s));
+        ev += 2;
+        a.row0 = r0;
+        a.nb = nb;
+        a.c_first = g0;
+        a.c_count = gc;
+        HIP_TRY(c, launch_score_part(a, c->part, c->n_cu, c->prec, s));
+      }
+    }
+    a.row0 = 0;
+    a.nb = c->N;
+    a.c_first = 0;
+    a.c_count = nch;
+    HIP_TRY(c, launch_finalize(a, c->part, s));
+  } else {
+    HIP_TRY(c, launch_score(a, c->part, c->n_cu, c->prec, s));
+  }
   HIP_TRY(c, hipEventRecord(c->ev[1], s));
   if (!a.no_exact) {
     ExactArgs x{a, c->part, c->master, c->D, exact_waves()};
@@ -733,7 +888,7 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
   HIP_TRY(c, hipEventRecord(c->ev[2], s));
   if (c->have_prev) HIP_TRY(c, launch_count_moved(c->a, c->a_prev, c->N, c->stat + 4, s));
   int32_t cnt[8];
-  unsigned long long stv[8];
+  unsigned long long stv[16];
   HIP_TRY(c, hipMemcpyAsync(cnt, c->counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipMemcpyAsync(stv, c->stat, sizeof(stv), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
@@ -766,6 +921,16 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
     st_out->ms_score = elapsed(c->ev[5], c->ev[1]);
     st_out->ms_exact = elapsed(c->ev[1], c->ev[2]);
     st_out->ms_index = use_index ? elapsed(c->ev[6], c->ev[7]) : 0.f;
+    st_out->head_terms = head ? c->head_H : 0;
+    st_out->score_launches = 1;
+    st_out->sparse_products = (double)stv[3];
+    if (head) {
+      float ms = 0.f;
+      for (size_t i = 0; i + 1 < c->head_ev.size(); i += 2) ms += elapsed(c->head_ev[i], c->head_ev[i + 1]);
+      st_out->ms_head = ms;
+      st_out->score_launches = (int32_t)(c->head_ev.size() / 2);
+      st_out->sparse_products = (double)stv[8];
+    }
     st_out->objective_assign = st_out->objective_update = st_out->max_shift_sq = -1.0;
   }
   return SKM_OK;
@@ -1012,13 +1177,49 @@ skm_status skm_score_dense(skm_ctx *c, const skm_csr *docs, float *out) {
     return st;
   }
   hipError_t e = launch_score_dense(r.indptr, r.indices, r.values, n, c->tile, c->D, c->k, c->scale,
-                                    tail_view(c, 0), c->prec, d_out, c->stream);
+                                    tail_view(c, 0), c->prec, nullptr, 0, d_out, c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(out, d_out, sizeof(float) * n * c->k, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   release();
   if (e != hipSuccess) return device_fail(c, "score_dense", e);
   return SKM_OK;
+}
+
+int32_t skm_head_terms(const skm_ctx *c) { return c ? c->head_H : 0; }
+
+skm_status skm_score_head(skm_ctx *c, int64_t row0, int64_t n_rows, float *out) {
+  ST_TRY(check_ctx(c));
+  if (!out) return fail(SKM_E_INVALID, "out is NULL");
+  if (c->head_H <= 0) return fail(SKM_E_STATE, "this context scores no head terms");
+  if (row0 < 0 || n_rows < 0 || row0 + n_rows > c->N ||
+      n_rows * c->k_pad > c->head_rows * c->head_chunks * kChunk)
+    return fail(SKM_E_INVALID, "row range outside the context or larger than one head batch");
+  if (n_rows == 0) return SKM_OK;
+  float *d_out = nullptr;
+  if (hipMalloc(&d_out, sizeof(float) * n_rows * c->k) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SKM_E_NOMEM, "temporary device allocation failed");
+  }
+  // all centroid columns of these rows at once (the batch buffer holds them)
+  hipError_t e = launch_head_gemm(c->xh, c->head_H, row0, n_rows, c->ch_head, 0, c->k_pad, c->hs,
+                                  c->k_pad, c->stream);
+  if (e == hipSuccess)
+    e = launch_score_dense(c->r_indptr + row0, c->r_indices, c->r_values, n_rows, c->tile, c->D,
+                           c->k, c->scale, tail_view(c, 0), c->prec, c->hs, c->k_pad, d_out,
+                           c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, d_out, sizeof(float) * n_rows * c->k, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(d_out);
+  if (e != hipSuccess) return device_fail(c, "score_head", e);
+  return SKM_OK;
+}
+
+double skm_error_bound_head(const skm_ctx *c, double s, int64_t nnz, double l1) {
+  if (!c || c->head_H <= 0) return -1.0;
+  return bound_kappa_head(nnz, c->head_H, c->uq) * s + bound_abs(nnz, l1, c->abs_coef) +
+         bound_abs_head(c->head_H, l1, c->abs_coef);
 }
 
 double skm_error_bound(const skm_ctx *c, double s, int64_t nnz, double l1) {

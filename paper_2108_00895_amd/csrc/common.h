@@ -167,6 +167,28 @@ __host__ __device__ inline double bound_kappa(int64_t n, double uq) {
   return k * (1.0 + 0x1p-20) + 0x1p-60;
 }
 
+// The same bound when the first part of the score came from the head product
+// (kernels_head.hip): H head terms with the row values rounded to BF16 (unit
+// 2^-8) and summed on the matrix cores, each of whose accumulation steps is
+// counted as two roundings; the sum then joins the sparse path's chain.  Every
+// product sees at most 2n + 2H + 4 roundings, and its inputs carry the
+// combined unit u' = u_x + u_q + u_x u_q.
+__host__ __device__ inline double bound_kappa_head(int64_t n, int64_t H, double uq) {
+  const double u = 0x1p-24, ux = 0x1p-8;
+  const double up = ux + uq + ux * uq;
+  double nn = 2.0 * (double)(n > 0 ? n : 1) + 2.0 * (double)H + 4.0;
+  double g = nn * u / (1.0 - nn * u);
+  double k = (g + up / (1.0 - up)) / (1.0 - g);
+  return k * (1.0 + 0x1p-20) + 0x1p-60;
+}
+
+// Absolute part for head scores: the encoding term grows with the rounded row
+// values (|x^| <= x (1 + 2^-8)), and values or partial sums below 2^-126 that
+// the matrix cores flush cost at most 2^-126 per head step.
+__host__ __device__ inline double bound_abs_head(int64_t H, double l1, double abs_coef) {
+  return abs_coef * l1 * 0x1p-7 + (double)H * 0x1p-120;
+}
+
 __host__ __device__ inline double bound_abs(int64_t n, double l1, double abs_coef) {
   return abs_coef * l1 + (double)(n > 0 ? n : 1) * 0x1p-140;
 }

@@ -30,6 +30,19 @@ struct ScoreArgs {
   const float *values;
   const double *xl1;          // per-row L1 norm (FP8 absolute error term)
   int64_t n_rows;
+  // rows the scoring kernel reads: the full rows, or only their terms outside
+  // the dense head when head scores are given
+  const int64_t *sc_indptr;
+  const int32_t *sc_indices;
+  const float *sc_values;
+  // head scores (kernels_head.hip) of rows [row0, row0 + nb) and chunks
+  // [c_first, c_first + c_count): hs[(row - row0) * hs_ld + column - 512 c_first],
+  // or nullptr
+  const float *hs;
+  int64_t hs_ld;
+  int64_t row0, nb;           // rows of this scoring launch
+  int32_t c_first, c_count;   // 512-centroid chunks of this launch (items = c_count x nb)
+  int32_t head_H;             // head terms in the partial scores' bound (0: none)
   // scoring copy, chunk-blocked term-major (see tile_index)
   const uint8_t *tile;
   int64_t D;
@@ -62,7 +75,8 @@ struct ScoreArgs {
   double *flag_L;
   uint8_t *flag_mode;         // 0 dense all, 1 NCC, 2 candidate list
   int32_t *counters;          // [0] flagged rows, [1] band overflows
-  unsigned long long *stat;   // [0] centroids scored, [1] NCC rows, [2] index rows
+  unsigned long long *stat;   // [0] centroids scored, [1] NCC rows, [2] index rows,
+                              // [3] products, [8] products of the sparse pass (head on)
 };
 
 // Top two of one row against one 512-centroid chunk.
@@ -237,6 +251,20 @@ struct skm_ctx {
   float ms_index_build = 0.f;
   int64_t idx_eligible = 0;
   int server_attached = 0;     // a request server reads this context
+  // dense head on the matrix cores (kernels_head.hip); head_H = 0: off
+  int32_t head_H = 0;
+  int32_t k_pad = 0;             // head-code rows (k rounded up to 512)
+  int64_t head_rows = 0;         // rows per head batch
+  int32_t head_chunks = 0;       // 512-centroid chunks per head batch
+  std::vector<hipEvent_t> head_ev;  // pairs around the head GEMM launches of one step
+  int32_t *head_terms = nullptr; // [H] term ids, ascending
+  int32_t *head_slot = nullptr;  // [D] slot of a head term, -1 otherwise
+  uint16_t *xh = nullptr;        // [N][H] BF16 head values of the rows
+  uint16_t *ch_head = nullptr;   // [k_pad][H] BF16 head codes of the centroids
+  float *hs = nullptr;           // [head_rows][k_pad] head scores of one batch
+  int64_t *r_indptr = nullptr;   // remainder CSR: the rows' non-head terms
+  int32_t *r_indices = nullptr;
+  float *r_values = nullptr;
   // segmented member sums of large clusters
   int4 *tasks = nullptr;         // [task cap]
   int64_t *task_r0 = nullptr;    // [task cap]
@@ -264,11 +292,15 @@ namespace skm {
 // n_cu: compute units of the device; the grid holds as many workgroups as fit
 // on them at once.
 hipError_t launch_score(const ScoreArgs &a, Partial *part, int n_cu, int prec, hipStream_t s);
+// The two halves of launch_score: partials of rows [a.row0, a.row0 + a.nb),
+// then the merge and certificate of all a.n_rows rows.
+hipError_t launch_score_part(const ScoreArgs &a, Partial *part, int n_cu, int prec, hipStream_t s);
+hipError_t launch_finalize(const ScoreArgs &a, const Partial *part, hipStream_t s);
 hipError_t launch_exact(const ExactArgs &a, int prec, hipStream_t s);
 hipError_t launch_score_dense(const int64_t *indptr, const int32_t *indices, const float *values,
                               int64_t n_rows, const uint8_t *tile, int64_t D, int32_t k,
-                              const float *scale, const TailView &tv, int prec, float *out,
-                              hipStream_t s);
+                              const float *scale, const TailView &tv, int prec, const float *hs,
+                              int64_t hs_ld, float *out, hipStream_t s);
 hipError_t launch_exact_scores(const int64_t *indptr, const int32_t *indices, const float *values,
                                int64_t n_rows, const int32_t *a, const double *master, int64_t D,
                                double *out, hipStream_t s);
@@ -332,5 +364,21 @@ hipError_t launch_renorm(const double *S, const int32_t *counts, const int32_t *
                          hipStream_t s);
 hipError_t launch_reduce_stats(const uint8_t *changed, const double *snorm, const double *shift,
                                const double *dot_old, int32_t k, double *out, hipStream_t s);
+
+// kernels_head.hip
+hipError_t launch_df(const int32_t *indices, int64_t nnz, uint32_t *df, int64_t D, hipStream_t s);
+int64_t head_split_scan_blocks(int64_t n_rows);
+hipError_t launch_head_split(const int64_t *indptr, const int32_t *indices, const float *values,
+                             int64_t n_rows, const int32_t *slot, int32_t H, int64_t *cnt,
+                             int64_t *scan_work, int64_t *r_indptr, int32_t *r_indices,
+                             float *r_values, uint16_t *xh, hipStream_t s);
+hipError_t launch_head_codes(const uint8_t *tile, int64_t D, int32_t k, int prec,
+                             const int32_t *terms, int32_t H, int32_t k_pad, uint16_t *ch,
+                             hipStream_t s);
+// hs[r][j] = sum_h xh[row0 + r][h] * ch[col0 + j][h], r < nb, j < ncols
+// (ncols a multiple of 256, col0 + ncols <= rows of ch).
+hipError_t launch_head_gemm(const uint16_t *xh, int32_t H, int64_t row0, int64_t nb,
+                            const uint16_t *ch, int64_t col0, int64_t ncols, float *hs,
+                            int64_t ldh, hipStream_t s);
 
 }  // namespace skm

@@ -270,6 +270,20 @@ __device__ inline RowPlan plan_row(const ScoreArgs &a, int64_t row, bool allow_n
   return p;
 }
 
+// Certified bound |s^ - s| <= kap * s^ + A of the scores behind the chunk
+// partials (head product plus sparse terms when head scores were used).
+__device__ inline void part_bound(const ScoreArgs &a, int64_t row, int64_t n, double &kap,
+                                  double &A) {
+  const double l1 = a.xl1[row];
+  if (a.head_H > 0) {
+    kap = bound_kappa_head(n, a.head_H, a.uq);
+    A = bound_abs(n, l1, a.abs_coef) + bound_abs_head(a.head_H, l1, a.abs_coef);
+  } else {
+    kap = bound_kappa(n, a.uq);
+    A = bound_abs(n, l1, a.abs_coef);
+  }
+}
+
 // Per-(row, chunk) top-two of the low-precision scores.  The grid is
 // persistent and walks items chunk-major (item = chunk * n_rows + row), so all
 // wavefronts sweep the same 512-centroid slice of the codes at the same time
@@ -285,15 +299,30 @@ __global__ __launch_bounds__(256) void k_score_part(ScoreArgs a, Partial *__rest
   zero_lacc(lacc);
   const int64_t stride = (int64_t)gridDim.x * 4;
   for (int64_t it = (int64_t)blockIdx.x * 4 + wave; it < n_items; it += stride) {
-    const int64_t c = uniform64(it / a.n_rows);
-    const int64_t row = uniform64(it - c * a.n_rows);
+    const int64_t ci = uniform64(it / a.nb);
+    const int64_t row = uniform64(a.row0 + (it - ci * a.nb));
+    const int64_t c = a.c_first + ci;
     const RowPlan pl = plan_row(a, row, true);
     const int64_t c0 = c * kChunk;
     if (c0 >= pl.ncols) continue;
-    const int64_t b = uniform64(a.indptr[row]);
-    const int64_t e = uniform64(a.indptr[row + 1]);
+    const int64_t b = uniform64(a.sc_indptr[row]);
+    const int64_t e = uniform64(a.sc_indptr[row + 1]);
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    score_chunk<P>(b, e, a.indices, a.values, pl.tile, a.D, c0, acc, *pl.tv, lacc);
+    if (a.hs) {
+      // start from the head scores of these 8 columns (kernels_head.hip)
+      const float4 *h = reinterpret_cast<const float4 *>(a.hs + (row - a.row0) * a.hs_ld +
+                                                         ci * kChunk + lane * kColsPerLane);
+      const float4 h0 = h[0], h1 = h[1];
+      acc[0] = h0.x;
+      acc[1] = h0.y;
+      acc[2] = h0.z;
+      acc[3] = h0.w;
+      acc[4] = h1.x;
+      acc[5] = h1.y;
+      acc[6] = h1.z;
+      acc[7] = h1.w;
+    }
+    score_chunk<P>(b, e, a.sc_indices, a.sc_values, pl.tile, a.D, c0, acc, *pl.tv, lacc);
     float b1 = -INFINITY, b2 = -INFINITY;
     int j1 = 0x7FFFFFFF;
 #pragma unroll
@@ -322,9 +351,9 @@ __global__ __launch_bounds__(256) void k_score_part(ScoreArgs a, Partial *__rest
 // bound; otherwise the row goes to the exact tier with L = the certified lower
 // bound of the maximum.  One thread per row.
 __global__ __launch_bounds__(256) void k_finalize(ScoreArgs a, const Partial *__restrict__ part) {
-  __shared__ unsigned long long sh[3][256];
+  __shared__ unsigned long long sh[4][256];
   const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  unsigned long long n_cols = 0, n_prod = 0, n_ncc = 0;
+  unsigned long long n_cols = 0, n_prod = 0, n_ncc = 0, n_sp = 0;
   const RowPlan pl = row < a.n_rows ? plan_row(a, row, true) : RowPlan{};
   if (row < a.n_rows && !pl.done) {
     const int64_t b = a.indptr[row], e = a.indptr[row + 1];
@@ -342,8 +371,8 @@ __global__ __launch_bounds__(256) void k_finalize(ScoreArgs a, const Partial *__
       }
     }
     const int64_t n = e - b;
-    const double kap = bound_kappa(n, a.uq);
-    const double A = bound_abs(n, a.xl1[row], a.abs_coef);
+    double kap, A;
+    part_bound(a, row, n, kap, A);
     auto lo_of = [&](float s) { return s == -INFINITY ? -INFINITY : (double)s - (kap * (double)s + A); };
     auto hi_of = [&](float s) { return s == -INFINITY ? -INFINITY : (double)s + (kap * (double)s + A); };
     int win;
@@ -380,6 +409,9 @@ __global__ __launch_bounds__(256) void k_finalize(ScoreArgs a, const Partial *__
     n_cols = (unsigned long long)pl.ncols;
     n_prod = (unsigned long long)pl.ncols * (unsigned long long)n;
     n_ncc = pl.ncc ? 1ull : 0ull;
+    if (a.head_H > 0)
+      n_sp = (unsigned long long)pl.ncols *
+             (unsigned long long)(a.sc_indptr[row + 1] - a.sc_indptr[row]);
     if (certain || a.no_exact) {
       a.a_out[row] = win;
       a.lo_out[row] = wlo;
@@ -394,12 +426,14 @@ __global__ __launch_bounds__(256) void k_finalize(ScoreArgs a, const Partial *__
   sh[0][threadIdx.x] = n_cols;
   sh[1][threadIdx.x] = n_prod;
   sh[2][threadIdx.x] = n_ncc;
+  sh[3][threadIdx.x] = n_sp;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) {
       sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
       sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
       sh[2][threadIdx.x] += sh[2][threadIdx.x + w];
+      sh[3][threadIdx.x] += sh[3][threadIdx.x + w];
     }
     __syncthreads();
   }
@@ -407,6 +441,7 @@ __global__ __launch_bounds__(256) void k_finalize(ScoreArgs a, const Partial *__
     atomicAdd(&a.stat[0], sh[0][0]);
     atomicAdd(&a.stat[3], sh[1][0]);
     if (sh[2][0]) atomicAdd(&a.stat[1], sh[2][0]);
+    if (a.head_H > 0) atomicAdd(&a.stat[8], sh[3][0]);   // products of the sparse pass
   }
 }
 
@@ -449,16 +484,22 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs x) {
       pl.ncc = true;
       pl.ap = a.a_prev[row];
     }
+    // bound of the rescoring below (all terms, sparse path)
     const double kap = bound_kappa(n, a.uq);
     const double A = bound_abs(n, a.xl1[row], a.abs_coef);
-    auto hi_of = [&](float s) { return s == -INFINITY ? -INFINITY : (double)s + (kap * (double)s + A); };
+    // bound of the partials of the scoring pass
+    double pkap, pA;
+    part_bound(a, row, n, pkap, pA);
+    auto phi_of = [&](float s) {
+      return s == -INFINITY ? -INFINITY : (double)s + (pkap * (double)s + pA);
+    };
     int nb = 0;
     for (int64_t c0 = 0; c0 < pl.ncols; c0 += kChunk) {
       // A chunk whose second-best upper bound is below L can only contribute
       // its best centroid: skip rescoring it.
       const Partial p = x.part[(c0 / kChunk) * a.n_rows + row];
-      if (hi_of(p.b2) < L) {
-        if (hi_of(p.b1) >= L) {
+      if (phi_of(p.b2) < L) {
+        if (phi_of(p.b1) >= L) {
           if (lane == 0 && nb < kBandCap) band[nb] = p.j1;
           nb += 1;
         }
@@ -538,7 +579,8 @@ template <int P>
 __global__ __launch_bounds__(256) void k_score_dense(const int64_t *indptr, const int32_t *indices,
                                                      const float *values, int64_t n_rows,
                                                      const uint8_t *tile, int64_t D, int32_t k,
-                                                     const float *scale, TailView tv, float *out) {
+                                                     const float *scale, TailView tv,
+                                                     const float *hs, int64_t hs_ld, float *out) {
   __shared__ float lacc_all[4][kChunk];
   const int wave = uniform32(threadIdx.x >> 6);
   const int64_t row = (int64_t)blockIdx.x * 4 + wave;
@@ -550,6 +592,10 @@ __global__ __launch_bounds__(256) void k_score_dense(const int64_t *indptr, cons
   const int64_t e = uniform64(indptr[row + 1]);
   for (int64_t c0 = 0; c0 < k; c0 += kChunk) {
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (hs) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) acc[c] = hs[row * hs_ld + c0 + lane * kColsPerLane + c];
+    }
     score_chunk<P>(b, e, indices, values, tile, D, c0, acc, tv, lacc);
     for (int c = 0; c < 8; ++c) {
       const int64_t col = c0 + lane * kColsPerLane + c;
@@ -577,7 +623,7 @@ __global__ __launch_bounds__(256) void k_exact_scores(const int64_t *indptr, con
 }
 
 template <int P>
-hipError_t launch_score_t(const ScoreArgs &a, Partial *part, int n_cu, hipStream_t s) {
+hipError_t launch_score_part_t(const ScoreArgs &a, Partial *part, int n_cu, hipStream_t s) {
   if (a.n_rows <= 0) return hipSuccess;
   // Workgroups resident per CU at this kernel's register and LDS use: the
   // persistent grid is exactly one wave of them, so no workgroup starts late
@@ -590,15 +636,11 @@ hipError_t launch_score_t(const ScoreArgs &a, Partial *part, int n_cu, hipStream
     (void)hipGetLastError();
     return n;
   }();
-  const int64_t nchunks = (a.k + kChunk - 1) / kChunk;
-  const int64_t n_items = nchunks * a.n_rows;
+  const int64_t n_items = (int64_t)a.c_count * a.nb;
   const int64_t need = (n_items + 3) / 4;
+  if (need <= 0) return hipSuccess;
   const int g = (int)std::min<int64_t>((int64_t)n_cu * per_cu, need);
   hipLaunchKernelGGL(k_score_part<P>, dim3((unsigned)g), dim3(256), 0, s, a, part, n_items);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_finalize, dim3((unsigned)((a.n_rows + 255) / 256)), dim3(256), 0, s, a,
-                     (const Partial *)part);
   return hipGetLastError();
 }
 
@@ -610,13 +652,25 @@ hipError_t launch_exact_t(const ExactArgs &x, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_score(const ScoreArgs &a, Partial *part, int n_cu, int prec, hipStream_t s) {
+hipError_t launch_score_part(const ScoreArgs &a, Partial *part, int n_cu, int prec, hipStream_t s) {
   switch (prec) {
-    case SKM_FP32: return launch_score_t<SKM_FP32>(a, part, n_cu, s);
-    case SKM_BF16: return launch_score_t<SKM_BF16>(a, part, n_cu, s);
-    case SKM_FP8_E4M3: return launch_score_t<SKM_FP8_E4M3>(a, part, n_cu, s);
+    case SKM_FP32: return launch_score_part_t<SKM_FP32>(a, part, n_cu, s);
+    case SKM_BF16: return launch_score_part_t<SKM_BF16>(a, part, n_cu, s);
+    case SKM_FP8_E4M3: return launch_score_part_t<SKM_FP8_E4M3>(a, part, n_cu, s);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_finalize(const ScoreArgs &a, const Partial *part, hipStream_t s) {
+  if (a.n_rows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)((a.n_rows + 255) / 256)), dim3(256), 0, s, a, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_score(const ScoreArgs &a, Partial *part, int n_cu, int prec, hipStream_t s) {
+  hipError_t e = launch_score_part(a, part, n_cu, prec, s);
+  if (e != hipSuccess) return e;
+  return launch_finalize(a, part, s);
 }
 
 hipError_t launch_exact(const ExactArgs &x, int prec, hipStream_t s) {
@@ -630,22 +684,22 @@ hipError_t launch_exact(const ExactArgs &x, int prec, hipStream_t s) {
 
 hipError_t launch_score_dense(const int64_t *indptr, const int32_t *indices, const float *values,
                               int64_t n_rows, const uint8_t *tile, int64_t D, int32_t k,
-                              const float *scale, const TailView &tv, int prec, float *out,
-                              hipStream_t s) {
+                              const float *scale, const TailView &tv, int prec, const float *hs,
+                              int64_t hs_ld, float *out, hipStream_t s) {
   if (n_rows <= 0) return hipSuccess;
   const dim3 g((unsigned)((n_rows + 3) / 4)), blk(256);
   switch (prec) {
     case SKM_FP32:
       hipLaunchKernelGGL(k_score_dense<SKM_FP32>, g, blk, 0, s, indptr, indices, values, n_rows, tile,
-                         D, k, nullptr, tv, out);
+                         D, k, nullptr, tv, hs, hs_ld, out);
       break;
     case SKM_BF16:
       hipLaunchKernelGGL(k_score_dense<SKM_BF16>, g, blk, 0, s, indptr, indices, values, n_rows, tile,
-                         D, k, nullptr, tv, out);
+                         D, k, nullptr, tv, hs, hs_ld, out);
       break;
     case SKM_FP8_E4M3:
       hipLaunchKernelGGL(k_score_dense<SKM_FP8_E4M3>, g, blk, 0, s, indptr, indices, values, n_rows,
-                         tile, D, k, scale, tv, out);
+                         tile, D, k, scale, tv, hs, hs_ld, out);
       break;
     default: return hipErrorInvalidValue;
   }

@@ -27,7 +27,8 @@ CODE_BYTES = {FP32: 4, BF16: 2, FP8_E4M3: 1}
 EXPORTED = [
     "skm_config_default", "skm_init", "skm_assign", "skm_update", "skm_iterate",
     "skm_assign_new", "skm_get_assignments", "skm_get_centroids", "skm_set_centroids",
-    "skm_get_tile", "skm_get_changed", "skm_score_dense", "skm_error_bound", "skm_get_index",
+    "skm_get_tile", "skm_get_changed", "skm_score_dense", "skm_error_bound", "skm_head_terms",
+    "skm_score_head", "skm_error_bound_head", "skm_get_index",
     "skm_index_query", "skm_server_config_default", "skm_server_start", "skm_server_submit",
     "skm_server_wait", "skm_server_get_stats", "skm_server_stop",
     "skm_hbm_bytes", "skm_last_error", "skm_destroy",
@@ -53,7 +54,8 @@ class Config(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("min_moved_frac", ctypes.c_double),
                 ("max_shift_sq", ctypes.c_double), ("init_rows", ctypes.c_void_p),
                 ("init_centroids", ctypes.c_void_p), ("hbm_budget_bytes", ctypes.c_size_t),
-                ("stream", ctypes.c_void_p), ("validate", ctypes.c_int32)]
+                ("stream", ctypes.c_void_p), ("validate", ctypes.c_int32),
+                ("head_max_terms", ctypes.c_int32), ("head_min_df", ctypes.c_double)]
 
 
 class IterStats(ctypes.Structure):
@@ -67,7 +69,9 @@ class IterStats(ctypes.Structure):
                 ("objective_assign", ctypes.c_double), ("objective_update", ctypes.c_double),
                 ("max_shift_sq", ctypes.c_double), ("ms_assign", ctypes.c_float),
                 ("ms_score", ctypes.c_float), ("ms_exact", ctypes.c_float), ("ms_update", ctypes.c_float),
-                ("ms_index", ctypes.c_float)]
+                ("ms_index", ctypes.c_float), ("head_terms", ctypes.c_int32),
+                ("ms_head", ctypes.c_float), ("score_launches", ctypes.c_int32),
+                ("sparse_products", ctypes.c_double)]
 
     def asdict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -136,6 +140,12 @@ def load():
     lib.skm_score_dense.restype = st
     lib.skm_error_bound.argtypes = [vp, ctypes.c_double, i64, ctypes.c_double]
     lib.skm_error_bound.restype = ctypes.c_double
+    lib.skm_head_terms.argtypes = [vp]
+    lib.skm_head_terms.restype = ctypes.c_int32
+    lib.skm_score_head.argtypes = [vp, i64, i64, vp]
+    lib.skm_score_head.restype = st
+    lib.skm_error_bound_head.argtypes = [vp, ctypes.c_double, i64, ctypes.c_double]
+    lib.skm_error_bound_head.restype = ctypes.c_double
     lib.skm_get_index.argtypes = [vp, i32, vp, vp, P(i64)]
     lib.skm_get_index.restype = st
     lib.skm_index_query.argtypes = [vp, P(Csr), i32, vp, vp, i64]
@@ -206,6 +216,8 @@ class Options:
     max_shift_sq: float = 1e-4
     hbm_budget_bytes: int = 0
     validate: bool = True
+    head_max_terms: int | None = None   # None: the library default (4096); 0: off
+    head_min_df: float | None = None    # None: the library default (1/128)
 
 
 class Context:
@@ -231,6 +243,10 @@ class Context:
         cfg.max_shift_sq = o.max_shift_sq
         cfg.hbm_budget_bytes = o.hbm_budget_bytes
         cfg.validate = 1 if o.validate else 0
+        if o.head_max_terms is not None:
+            cfg.head_max_terms = o.head_max_terms
+        if o.head_min_df is not None:
+            cfg.head_min_df = o.head_min_df
         keep = []
         if init_rows is not None:
             r = np.ascontiguousarray(init_rows, dtype=np.int32)
@@ -344,6 +360,19 @@ class Context:
 
     def error_bound(self, s, nnz, l1):
         return load().skm_error_bound(self._h, float(s), int(nnz), float(l1))
+
+    def head_terms(self):
+        """Terms scored on the matrix cores (0 = head off)."""
+        return int(load().skm_head_terms(self._h))
+
+    def score_head(self, row0, n_rows):
+        """Head-path low-precision scores of rows [row0, row0 + n_rows)."""
+        out = np.empty((n_rows, self.k), dtype=np.float32)
+        _check(load().skm_score_head(self._h, int(row0), int(n_rows), out.ctypes.data))
+        return out
+
+    def error_bound_head(self, s, nnz, l1):
+        return load().skm_error_bound_head(self._h, float(s), int(nnz), float(l1))
 
     def index_level(self, level):
         lib = load()

@@ -1,0 +1,143 @@
+"""The dense head on the matrix cores, through the C ABI (needs an MI355X).
+
+The most frequent terms are scored as a BF16 block on the matrix cores and
+the rest on the sparse path.  Checked against the oracle:
+  * every head-path score of a (row, centroid) pair lies within the certified
+    head bound of the FP64 score (oracle centroids fed in);
+  * assignments with the head forced on equal the oracle's, for the first
+    step, for whole trajectories, and across chunk groups with a ragged last
+    group and a ragged last centroid chunk;
+  * head on and head off give the same assignments;
+  * the head size follows the stated selection rule.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2108_00895_amd import Context
+
+from gpu_common import assert_assign_equal, corpus, say, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mid():
+    csr, c = corpus(3000, 9000, nnz_mean=60.0, nnz_max=400, seed=31)
+    rows = synth.seed_rows(c.n_docs, 700, 5)
+    return csr, c, rows
+
+
+def expected_head(csr, n_rows, max_terms, min_df):
+    """The selection rule, restated: terms in >= max(1, ceil(min_df * N)) rows,
+    count rounded up to 64, capped by max_terms (to 64) and by the terms present."""
+    df = np.bincount(csr[1], minlength=1)
+    thr = max(1.0, math.ceil(min_df * n_rows))
+    n_qual = int(np.count_nonzero(df >= thr))
+    n_pos = int(np.count_nonzero(df > 0))
+    H = min(-(-n_qual // 64) * 64, (max_terms // 64) * 64, (n_pos // 64) * 64)
+    return H if H >= 64 else 0
+
+
+def test_head_selection(mid):
+    csr, c, rows = mid
+    say("case: head selection")
+    for prec, mx, mdf in [("bf16", 4096, 1 / 128), ("bf16", 100, 1 / 128), ("fp8", 4096, 0.05),
+                          ("bf16", 4096, 0.9), ("bf16", 0, 1 / 128), ("fp32", 4096, 1 / 128),
+                          ("bf16", 64, 0.0)]:
+        ctx = Context(csr, c.n_terms, 50, init_rows=rows[:50], precision=prec,
+                      head_max_terms=mx, head_min_df=mdf)
+        want = 0 if prec == "fp32" else expected_head(csr, c.n_docs, mx, mdf)
+        assert ctx.head_terms() == want, (prec, mx, mdf, ctx.head_terms(), want)
+        st = ctx.assign()
+        assert st["head_terms"] == want
+        say(f"  {prec} max {mx} min_df {mdf:.4f}: H = {want}")
+        ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("H", [64, 640])
+def test_head_bound_holds_for_every_pair(prec, H, mid):
+    csr, c, rows = mid
+    say("case: head bound", prec, H)
+    ref = oracle.run(csr, c.n_terms, 300, rows[:300], max_iter=2, stop_rule="fixed")
+    C = ref.C
+    ctx = Context(csr, c.n_terms, 300, init_centroids=C, precision=prec, head_max_terms=H,
+                  head_min_df=0.0)
+    assert ctx.head_terms() == H
+    n = 500
+    Sg = ctx.score_head(0, n).astype(np.float64)
+    Sr = oracle.scores(csr, C, np.arange(n))
+    ip, ix, v = csr
+    nnz = np.diff(ip)[:n]
+    l1 = np.add.reduceat(v.astype(np.float64), ip[:-1])[:n]
+    worst = 0.0
+    for i in range(n):
+        E = np.array([ctx.error_bound_head(s, nnz[i], l1[i]) for s in Sg[i]])
+        worst = max(worst, float(np.max(np.abs(Sg[i] - Sr[i]) / E)))
+    assert worst <= 1.0, worst
+    # the same rows scored in a later batch position agree bit for bit
+    Sg2 = ctx.score_head(100, 50).astype(np.float64)
+    np.testing.assert_array_equal(Sg2, Sg[100:150])
+    say("  max |s^-s|/E =", worst)
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_head_trajectory_equals_oracle(prec, mid):
+    csr, c, rows = mid
+    say("case: head trajectory", prec)
+    ref = oracle.run(csr, c.n_terms, len(rows), rows, max_iter=5, stop_rule="fixed")
+    ctx = Context(to_device(csr), c.n_terms, len(rows), init_rows=rows, precision=prec,
+                  head_max_terms=192, head_min_df=0.0, stop_rule="fixed", max_iter=5)
+    for t, rec in enumerate(ref.records):
+        st = ctx.assign()
+        assert st["head_terms"] == 192
+        n_tie = assert_assign_equal(ctx.assignments(), rec.a, rec.s1, rec.s2, f"{prec} it {t}")
+        assert st["moved"] == rec.moved
+        u = ctx.update()
+        assert abs(u["objective_assign"] - rec.J_A) <= 1e-9 * abs(rec.J_A)
+        assert abs(u["objective_update"] - rec.J_U) <= 1e-9 * abs(rec.J_U)
+        say(f"  it {t}: flagged {st['flagged']} ties {n_tie}")
+    ctx.close()
+
+
+def test_head_on_and_off_give_the_same_assignments(mid):
+    csr, c, rows = mid
+    say("case: head on/off")
+    got = []
+    for mx in [0, 4096]:
+        ctx = Context(csr, c.n_terms, len(rows), init_rows=rows, precision="bf16", ncc=True,
+                      head_max_terms=mx, stop_rule="fixed", max_iter=4)
+        seq = []
+        for _ in range(4):
+            ctx.assign()
+            seq.append(ctx.assignments())
+            ctx.update()
+        got.append(seq)
+        ctx.close()
+    for a0, a1 in zip(*got):
+        np.testing.assert_array_equal(a0, a1)
+
+
+def test_head_chunk_groups_ragged():
+    """k = 5000: ten 512-centroid chunks, scored in head groups of four
+    (4, 4, 2), the last chunk 392 columns wide; 9000 rows (not a multiple of
+    the 256-row GEMM tile).  Several row batches are covered at full size by
+    test_gpu_fullsize.py (2e6 rows in batches of 2^20)."""
+    say("case: head chunk groups")
+    csr, c = corpus(9000, 3000, nnz_mean=40.0, nnz_max=200, seed=41)
+    rows = synth.seed_rows(c.n_docs, 5000, 9)
+    C0 = oracle.seed(csr, c.n_terms, rows)
+    a_ref, s1, s2 = oracle.assign(csr, C0)
+    ctx = Context(to_device(csr), c.n_terms, 5000, init_rows=rows, precision="bf16",
+                  head_max_terms=256, head_min_df=0.0)
+    assert ctx.head_terms() == 256
+    st = ctx.assign()
+    assert st["head_terms"] == 256
+    n_tie = assert_assign_equal(ctx.assignments(), a_ref, s1, s2, "chunk groups")
+    say(f"  flagged {st['flagged']} ties {n_tie}")
+    ctx.close()
