@@ -801,9 +801,11 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
   hipStream_t s = c->stream;
   ScoreArgs a = base_args(c);
   // Sec. 3.1 only pays when a good share of centroids is unchanged: with more
-  // than half changed, building the compacted copy costs more than the
-  // columns it saves, and every row scores the full copy instead.
-  const bool ncc = (c->cfg.flags & SKM_NCC) && c->have_prev && 2 * c->last_changed <= c->k;
+  // than half changed (a quarter when the head product runs, which NCC rows do
+  // not use), building the compacted copy costs more than the columns it
+  // saves, and every row scores the full copy instead.
+  const int64_t ncc_den = c->head_H > 0 ? 4 : 2;
+  const bool ncc = (c->cfg.flags & SKM_NCC) && c->have_prev && ncc_den * c->last_changed <= c->k;
   int32_t n_ch = c->k;
   HIP_TRY(c, hipEventRecord(c->ev[0], s));
   if (ncc) {

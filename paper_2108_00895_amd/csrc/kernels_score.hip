@@ -123,14 +123,17 @@ __device__ inline int32_t uniform32(int32_t v) { return __builtin_amdgcn_readfir
 // non-zero codes in this chunk, lanes over entries, products added into the
 // wave's 512-float LDS accumulator lacc, folded into acc at the end.  The
 // order of the sum differs from the term order; the error bound allows any
-// order (at most two roundings per term plus the final merge).
+// order (at most two roundings per term plus the final merge).  Lanes whose
+// columns all lie at or past nvalid (a ragged or narrow compacted chunk) issue
+// no loads.
 template <int P>
 __device__ inline void score_chunk(int64_t b, int64_t e, const int32_t *__restrict__ indices,
                                    const float *__restrict__ values, const uint8_t *__restrict__ tile,
-                                   int64_t D, int64_t c0, float acc[8], const TailView &tv,
-                                   float *lacc) {
+                                   int64_t D, int64_t c0, int64_t nvalid, float acc[8],
+                                   const TailView &tv, float *lacc) {
   using C = Codes<P>;
   const int lane = lane_id();
+  const bool act = (int64_t)lane * kColsPerLane < nvalid;
   const int64_t cc = c0 / kChunk;
   // chunk slab [D][512] as a buffer resource in scalar registers
   const uint8_t *slab = reinterpret_cast<const uint8_t *>(
@@ -161,18 +164,30 @@ __device__ inline void score_chunk(int64_t b, int64_t e, const int32_t *__restri
         u[v] = __builtin_ctzll(dmask);
         dmask &= dmask - 1;
       }
-      typename C::raw_t r[8];
+      int so[8];
+      float xs[8];
 #pragma unroll
-      for (int v = 0; v < 8; ++v)
-        r[v] = C::load(rs, voff, __builtin_amdgcn_readlane(my_t, u[v]) * rowbytes);
+      for (int v = 0; v < 8; ++v) {
+        so[v] = __builtin_amdgcn_readlane(my_t, u[v]) * rowbytes;
+        xs[v] = readlane_f(my_x, u[v]);
+      }
+      if (act) {
+        typename C::raw_t r[8];
 #pragma unroll
-      for (int v = 0; v < 8; ++v) C::fma8(r[v], readlane_f(my_x, u[v]), acc);
+        for (int v = 0; v < 8; ++v) r[v] = C::load(rs, voff, so[v]);
+#pragma unroll
+        for (int v = 0; v < 8; ++v) C::fma8(r[v], xs[v], acc);
+      }
     }
     while (dmask) {
       const int u = __builtin_ctzll(dmask);
       dmask &= dmask - 1;
-      typename C::raw_t r0 = C::load(rs, voff, __builtin_amdgcn_readlane(my_t, u) * rowbytes);
-      C::fma8(r0, readlane_f(my_x, u), acc);
+      const int so0 = __builtin_amdgcn_readlane(my_t, u) * rowbytes;
+      const float x0 = readlane_f(my_x, u);
+      if (act) {
+        typename C::raw_t r0 = C::load(rs, voff, so0);
+        C::fma8(r0, x0, acc);
+      }
     }
     if (tmask) {
       // All tail terms of the batch at once: lane l owns list [o0, o0 + len)
@@ -322,7 +337,8 @@ __global__ __launch_bounds__(256) void k_score_part(ScoreArgs a, Partial *__rest
       acc[6] = h1.z;
       acc[7] = h1.w;
     }
-    score_chunk<P>(b, e, a.sc_indices, a.sc_values, pl.tile, a.D, c0, acc, *pl.tv, lacc);
+    score_chunk<P>(b, e, a.sc_indices, a.sc_values, pl.tile, a.D, c0, pl.ncols - c0, acc, *pl.tv,
+                   lacc);
     float b1 = -INFINITY, b2 = -INFINITY;
     int j1 = 0x7FFFFFFF;
 #pragma unroll
@@ -506,7 +522,7 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs x) {
         continue;
       }
       float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      score_chunk<P>(b, e, a.indices, a.values, pl.tile, a.D, c0, acc, *pl.tv, lacc);
+      score_chunk<P>(b, e, a.indices, a.values, pl.tile, a.D, c0, pl.ncols - c0, acc, *pl.tv, lacc);
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         const int64_t col = c0 + lane * kColsPerLane + c;
@@ -596,7 +612,7 @@ __global__ __launch_bounds__(256) void k_score_dense(const int64_t *indptr, cons
 #pragma unroll
       for (int c = 0; c < 8; ++c) acc[c] = hs[row * hs_ld + c0 + lane * kColsPerLane + c];
     }
-    score_chunk<P>(b, e, indices, values, tile, D, c0, acc, tv, lacc);
+    score_chunk<P>(b, e, indices, values, tile, D, c0, k - c0, acc, tv, lacc);
     for (int c = 0; c < 8; ++c) {
       const int64_t col = c0 + lane * kColsPerLane + c;
       if (col < k) out[row * k + col] = scale ? acc[c] * scale[col] : acc[c];
