@@ -163,6 +163,21 @@ typedef struct {
                                  the sparse path (all of them when head_terms = 0) */
 } skm_iter_stats;
 
+/* One measured shape of the scoring work (skm_autotune). */
+typedef struct {
+  int32_t head_chunks;        /* 512-centroid chunks per head batch (0 = no head) */
+  int32_t workgroups_per_cu;  /* workgroups per compute unit of the persistent sparse
+                                 scoring grid */
+  int64_t head_rows;          /* rows per head batch (0 = no head) */
+  double ms;                  /* device time of one full scoring pass at this shape */
+} skm_tune_trial;
+
+typedef struct {
+  int32_t n_trials;
+  int32_t best;               /* index of the shape the context now uses */
+  skm_tune_trial trials[16];
+} skm_tune_report;
+
 /* Fills *cfg with defaults: k = 0 (must be set), FP32, no flags, the four
  * thresholds of Sec. 4.1, paper stop rule, max_iter 100, shift 1e-4, head of
  * at most 4096 terms with document frequency >= 1/128. */
@@ -236,6 +251,23 @@ double skm_error_bound(const skm_ctx *c, double s, int64_t nnz, double l1);
  * on the matrix cores; see head_max_terms), 0 when the head is off. */
 int32_t skm_head_terms(const skm_ctx *c);
 
+/* Autotuner: times one full scoring pass (low precision, all centroids, no
+ * exact tier) of the context's own rows for candidate shapes of the work —
+ * the workgroups per CU of the persistent sparse scoring grid around its
+ * occupancy limit, then the head batch shape (rows x 512-centroid chunks
+ * filling the head-score buffer) — and keeps the fastest for the following
+ * assignment steps.  Results are unaffected (the shape only changes the
+ * schedule).  Call it with no assignment pending (before skm_assign or after
+ * skm_update); SKM_E_STATE otherwise.  report (may be NULL) receives every
+ * trial. */
+skm_status skm_autotune(skm_ctx *c, skm_tune_report *report);
+
+/* Applies a shape found by skm_autotune (for instance on another context of
+ * the same workload): workgroups_per_cu, and head_chunks x head_rows when the
+ * context scores a head (they must fit its head-score buffer, else
+ * SKM_E_INVALID; ignored when the head is off).  ms is not read. */
+skm_status skm_set_schedule(skm_ctx *c, const skm_tune_trial *shape);
+
 /* Diagnostic: the low-precision scores of the context's own rows
  * [row0, row0 + n_rows) as an assignment step with the head computes them
  * (head product plus the rows' other terms), before any exact tier:
@@ -283,6 +315,8 @@ typedef struct {
   size_t hbm_budget_bytes;  /* device memory cap for the slots; n_slots shrinks to fit (0 = none) */
   int32_t max_wait_us;      /* a partly filled batch waits at most this long for more rows
                                when no batch is running, default 100 */
+  int32_t use_graphs;       /* 1 = each slot replays its compute pipeline as one captured
+                               HIP graph (default); 0 = launch the kernels one by one */
 } skm_server_config;
 
 typedef struct {

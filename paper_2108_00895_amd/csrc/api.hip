@@ -320,16 +320,11 @@ skm_status setup_head(skm_ctx *c) {
   dfree(c, cnt, sizeof(int64_t) * c->N);
   dfree(c, work, sizeof(int64_t) * nscan);
   if (e != hipSuccess) return device_fail(c, "head split", e);
-  const int64_t launches = ((c->N + rows - 1) / rows) * ((k_pad / kChunk + chunks - 1) / chunks);
-  c->head_ev.assign(2 * launches, nullptr);
-  for (hipEvent_t &x : c->head_ev) {
-    e = hipEventCreate(&x);
-    if (e != hipSuccess) return device_fail(c, "hipEventCreate", e);
-  }
   c->head_H = (int32_t)H;
   c->k_pad = k_pad;
   c->head_rows = rows;
   c->head_chunks = chunks;
+  c->hs_cap = rows * chunks * kChunk;
   return SKM_OK;
 }
 
@@ -340,6 +335,7 @@ ScoreArgs base_args(skm_ctx *c) {
   a.values = c->values;
   a.xl1 = c->xl1;
   a.n_rows = c->N;
+  a.n_dev = nullptr;
   a.sc_indptr = c->indptr;
   a.sc_indices = c->indices;
   a.sc_values = c->values;
@@ -533,8 +529,10 @@ skm_status set_error(skm_status st, const std::string &msg) { return fail(st, ms
 // Exact assignment of rows that are not part of the clustering (no NCC, no
 // index): low-precision scoring with certification, the FP64 exact tier for
 // uncertain rows, and the FP64 score of the chosen centroid.  Enqueues only.
-hipError_t launch_new_rows(skm_ctx *c, const NewRows &b, int64_t n, hipStream_t s) {
+hipError_t launch_new_rows(skm_ctx *c, const NewRows &b, int64_t n, hipStream_t s,
+                           const int64_t *n_dev) {
   ScoreArgs sa = base_args(c);
+  sa.n_dev = n_dev;
   sa.indptr = b.indptr;
   sa.indices = b.indices;
   sa.values = b.values;
@@ -564,7 +562,8 @@ hipError_t launch_new_rows(skm_ctx *c, const NewRows &b, int64_t n, hipStream_t 
     e = launch_exact(x, c->prec, s);
   }
   if (e == hipSuccess)
-    e = launch_exact_scores(b.indptr, b.indices, b.values, n, b.a, c->master, c->D, b.score, s);
+    e = launch_exact_scores(b.indptr, b.indices, b.values, n, b.a, c->master, c->D, b.score, s,
+                            n_dev);
   return e;
 }
 
@@ -796,6 +795,72 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
   return SKM_OK;
 }
 
+// Head GEMM launches of one pass at the current batch shape.
+int64_t head_launches(const skm_ctx *c) {
+  const int64_t nch = (c->k + kChunk - 1) / kChunk;
+  return ((c->N + c->head_rows - 1) / c->head_rows) * ((nch + c->head_chunks - 1) / c->head_chunks);
+}
+
+// Event pairs around the head GEMM launches of one pass.
+skm_status ensure_head_events(skm_ctx *c) {
+  const size_t need = 2 * (size_t)head_launches(c);
+  while (c->head_ev.size() < need) {
+    hipEvent_t x = nullptr;
+    hipError_t e = hipEventCreate(&x);
+    if (e != hipSuccess) return device_fail(c, "hipEventCreate", e);
+    c->head_ev.push_back(x);
+  }
+  return SKM_OK;
+}
+
+// Low-precision scoring of all rows with the head product, in batches of
+// head_rows rows x head_chunks chunks: head GEMM into hs, then the sparse
+// kernel adds the rows' other terms; one merge over all rows at the end.
+// Batches are large so that the sparse kernel still sweeps each chunk of codes
+// over many rows while its term rows are cached.
+skm_status head_pass(skm_ctx *c, ScoreArgs &a, hipStream_t s) {
+  ST_TRY(ensure_head_events(c));
+  a.sc_indptr = c->r_indptr;
+  a.sc_indices = c->r_indices;
+  a.sc_values = c->r_values;
+  a.hs = c->hs;
+  a.head_H = c->head_H;
+  const int32_t nch = (int32_t)((c->k + kChunk - 1) / kChunk);
+  a.hs_ld = (int64_t)c->head_chunks * kChunk;
+  size_t ev = 0;
+  for (int64_t r0 = 0; r0 < c->N; r0 += c->head_rows) {
+    const int64_t nb = std::min<int64_t>(c->head_rows, c->N - r0);
+    for (int32_t g0 = 0; g0 < nch; g0 += c->head_chunks) {
+      const int32_t gc = std::min<int32_t>(c->head_chunks, nch - g0);
+      HIP_TRY(c, hipEventRecord(c->head_ev[ev], s));
+      HIP_TRY(c, launch_head_gemm(c->xh, c->head_H, r0, nb, c->ch_head, (int64_t)g0 * kChunk,
+                                  (int64_t)gc * kChunk, c->hs, a.hs_ld, s));
+      HIP_TRY(c, hipEventRecord(c->head_ev[ev + 1], s));
+      ev += 2;
+      a.row0 = r0;
+      a.nb = nb;
+      a.c_first = g0;
+      a.c_count = gc;
+      HIP_TRY(c, launch_score_part(a, c->part, c->n_cu, c->prec, s, c->score_wpc));
+    }
+  }
+  a.row0 = 0;
+  a.nb = c->N;
+  a.c_first = 0;
+  a.c_count = nch;
+  HIP_TRY(c, launch_finalize(a, c->part, s));
+  return SKM_OK;
+}
+
+// Device time of the head GEMMs of the last pass (after a synchronisation).
+float head_ms(skm_ctx *c) {
+  float ms = 0.f;
+  const size_t n = 2 * (size_t)head_launches(c);
+  for (size_t i = 0; i + 1 < n && i + 1 < c->head_ev.size(); i += 2)
+    ms += elapsed(c->head_ev[i], c->head_ev[i + 1]);
+  return ms;
+}
+
 skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
   ST_TRY(check_ctx_writable(c));
   hipStream_t s = c->stream;
@@ -845,42 +910,9 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
   HIP_TRY(c, hipEventRecord(c->ev[5], s));
   const bool head = c->head_H > 0 && !ncc;
   if (head) {
-    // batches of rows: head product on the matrix cores, then the sparse
-    // kernel adds the remaining terms to it; one merge over all rows at the end
-    a.sc_indptr = c->r_indptr;
-    a.sc_indices = c->r_indices;
-    a.sc_values = c->r_values;
-    a.hs = c->hs;
-    a.hs_ld = c->k_pad;
-    a.head_H = c->head_H;
-    // Batches are large (up to a million rows) so that the sparse kernel still
-    // sweeps each chunk of codes over many rows while its term rows are cached.
-    const int32_t nch = (int32_t)((c->k + kChunk - 1) / kChunk);
-    a.hs_ld = (int64_t)c->head_chunks * kChunk;
-    size_t ev = 0;
-    for (int64_t r0 = 0; r0 < c->N; r0 += c->head_rows) {
-      const int64_t nb = std::min<int64_t>(c->head_rows, c->N - r0);
-      for (int32_t g0 = 0; g0 < nch; g0 += c->head_chunks) {
-        const int32_t gc = std::min<int32_t>(c->head_chunks, nch - g0);
-        HIP_TRY(c, hipEventRecord(c->head_ev[ev], s));
-        HIP_TRY(c, launch_head_gemm(c->xh, c->head_H, r0, nb, c->ch_head, (int64_t)g0 * kChunk,
-                                    (int64_t)gc * kChunk, c->hs, a.hs_ld, s));
-        HIP_TRY(c, hipEventRecord(c->head_ev[ev + 1], s));
-        ev += 2;
-        a.row0 = r0;
-        a.nb = nb;
-        a.c_first = g0;
-        a.c_count = gc;
-        HIP_TRY(c, launch_score_part(a, c->part, c->n_cu, c->prec, s));
-      }
-    }
-    a.row0 = 0;
-    a.nb = c->N;
-    a.c_first = 0;
-    a.c_count = nch;
-    HIP_TRY(c, launch_finalize(a, c->part, s));
+    ST_TRY(head_pass(c, a, s));
   } else {
-    HIP_TRY(c, launch_score(a, c->part, c->n_cu, c->prec, s));
+    HIP_TRY(c, launch_score(a, c->part, c->n_cu, c->prec, s, c->score_wpc));
   }
   HIP_TRY(c, hipEventRecord(c->ev[1], s));
   if (!a.no_exact) {
@@ -927,14 +959,112 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
     st_out->score_launches = 1;
     st_out->sparse_products = (double)stv[3];
     if (head) {
-      float ms = 0.f;
-      for (size_t i = 0; i + 1 < c->head_ev.size(); i += 2) ms += elapsed(c->head_ev[i], c->head_ev[i + 1]);
-      st_out->ms_head = ms;
-      st_out->score_launches = (int32_t)(c->head_ev.size() / 2);
+      st_out->ms_head = head_ms(c);
+      st_out->score_launches = (int32_t)head_launches(c);
       st_out->sparse_products = (double)stv[8];
     }
     st_out->objective_assign = st_out->objective_update = st_out->max_shift_sq = -1.0;
   }
+  return SKM_OK;
+}
+
+skm_status skm_autotune(skm_ctx *c, skm_tune_report *report) {
+  ST_TRY(check_ctx_writable(c));
+  if (c->assigned)
+    return fail(SKM_E_STATE, "skm_autotune needs no pending assignment (call it before "
+                             "skm_assign or after skm_update)");
+  hipStream_t s = c->stream;
+  skm_tune_report rep;
+  std::memset(&rep, 0, sizeof(rep));
+  // one full scoring pass (no exact tier, no NCC) at a given shape
+  auto pass = [&](int32_t chunks, int64_t rows, int32_t wpc, double *ms) -> skm_status {
+    c->head_chunks = chunks;
+    c->head_rows = rows;
+    c->score_wpc = wpc;
+    ScoreArgs a = base_args(c);
+    HIP_TRY(c, launch_fill_i32(c->counters, 0, 8, s));
+    HIP_TRY(c, launch_fill_i32(reinterpret_cast<int32_t *>(c->stat), 0, 32, s));
+    HIP_TRY(c, hipEventRecord(c->ev[5], s));
+    if (c->head_H > 0) {
+      ST_TRY(head_pass(c, a, s));
+    } else {
+      HIP_TRY(c, launch_score(a, c->part, c->n_cu, c->prec, s, wpc));
+    }
+    HIP_TRY(c, hipEventRecord(c->ev[1], s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    *ms = (double)elapsed(c->ev[5], c->ev[1]);
+    return SKM_OK;
+  };
+  auto trial = [&](int32_t chunks, int64_t rows, int32_t wpc) -> skm_status {
+    double ms = 0;
+    ST_TRY(pass(chunks, rows, wpc, &ms));
+    if (rep.n_trials < (int32_t)(sizeof(rep.trials) / sizeof(rep.trials[0]))) {
+      skm_tune_trial &t = rep.trials[rep.n_trials++];
+      t.head_chunks = c->head_H > 0 ? chunks : 0;
+      t.head_rows = c->head_H > 0 ? rows : 0;
+      t.workgroups_per_cu = wpc;
+      t.ms = ms;
+    }
+    return SKM_OK;
+  };
+  const int32_t chunks0 = c->head_chunks;
+  const int64_t rows0 = c->head_rows;
+  double warm = 0;
+  ST_TRY(pass(chunks0, rows0, c->score_wpc, &warm));   // first-use costs, not recorded
+  // stage 1: workgroups per CU of the sparse kernel around the occupancy limit
+  const int occ = score_occupancy(c->prec);
+  std::vector<int32_t> wpcs;
+  for (int32_t w : {occ, occ - 1, occ + 1, 8})
+    if (w >= 2 && w <= 8 && std::find(wpcs.begin(), wpcs.end(), w) == wpcs.end()) wpcs.push_back(w);
+  for (int32_t w : wpcs) ST_TRY(trial(chunks0, rows0, w));
+  // a candidate displaces the incumbent (the default shape, tried first) only
+  // when it is at least 2 % faster: closer timings are within run-to-run noise
+  auto best_of = [&]() {
+    int32_t b = 0;
+    for (int32_t i = 1; i < rep.n_trials; ++i)
+      if (rep.trials[i].ms < 0.98 * rep.trials[b].ms) b = i;
+    return b;
+  };
+  const int32_t wbest = rep.trials[best_of()].workgroups_per_cu;
+  // stage 2: the head batch shape (chunks x rows filling the head-score buffer)
+  if (c->head_H > 0) {
+    const int32_t nch = (int32_t)((c->k + kChunk - 1) / kChunk);
+    for (int32_t g : {1, 2, 4, 8}) {
+      if (g > nch || g == chunks0) continue;
+      int64_t rows = c->hs_cap / ((int64_t)g * kChunk) / 256 * 256;
+      rows = std::min<int64_t>(rows, round_up(c->N, 256));
+      if (rows < 256) continue;
+      ST_TRY(trial(g, rows, wbest));
+    }
+  }
+  rep.best = best_of();
+  const skm_tune_trial &b = rep.trials[rep.best];
+  c->score_wpc = b.workgroups_per_cu;
+  if (c->head_H > 0) {
+    c->head_chunks = b.head_chunks;
+    c->head_rows = b.head_rows;
+  } else {
+    c->head_chunks = chunks0;
+    c->head_rows = rows0;
+  }
+  if (report) *report = rep;
+  return SKM_OK;
+}
+
+skm_status skm_set_schedule(skm_ctx *c, const skm_tune_trial *shape) {
+  ST_TRY(check_ctx_writable(c));
+  if (!shape) return fail(SKM_E_INVALID, "shape is NULL");
+  if (shape->workgroups_per_cu < 0 || shape->workgroups_per_cu > 16)
+    return fail(SKM_E_INVALID, "workgroups_per_cu must be in [0, 16]");
+  if (c->head_H > 0) {
+    const int64_t nch = (c->k + kChunk - 1) / kChunk;
+    if (shape->head_chunks < 1 || shape->head_chunks > nch || shape->head_rows < 1 ||
+        shape->head_rows * shape->head_chunks * kChunk > c->hs_cap)
+      return fail(SKM_E_INVALID, "head batch shape does not fit the head-score buffer");
+    c->head_chunks = shape->head_chunks;
+    c->head_rows = shape->head_rows;
+  }
+  c->score_wpc = shape->workgroups_per_cu;
   return SKM_OK;
 }
 
@@ -1194,8 +1324,7 @@ skm_status skm_score_head(skm_ctx *c, int64_t row0, int64_t n_rows, float *out) 
   ST_TRY(check_ctx(c));
   if (!out) return fail(SKM_E_INVALID, "out is NULL");
   if (c->head_H <= 0) return fail(SKM_E_STATE, "this context scores no head terms");
-  if (row0 < 0 || n_rows < 0 || row0 + n_rows > c->N ||
-      n_rows * c->k_pad > c->head_rows * c->head_chunks * kChunk)
+  if (row0 < 0 || n_rows < 0 || row0 + n_rows > c->N || n_rows * c->k_pad > c->hs_cap)
     return fail(SKM_E_INVALID, "row range outside the context or larger than one head batch");
   if (n_rows == 0) return SKM_OK;
   float *d_out = nullptr;

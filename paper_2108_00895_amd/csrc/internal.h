@@ -29,7 +29,10 @@ struct ScoreArgs {
   const int32_t *indices;
   const float *values;
   const double *xl1;          // per-row L1 norm (FP8 absolute error term)
-  int64_t n_rows;
+  int64_t n_rows;             // rows (and the row stride of the chunk partials)
+  const int64_t *n_dev;       // rows actually present, read on the device (a captured
+                              // graph replayed for batches of different sizes), or
+                              // nullptr; launches are then sized for n_rows
   // rows the scoring kernel reads: the full rows, or only their terms outside
   // the dense head when head scores are given
   const int64_t *sc_indptr;
@@ -256,6 +259,8 @@ struct skm_ctx {
   int32_t k_pad = 0;             // head-code rows (k rounded up to 512)
   int64_t head_rows = 0;         // rows per head batch
   int32_t head_chunks = 0;       // 512-centroid chunks per head batch
+  int64_t hs_cap = 0;            // floats in hs (head_rows x head_chunks x 512 at most)
+  int32_t score_wpc = 0;         // scoring grid workgroups per CU (0 = as many as fit)
   std::vector<hipEvent_t> head_ev;  // pairs around the head GEMM launches of one step
   int32_t *head_terms = nullptr; // [H] term ids, ascending
   int32_t *head_slot = nullptr;  // [D] slot of a head term, -1 otherwise
@@ -291,10 +296,15 @@ namespace skm {
 // kernels_score.hip
 // n_cu: compute units of the device; the grid holds as many workgroups as fit
 // on them at once.
-hipError_t launch_score(const ScoreArgs &a, Partial *part, int n_cu, int prec, hipStream_t s);
+// wpc: workgroups per CU of the persistent scoring grid (0 = as many as fit).
+hipError_t launch_score(const ScoreArgs &a, Partial *part, int n_cu, int prec, hipStream_t s,
+                        int wpc = 0);
 // The two halves of launch_score: partials of rows [a.row0, a.row0 + a.nb),
 // then the merge and certificate of all a.n_rows rows.
-hipError_t launch_score_part(const ScoreArgs &a, Partial *part, int n_cu, int prec, hipStream_t s);
+hipError_t launch_score_part(const ScoreArgs &a, Partial *part, int n_cu, int prec, hipStream_t s,
+                             int wpc = 0);
+// Workgroups of the scoring kernel that fit on one CU at once.
+int score_occupancy(int prec);
 hipError_t launch_finalize(const ScoreArgs &a, const Partial *part, hipStream_t s);
 hipError_t launch_exact(const ExactArgs &a, int prec, hipStream_t s);
 hipError_t launch_score_dense(const int64_t *indptr, const int32_t *indices, const float *values,
@@ -303,10 +313,13 @@ hipError_t launch_score_dense(const int64_t *indptr, const int32_t *indices, con
                               int64_t hs_ld, float *out, hipStream_t s);
 hipError_t launch_exact_scores(const int64_t *indptr, const int32_t *indices, const float *values,
                                int64_t n_rows, const int32_t *a, const double *master, int64_t D,
-                               double *out, hipStream_t s);
+                               double *out, hipStream_t s, const int64_t *n_dev = nullptr);
 
 // api.hip
-hipError_t launch_new_rows(skm_ctx *c, const NewRows &b, int64_t n, hipStream_t s);
+// n rows of new rows; with n_dev the launches are sized for n rows of
+// capacity and the kernels read the actual count from *n_dev.
+hipError_t launch_new_rows(skm_ctx *c, const NewRows &b, int64_t n, hipStream_t s,
+                           const int64_t *n_dev = nullptr);
 skm_status set_error(skm_status st, const std::string &msg);  // thread-local last error
 
 // kernels_tail.hip
@@ -328,7 +341,8 @@ hipError_t index_score(const IndexArgs &x, int64_t n_slots, int32_t *a_out, doub
 
 // kernels_update.hip
 hipError_t launch_row_stats_only(const int64_t *indptr, const int32_t *indices, const float *values,
-                                 int64_t n_rows, double *xl1, hipStream_t s);
+                                 int64_t n_rows, double *xl1, hipStream_t s,
+                                 const int64_t *n_dev = nullptr);
 hipError_t launch_row_stats(const int64_t *indptr, const int32_t *indices, const float *values,
                             int64_t n_rows, int64_t D, double *xl1, double *xl2, int32_t *bad,
                             hipStream_t s);

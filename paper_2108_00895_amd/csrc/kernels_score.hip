@@ -313,9 +313,11 @@ __global__ __launch_bounds__(256) void k_score_part(ScoreArgs a, Partial *__rest
   float *lacc = lacc_all[wave];
   zero_lacc(lacc);
   const int64_t stride = (int64_t)gridDim.x * 4;
+  const int64_t nb = a.n_dev ? uniform64(*a.n_dev) : a.nb;
+  if (a.n_dev) n_items = (int64_t)a.c_count * nb;
   for (int64_t it = (int64_t)blockIdx.x * 4 + wave; it < n_items; it += stride) {
-    const int64_t ci = uniform64(it / a.nb);
-    const int64_t row = uniform64(a.row0 + (it - ci * a.nb));
+    const int64_t ci = uniform64(it / nb);
+    const int64_t row = uniform64(a.row0 + (it - ci * nb));
     const int64_t c = a.c_first + ci;
     const RowPlan pl = plan_row(a, row, true);
     const int64_t c0 = c * kChunk;
@@ -369,9 +371,10 @@ __global__ __launch_bounds__(256) void k_score_part(ScoreArgs a, Partial *__rest
 __global__ __launch_bounds__(256) void k_finalize(ScoreArgs a, const Partial *__restrict__ part) {
   __shared__ unsigned long long sh[4][256];
   const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n_rows = a.n_dev ? *a.n_dev : a.n_rows;
   unsigned long long n_cols = 0, n_prod = 0, n_ncc = 0, n_sp = 0;
-  const RowPlan pl = row < a.n_rows ? plan_row(a, row, true) : RowPlan{};
-  if (row < a.n_rows && !pl.done) {
+  const RowPlan pl = row < n_rows ? plan_row(a, row, true) : RowPlan{};
+  if (row < n_rows && !pl.done) {
     const int64_t b = a.indptr[row], e = a.indptr[row + 1];
     float b1 = -INFINITY, b2 = -INFINITY;
     int j1 = 0x7FFFFFFF;
@@ -624,11 +627,12 @@ __global__ __launch_bounds__(256) void k_score_dense(const int64_t *indptr, cons
 // lanes over terms, fixed-shape wave sum.
 __global__ __launch_bounds__(256) void k_exact_scores(const int64_t *indptr, const int32_t *indices,
                                                       const float *values, int64_t n_rows,
-                                                      const int32_t *asg, const double *master,
-                                                      int64_t D, double *out) {
+                                                      const int64_t *n_dev, const int32_t *asg,
+                                                      const double *master, int64_t D,
+                                                      double *out) {
   const int wave = uniform32(threadIdx.x >> 6);
   const int64_t row = (int64_t)blockIdx.x * 4 + wave;
-  if (row >= n_rows) return;
+  if (row >= (n_dev ? *n_dev : n_rows)) return;
   const int lane = lane_id();
   const int64_t b = indptr[row], e = indptr[row + 1];
   const double *c = master + (int64_t)asg[row] * D;
@@ -638,12 +642,9 @@ __global__ __launch_bounds__(256) void k_exact_scores(const int64_t *indptr, con
   if (lane == 0) out[row] = s;
 }
 
+// Workgroups of k_score_part<P> resident per CU at its register and LDS use.
 template <int P>
-hipError_t launch_score_part_t(const ScoreArgs &a, Partial *part, int n_cu, hipStream_t s) {
-  if (a.n_rows <= 0) return hipSuccess;
-  // Workgroups resident per CU at this kernel's register and LDS use: the
-  // persistent grid is exactly one wave of them, so no workgroup starts late
-  // and sweeps the chunks out of step with the rest.
+int occupancy_t() {
   static const int per_cu = [] {
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_score_part<P>, 256, 0) != hipSuccess ||
@@ -652,6 +653,17 @@ hipError_t launch_score_part_t(const ScoreArgs &a, Partial *part, int n_cu, hipS
     (void)hipGetLastError();
     return n;
   }();
+  return per_cu;
+}
+
+template <int P>
+hipError_t launch_score_part_t(const ScoreArgs &a, Partial *part, int n_cu, int wpc, hipStream_t s) {
+  if (a.n_rows <= 0) return hipSuccess;
+  // By default the persistent grid is exactly one wave of resident
+  // workgroups, so no workgroup starts late and sweeps the chunks out of step
+  // with the rest; wpc > 0 overrides the workgroups per CU (autotuning).
+  const int per_cu = wpc > 0 ? wpc : occupancy_t<P>();
+  // with a device row count, nb is the capacity the grid is sized for
   const int64_t n_items = (int64_t)a.c_count * a.nb;
   const int64_t need = (n_items + 3) / 4;
   if (need <= 0) return hipSuccess;
@@ -668,13 +680,22 @@ hipError_t launch_exact_t(const ExactArgs &x, hipStream_t s) {
 
 }  // namespace
 
-hipError_t launch_score_part(const ScoreArgs &a, Partial *part, int n_cu, int prec, hipStream_t s) {
+hipError_t launch_score_part(const ScoreArgs &a, Partial *part, int n_cu, int prec, hipStream_t s,
+                             int wpc) {
   switch (prec) {
-    case SKM_FP32: return launch_score_part_t<SKM_FP32>(a, part, n_cu, s);
-    case SKM_BF16: return launch_score_part_t<SKM_BF16>(a, part, n_cu, s);
-    case SKM_FP8_E4M3: return launch_score_part_t<SKM_FP8_E4M3>(a, part, n_cu, s);
+    case SKM_FP32: return launch_score_part_t<SKM_FP32>(a, part, n_cu, wpc, s);
+    case SKM_BF16: return launch_score_part_t<SKM_BF16>(a, part, n_cu, wpc, s);
+    case SKM_FP8_E4M3: return launch_score_part_t<SKM_FP8_E4M3>(a, part, n_cu, wpc, s);
   }
   return hipErrorInvalidValue;
+}
+
+int score_occupancy(int prec) {
+  switch (prec) {
+    case SKM_FP32: return occupancy_t<SKM_FP32>();
+    case SKM_BF16: return occupancy_t<SKM_BF16>();
+    default: return occupancy_t<SKM_FP8_E4M3>();
+  }
 }
 
 hipError_t launch_finalize(const ScoreArgs &a, const Partial *part, hipStream_t s) {
@@ -683,8 +704,9 @@ hipError_t launch_finalize(const ScoreArgs &a, const Partial *part, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_score(const ScoreArgs &a, Partial *part, int n_cu, int prec, hipStream_t s) {
-  hipError_t e = launch_score_part(a, part, n_cu, prec, s);
+hipError_t launch_score(const ScoreArgs &a, Partial *part, int n_cu, int prec, hipStream_t s,
+                        int wpc) {
+  hipError_t e = launch_score_part(a, part, n_cu, prec, s, wpc);
   if (e != hipSuccess) return e;
   return launch_finalize(a, part, s);
 }
@@ -724,10 +746,10 @@ hipError_t launch_score_dense(const int64_t *indptr, const int32_t *indices, con
 
 hipError_t launch_exact_scores(const int64_t *indptr, const int32_t *indices, const float *values,
                                int64_t n_rows, const int32_t *asg, const double *master, int64_t D,
-                               double *out, hipStream_t s) {
+                               double *out, hipStream_t s, const int64_t *n_dev) {
   if (n_rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_exact_scores, dim3((unsigned)((n_rows + 3) / 4)), dim3(256), 0, s, indptr,
-                     indices, values, n_rows, asg, master, D, out);
+                     indices, values, n_rows, n_dev, asg, master, D, out);
   return hipGetLastError();
 }
 

@@ -68,10 +68,11 @@ __global__ void k_row_stats(const int64_t *indptr, const int32_t *indices, const
 }
 
 // L1 norm per row only (rows already checked on the host).
-__global__ void k_row_l1(const int64_t *indptr, const float *values, int64_t n_rows, double *xl1) {
+__global__ void k_row_l1(const int64_t *indptr, const float *values, int64_t n_rows,
+                         const int64_t *n_dev, double *xl1) {
   const int lane = lane_id();
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= n_rows) return;
+  if (row >= (n_dev ? *n_dev : n_rows)) return;
   double s1 = 0.0;
   for (int64_t q = indptr[row] + lane; q < indptr[row + 1]; q += kWave) s1 += (double)values[q];
   s1 = wave_sum_d(s1);
@@ -413,11 +414,11 @@ hipError_t launch_row_stats(const int64_t *indptr, const int32_t *indices, const
 }
 
 hipError_t launch_row_stats_only(const int64_t *indptr, const int32_t *indices, const float *values,
-                                 int64_t n_rows, double *xl1, hipStream_t s) {
+                                 int64_t n_rows, double *xl1, hipStream_t s, const int64_t *n_dev) {
   (void)indices;
   if (n_rows <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_row_l1, dim3((unsigned)((n_rows + 3) / 4)), dim3(256), 0, s, indptr, values,
-                     n_rows, xl1);
+                     n_rows, n_dev, xl1);
   return hipGetLastError();
 }
 

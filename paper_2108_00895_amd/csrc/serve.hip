@@ -10,6 +10,9 @@
 // scores) and copies the answers back; a completed slot's answers are
 // scattered to the requests' output buffers and their waiters are woken.
 // Different slots run on different streams, so batches overlap on the device.
+// With use_graphs, each slot's compute pipeline is captured once into a HIP
+// graph sized for the slot's capacity; a batch then costs the copies plus one
+// graph launch, and the kernels read the batch's row count from the device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -58,6 +61,10 @@ struct Slot {
   int32_t *d_indices = nullptr;
   float *d_values = nullptr;
   double *d_xl1 = nullptr;
+  int64_t *h_n = nullptr;            // rows of the current batch (pinned)
+  int64_t *d_n = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
   std::vector<std::shared_ptr<Request>> reqs;
   int64_t rows = 0;
   bool busy = false;
@@ -124,6 +131,8 @@ bool host_alloc(skm_server *s, T **p, size_t count) {
 void release(skm_server *s) {
   for (Slot &sl : s->slots) {
     if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
+    if (sl.graph) (void)hipGraphDestroy(sl.graph);
     if (sl.done_ev) (void)hipEventDestroy(sl.done_ev);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
   }
@@ -145,12 +154,28 @@ bool make_slot(skm_server *s, Slot &sl) {
        dev_alloc(s, &sl.d.lo, R) && dev_alloc(s, &sl.d.hi, R) && dev_alloc(s, &sl.d.flag_rows, R) &&
        dev_alloc(s, &sl.d.flag_L, R) && dev_alloc(s, &sl.d.flag_mode, R) &&
        dev_alloc(s, &sl.d.counters, 8) && dev_alloc(s, &sl.d.stat, 16) &&
-       dev_alloc(s, &sl.d.score, R);
+       dev_alloc(s, &sl.d.score, R) && host_alloc(s, &sl.h_n, 1) && dev_alloc(s, &sl.d_n, 1);
   sl.d.indptr = sl.d_indptr;
   sl.d.indices = sl.d_indices;
   sl.d.values = sl.d_values;
   sl.d.xl1 = sl.d_xl1;
-  return ok;
+  if (!ok || !s->cfg.use_graphs) return ok;
+  // capture the compute pipeline for R rows of capacity; the row count is read
+  // from d_n, which each batch copies in before the replay
+  hipStream_t st = sl.stream;
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+  hipError_t e = launch_row_stats_only(sl.d_indptr, sl.d_indices, sl.d_values, R, sl.d_xl1, st, sl.d_n);
+  if (e == hipSuccess) e = launch_new_rows(s->c, sl.d, R, st, sl.d_n);
+  const hipError_t e2 = hipStreamEndCapture(st, &sl.graph);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  if (hipGraphInstantiate(&sl.exec, sl.graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return true;
 }
 
 // Packs the requests at the head of the queue into a free slot and launches
@@ -178,8 +203,15 @@ void launch_slot(skm_server *s, Slot &sl) {
     e = hipMemcpyAsync(sl.d_indices, sl.h_indices, 4 * nnz, hipMemcpyHostToDevice, st);
   if (e == hipSuccess && nnz > 0)
     e = hipMemcpyAsync(sl.d_values, sl.h_values, 4 * nnz, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = launch_row_stats_only(sl.d_indptr, sl.d_indices, sl.d_values, rows, sl.d_xl1, st);
-  if (e == hipSuccess) e = launch_new_rows(s->c, sl.d, rows, st);
+  if (sl.exec) {
+    *sl.h_n = rows;
+    if (e == hipSuccess) e = hipMemcpyAsync(sl.d_n, sl.h_n, 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipGraphLaunch(sl.exec, st);
+  } else {
+    if (e == hipSuccess)
+      e = launch_row_stats_only(sl.d_indptr, sl.d_indices, sl.d_values, rows, sl.d_xl1, st);
+    if (e == hipSuccess) e = launch_new_rows(s->c, sl.d, rows, st);
+  }
   if (e == hipSuccess) e = hipMemcpyAsync(sl.h_a, sl.d.a, 4 * rows, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipMemcpyAsync(sl.h_s, sl.d.score, 8 * rows, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipEventRecord(sl.done_ev, st);
@@ -269,6 +301,7 @@ void skm_server_config_default(skm_server_config *cfg) {
   cfg->slot_nnz = 4 * 1024 * 1024;
   cfg->hbm_budget_bytes = 0;
   cfg->max_wait_us = 100;
+  cfg->use_graphs = 1;
 }
 
 skm_status skm_server_start(skm_ctx *c, const skm_server_config *cfg, skm_server **out) {

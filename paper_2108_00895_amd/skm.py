@@ -28,7 +28,7 @@ EXPORTED = [
     "skm_config_default", "skm_init", "skm_assign", "skm_update", "skm_iterate",
     "skm_assign_new", "skm_get_assignments", "skm_get_centroids", "skm_set_centroids",
     "skm_get_tile", "skm_get_changed", "skm_score_dense", "skm_error_bound", "skm_head_terms",
-    "skm_score_head", "skm_error_bound_head", "skm_get_index",
+    "skm_score_head", "skm_error_bound_head", "skm_autotune", "skm_set_schedule", "skm_get_index",
     "skm_index_query", "skm_server_config_default", "skm_server_start", "skm_server_submit",
     "skm_server_wait", "skm_server_get_stats", "skm_server_stop",
     "skm_hbm_bytes", "skm_last_error", "skm_destroy",
@@ -77,10 +77,20 @@ class IterStats(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class TuneTrial(ctypes.Structure):
+    _fields_ = [("head_chunks", ctypes.c_int32), ("workgroups_per_cu", ctypes.c_int32),
+                ("head_rows", ctypes.c_int64), ("ms", ctypes.c_double)]
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("n_trials", ctypes.c_int32), ("best", ctypes.c_int32),
+                ("trials", TuneTrial * 16)]
+
+
 class ServerConfig(ctypes.Structure):
     _fields_ = [("n_slots", ctypes.c_int32), ("slot_rows", ctypes.c_int32),
                 ("slot_nnz", ctypes.c_int64), ("hbm_budget_bytes", ctypes.c_size_t),
-                ("max_wait_us", ctypes.c_int32)]
+                ("max_wait_us", ctypes.c_int32), ("use_graphs", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -140,6 +150,10 @@ def load():
     lib.skm_score_dense.restype = st
     lib.skm_error_bound.argtypes = [vp, ctypes.c_double, i64, ctypes.c_double]
     lib.skm_error_bound.restype = ctypes.c_double
+    lib.skm_autotune.argtypes = [vp, P(TuneReport)]
+    lib.skm_autotune.restype = st
+    lib.skm_set_schedule.argtypes = [vp, P(TuneTrial)]
+    lib.skm_set_schedule.restype = st
     lib.skm_head_terms.argtypes = [vp]
     lib.skm_head_terms.restype = ctypes.c_int32
     lib.skm_score_head.argtypes = [vp, i64, i64, vp]
@@ -361,6 +375,22 @@ class Context:
     def error_bound(self, s, nnz, l1):
         return load().skm_error_bound(self._h, float(s), int(nnz), float(l1))
 
+    def autotune(self):
+        """Times candidate shapes of the scoring work and keeps the fastest;
+        returns {"best": {...}, "trials": [{...}, ...]}."""
+        rep = TuneReport()
+        _check(load().skm_autotune(self._h, ctypes.byref(rep)))
+        trials = [{f: getattr(rep.trials[i], f) for f, _ in TuneTrial._fields_}
+                  for i in range(rep.n_trials)]
+        return {"best": trials[rep.best], "trials": trials}
+
+    def set_schedule(self, shape):
+        """Applies a shape returned by autotune() (a dict of TuneTrial fields)."""
+        t = TuneTrial()
+        for f, _ in TuneTrial._fields_:
+            setattr(t, f, shape.get(f, 0))
+        _check(load().skm_set_schedule(self._h, ctypes.byref(t)))
+
     def head_terms(self):
         """Terms scored on the matrix cores (0 = head off)."""
         return int(load().skm_head_terms(self._h))
@@ -403,12 +433,13 @@ class Server:
     wait(ticket) returns (assignments, scores)."""
 
     def __init__(self, ctx: Context, n_slots=4, slot_rows=16384, slot_nnz=4 * 1024 * 1024,
-                 hbm_budget_bytes=0, max_wait_us=100):
+                 hbm_budget_bytes=0, max_wait_us=100, use_graphs=True):
         lib = load()
         cfg = ServerConfig()
         lib.skm_server_config_default(ctypes.byref(cfg))
         cfg.n_slots, cfg.slot_rows, cfg.slot_nnz = n_slots, slot_rows, slot_nnz
         cfg.hbm_budget_bytes, cfg.max_wait_us = hbm_budget_bytes, max_wait_us
+        cfg.use_graphs = 1 if use_graphs else 0
         h = ctypes.c_void_p()
         _check(lib.skm_server_start(ctx._h, ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

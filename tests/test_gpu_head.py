@@ -17,7 +17,7 @@ import pytest
 
 import oracle
 import synth
-from paper_2108_00895_amd import Context
+from paper_2108_00895_amd import Context, SkmError, skm
 
 from gpu_common import assert_assign_equal, corpus, say, to_device
 
@@ -141,3 +141,56 @@ def test_head_chunk_groups_ragged():
     n_tie = assert_assign_equal(ctx.assignments(), a_ref, s1, s2, "chunk groups")
     say(f"  flagged {st['flagged']} ties {n_tie}")
     ctx.close()
+
+
+def test_autotune_changes_only_the_schedule(mid):
+    csr, c, rows = mid
+    say("case: autotune")
+    got = []
+    for tune in [False, True]:
+        ctx = Context(csr, c.n_terms, len(rows), init_rows=rows, precision="bf16",
+                      stop_rule="fixed", max_iter=4)
+        seq = []
+        for it in range(4):
+            if tune and it == 2:
+                rep = ctx.autotune()
+                assert 1 <= len(rep["trials"]) <= 16 and rep["best"] in rep["trials"]
+                assert all(t["ms"] > 0 for t in rep["trials"])
+                # the incumbent is displaced only by a trial at least 2 % faster
+                assert min(t["ms"] for t in rep["trials"]) >= 0.98 * rep["best"]["ms"] - 1e-9
+                say("  autotune best", rep["best"])
+            st = ctx.assign()
+            if tune and it == 2:
+                with pytest.raises(SkmError) as e:
+                    ctx.autotune()               # an assignment is pending
+                assert e.value.status == skm.SKM_E_STATE
+            seq.append((ctx.assignments(), st["moved"]))
+            ctx.update()
+        got.append(seq)
+        ctx.close()
+    for (a0, m0), (a1, m1) in zip(*got):
+        np.testing.assert_array_equal(a0, a1)
+        assert m0 == m1
+
+
+def test_set_schedule_validates(mid):
+    csr, c, rows = mid
+    say("case: set schedule")
+    ctx = Context(csr, c.n_terms, len(rows), init_rows=rows, precision="bf16")
+    a0 = ctx.assign()
+    base = ctx.assignments()
+    ctx.update()
+    rep = ctx.autotune()
+    other = Context(csr, c.n_terms, len(rows), init_rows=rows, precision="bf16")
+    other.set_schedule(rep["best"])
+    other.assign()
+    np.testing.assert_array_equal(other.assignments(), base)
+    for bad in [{"head_chunks": 99, "head_rows": 256, "workgroups_per_cu": 4},
+                {"head_chunks": 1, "head_rows": 1 << 40, "workgroups_per_cu": 4},
+                {"head_chunks": 1, "head_rows": 256, "workgroups_per_cu": 99}]:
+        with pytest.raises(SkmError) as e:
+            other.set_schedule(bad)
+        assert e.value.status == skm.SKM_E_INVALID
+    say("  flagged", a0["flagged"], "best", rep["best"])
+    ctx.close()
+    other.close()

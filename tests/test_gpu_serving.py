@@ -2,6 +2,9 @@
 
 Every request's answer must be the same alone (skm_assign_new) and in the mix
 (batched with other requests by the server), and equal to the FP64 oracle.
+With captured graphs every batch replays a slot's graph (sized for the slot,
+the batch's row count read on the device), interleaved with the eager work of
+other slots; each replay's answers are checked.
 """
 import threading
 
@@ -39,15 +42,16 @@ def _requests(D, n_req, seed):
     return out
 
 
-@pytest.mark.parametrize("prec", ["bf16", "fp8"])
-def test_mix_equals_alone_and_oracle(prec, resident):
+@pytest.mark.parametrize("prec,graphs", [("bf16", True), ("fp8", True), ("bf16", False)])
+def test_mix_equals_alone_and_oracle(prec, graphs, resident):
     csr, c, C = resident
-    say("case: serving mix", prec)
+    say("case: serving mix", prec, "graphs" if graphs else "eager")
     ctx = Context(csr, c.n_terms, 600, init_centroids=C, precision=prec)
     reqs = _requests(c.n_terms, 150, seed=7)
     alone = [ctx.assign_new(r) for r in reqs]
     got = [None] * len(reqs)
-    with Server(ctx, n_slots=3, slot_rows=512, slot_nnz=512 * 400, max_wait_us=200) as srv:
+    with Server(ctx, n_slots=3, slot_rows=512, slot_nnz=512 * 400, max_wait_us=200,
+                use_graphs=graphs) as srv:
         def client(ids):
             tickets = [(i, srv.submit(reqs[i])) for i in ids]
             for i, t in tickets:

@@ -37,11 +37,18 @@ def test_struct_layouts_match_header():
     assert cfg.head_max_terms == 4096 and cfg.head_min_df == 1.0 / 128
 
 
+def test_tune_structs():
+    assert ctypes.sizeof(skm.TuneTrial) == 4 + 4 + 8 + 8
+    assert ctypes.sizeof(skm.TuneReport) == 4 + 4 + 16 * 24
+    assert skm.load().skm_autotune(None, None) == skm.SKM_E_INVALID
+
+
 def test_server_structs():
-    assert ctypes.sizeof(skm.ServerConfig) == 4 + 4 + 8 + 8 + 8
+    assert ctypes.sizeof(skm.ServerConfig) == 4 + 4 + 8 + 8 + 4 + 4
     cfg = skm.ServerConfig()
     skm.load().skm_server_config_default(ctypes.byref(cfg))
     assert cfg.n_slots == 4 and cfg.slot_rows == 16384 and cfg.max_wait_us == 100
+    assert cfg.use_graphs == 1
     assert skm.load().skm_server_start(None, None, ctypes.byref(ctypes.c_void_p())) == skm.SKM_E_INVALID
 
 
