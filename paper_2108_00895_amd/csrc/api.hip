@@ -556,7 +556,7 @@ hipError_t launch_new_rows(skm_ctx *c, const NewRows &b, int64_t n, hipStream_t 
   sa.mode = nullptr;
   hipError_t e = launch_fill_i32(b.counters, 0, 8, s);
   if (e == hipSuccess) e = launch_fill_i32(reinterpret_cast<int32_t *>(b.stat), 0, 16, s);
-  if (e == hipSuccess) e = launch_score(sa, b.part, c->n_cu, c->prec, s);
+  if (e == hipSuccess) e = launch_score(sa, b.part, c->n_cu, c->prec, s, c->score_wpc);
   if (e == hipSuccess) {
     ExactArgs x{sa, b.part, c->master, c->D, exact_waves()};
     e = launch_exact(x, c->prec, s);
