@@ -133,7 +133,8 @@ typedef struct {
                                  (all of them at iteration 0) */
   int64_t moved;              /* rows whose assignment changed (n_rows at 0) */
   int64_t flagged;            /* rows sent to the exact FP64 tier */
-  int64_t band_overflow;      /* flagged rows rescored against every candidate */
+  int64_t band_overflow;      /* flagged rows whose band of possible winners exceeded
+                                 the exact tier's buffer (scored in several passes) */
   int64_t ncc_rows;           /* rows that only compared changed centroids */
   int64_t index_rows;         /* rows whose candidates came from the index */
   int64_t index_no_level;     /* index-eligible rows whose baseline reached no

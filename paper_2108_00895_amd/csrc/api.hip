@@ -294,7 +294,8 @@ skm_status setup_head(skm_ctx *c) {
   const int64_t rows = std::min<int64_t>(1ll << 20, round_up(c->N, 256));
   const int64_t nscan = head_split_scan_blocks(c->N);
   const size_t need = 4 * (size_t)H + 4 * (size_t)c->D + 2 * (size_t)c->N * H +
-                      2 * (size_t)k_pad * H + 4 * (size_t)rows * chunks * kChunk +
+                      2 * (size_t)k_pad * H * ((c->cfg.flags & SKM_NCC) ? 2 : 1) +
+                      4 * (size_t)rows * chunks * kChunk + 4 * (size_t)c->N +
                       8 * (size_t)(c->N + 1) +
                       8 * (size_t)rest_nnz + 8 * (size_t)c->N + 8 * (size_t)nscan + 16 * 256;
   if (c->cfg.hbm_budget_bytes && c->hbm_bytes + need > c->cfg.hbm_budget_bytes) return SKM_OK;
@@ -303,6 +304,10 @@ skm_status setup_head(skm_ctx *c) {
   ST_TRY(dalloc(c, &c->head_slot, (size_t)c->D));
   ST_TRY(dalloc(c, &c->xh, (size_t)c->N * H));
   ST_TRY(dalloc(c, &c->ch_head, (size_t)k_pad * H));
+  if (c->cfg.flags & SKM_NCC) {
+    ST_TRY(dalloc(c, &c->ch_head_ch, (size_t)k_pad * H));
+    ST_TRY(dalloc(c, &c->full_rows, (size_t)c->N));
+  }
   ST_TRY(dalloc(c, &c->hs, (size_t)rows * chunks * kChunk));
   ST_TRY(dalloc(c, &c->r_indptr, (size_t)c->N + 1));
   ST_TRY(dalloc(c, &c->r_indices, (size_t)std::max<int64_t>(rest_nnz, 1)));
@@ -345,7 +350,10 @@ ScoreArgs base_args(skm_ctx *c) {
   a.nb = c->N;
   a.c_first = 0;
   a.c_count = (int32_t)((c->k + kChunk - 1) / kChunk);
+  a.row_list = nullptr;
+  a.ncc_only = 0;
   a.head_H = 0;
+  a.top = c->prec == SKM_FP8_E4M3 ? kTop : 2;
   a.tile = c->tile;
   a.D = c->D;
   a.k = c->k;
@@ -795,45 +803,35 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
   return SKM_OK;
 }
 
-// Head GEMM launches of one pass at the current batch shape.
-int64_t head_launches(const skm_ctx *c) {
-  const int64_t nch = (c->k + kChunk - 1) / kChunk;
-  return ((c->N + c->head_rows - 1) / c->head_rows) * ((nch + c->head_chunks - 1) / c->head_chunks);
-}
-
-// Event pairs around the head GEMM launches of one pass.
-skm_status ensure_head_events(skm_ctx *c) {
-  const size_t need = 2 * (size_t)head_launches(c);
-  while (c->head_ev.size() < need) {
-    hipEvent_t x = nullptr;
-    hipError_t e = hipEventCreate(&x);
-    if (e != hipSuccess) return device_fail(c, "hipEventCreate", e);
-    c->head_ev.push_back(x);
-  }
-  return SKM_OK;
-}
-
-// Low-precision scoring of all rows with the head product, in batches of
-// head_rows rows x head_chunks chunks: head GEMM into hs, then the sparse
-// kernel adds the rows' other terms; one merge over all rows at the end.
-// Batches are large so that the sparse kernel still sweeps each chunk of codes
-// over many rows while its term rows are cached.
-skm_status head_pass(skm_ctx *c, ScoreArgs &a, hipStream_t s) {
-  ST_TRY(ensure_head_events(c));
+// Low-precision scoring with the head product of the rows [0, n_rows), or of
+// the listed rows, against the first ncols columns of a code copy whose head
+// codes are chead: in batches of head_rows rows x head_chunks chunks, head
+// GEMM into hs, then the sparse kernel adds the rows' other terms.  Batches
+// are large so that the sparse kernel still sweeps each chunk of codes over
+// many rows while its term rows are cached.  GEMM launches are bracketed by
+// event pairs from head_ev[ev] on (created on demand).
+skm_status head_pass(skm_ctx *c, ScoreArgs &a, hipStream_t s, const uint16_t *chead,
+                     int64_t ncols, const int32_t *rows, int64_t n_rows, size_t &ev) {
   a.sc_indptr = c->r_indptr;
   a.sc_indices = c->r_indices;
   a.sc_values = c->r_values;
   a.hs = c->hs;
   a.head_H = c->head_H;
-  const int32_t nch = (int32_t)((c->k + kChunk - 1) / kChunk);
+  a.row_list = rows;
+  const int32_t nch = (int32_t)((ncols + kChunk - 1) / kChunk);
   a.hs_ld = (int64_t)c->head_chunks * kChunk;
-  size_t ev = 0;
-  for (int64_t r0 = 0; r0 < c->N; r0 += c->head_rows) {
-    const int64_t nb = std::min<int64_t>(c->head_rows, c->N - r0);
+  for (int64_t r0 = 0; r0 < n_rows; r0 += c->head_rows) {
+    const int64_t nb = std::min<int64_t>(c->head_rows, n_rows - r0);
     for (int32_t g0 = 0; g0 < nch; g0 += c->head_chunks) {
       const int32_t gc = std::min<int32_t>(c->head_chunks, nch - g0);
+      while (c->head_ev.size() < ev + 2) {
+        hipEvent_t x = nullptr;
+        hipError_t e = hipEventCreate(&x);
+        if (e != hipSuccess) return device_fail(c, "hipEventCreate", e);
+        c->head_ev.push_back(x);
+      }
       HIP_TRY(c, hipEventRecord(c->head_ev[ev], s));
-      HIP_TRY(c, launch_head_gemm(c->xh, c->head_H, r0, nb, c->ch_head, (int64_t)g0 * kChunk,
+      HIP_TRY(c, launch_head_gemm(c->xh, c->head_H, r0, nb, rows, chead, (int64_t)g0 * kChunk,
                                   (int64_t)gc * kChunk, c->hs, a.hs_ld, s));
       HIP_TRY(c, hipEventRecord(c->head_ev[ev + 1], s));
       ev += 2;
@@ -844,19 +842,19 @@ skm_status head_pass(skm_ctx *c, ScoreArgs &a, hipStream_t s) {
       HIP_TRY(c, launch_score_part(a, c->part, c->n_cu, c->prec, s, c->score_wpc));
     }
   }
+  a.row_list = nullptr;
   a.row0 = 0;
   a.nb = c->N;
   a.c_first = 0;
-  a.c_count = nch;
-  HIP_TRY(c, launch_finalize(a, c->part, s));
+  a.c_count = (int32_t)((c->k + kChunk - 1) / kChunk);
   return SKM_OK;
 }
 
-// Device time of the head GEMMs of the last pass (after a synchronisation).
-float head_ms(skm_ctx *c) {
+// Device time of the head GEMMs recorded by the last step's passes (after a
+// synchronisation).
+float head_ms(skm_ctx *c, size_t n_ev) {
   float ms = 0.f;
-  const size_t n = 2 * (size_t)head_launches(c);
-  for (size_t i = 0; i + 1 < n && i + 1 < c->head_ev.size(); i += 2)
+  for (size_t i = 0; i + 1 < n_ev && i + 1 < c->head_ev.size(); i += 2)
     ms += elapsed(c->head_ev[i], c->head_ev[i + 1]);
   return ms;
 }
@@ -866,11 +864,9 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
   hipStream_t s = c->stream;
   ScoreArgs a = base_args(c);
   // Sec. 3.1 only pays when a good share of centroids is unchanged: with more
-  // than half changed (a quarter when the head product runs, which NCC rows do
-  // not use), building the compacted copy costs more than the columns it
-  // saves, and every row scores the full copy instead.
-  const int64_t ncc_den = c->head_H > 0 ? 4 : 2;
-  const bool ncc = (c->cfg.flags & SKM_NCC) && c->have_prev && ncc_den * c->last_changed <= c->k;
+  // than half changed, building the compacted copy costs more than the
+  // columns it saves, and every row scores the full copy instead.
+  const bool ncc = (c->cfg.flags & SKM_NCC) && c->have_prev && 2 * c->last_changed <= c->k;
   int32_t n_ch = c->k;
   HIP_TRY(c, hipEventRecord(c->ev[0], s));
   if (ncc) {
@@ -908,12 +904,31 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
     c->idx_eligible = n_rows_idx;
   }
   HIP_TRY(c, hipEventRecord(c->ev[5], s));
-  const bool head = c->head_H > 0 && !ncc;
-  if (head) {
-    ST_TRY(head_pass(c, a, s));
+  const bool head = c->head_H > 0;
+  size_t n_ev = 0;
+  int32_t launches = 1;
+  if (head && !ncc) {
+    ST_TRY(head_pass(c, a, s, c->ch_head, c->k, nullptr, c->N, n_ev));
+    HIP_TRY(c, launch_finalize(a, c->part, s));
+  } else if (head) {
+    // Sec. 3.1 with the head: every row keeping its previous centroid scores
+    // the changed centroids only (their head codes compacted alongside the
+    // compacted code copy); the rows whose previous centroid changed score
+    // all centroids, from their list.  One merge over all rows at the end.
+    int32_t n_full = 0;
+    HIP_TRY(c, launch_gather_head(c->ch_head, c->head_H, c->ch_ids, n_ch, c->ch_head_ch, s));
+    HIP_TRY(c, index_rows(c->a_prev, c->changed, c->N, c->full_rows, c->ids_count, s));
+    HIP_TRY(c, hipMemcpyAsync(&n_full, c->ids_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    a.ncc_only = 1;
+    ST_TRY(head_pass(c, a, s, c->ch_head_ch, n_ch, nullptr, c->N, n_ev));
+    a.ncc_only = 0;
+    ST_TRY(head_pass(c, a, s, c->ch_head, c->k, c->full_rows, n_full, n_ev));
+    HIP_TRY(c, launch_finalize(a, c->part, s));
   } else {
     HIP_TRY(c, launch_score(a, c->part, c->n_cu, c->prec, s, c->score_wpc));
   }
+  launches = head ? std::max<int32_t>(1, (int32_t)(n_ev / 2)) : 1;
   HIP_TRY(c, hipEventRecord(c->ev[1], s));
   if (!a.no_exact) {
     ExactArgs x{a, c->part, c->master, c->D, exact_waves()};
@@ -959,8 +974,8 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
     st_out->score_launches = 1;
     st_out->sparse_products = (double)stv[3];
     if (head) {
-      st_out->ms_head = head_ms(c);
-      st_out->score_launches = (int32_t)head_launches(c);
+      st_out->ms_head = head_ms(c, n_ev);
+      st_out->score_launches = launches;
       st_out->sparse_products = (double)stv[8];
     }
     st_out->objective_assign = st_out->objective_update = st_out->max_shift_sq = -1.0;
@@ -986,7 +1001,9 @@ skm_status skm_autotune(skm_ctx *c, skm_tune_report *report) {
     HIP_TRY(c, launch_fill_i32(reinterpret_cast<int32_t *>(c->stat), 0, 32, s));
     HIP_TRY(c, hipEventRecord(c->ev[5], s));
     if (c->head_H > 0) {
-      ST_TRY(head_pass(c, a, s));
+      size_t n_ev = 0;
+      ST_TRY(head_pass(c, a, s, c->ch_head, c->k, nullptr, c->N, n_ev));
+      HIP_TRY(c, launch_finalize(a, c->part, s));
     } else {
       HIP_TRY(c, launch_score(a, c->part, c->n_cu, c->prec, s, wpc));
     }
@@ -1333,8 +1350,8 @@ skm_status skm_score_head(skm_ctx *c, int64_t row0, int64_t n_rows, float *out) 
     return fail(SKM_E_NOMEM, "temporary device allocation failed");
   }
   // all centroid columns of these rows at once (the batch buffer holds them)
-  hipError_t e = launch_head_gemm(c->xh, c->head_H, row0, n_rows, c->ch_head, 0, c->k_pad, c->hs,
-                                  c->k_pad, c->stream);
+  hipError_t e = launch_head_gemm(c->xh, c->head_H, row0, n_rows, nullptr, c->ch_head, 0, c->k_pad,
+                                  c->hs, c->k_pad, c->stream);
   if (e == hipSuccess)
     e = launch_score_dense(c->r_indptr + row0, c->r_indices, c->r_values, n_rows, c->tile, c->D,
                            c->k, c->scale, tail_view(c, 0), c->prec, c->hs, c->k_pad, d_out,

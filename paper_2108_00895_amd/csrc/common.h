@@ -13,7 +13,7 @@ namespace skm {
 constexpr int kWave = 64;
 constexpr int kColsPerLane = 8;
 constexpr int kChunk = kWave * kColsPerLane;  // centroid columns per wave pass
-constexpr int kBandCap = 256;                 // exact-tier band kept in LDS per row
+constexpr int kBandCap = 1024;                // exact-tier band buffer in LDS per wave (>= 2 chunks)
 
 __host__ __device__ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -51,7 +51,7 @@ __device__ inline bool better_d(double s, int j, double bs, int bj) {
   return s > bs || (s == bs && j < bj);
 }
 
-// Merge (b1, j1, b2) top-two summaries across the wave; every lane ends with
+// Merges (b1, j1, b2) top-two summaries across the wave; every lane ends with
 // the wave's result.  b2 is the best score among all candidates other than j1.
 __device__ inline void wave_top2(float &b1, int &j1, float &b2) {
 #pragma unroll
@@ -66,6 +66,42 @@ __device__ inline void wave_top2(float &b1, int &j1, float &b2) {
     } else {
       b2 = fmaxf(b2, o1);
     }
+  }
+}
+
+// Inserts (s, j) into a list of four kept best first (better(): higher score,
+// then lower index), dropping the fifth.
+__device__ inline void top4_insert(float s, int j, float ts[4], int tj[4]) {
+  if (!better(s, j, ts[3], tj[3])) return;
+  ts[3] = s;
+  tj[3] = j;
+#pragma unroll
+  for (int q = 3; q > 0; --q) {
+    if (better(ts[q], tj[q], ts[q - 1], tj[q - 1])) {
+      const float x = ts[q];
+      ts[q] = ts[q - 1];
+      ts[q - 1] = x;
+      const int y = tj[q];
+      tj[q] = tj[q - 1];
+      tj[q - 1] = y;
+    }
+  }
+}
+
+// Top four over the wavefront (butterfly: the two halves merged at each step
+// hold disjoint columns); every lane ends with the result.
+__device__ inline void wave_top4(float ts[4], int tj[4]) {
+#pragma unroll
+  for (int m = 1; m < kWave; m <<= 1) {
+    float os[4];
+    int oj[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      os[q] = __shfl_xor(ts[q], m, kWave);
+      oj[q] = __shfl_xor(tj[q], m, kWave);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) top4_insert(os[q], oj[q], ts, tj);
   }
 }
 

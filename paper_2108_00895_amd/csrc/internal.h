@@ -43,9 +43,14 @@ struct ScoreArgs {
   // or nullptr
   const float *hs;
   int64_t hs_ld;
-  int64_t row0, nb;           // rows of this scoring launch
+  int64_t row0, nb;           // rows of this scoring launch: row0 .. row0 + nb, or
+                              // row_list[row0 .. row0 + nb) when row_list is given
+  const int32_t *row_list;
   int32_t c_first, c_count;   // 512-centroid chunks of this launch (items = c_count x nb)
+  int32_t ncc_only;           // 1: rows whose previous centroid changed are left out
+                              // (a second launch over their list scores them)
   int32_t head_H;             // head terms in the partial scores' bound (0: none)
+  int32_t top;                // entries kept per (row, chunk) partial: 2 or 4
   // scoring copy, chunk-blocked term-major (see tile_index)
   const uint8_t *tile;
   int64_t D;
@@ -82,12 +87,19 @@ struct ScoreArgs {
                               // [3] products, [8] products of the sparse pass (head on)
 };
 
-// Top two of one row against one 512-centroid chunk.
-struct Partial {
-  float b1;
-  int32_t j1;
-  float b2;
-  int32_t pad;
+// Best scores of one row against one 512-centroid chunk, best first (higher
+// score, then lower centroid index); -inf where the chunk has fewer columns.
+// With top = 4 (FP8 scoring, whose wide bound makes large bands) all four
+// entries are kept and the exact tier takes a chunk's band members from them
+// without rescoring the chunk when the fourth cannot reach the row's bound;
+// with top = 2 only e[0] and the score of e[1] are kept.  The merge certifies
+// from the first two.
+constexpr int kTop = 4;
+struct __align__(16) Partial {
+  struct {
+    float s;
+    int32_t j;
+  } e[kTop];
 };
 
 struct ExactArgs {
@@ -266,6 +278,8 @@ struct skm_ctx {
   int32_t *head_slot = nullptr;  // [D] slot of a head term, -1 otherwise
   uint16_t *xh = nullptr;        // [N][H] BF16 head values of the rows
   uint16_t *ch_head = nullptr;   // [k_pad][H] BF16 head codes of the centroids
+  uint16_t *ch_head_ch = nullptr; // the same for the changed centroids, compacted (NCC)
+  int32_t *full_rows = nullptr;  // [N] rows whose previous centroid changed (NCC)
   float *hs = nullptr;           // [head_rows][k_pad] head scores of one batch
   int64_t *r_indptr = nullptr;   // remainder CSR: the rows' non-head terms
   int32_t *r_indices = nullptr;
@@ -389,10 +403,14 @@ hipError_t launch_head_split(const int64_t *indptr, const int32_t *indices, cons
 hipError_t launch_head_codes(const uint8_t *tile, int64_t D, int32_t k, int prec,
                              const int32_t *terms, int32_t H, int32_t k_pad, uint16_t *ch,
                              hipStream_t s);
-// hs[r][j] = sum_h xh[row0 + r][h] * ch[col0 + j][h], r < nb, j < ncols
-// (ncols a multiple of 256, col0 + ncols <= rows of ch).
+// hs[r][j] = sum_h xh[x_r][h] * ch[col0 + j][h], r < nb, j < ncols, where
+// x_r = row0 + r, or rows[row0 + r] when rows is given (ncols a multiple of
+// 256, col0 + ncols <= rows of ch).
 hipError_t launch_head_gemm(const uint16_t *xh, int32_t H, int64_t row0, int64_t nb,
-                            const uint16_t *ch, int64_t col0, int64_t ncols, float *hs,
-                            int64_t ldh, hipStream_t s);
+                            const int32_t *rows, const uint16_t *ch, int64_t col0, int64_t ncols,
+                            float *hs, int64_t ldh, hipStream_t s);
+// out[o][:] = ch[ids[o]][:] for o < n (rows of H BF16 codes).
+hipError_t launch_gather_head(const uint16_t *ch, int32_t H, const int32_t *ids, int32_t n,
+                              uint16_t *out, hipStream_t s);
 
 }  // namespace skm

@@ -119,6 +119,14 @@ __global__ __launch_bounds__(256) void k_head_codes(const uint8_t *tile, int64_t
   }
 }
 
+// Rows of head codes of the listed centroids (16-byte copies; H % 8 == 0).
+__global__ __launch_bounds__(256) void k_gather_head(const uint16_t *ch, int32_t H,
+                                                     const int32_t *ids, uint16_t *out) {
+  const uint4 *src = reinterpret_cast<const uint4 *>(ch + (int64_t)ids[blockIdx.x] * H);
+  uint4 *dst = reinterpret_cast<uint4 *>(out + (int64_t)blockIdx.x * H);
+  for (int i = threadIdx.x; i < H / 8; i += blockDim.x) dst[i] = src[i];
+}
+
 // ------------------------------------------------------------------ GEMM
 // hs[r][j] = sum_h xh[row0 + r][h] * ch[j][h] for r < nb, j < ncp (ch already
 // offset to the first column).  Consecutive workgroups take consecutive column
@@ -138,6 +146,7 @@ constexpr int kGTile = kGM * kGRow;   // bytes per operand tile
 
 __global__ __launch_bounds__(512) void k_head_gemm(const uint16_t *__restrict__ xh, int32_t H,
                                                    int64_t row0, int64_t nb,
+                                                   const int32_t *__restrict__ rows,
                                                    const uint16_t *__restrict__ ch, int64_t ncp,
                                                    float *__restrict__ hs, int64_t ldh) {
   __shared__ __attribute__((aligned(16))) uint8_t lds[2][2][kGTile];
@@ -159,7 +168,9 @@ __global__ __launch_bounds__(512) void k_head_gemm(const uint16_t *__restrict__ 
   const uint4 *xv = reinterpret_cast<const uint4 *>(xh);
   const uint4 *cv = reinterpret_cast<const uint4 *>(ch);
   const int64_t h8 = H / 8;
-#define SKM_AROW(u) (row0 + min<int64_t>(r_base + pr + 64 * (u), nb - 1))
+#define SKM_AROW(u)                                                   \
+  (rows ? (int64_t)rows[row0 + min<int64_t>(r_base + pr + 64 * (u), nb - 1)] \
+        : row0 + min<int64_t>(r_base + pr + 64 * (u), nb - 1))
   const int64_t oa0 = SKM_AROW(0) * h8 + kq, oa1 = SKM_AROW(1) * h8 + kq;
   const int64_t oa2 = SKM_AROW(2) * h8 + kq, oa3 = SKM_AROW(3) * h8 + kq;
 #undef SKM_AROW
@@ -357,13 +368,20 @@ hipError_t launch_head_codes(const uint8_t *tile, int64_t D, int32_t k, int prec
 }
 
 hipError_t launch_head_gemm(const uint16_t *xh, int32_t H, int64_t row0, int64_t nb,
-                            const uint16_t *ch, int64_t col0, int64_t ncols, float *hs,
-                            int64_t ldh, hipStream_t s) {
+                            const int32_t *rows, const uint16_t *ch, int64_t col0, int64_t ncols,
+                            float *hs, int64_t ldh, hipStream_t s) {
   if (nb <= 0) return hipSuccess;
   if (H % kGK != 0 || ncols % kGN != 0 || ldh < ncols) return hipErrorInvalidValue;
   const int64_t blocks = ((nb + kGM - 1) / kGM) * (ncols / kGN);
-  hipLaunchKernelGGL(k_head_gemm, dim3((unsigned)blocks), dim3(512), 0, s, xh, H, row0, nb,
+  hipLaunchKernelGGL(k_head_gemm, dim3((unsigned)blocks), dim3(512), 0, s, xh, H, row0, nb, rows,
                      ch + col0 * (int64_t)H, ncols, hs, ldh);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_head(const uint16_t *ch, int32_t H, const int32_t *ids, int32_t n,
+                              uint16_t *out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_head, dim3((unsigned)n), dim3(256), 0, s, ch, H, ids, out);
   return hipGetLastError();
 }
 

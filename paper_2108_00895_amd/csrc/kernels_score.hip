@@ -317,9 +317,11 @@ __global__ __launch_bounds__(256) void k_score_part(ScoreArgs a, Partial *__rest
   if (a.n_dev) n_items = (int64_t)a.c_count * nb;
   for (int64_t it = (int64_t)blockIdx.x * 4 + wave; it < n_items; it += stride) {
     const int64_t ci = uniform64(it / nb);
-    const int64_t row = uniform64(a.row0 + (it - ci * nb));
+    const int64_t r = uniform64(it - ci * nb);
+    const int64_t row = a.row_list ? uniform64((int64_t)a.row_list[a.row0 + r]) : a.row0 + r;
     const int64_t c = a.c_first + ci;
     const RowPlan pl = plan_row(a, row, true);
+    if (a.ncc_only && !pl.ncc) continue;
     const int64_t c0 = c * kChunk;
     if (c0 >= pl.ncols) continue;
     const int64_t b = uniform64(a.sc_indptr[row]);
@@ -327,8 +329,8 @@ __global__ __launch_bounds__(256) void k_score_part(ScoreArgs a, Partial *__rest
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (a.hs) {
       // start from the head scores of these 8 columns (kernels_head.hip)
-      const float4 *h = reinterpret_cast<const float4 *>(a.hs + (row - a.row0) * a.hs_ld +
-                                                         ci * kChunk + lane * kColsPerLane);
+      const float4 *h = reinterpret_cast<const float4 *>(a.hs + r * a.hs_ld + ci * kChunk +
+                                                         lane * kColsPerLane);
       const float4 h0 = h[0], h1 = h[1];
       acc[0] = h0.x;
       acc[1] = h0.y;
@@ -341,26 +343,55 @@ __global__ __launch_bounds__(256) void k_score_part(ScoreArgs a, Partial *__rest
     }
     score_chunk<P>(b, e, a.sc_indices, a.sc_values, pl.tile, a.D, c0, pl.ncols - c0, acc, *pl.tv,
                    lacc);
-    float b1 = -INFINITY, b2 = -INFINITY;
-    int j1 = 0x7FFFFFFF;
+    if (a.top == kTop) {
+      float ts[kTop] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+      int tj[kTop] = {0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF};
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int64_t col = c0 + lane * kColsPerLane + q;
-      if (col < pl.ncols) {
-        const int j = pl.colmap ? pl.colmap[col] : (int)col;
-        float s = acc[q];
-        if (a.scale) s *= a.scale[j];
-        if (better(s, j, b1, j1)) {
-          b2 = b1;
-          b1 = s;
-          j1 = j;
-        } else if (s > b2) {
-          b2 = s;
+      for (int q = 0; q < 8; ++q) {
+        const int64_t col = c0 + lane * kColsPerLane + q;
+        if (col < pl.ncols) {
+          const int j = pl.colmap ? pl.colmap[col] : (int)col;
+          float s = acc[q];
+          if (a.scale) s *= a.scale[j];
+          top4_insert(s, j, ts, tj);
         }
       }
+      wave_top4(ts, tj);
+      if (lane == 0) {
+        Partial p;
+#pragma unroll
+        for (int q = 0; q < kTop; ++q) {
+          p.e[q].s = ts[q];
+          p.e[q].j = tj[q];
+        }
+        part[c * a.n_rows + row] = p;
+      }
+    } else {
+      float b1 = -INFINITY, b2 = -INFINITY;
+      int j1 = 0x7FFFFFFF;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int64_t col = c0 + lane * kColsPerLane + q;
+        if (col < pl.ncols) {
+          const int j = pl.colmap ? pl.colmap[col] : (int)col;
+          float s = acc[q];
+          if (a.scale) s *= a.scale[j];
+          if (better(s, j, b1, j1)) {
+            b2 = b1;
+            b1 = s;
+            j1 = j;
+          } else if (s > b2) {
+            b2 = s;
+          }
+        }
+      }
+      wave_top2(b1, j1, b2);
+      if (lane == 0) {
+        // the first two entries only (16 bytes)
+        float4 *dst = reinterpret_cast<float4 *>(&part[c * a.n_rows + row]);
+        *dst = make_float4(b1, __int_as_float(j1), b2, __int_as_float(0x7FFFFFFF));
+      }
     }
-    wave_top2(b1, j1, b2);
-    if (lane == 0) part[c * a.n_rows + row] = Partial{b1, j1, b2, 0};
   }
 }
 
@@ -381,12 +412,12 @@ __global__ __launch_bounds__(256) void k_finalize(ScoreArgs a, const Partial *__
     const int64_t nch = (pl.ncols + kChunk - 1) / kChunk;
     for (int64_t c = 0; c < nch; ++c) {
       const Partial p = part[c * a.n_rows + row];
-      if (better(p.b1, p.j1, b1, j1)) {
-        b2 = fmaxf(b1, p.b2);
-        b1 = p.b1;
-        j1 = p.j1;
+      if (better(p.e[0].s, p.e[0].j, b1, j1)) {
+        b2 = fmaxf(b1, p.e[1].s);
+        b1 = p.e[0].s;
+        j1 = p.e[0].j;
       } else {
-        b2 = fmaxf(b2, p.b1);
+        b2 = fmaxf(b2, p.e[0].s);
       }
     }
     const int64_t n = e - b;
@@ -471,11 +502,15 @@ __device__ inline double dot64(int64_t b, int64_t e, const int32_t *__restrict__
   return s;
 }
 
-// Exact tier.  For each flagged row: recompute the low-precision scores, keep
-// the band of candidates whose upper bound reaches the row's certified lower
-// bound L (every centroid that can be the true maximum), and decide among them
-// in FP64 against the FP64 centroids (lowest index on ties).  When the band
-// exceeds kBandCap every candidate is rescored in FP64.
+// Exact tier.  For each flagged row: first the FP64 scores of the
+// low-precision winner (and, for an NCC row, of the previous centroid); the
+// best of them, less its FP64 error, is a lower bound of the true maximum at
+// least as high as the row's certified L and narrows the band.  Then recompute
+// the low-precision scores, keep the band of candidates whose upper bound
+// reaches that bound (every centroid that can be the true maximum) and decide
+// among them in FP64 against the FP64 centroids (lowest index on ties).  The
+// band is collected in LDS and scored whenever the buffer could overflow, so
+// its size is not limited.
 template <int P>
 __global__ __launch_bounds__(256) void k_exact(ExactArgs x) {
   __shared__ int32_t band_all[4][kBandCap];
@@ -489,7 +524,6 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs x) {
   const int32_t n_flag = uniform32(*(volatile int32_t *)&a.counters[0]);
   for (int64_t f = (int64_t)blockIdx.x * 4 + wave; f < n_flag; f += (int64_t)gridDim.x * 4) {
     const int64_t row = uniform64(a.flag_rows[f]);
-    const double L = a.flag_L[f];
     const bool ncc_row = a.flag_mode[f] == 1;
     const int64_t b = uniform64(a.indptr[row]);
     const int64_t e = uniform64(a.indptr[row + 1]);
@@ -503,6 +537,34 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs x) {
       pl.ncc = true;
       pl.ap = a.a_prev[row];
     }
+    const int64_t nch = (pl.ncols + kChunk - 1) / kChunk;
+    // seeds: the merged low-precision winner and the previous centroid
+    float w1 = -INFINITY;
+    int wj = 0x7FFFFFFF;
+    for (int64_t c = 0; c < nch; ++c) {
+      const Partial p = x.part[c * a.n_rows + row];
+      if (better(p.e[0].s, p.e[0].j, w1, wj)) {
+        w1 = p.e[0].s;
+        wj = p.e[0].j;
+      }
+    }
+    // (each seed's FP64 dot product by the whole wavefront, lanes over terms)
+    double bs = -INFINITY;
+    int bj = 0x7FFFFFFF;
+    double L = a.flag_L[f];
+    for (int q = 0; q < 2; ++q) {
+      const int seed = q == 0 ? (w1 == -INFINITY ? -1 : wj) : (pl.ncc ? pl.ap : -1);
+      if (seed < 0) continue;
+      const double *crow = x.master + (int64_t)seed * x.D;
+      double t = 0.0;
+      for (int64_t k = b + lane; k < e; k += kWave) t = fma((double)a.values[k], crow[a.indices[k]], t);
+      t = wave_sum_d(t);
+      L = fmax(L, t - exact_err(n, t));
+      if (lane == q && better_d(t, seed, bs, bj)) {
+        bs = t;
+        bj = seed;
+      }
+    }
     // bound of the rescoring below (all terms, sparse path)
     const double kap = bound_kappa(n, a.uq);
     const double A = bound_abs(n, a.xl1[row], a.abs_coef);
@@ -512,15 +574,39 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs x) {
     auto phi_of = [&](float s) {
       return s == -INFINITY ? -INFINITY : (double)s + (pkap * (double)s + pA);
     };
-    int nb = 0;
+    int nb = 0;           // members in the buffer
+    int64_t total = 0;    // band size
+    auto flush = [&]() {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int i = lane; i < nb; i += kWave) {
+        const int j = band[i];
+        const double s = dot64(b, e, a.indices, a.values, x.master + (int64_t)j * x.D);
+        if (better_d(s, j, bs, bj)) {
+          bs = s;
+          bj = j;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      total += nb;
+      nb = 0;
+    };
     for (int64_t c0 = 0; c0 < pl.ncols; c0 += kChunk) {
-      // A chunk whose second-best upper bound is below L can only contribute
-      // its best centroid: skip rescoring it.
+      if (nb + kChunk > kBandCap) flush();
+      // A chunk whose last kept score cannot reach L contributes only kept
+      // entries (its best one when two are kept, whose second then misses
+      // L): take them without rescoring the chunk.
       const Partial p = x.part[(c0 / kChunk) * a.n_rows + row];
-      if (phi_of(p.b2) < L) {
-        if (phi_of(p.b1) >= L) {
-          if (lane == 0 && nb < kBandCap) band[nb] = p.j1;
-          nb += 1;
+      const int kept = a.top == kTop ? kTop : 2;
+      if (phi_of(p.e[kept - 1].s) < L) {
+        for (int q = 0; q < kept - 1; ++q) {
+          if (phi_of(p.e[q].s) >= L) {
+            if (lane == 0) band[nb] = p.e[q].j;
+            nb += 1;
+          }
         }
         continue;
       }
@@ -538,56 +624,18 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs x) {
           in = s + (kap * s + A) >= L;
         }
         const uint64_t m = __ballot(in);
-        if (in) {
-          const int pos = nb + __popcll(m & lanemask_lt());
-          if (pos < kBandCap) band[pos] = j;
-        }
+        if (in) band[nb + __popcll(m & lanemask_lt())] = j;
         nb += __popcll(m);
       }
     }
-    if (pl.ncc) {
-      if (lane == 0 && nb < kBandCap) band[nb] = pl.ap;
-      nb += 1;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-    double bs = -INFINITY;
-    int bj = 0x7FFFFFFF;
-    if (nb <= kBandCap) {
-      for (int i = lane; i < nb; i += kWave) {
-        const int j = band[i];
-        const double s = dot64(b, e, a.indices, a.values, x.master + (int64_t)j * x.D);
-        if (better_d(s, j, bs, bj)) {
-          bs = s;
-          bj = j;
-        }
-      }
-    } else {
-      for (int64_t col = lane; col < pl.ncols; col += kWave) {
-        const int j = pl.colmap ? pl.colmap[col] : (int)col;
-        const double s = dot64(b, e, a.indices, a.values, x.master + (int64_t)j * x.D);
-        if (better_d(s, j, bs, bj)) {
-          bs = s;
-          bj = j;
-        }
-      }
-      if (pl.ncc && lane == 0) {
-        const double s = dot64(b, e, a.indices, a.values, x.master + (int64_t)pl.ap * x.D);
-        if (better_d(s, pl.ap, bs, bj)) {
-          bs = s;
-          bj = pl.ap;
-        }
-      }
-    }
+    flush();
     wave_best_d(bs, bj);
     if (lane == 0) {
       const double err = exact_err(n, bs);
       a.a_out[row] = bj;
       a.lo_out[row] = bs - err;
       a.hi_out[row] = bs + err;
-      if (nb > kBandCap) atomicAdd(&a.counters[1], 1);
+      if (total > kBandCap) atomicAdd(&a.counters[1], 1);
     }
     __builtin_amdgcn_wave_barrier();
   }

@@ -194,3 +194,33 @@ def test_set_schedule_validates(mid):
     say("  flagged", a0["flagged"], "best", rep["best"])
     ctx.close()
     other.close()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_head_with_ncc_trajectory_equals_oracle(prec):
+    """NCC iterations with the head: rows keeping their centroid score the
+    compacted changed centroids (head codes compacted too), the others score
+    all centroids from their list; every step must equal the oracle.  40 rows
+    per cluster keep a partial changed set for several iterations."""
+    say("case: head + ncc trajectory", prec)
+    csr, c = corpus(8000, 6000, nnz_mean=50.0, nnz_max=300, seed=47)
+    k, T = 200, 14
+    rows = synth.seed_rows(c.n_docs, k, 3)
+    ref = oracle.run(csr, c.n_terms, k, rows, max_iter=T, stop_rule="fixed")
+    ctx = Context(to_device(csr), c.n_terms, k, init_rows=rows, precision=prec, ncc=True,
+                  head_max_terms=128, head_min_df=0.0, stop_rule="fixed", max_iter=T)
+    both = 0
+    for t, rec in enumerate(ref.records):
+        st = ctx.assign()
+        assert st["head_terms"] == 128
+        # both passes ran: some rows kept their centroid, some did not, and
+        # some (but not all) centroids changed
+        both += 0 < st["ncc_rows"] < c.n_docs and 0 < st["changed_centroids"] <= k // 2
+        assert_assign_equal(ctx.assignments(), rec.a, rec.s1, rec.s2, f"{prec} it {t}")
+        assert st["moved"] == rec.moved
+        u = ctx.update()
+        assert abs(u["objective_update"] - rec.J_U) <= 1e-9 * abs(rec.J_U)
+        say(f"  it {t}: changed {st['changed_centroids']} ncc rows {st['ncc_rows']} "
+            f"flagged {st['flagged']}")
+    assert both >= 3, "NCC with the head did not run with a partial changed set"
+    ctx.close()
