@@ -223,6 +223,15 @@ skm_status skm_get_assignments(const skm_ctx *c, int32_t *out, int32_t on_device
 /* Current FP64 centroids, k x n_cols row-major, into out. */
 skm_status skm_get_centroids(const skm_ctx *c, double *out, int32_t on_device);
 
+/* FP64 centroid values at the listed terms: out[j * n_terms + q] = c_j[terms[q]]
+ * for every centroid j (host arrays; out holds k * n_terms doubles).  For checks
+ * at sizes where the dense k x n_cols copy is too large to fetch. */
+skm_status skm_get_centroid_columns(const skm_ctx *c, const int32_t *terms, int32_t n_terms,
+                                    double *out);
+
+/* FP64 centroids of the listed ids: out[q * n_cols + t] = c_{ids[q]}[t] (host). */
+skm_status skm_get_centroid_rows(const skm_ctx *c, const int32_t *ids, int32_t n, double *out);
+
 /* Replaces the centroids (host, k x n_cols, unit rows, non-negative), rebuilds
  * the scoring copies and marks every centroid changed.  For checks that feed
  * known centroids into one assignment step. */

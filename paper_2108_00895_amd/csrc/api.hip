@@ -1249,6 +1249,48 @@ skm_status skm_get_centroids(const skm_ctx *c, double *out, int32_t on_device) {
   return SKM_OK;
 }
 
+skm_status skm_get_centroid_columns(const skm_ctx *c, const int32_t *terms, int32_t n_terms,
+                                    double *out) {
+  ST_TRY(check_ctx(c));
+  if (n_terms < 0 || (n_terms > 0 && (!terms || !out)))
+    return fail(SKM_E_INVALID, "terms or out is NULL");
+  if (n_terms == 0) return SKM_OK;
+  for (int32_t q = 0; q < n_terms; ++q)
+    if (terms[q] < 0 || terms[q] >= c->D) return fail(SKM_E_INVALID, "term index out of range");
+  int32_t *d_terms = nullptr;
+  double *d_out = nullptr;
+  if (hipMalloc(&d_terms, sizeof(int32_t) * n_terms) != hipSuccess ||
+      hipMalloc(&d_out, sizeof(double) * n_terms * (size_t)c->k) != hipSuccess) {
+    (void)hipGetLastError();
+    if (d_terms) (void)hipFree(d_terms);
+    return fail(SKM_E_NOMEM, "temporary device allocation failed");
+  }
+  hipStream_t s = c->stream;
+  hipError_t e = hipMemcpyAsync(d_terms, terms, sizeof(int32_t) * n_terms, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_centroid_columns(c->master, c->k, c->D, d_terms, n_terms, d_out, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, d_out, sizeof(double) * n_terms * (size_t)c->k, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d_terms);
+  (void)hipFree(d_out);
+  if (e != hipSuccess) return device_fail(const_cast<skm_ctx *>(c), "get_centroid_columns", e);
+  return SKM_OK;
+}
+
+skm_status skm_get_centroid_rows(const skm_ctx *c, const int32_t *ids, int32_t n, double *out) {
+  ST_TRY(check_ctx(c));
+  if (n < 0 || (n > 0 && (!ids || !out))) return fail(SKM_E_INVALID, "ids or out is NULL");
+  for (int32_t q = 0; q < n; ++q)
+    if (ids[q] < 0 || ids[q] >= c->k) return fail(SKM_E_INVALID, "centroid id out of range");
+  hipError_t e = hipSuccess;
+  for (int32_t q = 0; q < n && e == hipSuccess; ++q)
+    e = hipMemcpyAsync(out + (size_t)q * c->D, c->master + (size_t)ids[q] * c->D,
+                       sizeof(double) * c->D, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return device_fail(const_cast<skm_ctx *>(c), "get_centroid_rows", e);
+  return SKM_OK;
+}
+
 skm_status skm_set_centroids(skm_ctx *c, const double *centroids) {
   ST_TRY(check_ctx_writable(c));
   if (!centroids) return fail(SKM_E_INVALID, "centroids is NULL");

@@ -377,6 +377,8 @@ hipError_t launch_compact_changed(const uint8_t *changed, int32_t k, int32_t *id
                                   hipStream_t s);
 hipError_t launch_gather_tile(const uint8_t *tile, int64_t D, int esize, const int32_t *ids,
                               int32_t n, uint8_t *out, hipStream_t s);
+hipError_t launch_centroid_columns(const double *master, int32_t k, int64_t D, const int32_t *terms,
+                                   int32_t n, double *out, hipStream_t s);
 hipError_t launch_bucket(const int32_t *a, int64_t n, int32_t k, int64_t nblk, int32_t *hist,
                          int32_t *counts, int64_t *offsets, int32_t *members, hipStream_t s);
 hipError_t launch_sum_members(const int64_t *indptr, const int32_t *indices, const float *values,

@@ -198,6 +198,14 @@ __global__ void k_gather_tile(const T *tile, int64_t D, const int32_t *ids, int3
     out[tile_index(t, o, D)] = tile[tile_index(t, ids[o], D)];
 }
 
+// out[j * n + q] = master[j][terms[q]] (one workgroup per centroid).
+__global__ __launch_bounds__(256) void k_centroid_columns(const double *master, int64_t D,
+                                                          const int32_t *terms, int32_t n,
+                                                          double *out) {
+  const int64_t j = blockIdx.x;
+  for (int q = threadIdx.x; q < n; q += blockDim.x) out[j * n + q] = master[j * D + terms[q]];
+}
+
 // ---- stable counting sort of rows by cluster
 
 __global__ void k_block_hist(const int32_t *a, int64_t n, int32_t k, int32_t *hist) {
@@ -511,6 +519,13 @@ hipError_t launch_gather_tile(const uint8_t *tile, int64_t D, int esize, const i
       break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_centroid_columns(const double *master, int32_t k, int64_t D, const int32_t *terms,
+                                   int32_t n, double *out, hipStream_t s) {
+  if (n <= 0 || k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_centroid_columns, dim3((unsigned)k), dim3(256), 0, s, master, D, terms, n, out);
   return hipGetLastError();
 }
 

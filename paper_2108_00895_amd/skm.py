@@ -26,7 +26,8 @@ CODE_BYTES = {FP32: 4, BF16: 2, FP8_E4M3: 1}
 
 EXPORTED = [
     "skm_config_default", "skm_init", "skm_assign", "skm_update", "skm_iterate",
-    "skm_assign_new", "skm_get_assignments", "skm_get_centroids", "skm_set_centroids",
+    "skm_assign_new", "skm_get_assignments", "skm_get_centroids", "skm_get_centroid_columns",
+    "skm_get_centroid_rows", "skm_set_centroids",
     "skm_get_tile", "skm_get_changed", "skm_score_dense", "skm_error_bound", "skm_head_terms",
     "skm_score_head", "skm_error_bound_head", "skm_autotune", "skm_set_schedule", "skm_get_index",
     "skm_index_query", "skm_server_config_default", "skm_server_start", "skm_server_submit",
@@ -150,6 +151,10 @@ def load():
     lib.skm_score_dense.restype = st
     lib.skm_error_bound.argtypes = [vp, ctypes.c_double, i64, ctypes.c_double]
     lib.skm_error_bound.restype = ctypes.c_double
+    lib.skm_get_centroid_rows.argtypes = [vp, vp, i32, vp]
+    lib.skm_get_centroid_rows.restype = st
+    lib.skm_get_centroid_columns.argtypes = [vp, vp, i32, vp]
+    lib.skm_get_centroid_columns.restype = st
     lib.skm_autotune.argtypes = [vp, P(TuneReport)]
     lib.skm_autotune.restype = st
     lib.skm_set_schedule.argtypes = [vp, P(TuneTrial)]
@@ -374,6 +379,20 @@ class Context:
 
     def error_bound(self, s, nnz, l1):
         return load().skm_error_bound(self._h, float(s), int(nnz), float(l1))
+
+    def centroid_rows(self, ids):
+        """FP64 centroids of the given ids, len(ids) x n_cols."""
+        t = np.ascontiguousarray(ids, dtype=np.int32)
+        out = np.empty((len(t), self.n_cols), dtype=np.float64)
+        _check(load().skm_get_centroid_rows(self._h, t.ctypes.data, len(t), out.ctypes.data))
+        return out
+
+    def centroid_columns(self, terms):
+        """FP64 centroid values at the given terms, k x len(terms)."""
+        t = np.ascontiguousarray(terms, dtype=np.int32)
+        out = np.empty((self.k, len(t)), dtype=np.float64)
+        _check(load().skm_get_centroid_columns(self._h, t.ctypes.data, len(t), out.ctypes.data))
+        return out
 
     def autotune(self):
         """Times candidate shapes of the scoring work and keeps the fastest;
