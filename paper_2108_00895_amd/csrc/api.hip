@@ -188,35 +188,55 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 int ent_words(int prec) { return prec == SKM_FP32 ? 2 : 1; }
 
 // Tail lists (kernels_tail.hip) of copy `which` (0 full, 1 compacted) with
-// ncols columns; the entry buffer grows on demand.
-skm_status build_tail(skm_ctx *c, int which, const uint8_t *tile, int32_t ncols) {
+// ncols columns.  `chunks` (ascending) lists the chunks whose codes changed
+// since the last build, nullptr = all; the other chunks keep their lists.
+// Each chunk owns `stride` entries of the entry buffer; when a chunk outgrows
+// it the buffer is reallocated with 25 % headroom and every chunk refilled.
+skm_status build_tail(skm_ctx *c, int which, const uint8_t *tile, int32_t ncols,
+                      const std::vector<int32_t> *chunks) {
   skm_ctx::Tail &T = c->tails[which];
+  const bool was_ready = T.ready;
   T.ready = false;
   if (!c->use_tail || ncols <= 0) return SKM_OK;
   hipStream_t s = c->stream;
-  const int nch = (ncols + kChunk - 1) / kChunk;
-  const int64_t dense_max = c->D;   // no cap on the dense set
-  HIP_TRY(c, tail_count(tile, c->D, ncols, c->prec, dense_max, T.cnt, T.cf, T.hist, T.tail, T.off,
-                        T.base, s));
-  uint64_t total = 0;
-  HIP_TRY(c, hipMemcpyAsync(&total, T.base + nch, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-  HIP_TRY(c, hipStreamSynchronize(s));
-  const int64_t words = (int64_t)total * ent_words(c->prec);
-  if (words > T.cap_entries) {
-    // free the old list and allocate 25 % headroom
-    if (T.ent) {
-      auto it = std::find(c->allocations.begin(), c->allocations.end(), (void *)T.ent);
-      if (it != c->allocations.end()) c->allocations.erase(it);
-      (void)hipFree(T.ent);
-      c->hbm_bytes -= round_up(std::max<int64_t>(T.cap_entries * 4, 1), 256);
-      T.ent = nullptr;
-      T.cap_entries = 0;
-    }
-    const int64_t cap = std::max<int64_t>(words + words / 4, 1024);
-    ST_TRY(dalloc(c, &T.ent, (size_t)cap));
-    T.cap_entries = cap;
+  const int32_t nch = (ncols + kChunk - 1) / kChunk;
+  const int32_t nch_max = (c->k + kChunk - 1) / kChunk;
+  std::vector<int32_t> all(nch);
+  for (int32_t q = 0; q < nch; ++q) all[q] = q;
+  const bool partial = chunks && was_ready && (int32_t)T.h_total.size() == nch;
+  const std::vector<int32_t> &list = partial ? *chunks : all;
+  T.h_total.resize(nch, 0);
+  const int32_t n = (int32_t)list.size();
+  if (n > 0) {
+    std::vector<uint32_t> tot(n);
+    HIP_TRY(c, hipMemcpyAsync(T.chunks, list.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+    HIP_TRY(c, tail_count(tile, c->D, ncols, c->prec, T.chunks, n, T.cnt, T.tail, T.off, T.totals,
+                          s));
+    HIP_TRY(c, hipMemcpyAsync(tot.data(), T.totals, sizeof(uint32_t) * n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    for (int32_t q = 0; q < n; ++q) T.h_total[list[q]] = tot[q];
   }
-  HIP_TRY(c, tail_fill(tile, c->D, ncols, c->prec, T.tail, T.off, T.base, T.ent, s));
+  int64_t need = 0;
+  for (int64_t v : T.h_total) need = std::max(need, v);
+  need *= ent_words(c->prec);
+  const std::vector<int32_t> *fill = &list;
+  if (need > T.stride) {
+    if (T.ent) dfree(c, T.ent, sizeof(uint32_t) * T.stride * nch_max);
+    T.ent = nullptr;
+    T.stride = 0;
+    const int64_t stride = std::max<int64_t>(need + need / 4, 1024);
+    ST_TRY(dalloc(c, &T.ent, (size_t)(stride * nch_max)));
+    T.stride = stride;
+    HIP_TRY(c, tail_bases(T.base, nch_max, stride / ent_words(c->prec), s));
+    if (partial && n != nch) {
+      HIP_TRY(c, hipMemcpyAsync(T.chunks, all.data(), sizeof(int32_t) * nch, hipMemcpyHostToDevice,
+                                s));
+      fill = &all;
+    }
+  }
+  HIP_TRY(c, tail_fill(tile, c->D, ncols, c->prec, T.chunks, (int32_t)fill->size(), T.tail, T.off,
+                       T.stride / ent_words(c->prec), T.ent, s));
+  if (fill == &all && partial) HIP_TRY(c, hipStreamSynchronize(s));   // `all` leaves scope
   T.ready = true;
   return SKM_OK;
 }
@@ -228,13 +248,14 @@ TailView tail_view(const skm_ctx *c, int which) {
 }
 
 // Scoring copies of the centroids flagged in `changed` (all when nullptr),
-// and the full copy's tail lists.
-skm_status rebuild_tiles(skm_ctx *c, const uint8_t *changed) {
+// and the full copy's tail lists (of the chunks in `chunks` when given).
+skm_status rebuild_tiles(skm_ctx *c, const uint8_t *changed,
+                         const std::vector<int32_t> *chunks) {
   if (c->prec == SKM_FP8_E4M3)
     HIP_TRY(c, launch_fp8_scales(c->master, c->k, c->D, changed, c->scale, c->stream));
   HIP_TRY(c, launch_quantize(c->master, c->k, c->D, changed, c->scale, c->prec, c->tile,
                              c->stream));
-  ST_TRY(build_tail(c, 0, c->tile, c->k));
+  ST_TRY(build_tail(c, 0, c->tile, c->k, changed ? chunks : nullptr));
   if (c->head_H > 0)
     HIP_TRY(c, launch_head_codes(c->tile, c->D, c->k, c->prec, c->head_terms, c->head_H, c->k_pad,
                                  c->ch_head, c->stream));
@@ -383,10 +404,12 @@ constexpr int64_t kWorkBytes = 2ll << 30;  // partial-row workspace cap
 // with at most kSegRows members are summed by one workgroup each; larger ones
 // are split into segments summed in parallel into workspace rows and combined
 // in segment order.  Rounds keep the workspace within kWorkBytes.
-skm_status sum_changed(skm_ctx *c, int32_t n_ids) {
+skm_status sum_changed(skm_ctx *c, int32_t n_ids, std::vector<int32_t> &ids) {
+  ids.clear();
   if (n_ids <= 0) return SKM_OK;
   hipStream_t s = c->stream;
-  std::vector<int32_t> ids(n_ids), counts(c->k);
+  ids.resize(n_ids);
+  std::vector<int32_t> counts(c->k);
   std::vector<int64_t> offs(c->k + 1);
   HIP_TRY(c, hipMemcpyAsync(ids.data(), c->ch_ids, 4 * n_ids, hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipMemcpyAsync(counts.data(), c->counts, 4 * c->k, hipMemcpyDeviceToHost, s));
@@ -729,18 +752,19 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
   A_(c->counts, k);
   A_(c->offsets, k + 1);
   A_(c->members, N);
+  A_(c->list_work, index_rows_work(N));
   A_(c->red, 8);
   A_(c->ids_count, 1);
   A_(c->part, ((int64_t)c->k + kChunk - 1) / kChunk * N);
   c->use_tail = !(c->cfg.flags & SKM_DENSE_ONLY);
   for (int w = 0; w < ((c->cfg.flags & SKM_NCC) ? 2 : 1) && c->use_tail; ++w) {
     const int64_t nch = ((int64_t)c->k + kChunk - 1) / kChunk;
-    A_(c->tails[w].tail, c->D);
+    A_(c->tails[w].tail, nch * c->D);
     A_(c->tails[w].cnt, nch * c->D);
     A_(c->tails[w].off, nch * (c->D + 1));
     A_(c->tails[w].base, nch + 1);
-    A_(c->tails[w].cf, c->D);
-    A_(c->tails[w].hist, (int64_t)c->k + 2);
+    A_(c->tails[w].totals, nch);
+    A_(c->tails[w].chunks, nch);
   }
   if (c->cfg.flags & SKM_NCC) A_(c->tile_ch, c->D * c->ld * c->esize);
   if (c->cfg.flags & SKM_INDEX) {
@@ -792,7 +816,7 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
     }
   }
   if ((st = setup_head(c)) != SKM_OK) return cleanup(st);
-  if ((st = rebuild_tiles(c, nullptr)) != SKM_OK) return cleanup(st);
+  if ((st = rebuild_tiles(c, nullptr, nullptr)) != SKM_OK) return cleanup(st);
   if ((c->cfg.flags & SKM_INDEX) && (st = build_index(c)) != SKM_OK) return cleanup(st);
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return cleanup(device_fail(c, "init sync", e));
@@ -874,7 +898,7 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
     HIP_TRY(c, hipMemcpyAsync(&n_ch, c->ids_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
     HIP_TRY(c, launch_gather_tile(c->tile, c->D, c->esize, c->ch_ids, n_ch, c->tile_ch, s));
-    ST_TRY(build_tail(c, 1, c->tile_ch, n_ch));
+    ST_TRY(build_tail(c, 1, c->tile_ch, n_ch, nullptr));
     a.a_prev = c->a_prev;
     a.changed = c->changed;
     a.tile_ch = c->tile_ch;
@@ -892,7 +916,7 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
     HIP_TRY(c, hipEventRecord(c->ev[6], s));
     HIP_TRY(c, launch_fill_u8(c->mode, 0, c->N, s));
     HIP_TRY(c, index_rows(c->a_prev, (c->cfg.flags & SKM_NCC) ? c->changed : nullptr, c->N,
-                          c->idx_rows, c->ids_count, s));
+                          c->idx_rows, c->ids_count, c->list_work, s));
     int32_t n_rows_idx = 0;
     HIP_TRY(c, hipMemcpyAsync(&n_rows_idx, c->ids_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
@@ -917,7 +941,7 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
     // all centroids, from their list.  One merge over all rows at the end.
     int32_t n_full = 0;
     HIP_TRY(c, launch_gather_head(c->ch_head, c->head_H, c->ch_ids, n_ch, c->ch_head_ch, s));
-    HIP_TRY(c, index_rows(c->a_prev, c->changed, c->N, c->full_rows, c->ids_count, s));
+    HIP_TRY(c, index_rows(c->a_prev, c->changed, c->N, c->full_rows, c->ids_count, c->list_work, s));
     HIP_TRY(c, hipMemcpyAsync(&n_full, c->ids_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
     a.ncc_only = 1;
@@ -1101,11 +1125,14 @@ skm_status skm_update(skm_ctx *c, skm_iter_stats *st_out) {
   HIP_TRY(c, hipMemcpyAsync(&n_ids, c->ids_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, launch_bucket(c->a, c->N, c->k, c->nblk, c->hist, c->counts, c->offsets, c->members, s));
   HIP_TRY(c, hipStreamSynchronize(s));
-  ST_TRY(sum_changed(c, n_ids));
+  std::vector<int32_t> ids, chunks;
+  ST_TRY(sum_changed(c, n_ids, ids));
+  for (int32_t j : ids)   // ascending ids: ascending chunks
+    if (chunks.empty() || chunks.back() != j / kChunk) chunks.push_back(j / kChunk);
   HIP_TRY(c, launch_renorm(c->S, c->counts, c->ch_ids, n_ids, c->D, c->master, c->snorm, c->shift,
                            c->dot_old, s));
   HIP_TRY(c, launch_reduce_stats(c->changed, c->snorm, c->shift, c->dot_old, c->k, c->red, s));
-  ST_TRY(rebuild_tiles(c, c->changed));
+  ST_TRY(rebuild_tiles(c, c->changed, &chunks));
   HIP_TRY(c, hipEventRecord(c->ev[4], s));
   c->ms_index_build = 0.f;
   c->index_ready = false;
@@ -1296,7 +1323,7 @@ skm_status skm_set_centroids(skm_ctx *c, const double *centroids) {
   if (!centroids) return fail(SKM_E_INVALID, "centroids is NULL");
   HIP_TRY(c, hipMemcpyAsync(c->master, centroids, sizeof(double) * c->k * c->D,
                             hipMemcpyHostToDevice, c->stream));
-  ST_TRY(rebuild_tiles(c, nullptr));
+  ST_TRY(rebuild_tiles(c, nullptr, nullptr));
   if (c->cfg.flags & SKM_INDEX) ST_TRY(build_index(c));
   HIP_TRY(c, launch_fill_u8(c->changed, 1, c->k, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));

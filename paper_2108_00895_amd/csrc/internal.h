@@ -17,7 +17,7 @@ namespace skm {
 // Lists of non-zero codes of the tail terms of one scoring copy (see
 // kernels_tail.hip).  tail == nullptr: every term takes the dense path.
 struct TailView {
-  const uint8_t *tail;    // [D] 1 = tail term
+  const uint8_t *tail;    // [nch][D] 1 = list term of chunk cc
   const uint32_t *off;    // [nch][D + 1] entry offsets within chunk cc's entries
   const uint64_t *base;   // [nch + 1] first entry of chunk cc
   const uint32_t *ent;    // entries (BF16 / FP8: (col << 16) | code; FP32: (col, bits))
@@ -235,10 +235,13 @@ struct skm_ctx {
   skm::Partial *part = nullptr;  // [ceil(k / 512)][N] scoring partials
   // tail lists: [0] of the full copy, [1] of the compacted (NCC) copy
   struct Tail {
-    uint8_t *tail = nullptr;
-    uint32_t *cnt = nullptr, *off = nullptr, *ent = nullptr, *cf = nullptr, *hist = nullptr;
-    uint64_t *base = nullptr;
-    int64_t cap_entries = 0;
+    uint8_t *tail = nullptr;     // [nch][D] 1 = list term in chunk cc
+    uint32_t *cnt = nullptr, *off = nullptr, *ent = nullptr;
+    uint32_t *totals = nullptr;  // [nch] entries per listed chunk (last build)
+    int32_t *chunks = nullptr;   // [nch] chunk list of the last build
+    uint64_t *base = nullptr;    // [nch + 1] = cc * stride
+    int64_t stride = 0;          // entries reserved per chunk
+    std::vector<int64_t> h_total;  // entries per chunk, host copy
     bool ready = false;
   } tails[2];
   bool use_tail = true;
@@ -280,6 +283,7 @@ struct skm_ctx {
   uint16_t *ch_head = nullptr;   // [k_pad][H] BF16 head codes of the centroids
   uint16_t *ch_head_ch = nullptr; // the same for the changed centroids, compacted (NCC)
   int32_t *full_rows = nullptr;  // [N] rows whose previous centroid changed (NCC)
+  int32_t *list_work = nullptr;  // row-list compaction workspace
   float *hs = nullptr;           // [head_rows][k_pad] head scores of one batch
   int64_t *r_indptr = nullptr;   // remainder CSR: the rows' non-head terms
   int32_t *r_indices = nullptr;
@@ -337,18 +341,27 @@ hipError_t launch_new_rows(skm_ctx *c, const NewRows &b, int64_t n, hipStream_t 
 skm_status set_error(skm_status st, const std::string &msg);  // thread-local last error
 
 // kernels_tail.hip
-hipError_t tail_count(const uint8_t *tile, int64_t D, int32_t ncols, int prec, int64_t dense_max,
-                      uint32_t *cnt, uint32_t *cf, uint32_t *hist, uint8_t *tail, uint32_t *off,
-                      uint64_t *base, hipStream_t s);
-hipError_t tail_fill(const uint8_t *tile, int64_t D, int32_t ncols, int prec, const uint8_t *tail,
-                     const uint32_t *off, const uint64_t *base, uint32_t *ent, hipStream_t s);
+// Chunks chunks[0 .. n_list) of a copy with ncols columns: classification,
+// counts and per-chunk offsets (totals[q] = entries of chunks[q]); then the
+// entries, chunk cc's from entry cc * stride.
+hipError_t tail_count(const uint8_t *tile, int64_t D, int32_t ncols, int prec,
+                      const int32_t *chunks, int32_t n_list, uint32_t *cnt, uint8_t *tail,
+                      uint32_t *off, uint32_t *totals, hipStream_t s);
+hipError_t tail_fill(const uint8_t *tile, int64_t D, int32_t ncols, int prec,
+                     const int32_t *chunks, int32_t n_list, const uint8_t *tail,
+                     const uint32_t *off, int64_t stride, uint32_t *ent, hipStream_t s);
+hipError_t tail_bases(uint64_t *base, int32_t nch, int64_t stride, hipStream_t s);
 
 // kernels_index.hip
 hipError_t index_build_counts(const double *master, int32_t k, int64_t D, int32_t *cnt,
                               int64_t *eoff, hipStream_t s);
 hipError_t index_build_rest(const IndexBuild &ib, hipStream_t s);
+// Ascending list of the rows whose previous centroid is flagged in `changed`
+// (all rows when nullptr) and its length; `work` holds index_rows_work(n)
+// int32 values.
+int64_t index_rows_work(int64_t n);
 hipError_t index_rows(const int32_t *a_prev, const uint8_t *changed, int64_t n, int32_t *rows,
-                      int32_t *count, hipStream_t s);
+                      int32_t *count, int32_t *work, hipStream_t s);
 hipError_t index_query(const IndexArgs &x, int64_t n_slots, hipStream_t s);
 hipError_t index_score(const IndexArgs &x, int64_t n_slots, int32_t *a_out, double *lo_out,
                        double *hi_out, hipStream_t s);

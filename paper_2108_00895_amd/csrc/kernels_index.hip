@@ -437,26 +437,76 @@ __global__ __launch_bounds__(256) void k_index_score(IndexArgs x, int64_t n_slot
 }
 
 // Rows whose previous centroid changed, in ascending order (index path).
-__global__ __launch_bounds__(1024) void k_index_rows(const int32_t *a_prev, const uint8_t *changed,
-                                                     int64_t n, int32_t *rows, int32_t *count) {
-  __shared__ int32_t sh[1024];
-  const int t = threadIdx.x;
-  const int64_t per = (n + 1023) / 1024;
-  const int64_t lo = min<int64_t>(t * per, n), hi = min(n, lo + per);
+// Stable compaction of the rows whose previous centroid is flagged in
+// `changed` (all rows when changed == nullptr) into an ascending list, in
+// three launches: per-block counts, a scan of the block counts, and the
+// writes (ballot ranks within a wave, wave counts through LDS).
+constexpr int64_t kListBlock = 4096;   // rows per block
+
+__device__ inline bool list_sel(const int32_t *a_prev, const uint8_t *changed, int64_t i) {
+  return !changed || changed[a_prev[i]];
+}
+
+__global__ __launch_bounds__(256) void k_list_count(const int32_t *a_prev, const uint8_t *changed,
+                                                    int64_t n, int32_t *bcnt) {
+  __shared__ int32_t ws[4];
+  const int64_t lo = (int64_t)blockIdx.x * kListBlock, hi = min(n, lo + kListBlock);
   int c = 0;
-  for (int64_t i = lo; i < hi; ++i) c += (!changed || changed[a_prev[i]]) ? 1 : 0;
-  sh[t] = c;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) c += list_sel(a_prev, changed, i) ? 1 : 0;
+  for (int m = 1; m < kWave; m <<= 1) c += __shfl_xor(c, m, kWave);
+  if (lane_id() == 0) ws[threadIdx.x >> 6] = c;
   __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    int v = t >= o ? sh[t - o] : 0;
+  if (threadIdx.x == 0) bcnt[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+// Exclusive scan of the block counts in place; the total into *count.
+__global__ __launch_bounds__(1024) void k_list_scan(int32_t *bcnt, int64_t nblk, int32_t *count) {
+  __shared__ int32_t wsum[16];
+  const int t = threadIdx.x, lane = lane_id(), wave = t >> 6;
+  int32_t carry = 0;
+  for (int64_t i0 = 0; i0 < nblk; i0 += 1024) {
+    const int64_t i = i0 + t;
+    const int32_t v = i < nblk ? bcnt[i] : 0;
+    int32_t incl = v;
+    for (int m = 1; m < kWave; m <<= 1) {
+      const int32_t y = __shfl_up(incl, m, kWave);
+      if (lane >= m) incl += y;
+    }
+    if (lane == kWave - 1) wsum[wave] = incl;
     __syncthreads();
-    sh[t] += v;
+    int32_t before = 0, step = 0;
+    for (int w = 0; w < 16; ++w) {
+      if (w < wave) before += wsum[w];
+      step += wsum[w];
+    }
+    if (i < nblk) bcnt[i] = carry + before + incl - v;
+    carry += step;
     __syncthreads();
   }
-  int pos = sh[t] - c;
-  for (int64_t i = lo; i < hi; ++i)
-    if (!changed || changed[a_prev[i]]) rows[pos++] = (int32_t)i;
-  if (t == 1023) *count = sh[1023];
+  if (t == 0) *count = carry;
+}
+
+__global__ __launch_bounds__(256) void k_list_write(const int32_t *a_prev, const uint8_t *changed,
+                                                    int64_t n, const int32_t *boff, int32_t *rows) {
+  __shared__ int32_t ws[4];
+  const int64_t lo = (int64_t)blockIdx.x * kListBlock, hi = min(n, lo + kListBlock);
+  const int wave = threadIdx.x >> 6;
+  int32_t pos = boff[blockIdx.x];
+  for (int64_t b0 = lo; b0 < hi; b0 += 256) {
+    const int64_t i = b0 + threadIdx.x;
+    const bool sel = i < hi && list_sel(a_prev, changed, i);
+    const uint64_t m = __ballot(sel);
+    if (lane_id() == 0) ws[wave] = __popcll(m);
+    __syncthreads();
+    int32_t before = 0, step = 0;
+    for (int w = 0; w < 4; ++w) {
+      if (w < wave) before += ws[w];
+      step += ws[w];
+    }
+    if (sel) rows[pos + before + __popcll(m & lanemask_lt())] = (int32_t)i;
+    pos += step;
+    __syncthreads();
+  }
 }
 
 }  // namespace
@@ -486,9 +536,20 @@ hipError_t index_build_rest(const IndexBuild &ib, hipStream_t s) {
   return hipGetLastError();
 }
 
+int64_t index_rows_work(int64_t n) { return std::max<int64_t>(1, (n + kListBlock - 1) / kListBlock); }
+
 hipError_t index_rows(const int32_t *a_prev, const uint8_t *changed, int64_t n, int32_t *rows,
-                      int32_t *count, hipStream_t s) {
-  hipLaunchKernelGGL(k_index_rows, dim3(1), dim3(1024), 0, s, a_prev, changed, n, rows, count);
+                      int32_t *count, int32_t *work, hipStream_t s) {
+  const int64_t nblk = (n + kListBlock - 1) / kListBlock;
+  if (nblk > 0) {
+    hipLaunchKernelGGL(k_list_count, dim3((unsigned)nblk), dim3(256), 0, s, a_prev, changed, n,
+                       work);
+  }
+  hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, s, work, nblk, count);
+  if (nblk > 0) {
+    hipLaunchKernelGGL(k_list_write, dim3((unsigned)nblk), dim3(256), 0, s, a_prev, changed, n,
+                       work, rows);
+  }
   return hipGetLastError();
 }
 

@@ -119,7 +119,7 @@ __device__ inline int32_t uniform32(int32_t v) { return __builtin_amdgcn_readfir
 
 // acc[c] += sum over the row's terms of x_t * code(t, c0 + 8*lane + c).
 // Head terms: one slab-row load per term (8 loads in flight per lane) and
-// eight FMAs into registers.  Tail terms (tv.tail[t] != 0): the term's list of
+// eight FMAs into registers.  Tail terms of the chunk: the term's list of
 // non-zero codes in this chunk, lanes over entries, products added into the
 // wave's 512-float LDS accumulator lacc, folded into acc at the end.  The
 // order of the sum differs from the term order; the error bound allows any
@@ -142,6 +142,7 @@ __device__ inline void score_chunk(int64_t b, int64_t e, const int32_t *__restri
       const_cast<uint8_t *>(slab), 0, (int)(D * kChunk * C::kBytes), 0x00020000);
   const int voff = lane * kColsPerLane * C::kBytes;
   constexpr int rowbytes = kChunk * C::kBytes;
+  const uint8_t *ttail = tv.tail ? tv.tail + cc * D : nullptr;
   const uint32_t *toff = tv.tail ? tv.off + cc * (D + 1) : nullptr;
   const uint32_t *tent = tv.tail ? tv.ent + (int64_t)tv.base[cc] * C::kEntWords : nullptr;
   bool used_lds = false;
@@ -153,7 +154,7 @@ __device__ inline void score_chunk(int64_t b, int64_t e, const int32_t *__restri
     if (lane < cnt) {
       my_t = indices[q0 + lane];
       my_x = values[q0 + lane];
-      my_tail = tv.tail && tv.tail[my_t];
+      my_tail = ttail && ttail[my_t];
     }
     uint64_t dmask = __ballot(lane < cnt && !my_tail);
     uint64_t tmask = __ballot(my_tail);
