@@ -268,19 +268,53 @@ skm_status rebuild_tiles(skm_ctx *c, const uint8_t *changed,
 // BF16 head block and the remainder CSR once (the rows never change).  The
 // head stays off for FP32 scoring, when fewer than 64 terms qualify, or when
 // its buffers would not fit the HBM budget.
-skm_status setup_head(skm_ctx *c) {
-  c->head_H = 0;
-  if (c->prec == SKM_FP32 || c->cfg.head_max_terms < 64 || c->Z == 0) return SKM_OK;
+// Document frequency of every term (rows containing it), on the host.
+skm_status term_df(skm_ctx *c, std::vector<uint32_t> &df) {
+  df.assign(c->D, 0u);
+  if (c->Z == 0) return SKM_OK;
   hipStream_t s = c->stream;
   uint32_t *d_df = nullptr;
   ST_TRY(dalloc(c, &d_df, (size_t)c->D));
-  std::vector<uint32_t> df(c->D);
   hipError_t e = launch_df(c->indices, c->Z, d_df, c->D, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(df.data(), d_df, sizeof(uint32_t) * c->D, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   dfree(c, d_df, sizeof(uint32_t) * c->D);
-  if (e != hipSuccess) return device_fail(c, "head df", e);
+  if (e != hipSuccess) return device_fail(c, "term df", e);
+  return SKM_OK;
+}
+
+// The kSumHot most frequent terms (ties: lower id), whose member sums the
+// update accumulates in LDS.
+skm_status setup_sum_hot(skm_ctx *c, const std::vector<uint32_t> &df) {
+  std::vector<int32_t> order;
+  for (int64_t t = 0; t < c->D; ++t)
+    if (df[t] > 0) order.push_back((int32_t)t);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return df[x] > df[y]; });
+  if ((int64_t)order.size() > kSumHot) order.resize(kSumHot);
+  std::sort(order.begin(), order.end());
+  c->n_sum_hot = 0;
+  if (order.empty()) return SKM_OK;
+  std::vector<int32_t> slot(c->D, -1);
+  for (size_t h = 0; h < order.size(); ++h) slot[order[h]] = (int32_t)h;
+  ST_TRY(dalloc(c, &c->sum_hot_slot, (size_t)c->D));
+  ST_TRY(dalloc(c, &c->sum_hot_terms, order.size()));
+  hipStream_t s = c->stream;
+  HIP_TRY(c, hipMemcpyAsync(c->sum_hot_slot, slot.data(), sizeof(int32_t) * c->D,
+                            hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipMemcpyAsync(c->sum_hot_terms, order.data(), sizeof(int32_t) * order.size(),
+                            hipMemcpyHostToDevice, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  c->n_sum_hot = (int32_t)order.size();
+  return SKM_OK;
+}
+
+skm_status setup_head(skm_ctx *c, const std::vector<uint32_t> &df) {
+  c->head_H = 0;
+  if (c->prec == SKM_FP32 || c->cfg.head_max_terms < 64 || c->Z == 0) return SKM_OK;
+  hipStream_t s = c->stream;
+  hipError_t e = hipSuccess;
 
   const double thr = std::max(1.0, std::ceil(c->cfg.head_min_df * (double)c->N));
   std::vector<int32_t> order;
@@ -398,7 +432,7 @@ ScoreArgs base_args(skm_ctx *c) {
 int exact_waves() { return 4096; }
 
 constexpr int64_t kSegRows = 256;       // members per summation segment
-constexpr int64_t kWorkBytes = 2ll << 30;  // partial-row workspace cap
+constexpr int64_t kWorkBytes = 8ll << 30;  // partial-row workspace cap
 
 // FP64 member sums of the n_ids changed clusters (ids in c->ch_ids): clusters
 // with at most kSegRows members are summed by one workgroup each; larger ones
@@ -471,7 +505,8 @@ skm_status sum_changed(skm_ctx *c, int32_t n_ids, std::vector<int32_t> &ids) {
       HIP_TRY(c, hipMemcpyAsync(c->groups, groups.data(), sizeof(int4) * groups.size(),
                                 hipMemcpyHostToDevice, s));
     HIP_TRY(c, launch_sum_tasks(c->indptr, c->indices, c->values, c->members, c->tasks, c->task_r0,
-                                (int32_t)tasks.size(), c->D, c->S, c->work, s));
+                                (int32_t)tasks.size(), c->D, c->S, c->work, c->sum_hot_slot,
+                                c->sum_hot_terms, c->n_sum_hot, s));
     HIP_TRY(c, launch_combine(c->groups, (int32_t)groups.size(), c->D, c->work, c->S, s));
     // the host vectors are reused next round: wait for the copies to finish
     HIP_TRY(c, hipStreamSynchronize(s));
@@ -815,7 +850,12 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
       if (e != hipSuccess) return cleanup(device_fail(c, "init centroids", e));
     }
   }
-  if ((st = setup_head(c)) != SKM_OK) return cleanup(st);
+  {
+    std::vector<uint32_t> df;
+    if ((st = term_df(c, df)) != SKM_OK) return cleanup(st);
+    if ((st = setup_sum_hot(c, df)) != SKM_OK) return cleanup(st);
+    if ((st = setup_head(c, df)) != SKM_OK) return cleanup(st);
+  }
   if ((st = rebuild_tiles(c, nullptr, nullptr)) != SKM_OK) return cleanup(st);
   if ((c->cfg.flags & SKM_INDEX) && (st = build_index(c)) != SKM_OK) return cleanup(st);
   e = hipStreamSynchronize(s);
@@ -945,7 +985,13 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
     HIP_TRY(c, hipMemcpyAsync(&n_full, c->ids_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
     a.ncc_only = 1;
-    ST_TRY(head_pass(c, a, s, c->ch_head_ch, n_ch, nullptr, c->N, n_ev));
+    if (n_ch <= kNarrowMax) {
+      // few changed centroids: all terms of those rows straight from the
+      // compacted codes, no head product
+      HIP_TRY(c, launch_score_narrow(a, c->part, c->prec, s));
+    } else {
+      ST_TRY(head_pass(c, a, s, c->ch_head_ch, n_ch, nullptr, c->N, n_ev));
+    }
     a.ncc_only = 0;
     ST_TRY(head_pass(c, a, s, c->ch_head, c->k, c->full_rows, n_full, n_ev));
     HIP_TRY(c, launch_finalize(a, c->part, s));

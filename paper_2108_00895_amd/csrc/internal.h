@@ -12,6 +12,9 @@
 
 namespace skm {
 
+// Terms summed in LDS by the member-sum kernel (the most frequent ones).
+constexpr int kSumHot = 2048;
+
 // ------------------------------------------------------------ argument blocks
 
 // Lists of non-zero codes of the tail terms of one scoring copy (see
@@ -279,6 +282,9 @@ struct skm_ctx {
   std::vector<hipEvent_t> head_ev;  // pairs around the head GEMM launches of one step
   int32_t *head_terms = nullptr; // [H] term ids, ascending
   int32_t *head_slot = nullptr;  // [D] slot of a head term, -1 otherwise
+  int32_t *sum_hot_slot = nullptr;   // [D] LDS slot of a term in the member sums, -1 otherwise
+  int32_t *sum_hot_terms = nullptr;  // [n_sum_hot] the kSumHot most frequent terms, ascending
+  int32_t n_sum_hot = 0;
   uint16_t *xh = nullptr;        // [N][H] BF16 head values of the rows
   uint16_t *ch_head = nullptr;   // [k_pad][H] BF16 head codes of the centroids
   uint16_t *ch_head_ch = nullptr; // the same for the changed centroids, compacted (NCC)
@@ -321,6 +327,11 @@ hipError_t launch_score(const ScoreArgs &a, Partial *part, int n_cu, int prec, h
 // then the merge and certificate of all a.n_rows rows.
 hipError_t launch_score_part(const ScoreArgs &a, Partial *part, int n_cu, int prec, hipStream_t s,
                              int wpc = 0);
+// Sec. 3.1 rows keeping their centroid against at most kNarrowMax compacted
+// changed centroids (a.tile_ch, a.n_ch, a.ch_ids), all terms, no head scores:
+// partials of compacted chunk 0; the other rows are left untouched.
+constexpr int kNarrowMax = 64;
+hipError_t launch_score_narrow(const ScoreArgs &a, Partial *part, int prec, hipStream_t s);
 // Workgroups of the scoring kernel that fit on one CU at once.
 int score_occupancy(int prec);
 hipError_t launch_finalize(const ScoreArgs &a, const Partial *part, hipStream_t s);
@@ -394,12 +405,13 @@ hipError_t launch_centroid_columns(const double *master, int32_t k, int64_t D, c
                                    int32_t n, double *out, hipStream_t s);
 hipError_t launch_bucket(const int32_t *a, int64_t n, int32_t k, int64_t nblk, int32_t *hist,
                          int32_t *counts, int64_t *offsets, int32_t *members, hipStream_t s);
-hipError_t launch_sum_members(const int64_t *indptr, const int32_t *indices, const float *values,
-                              const int64_t *offsets, const int32_t *members, const int32_t *ids,
-                              int32_t n_ids, int64_t D, double *S, hipStream_t s);
+// Member sums of the tasks; terms with hot_slot[t] >= 0 (n_hot <= kSumHot of
+// them, hot_terms[slot] = t) are summed in LDS.
 hipError_t launch_sum_tasks(const int64_t *indptr, const int32_t *indices, const float *values,
                             const int32_t *members, const int4 *tasks, const int64_t *task_r0,
-                            int32_t n_tasks, int64_t D, double *S, double *work, hipStream_t s);
+                            int32_t n_tasks, int64_t D, double *S, double *work,
+                            const int32_t *hot_slot, const int32_t *hot_terms, int32_t n_hot,
+                            hipStream_t s);
 hipError_t launch_combine(const int4 *groups, int32_t n_groups, int64_t D, const double *work,
                           double *S, hipStream_t s);
 hipError_t launch_renorm(const double *S, const int32_t *counts, const int32_t *ids, int32_t n_ids,

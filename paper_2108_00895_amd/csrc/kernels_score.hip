@@ -396,6 +396,89 @@ __global__ __launch_bounds__(256) void k_score_part(ScoreArgs a, Partial *__rest
   }
 }
 
+// Sec. 3.1 with few changed centroids (n_ch <= 8 * NG <= kNarrowMax): a row
+// whose previous centroid is unchanged scores only the compacted changed
+// centroids, here without the head product.  One wavefront per row; lanes
+// take the row's terms (all of them), each loading its term's n_ch codes from
+// the compacted copy and accumulating them, and a butterfly over the wave
+// adds the lane sums (any summation order is inside the bound).  Writes the
+// row's partial of compacted chunk 0; rows whose previous centroid changed
+// are left to the full pass.
+template <int P, int NG>
+__global__ __launch_bounds__(256) void k_score_narrow(ScoreArgs a, Partial *__restrict__ part) {
+  using C = Codes<P>;
+  const int lane = lane_id();
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= a.n_rows) return;
+  const RowPlan pl = plan_row(a, row, true);
+  if (!pl.ncc || pl.done) return;
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint8_t *>(a.tile_ch), 0, (int)(a.D * kChunk * C::kBytes), 0x00020000);
+  float acc[NG * 8];
+#pragma unroll
+  for (int c = 0; c < NG * 8; ++c) acc[c] = 0.f;
+  const int64_t b = uniform64(a.indptr[row]), e = uniform64(a.indptr[row + 1]);
+  for (int64_t q = b + lane; q < e; q += kWave) {
+    const int t = a.indices[q];
+    const float x = a.values[q];
+    const int vo = t * (kChunk * C::kBytes);
+    typename C::raw_t r[NG];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) r[g] = C::load(rs, vo + g * 8 * C::kBytes, 0);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) C::fma8(r[g], x, acc + 8 * g);
+  }
+#pragma unroll
+  for (int c = 0; c < NG * 8; ++c) {
+    float v = acc[c];
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) v += __shfl_xor(v, m, kWave);
+    acc[c] = v;
+  }
+  if (lane != 0) return;
+  const int n_ch = a.n_ch;
+  if (a.top == kTop) {
+    float ts[kTop] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    int tj[kTop] = {0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF};
+#pragma unroll
+    for (int c = 0; c < NG * 8; ++c) {
+      if (c < n_ch) {
+        const int j = a.ch_ids[c];
+        float s = acc[c];
+        if (a.scale) s *= a.scale[j];
+        top4_insert(s, j, ts, tj);
+      }
+    }
+    Partial p;
+#pragma unroll
+    for (int q = 0; q < kTop; ++q) {
+      p.e[q].s = ts[q];
+      p.e[q].j = tj[q];
+    }
+    part[row] = p;
+  } else {
+    float b1 = -INFINITY, b2 = -INFINITY;
+    int j1 = 0x7FFFFFFF;
+#pragma unroll
+    for (int c = 0; c < NG * 8; ++c) {
+      if (c < n_ch) {
+        const int j = a.ch_ids[c];
+        float s = acc[c];
+        if (a.scale) s *= a.scale[j];
+        if (better(s, j, b1, j1)) {
+          b2 = b1;
+          b1 = s;
+          j1 = j;
+        } else if (s > b2) {
+          b2 = s;
+        }
+      }
+    }
+    *reinterpret_cast<float4 *>(&part[row]) =
+        make_float4(b1, __int_as_float(j1), b2, __int_as_float(0x7FFFFFFF));
+  }
+}
+
 // Merges a row's chunk partials in chunk order and certifies the winner:
 // certain when the winner's lower bound exceeds every other candidate's upper
 // bound; otherwise the row goes to the exact tier with L = the certified lower
@@ -735,6 +818,34 @@ hipError_t launch_score_part(const ScoreArgs &a, Partial *part, int n_cu, int pr
     case SKM_FP32: return launch_score_part_t<SKM_FP32>(a, part, n_cu, wpc, s);
     case SKM_BF16: return launch_score_part_t<SKM_BF16>(a, part, n_cu, wpc, s);
     case SKM_FP8_E4M3: return launch_score_part_t<SKM_FP8_E4M3>(a, part, n_cu, wpc, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int P>
+hipError_t launch_score_narrow_t(const ScoreArgs &a, Partial *part, hipStream_t s) {
+  const dim3 g((unsigned)((a.n_rows + 3) / 4)), b(256);
+  if (a.n_ch <= 8) {
+    hipLaunchKernelGGL((k_score_narrow<P, 1>), g, b, 0, s, a, part);
+  } else if (a.n_ch <= 16) {
+    hipLaunchKernelGGL((k_score_narrow<P, 2>), g, b, 0, s, a, part);
+  } else if (a.n_ch <= 32) {
+    hipLaunchKernelGGL((k_score_narrow<P, 4>), g, b, 0, s, a, part);
+  } else {
+    hipLaunchKernelGGL((k_score_narrow<P, 8>), g, b, 0, s, a, part);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_score_narrow(const ScoreArgs &a, Partial *part, int prec, hipStream_t s) {
+  if (a.n_rows <= 0 || a.n_ch <= 0) return hipSuccess;
+  if (a.n_ch > kNarrowMax || !a.tile_ch || !a.ch_ids || !a.a_prev || !a.changed ||
+      a.D * kChunk * 4 > INT32_MAX)
+    return hipErrorInvalidValue;
+  switch (prec) {
+    case SKM_FP32: return launch_score_narrow_t<SKM_FP32>(a, part, s);
+    case SKM_BF16: return launch_score_narrow_t<SKM_BF16>(a, part, s);
+    case SKM_FP8_E4M3: return launch_score_narrow_t<SKM_FP8_E4M3>(a, part, s);
   }
   return hipErrorInvalidValue;
 }

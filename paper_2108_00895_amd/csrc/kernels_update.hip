@@ -113,39 +113,108 @@ __global__ void k_fp8_scales(const double *master, int64_t D, const uint8_t *cha
   if (threadIdx.x == 0) scale[j] = ldexpf(1.0f, e4m3_scale_exp(sh[0]));
 }
 
-// Scoring copy: transpose 64 centroids x 64 terms of the FP64 master through
-// LDS and encode (term-major output, 64 consecutive codes per term row).
+// Scoring copy: 64 centroids x 128 terms of the FP64 master per workgroup,
+// encoded on load (16-byte loads along each centroid row) and transposed
+// through LDS as codes, then written term-major (64 consecutive codes per
+// term row).  Workgroups whose 64 centroids are all unchanged exit at once.
+template <int P>
+struct CodeOf {
+  using T = uint32_t;
+};
+template <>
+struct CodeOf<SKM_BF16> {
+  using T = uint16_t;
+};
+template <>
+struct CodeOf<SKM_FP8_E4M3> {
+  using T = uint8_t;
+};
+
+constexpr int kQT = 128;   // terms per quantize tile
+
+template <int P>
+__device__ inline typename CodeOf<P>::T encode_code(double c, int e) {
+  if (P == SKM_FP32) {
+    const float f = (float)c;
+    return __float_as_uint(f);
+  } else if (P == SKM_BF16) {
+    return encode_bf16(c);
+  } else {
+    return encode_e4m3(ldexp(c, -e));
+  }
+}
+
 template <int P>
 __global__ __launch_bounds__(256) void k_quantize(const double *master, int32_t k, int64_t D,
                                                   const uint8_t *changed, const float *scale,
                                                   uint8_t *tile) {
-  __shared__ double buf[64][65];
+  using T = typename CodeOf<P>::T;
+  constexpr int pitch = kQT + 4 / (int)sizeof(T);   // one 32-bit word of padding per row
+  __shared__ T buf[64][pitch];
   const int64_t j0 = (int64_t)blockIdx.x * 64;
-  const int64_t t0 = (int64_t)blockIdx.y * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int64_t t0 = (int64_t)blockIdx.y * kQT;
+  const int tid = threadIdx.x;
   int any = 0;
-  if (threadIdx.x < 64) {
-    const int64_t j = j0 + threadIdx.x;
+  if (tid < 64) {
+    const int64_t j = j0 + tid;
     any = (j < k) && (changed == nullptr || changed[j]);
   }
   if (!__syncthreads_or(any)) return;
-  for (int jj = ty; jj < 64; jj += 4) {
-    const int64_t j = j0 + jj, t = t0 + tx;
-    buf[jj][tx] = (j < k && t < D) ? master[j * D + t] : 0.0;
+  const bool vec = (D % 2 == 0) && (t0 + kQT <= D);
+  // 64 rows x 64 term pairs
+#pragma unroll 4
+  for (int p = 0; p < 16; ++p) {
+    const int idx = p * 256 + tid;
+    const int jj = idx >> 6, q = idx & 63;
+    const int64_t j = j0 + jj, t = t0 + 2 * q;
+    double c0 = 0.0, c1 = 0.0;
+    if (j < k) {
+      const double *row = master + j * D;
+      if (vec) {
+        const double2 v = *reinterpret_cast<const double2 *>(row + t);
+        c0 = v.x;
+        c1 = v.y;
+      } else {
+        if (t < D) c0 = row[t];
+        if (t + 1 < D) c1 = row[t + 1];
+      }
+    }
+    const int e = (P == SKM_FP8_E4M3 && j < k) ? ilogbf(scale[j]) : 0;
+    buf[jj][2 * q] = encode_code<P>(c0, e);
+    buf[jj][2 * q + 1] = encode_code<P>(c1, e);
   }
   __syncthreads();
-  for (int tt = ty; tt < 64; tt += 4) {
-    const int64_t t = t0 + tt, j = j0 + tx;
-    if (t >= D || j >= k) continue;
-    const double c = buf[tx][tt];
-    const int64_t o = tile_index(t, j, D);
-    if (P == SKM_FP32) {
-      reinterpret_cast<float *>(tile)[o] = (float)c;
-    } else if (P == SKM_BF16) {
-      reinterpret_cast<uint16_t *>(tile)[o] = encode_bf16(c);
+  // term rows: 64 codes each, 8 per thread
+  const int64_t ncols = min<int64_t>(64, (int64_t)k - j0);
+  for (int p = 0; p < kQT / 32; ++p) {
+    const int tt = p * 32 + (tid >> 3);
+    const int g = (tid & 7) * 8;
+    const int64_t t = t0 + tt;
+    if (t >= D) continue;
+    T* dst = reinterpret_cast<T *>(tile) + tile_index(t, j0 + g, D);
+    if (g + 8 <= ncols) {
+      T v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = buf[g + q][tt];
+      if (sizeof(T) == 2) {
+        uint4 w;
+        w.x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
+        w.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
+        w.z = (uint32_t)v[4] | ((uint32_t)v[5] << 16);
+        w.w = (uint32_t)v[6] | ((uint32_t)v[7] << 16);
+        *reinterpret_cast<uint4 *>(dst) = w;
+      } else if (sizeof(T) == 1) {
+        uint2 w;
+        w.x = (uint32_t)v[0] | ((uint32_t)v[1] << 8) | ((uint32_t)v[2] << 16) | ((uint32_t)v[3] << 24);
+        w.y = (uint32_t)v[4] | ((uint32_t)v[5] << 8) | ((uint32_t)v[6] << 16) | ((uint32_t)v[7] << 24);
+        *reinterpret_cast<uint2 *>(dst) = w;
+      } else {
+        uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+        d4[0] = make_uint4(v[0], v[1], v[2], v[3]);
+        d4[1] = make_uint4(v[4], v[5], v[6], v[7]);
+      }
     } else {
-      const int e = ilogbf(scale[j]);
-      tile[o] = encode_e4m3(ldexp(c, -e));
+      for (int q = 0; q < 8 && g + q < ncols; ++q) dst[q] = buf[g + q][tt];
     }
   }
 }
@@ -284,46 +353,88 @@ __global__ __launch_bounds__(64) void k_block_scatter(const int32_t *a, int64_t 
   }
 }
 
-// S_j = sum of member rows in ascending row order (member lists are sorted),
-// FP64, for each listed cluster.  One workgroup per cluster, so no atomics:
-// entries of one row have distinct terms, and rows are separated by barriers.
-__global__ __launch_bounds__(256) void k_sum_members(const int64_t *indptr, const int32_t *indices,
-                                                     const float *values, const int64_t *offsets,
-                                                     const int32_t *members, const int32_t *ids,
-                                                     int64_t D, double *S) {
-  const int32_t j = ids[blockIdx.x];
-  double *Sj = S + (int64_t)j * D;
-  for (int64_t t = threadIdx.x; t < D; t += 256) Sj[t] = 0.0;
-  __syncthreads();
-  const int64_t r0 = offsets[j], r1 = offsets[j + 1];
-  for (int64_t r = r0; r < r1; ++r) {
-    const int64_t i = members[r];
-    const int64_t b = indptr[i], e = indptr[i + 1];
-    for (int64_t q = b + threadIdx.x; q < e; q += 256) Sj[indices[q]] += (double)values[q];
-    __syncthreads();
-  }
-}
-
-// Segmented variant: task = (cluster, member range [r0, r1), destination).  A
-// cluster with more members than one segment is split into fixed segments
+// Segmented member sums: task = (cluster, member range [r0, r1), destination).
+// A cluster with more members than one segment is split into fixed segments
 // whose sums go to partial rows of a workspace (dest >= 0) and are added in
 // segment order by k_combine; small clusters sum straight into S_j (dest < 0).
-// Every sum still runs in a fixed order, so results are reproducible.
+// One workgroup per task adds its member rows in ascending row order (member
+// lists are sorted): the entries of one row have distinct terms and rows are
+// separated by barriers, so every sum runs in a fixed order without atomics
+// and results are reproducible.  The most frequent terms (hot_slot[t] >= 0)
+// are summed in LDS and written once at the end; the others go to the FP64
+// destination row directly.
 __global__ __launch_bounds__(256) void k_sum_tasks(const int64_t *indptr, const int32_t *indices,
                                                    const float *values, const int32_t *members,
                                                    const int4 *tasks, const int64_t *task_r0,
-                                                   int64_t D, double *S, double *work) {
+                                                   int64_t D, double *S, double *work,
+                                                   const int32_t *hot_slot,
+                                                   const int32_t *hot_terms, int32_t n_hot) {
+  __shared__ double hot[kSumHot];
   const int4 tk = tasks[blockIdx.x];   // x = cluster, y = count, z = dest slot (-1: S_j)
   double *dst = tk.z < 0 ? S + (int64_t)tk.x * D : work + (int64_t)tk.z * D;
-  for (int64_t t = threadIdx.x; t < D; t += 256) dst[t] = 0.0;
-  __syncthreads();
-  const int64_t r0 = task_r0[blockIdx.x], r1 = r0 + tk.y;
-  for (int64_t r = r0; r < r1; ++r) {
-    const int64_t i = members[r];
-    const int64_t b = indptr[i], e = indptr[i + 1];
-    for (int64_t q = b + threadIdx.x; q < e; q += 256) dst[indices[q]] += (double)values[q];
-    __syncthreads();
+  const int tid = threadIdx.x;
+  if (D % 2 == 0) {
+    double2 *d2 = reinterpret_cast<double2 *>(dst);
+    for (int64_t t = tid; t < D / 2; t += 256) d2[t] = make_double2(0.0, 0.0);
+  } else {
+    for (int64_t t = tid; t < D; t += 256) dst[t] = 0.0;
   }
+  for (int h = tid; h < n_hot; h += 256) hot[h] = 0.0;
+  // Member row ranges are staged in LDS 256 rows at a time, and each thread's
+  // first entry of the next row is loaded before the current row's adds, so
+  // those loads overlap the adds and the barrier.
+  __shared__ int64_t rb[256], re[256];
+  const int64_t r0 = task_r0[blockIdx.x], r1 = r0 + tk.y;
+  for (int64_t g0 = r0; g0 < r1; g0 += 256) {
+    const int nr = (int)min<int64_t>(256, r1 - g0);
+    __syncthreads();   // the zeroing, or the previous group's rows, are done
+    if (tid < nr) {
+      const int64_t i = members[g0 + tid];
+      rb[tid] = indptr[i];
+      re[tid] = indptr[i + 1];
+    }
+    __syncthreads();
+    int32_t t1 = 0, h1 = -1;
+    double v1 = 0.0;
+    bool has1 = rb[0] + tid < re[0];
+    if (has1) {
+      t1 = indices[rb[0] + tid];
+      v1 = (double)values[rb[0] + tid];
+      h1 = hot_slot ? hot_slot[t1] : -1;
+    }
+    for (int q = 0; q < nr; ++q) {
+      const int64_t b = rb[q], e = re[q];
+      const int32_t t0 = t1, h0 = h1;
+      const double v0 = v1;
+      const bool has0 = has1;
+      has1 = q + 1 < nr && rb[q + 1] + tid < re[q + 1];
+      if (has1) {
+        t1 = indices[rb[q + 1] + tid];
+        v1 = (double)values[rb[q + 1] + tid];
+        h1 = hot_slot ? hot_slot[t1] : -1;
+      }
+      if (has0) {
+        if (h0 >= 0) {
+          hot[h0] += v0;
+        } else {
+          dst[t0] += v0;
+        }
+      }
+      for (int64_t p = b + 256 + tid; p < e; p += 256) {   // rows longer than 256 entries
+        const int32_t t = indices[p];
+        const double v = (double)values[p];
+        const int32_t h = hot_slot ? hot_slot[t] : -1;
+        if (h >= 0) {
+          hot[h] += v;
+        } else {
+          dst[t] += v;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  for (int h = tid; h < n_hot; h += 256) dst[hot_terms[h]] = hot[h];
 }
 
 // S_j = sum of its segment partials, in segment order.  Block (group, term block).
@@ -339,7 +450,9 @@ __global__ __launch_bounds__(256) void k_combine(const int4 *groups, int64_t D, 
 }
 
 // c_j = S_j / ||S_j|| (empty clusters keep c_j), with the per-cluster shift
-// ||c_j(new) - c_j(old)||^2 and S_j . c_j(old).
+// ||c_j(new) - c_j(old)||^2 and S_j . c_j(old).  One workgroup per cluster;
+// 16-byte loads, four in flight per thread (rows start 16-byte aligned when D
+// is even; odd D takes the scalar loop).
 __global__ __launch_bounds__(256) void k_renorm(const double *S, const int32_t *counts,
                                                 const int32_t *ids, int64_t D, double *master,
                                                 double *snorm, double *shift, double *dot_old) {
@@ -355,22 +468,54 @@ __global__ __launch_bounds__(256) void k_renorm(const double *S, const int32_t *
     }
     return;
   }
+  const int tid = threadIdx.x;
+  const int64_t D2 = (D % 2 == 0) ? D / 2 : 0;
+  const double2 *S2 = reinterpret_cast<const double2 *>(Sj);
+  double2 *M2 = reinterpret_cast<double2 *>(Mj);
   double ss = 0.0;
-  for (int64_t t = threadIdx.x; t < D; t += 256) ss += Sj[t] * Sj[t];
+  int64_t i = tid;
+  for (; i + 768 < D2; i += 1024) {
+    const double2 a0 = S2[i], a1 = S2[i + 256], a2 = S2[i + 512], a3 = S2[i + 768];
+    ss += a0.x * a0.x + a0.y * a0.y + a1.x * a1.x + a1.y * a1.y;
+    ss += a2.x * a2.x + a2.y * a2.y + a3.x * a3.x + a3.y * a3.y;
+  }
+  for (; i < D2; i += 256) {
+    const double2 a0 = S2[i];
+    ss += a0.x * a0.x + a0.y * a0.y;
+  }
+  for (int64_t t = 2 * D2 + tid; t < D; t += 256) ss += Sj[t] * Sj[t];
   const double nrm = sqrt(block_sum_256(ss, sh));
   double sh2 = 0.0, dot = 0.0;
-  for (int64_t t = threadIdx.x; t < D; t += 256) {
-    const double s = Sj[t];
-    const double o = Mj[t];
+  auto one = [&](double s, double o) -> double {
     const double c = s / nrm;
     const double d = c - o;
     sh2 += d * d;
     dot += s * o;
-    Mj[t] = c;
+    return c;
+  };
+  i = tid;
+  for (; i + 256 < D2; i += 512) {
+    const double2 a0 = S2[i], a1 = S2[i + 256];
+    const double2 o0 = M2[i], o1 = M2[i + 256];
+    double2 c0, c1;
+    c0.x = one(a0.x, o0.x);
+    c0.y = one(a0.y, o0.y);
+    c1.x = one(a1.x, o1.x);
+    c1.y = one(a1.y, o1.y);
+    M2[i] = c0;
+    M2[i + 256] = c1;
   }
+  for (; i < D2; i += 256) {
+    const double2 a0 = S2[i], o0 = M2[i];
+    double2 c0;
+    c0.x = one(a0.x, o0.x);
+    c0.y = one(a0.y, o0.y);
+    M2[i] = c0;
+  }
+  for (int64_t t = 2 * D2 + tid; t < D; t += 256) Mj[t] = one(Sj[t], Mj[t]);
   sh2 = block_sum_256(sh2, sh);
   dot = block_sum_256(dot, sh);
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     snorm[j] = nrm;
     shift[j] = sh2;
     dot_old[j] = dot;
@@ -463,7 +608,7 @@ hipError_t launch_fp8_scales(const double *master, int32_t k, int64_t D, const u
 
 hipError_t launch_quantize(const double *master, int32_t k, int64_t D, const uint8_t *changed,
                            const float *scale, int prec, uint8_t *tile, hipStream_t s) {
-  const dim3 g((unsigned)((k + 63) / 64), (unsigned)((D + 63) / 64)), b(256);
+  const dim3 g((unsigned)((k + 63) / 64), (unsigned)((D + kQT - 1) / kQT)), b(256);
   switch (prec) {
     case SKM_FP32:
       hipLaunchKernelGGL(k_quantize<SKM_FP32>, g, b, 0, s, master, k, D, changed, scale, tile);
@@ -550,21 +695,16 @@ hipError_t launch_bucket(const int32_t *a, int64_t n, int32_t k, int64_t nblk, i
   return err;
 }
 
-hipError_t launch_sum_members(const int64_t *indptr, const int32_t *indices, const float *values,
-                              const int64_t *offsets, const int32_t *members, const int32_t *ids,
-                              int32_t n_ids, int64_t D, double *S, hipStream_t s) {
-  if (n_ids <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sum_members, dim3((unsigned)n_ids), dim3(256), 0, s, indptr, indices, values,
-                     offsets, members, ids, D, S);
-  return hipGetLastError();
-}
-
 hipError_t launch_sum_tasks(const int64_t *indptr, const int32_t *indices, const float *values,
                             const int32_t *members, const int4 *tasks, const int64_t *task_r0,
-                            int32_t n_tasks, int64_t D, double *S, double *work, hipStream_t s) {
+                            int32_t n_tasks, int64_t D, double *S, double *work,
+                            const int32_t *hot_slot, const int32_t *hot_terms, int32_t n_hot,
+                            hipStream_t s) {
   if (n_tasks <= 0) return hipSuccess;
+  if (n_hot > kSumHot || (n_hot > 0 && (!hot_slot || !hot_terms))) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_sum_tasks, dim3((unsigned)n_tasks), dim3(256), 0, s, indptr, indices, values,
-                     members, tasks, task_r0, D, S, work);
+                     members, tasks, task_r0, D, S, work, n_hot > 0 ? hot_slot : nullptr, hot_terms,
+                     n_hot);
   return hipGetLastError();
 }
 

@@ -199,9 +199,12 @@ def test_set_schedule_validates(mid):
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
 def test_head_with_ncc_trajectory_equals_oracle(prec):
     """NCC iterations with the head: rows keeping their centroid score the
-    compacted changed centroids (head codes compacted too), the others score
-    all centroids from their list; every step must equal the oracle.  40 rows
-    per cluster keep a partial changed set for several iterations."""
+    compacted changed centroids (head codes compacted too when more than 64
+    changed, every term from the compacted codes without the head product
+    when at most 64 did), the others score all centroids from their list;
+    every step must equal the oracle.  40 rows per cluster keep a partial
+    changed set for several iterations (86, 53, 32, 19, 9, 6, 4, ... changed
+    centroids: both variants and every narrow width run)."""
     say("case: head + ncc trajectory", prec)
     csr, c = corpus(8000, 6000, nnz_mean=50.0, nnz_max=300, seed=47)
     k, T = 200, 14
@@ -210,12 +213,17 @@ def test_head_with_ncc_trajectory_equals_oracle(prec):
     ctx = Context(to_device(csr), c.n_terms, k, init_rows=rows, precision=prec, ncc=True,
                   head_max_terms=128, head_min_df=0.0, stop_rule="fixed", max_iter=T)
     both = 0
+    widths = set()
     for t, rec in enumerate(ref.records):
         st = ctx.assign()
         assert st["head_terms"] == 128
         # both passes ran: some rows kept their centroid, some did not, and
         # some (but not all) centroids changed
-        both += 0 < st["ncc_rows"] < c.n_docs and 0 < st["changed_centroids"] <= k // 2
+        ok = 0 < st["ncc_rows"] < c.n_docs and 0 < st["changed_centroids"] <= k // 2
+        both += ok
+        if ok:
+            n_ch = st["changed_centroids"]
+            widths.add("head" if n_ch > 64 else min(w for w in (8, 16, 32, 64) if n_ch <= w))
         assert_assign_equal(ctx.assignments(), rec.a, rec.s1, rec.s2, f"{prec} it {t}")
         assert st["moved"] == rec.moved
         u = ctx.update()
@@ -223,4 +231,5 @@ def test_head_with_ncc_trajectory_equals_oracle(prec):
         say(f"  it {t}: changed {st['changed_centroids']} ncc rows {st['ncc_rows']} "
             f"flagged {st['flagged']}")
     assert both >= 3, "NCC with the head did not run with a partial changed set"
+    assert widths == {"head", 8, 16, 32, 64}, widths
     ctx.close()
