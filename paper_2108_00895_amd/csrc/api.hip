@@ -350,7 +350,8 @@ skm_status setup_head(skm_ctx *c, const std::vector<uint32_t> &df) {
   const int64_t nscan = head_split_scan_blocks(c->N);
   const size_t need = 4 * (size_t)H + 4 * (size_t)c->D + 2 * (size_t)c->N * H +
                       2 * (size_t)k_pad * H * ((c->cfg.flags & SKM_NCC) ? 2 : 1) +
-                      4 * (size_t)rows * chunks * kChunk + 4 * (size_t)c->N +
+                      4 * (size_t)rows * chunks * kChunk +
+                      4 * (size_t)c->N * ((c->cfg.flags & SKM_NCC) ? 2 : 0) +
                       8 * (size_t)(c->N + 1) +
                       8 * (size_t)rest_nnz + 8 * (size_t)c->N + 8 * (size_t)nscan + 16 * 256;
   if (c->cfg.hbm_budget_bytes && c->hbm_bytes + need > c->cfg.hbm_budget_bytes) return SKM_OK;
@@ -362,6 +363,7 @@ skm_status setup_head(skm_ctx *c, const std::vector<uint32_t> &df) {
   if (c->cfg.flags & SKM_NCC) {
     ST_TRY(dalloc(c, &c->ch_head_ch, (size_t)k_pad * H));
     ST_TRY(dalloc(c, &c->full_rows, (size_t)c->N));
+    ST_TRY(dalloc(c, &c->ncc_list, (size_t)c->N));
   }
   ST_TRY(dalloc(c, &c->hs, (size_t)rows * chunks * kChunk));
   ST_TRY(dalloc(c, &c->r_indptr, (size_t)c->N + 1));
@@ -440,6 +442,7 @@ constexpr int64_t kWorkBytes = 8ll << 30;  // partial-row workspace cap
 // in segment order.  Rounds keep the workspace within kWorkBytes.
 skm_status sum_changed(skm_ctx *c, int32_t n_ids, std::vector<int32_t> &ids) {
   ids.clear();
+  c->full_frac = 0.0;
   if (n_ids <= 0) return SKM_OK;
   hipStream_t s = c->stream;
   ids.resize(n_ids);
@@ -449,6 +452,9 @@ skm_status sum_changed(skm_ctx *c, int32_t n_ids, std::vector<int32_t> &ids) {
   HIP_TRY(c, hipMemcpyAsync(counts.data(), c->counts, 4 * c->k, hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipMemcpyAsync(offs.data(), c->offsets, 8 * (c->k + 1), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
+  int64_t n_full = 0;   // rows of the changed clusters: they score every centroid next time
+  for (int32_t j : ids) n_full += counts[j];
+  c->full_frac = c->N > 0 ? (double)n_full / (double)c->N : 0.0;
   const int64_t max_slots = std::max<int64_t>(1, kWorkBytes / (8 * c->D));
   size_t pos = 0;
   std::vector<int4> tasks, groups;
@@ -789,7 +795,7 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
   A_(c->members, N);
   A_(c->list_work, index_rows_work(N));
   A_(c->red, 8);
-  A_(c->ids_count, 1);
+  A_(c->ids_count, 2);
   A_(c->part, ((int64_t)c->k + kChunk - 1) / kChunk * N);
   c->use_tail = !(c->cfg.flags & SKM_DENSE_ONLY);
   for (int w = 0; w < ((c->cfg.flags & SKM_NCC) ? 2 : 1) && c->use_tail; ++w) {
@@ -927,10 +933,12 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
   ST_TRY(check_ctx_writable(c));
   hipStream_t s = c->stream;
   ScoreArgs a = base_args(c);
-  // Sec. 3.1 only pays when a good share of centroids is unchanged: with more
-  // than half changed, building the compacted copy costs more than the
-  // columns it saves, and every row scores the full copy instead.
-  const bool ncc = (c->cfg.flags & SKM_NCC) && c->have_prev && 2 * c->last_changed <= c->k;
+  // Sec. 3.1 pays when the work it leaves, (1 - r) n_ch / k of the scores of
+  // the rows keeping their centroid plus the share r of rows whose centroid
+  // changed (all of theirs), is clearly below a full pass; otherwise every
+  // row scores the full copy.
+  const double ncc_cost = (1.0 - c->full_frac) * (double)c->last_changed / (double)c->k + c->full_frac;
+  const bool ncc = (c->cfg.flags & SKM_NCC) && c->have_prev && ncc_cost <= kNccMaxCost;
   int32_t n_ch = c->k;
   HIP_TRY(c, hipEventRecord(c->ev[0], s));
   if (ncc) {
@@ -979,10 +987,16 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
     // the changed centroids only (their head codes compacted alongside the
     // compacted code copy); the rows whose previous centroid changed score
     // all centroids, from their list.  One merge over all rows at the end.
-    int32_t n_full = 0;
-    HIP_TRY(c, launch_gather_head(c->ch_head, c->head_H, c->ch_ids, n_ch, c->ch_head_ch, s));
+    int32_t n_full = 0, n_keep = 0;
     HIP_TRY(c, index_rows(c->a_prev, c->changed, c->N, c->full_rows, c->ids_count, c->list_work, s));
     HIP_TRY(c, hipMemcpyAsync(&n_full, c->ids_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (n_ch > kNarrowMax) {
+      HIP_TRY(c, launch_gather_head(c->ch_head, c->head_H, c->ch_ids, n_ch, c->ch_head_ch, s));
+      HIP_TRY(c, index_rows(c->a_prev, c->changed, c->N, c->ncc_list, c->ids_count + 1,
+                            c->list_work, s, 1));
+      HIP_TRY(c, hipMemcpyAsync(&n_keep, c->ids_count + 1, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                s));
+    }
     HIP_TRY(c, hipStreamSynchronize(s));
     a.ncc_only = 1;
     if (n_ch <= kNarrowMax) {
@@ -990,7 +1004,8 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
       // compacted codes, no head product
       HIP_TRY(c, launch_score_narrow(a, c->part, c->prec, s));
     } else {
-      ST_TRY(head_pass(c, a, s, c->ch_head_ch, n_ch, nullptr, c->N, n_ev));
+      // head products of the rows keeping their centroid only
+      ST_TRY(head_pass(c, a, s, c->ch_head_ch, n_ch, c->ncc_list, n_keep, n_ev));
     }
     a.ncc_only = 0;
     ST_TRY(head_pass(c, a, s, c->ch_head, c->k, c->full_rows, n_full, n_ev));

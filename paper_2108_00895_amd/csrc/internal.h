@@ -289,7 +289,9 @@ struct skm_ctx {
   uint16_t *ch_head = nullptr;   // [k_pad][H] BF16 head codes of the centroids
   uint16_t *ch_head_ch = nullptr; // the same for the changed centroids, compacted (NCC)
   int32_t *full_rows = nullptr;  // [N] rows whose previous centroid changed (NCC)
+  int32_t *ncc_list = nullptr;   // [N] rows whose previous centroid is unchanged (NCC)
   int32_t *list_work = nullptr;  // row-list compaction workspace
+  double full_frac = 1.0;        // share of rows whose centroid changed in the last update
   float *hs = nullptr;           // [head_rows][k_pad] head scores of one batch
   int64_t *r_indptr = nullptr;   // remainder CSR: the rows' non-head terms
   int32_t *r_indices = nullptr;
@@ -331,6 +333,9 @@ hipError_t launch_score_part(const ScoreArgs &a, Partial *part, int n_cu, int pr
 // changed centroids (a.tile_ch, a.n_ch, a.ch_ids), all terms, no head scores:
 // partials of compacted chunk 0; the other rows are left untouched.
 constexpr int kNarrowMax = 64;
+// Sec. 3.1 is used when its estimated share of a full scoring pass is at most
+// this (the compacted copy and the two passes cost the rest).
+constexpr double kNccMaxCost = 0.9;
 hipError_t launch_score_narrow(const ScoreArgs &a, Partial *part, int prec, hipStream_t s);
 // Workgroups of the scoring kernel that fit on one CU at once.
 int score_occupancy(int prec);
@@ -368,11 +373,11 @@ hipError_t index_build_counts(const double *master, int32_t k, int64_t D, int32_
                               int64_t *eoff, hipStream_t s);
 hipError_t index_build_rest(const IndexBuild &ib, hipStream_t s);
 // Ascending list of the rows whose previous centroid is flagged in `changed`
-// (all rows when nullptr) and its length; `work` holds index_rows_work(n)
-// int32 values.
+// (keep = 0) or not flagged (keep = 1), all rows when changed is nullptr, and
+// its length; `work` holds index_rows_work(n) int32 values.
 int64_t index_rows_work(int64_t n);
 hipError_t index_rows(const int32_t *a_prev, const uint8_t *changed, int64_t n, int32_t *rows,
-                      int32_t *count, int32_t *work, hipStream_t s);
+                      int32_t *count, int32_t *work, hipStream_t s, int32_t keep = 0);
 hipError_t index_query(const IndexArgs &x, int64_t n_slots, hipStream_t s);
 hipError_t index_score(const IndexArgs &x, int64_t n_slots, int32_t *a_out, double *lo_out,
                        double *hi_out, hipStream_t s);

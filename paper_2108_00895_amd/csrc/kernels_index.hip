@@ -43,33 +43,40 @@ __global__ __launch_bounds__(256) void k_centroid_nnz(const double *master, int6
   if (threadIdx.x == 0) cnt[j] = sh[0];
 }
 
-// Entries of centroid j in term order: key = ~bits(value) (ascending key =
-// descending value, values are positive), term.
+// Entries of centroid j: key = ~bits(value) (ascending key = descending
+// value, values are positive), term.  Coalesced sweeps of the FP64 row, each
+// wavefront appending its non-zeros by ballot at a workgroup counter; the
+// order within the segment is arbitrary, since k_sort_segments orders the
+// (key, term) pairs, which are unique, completely.
 __global__ __launch_bounds__(256) void k_extract(const double *master, int64_t D, const int64_t *eoff,
                                                  uint64_t *key, int32_t *term) {
-  __shared__ int32_t sh[256];
+  __shared__ int32_t fill;
   const int j = blockIdx.x;
   const double *row = master + (int64_t)j * D;
-  int64_t base = eoff[j];
-  const int64_t per = (D + 255) / 256;
-  const int64_t lo = threadIdx.x * per, hi = min(D, lo + per);
-  int c = 0;
-  for (int64_t t = lo; t < hi; ++t) c += row[t] != 0.0;
-  sh[threadIdx.x] = c;
+  const int64_t base = eoff[j];
+  const int lane = lane_id();
+  if (threadIdx.x == 0) fill = 0;
   __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    int v = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
-    __syncthreads();
-    sh[threadIdx.x] += v;
-    __syncthreads();
-  }
-  int64_t pos = base + sh[threadIdx.x] - c;
-  for (int64_t t = lo; t < hi; ++t) {
-    const double v = row[t];
-    if (v != 0.0) {
-      key[pos] = ~(uint64_t)__double_as_longlong(v);
-      term[pos] = (int32_t)t;
-      ++pos;
+  for (int64_t t0 = 0; t0 < D; t0 += 1024) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t t = t0 + u * 256 + threadIdx.x;
+      v[u] = t < D ? row[t] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t t = t0 + u * 256 + threadIdx.x;
+      const bool nz = v[u] != 0.0;
+      const uint64_t m = __ballot(nz);
+      int wb = 0;
+      if (lane == 0 && m) wb = atomicAdd(&fill, __popcll(m));
+      wb = __shfl(wb, 0, kWave);
+      if (nz) {
+        const int64_t p = base + wb + __popcll(m & lanemask_lt());
+        key[p] = ~(uint64_t)__double_as_longlong(v[u]);
+        term[p] = (int32_t)t;
+      }
     }
   }
 }
@@ -438,21 +445,23 @@ __global__ __launch_bounds__(256) void k_index_score(IndexArgs x, int64_t n_slot
 
 // Rows whose previous centroid changed, in ascending order (index path).
 // Stable compaction of the rows whose previous centroid is flagged in
-// `changed` (all rows when changed == nullptr) into an ascending list, in
+// `changed` (keep = 0) or not flagged (keep = 1), all rows when changed ==
+// nullptr, into an ascending list, in
 // three launches: per-block counts, a scan of the block counts, and the
 // writes (ballot ranks within a wave, wave counts through LDS).
 constexpr int64_t kListBlock = 4096;   // rows per block
 
-__device__ inline bool list_sel(const int32_t *a_prev, const uint8_t *changed, int64_t i) {
-  return !changed || changed[a_prev[i]];
+__device__ inline bool list_sel(const int32_t *a_prev, const uint8_t *changed, int64_t i,
+                                int32_t keep) {
+  return !changed || (changed[a_prev[i]] != 0) != (keep != 0);
 }
 
 __global__ __launch_bounds__(256) void k_list_count(const int32_t *a_prev, const uint8_t *changed,
-                                                    int64_t n, int32_t *bcnt) {
+                                                    int32_t keep, int64_t n, int32_t *bcnt) {
   __shared__ int32_t ws[4];
   const int64_t lo = (int64_t)blockIdx.x * kListBlock, hi = min(n, lo + kListBlock);
   int c = 0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) c += list_sel(a_prev, changed, i) ? 1 : 0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) c += list_sel(a_prev, changed, i, keep) ? 1 : 0;
   for (int m = 1; m < kWave; m <<= 1) c += __shfl_xor(c, m, kWave);
   if (lane_id() == 0) ws[threadIdx.x >> 6] = c;
   __syncthreads();
@@ -487,14 +496,15 @@ __global__ __launch_bounds__(1024) void k_list_scan(int32_t *bcnt, int64_t nblk,
 }
 
 __global__ __launch_bounds__(256) void k_list_write(const int32_t *a_prev, const uint8_t *changed,
-                                                    int64_t n, const int32_t *boff, int32_t *rows) {
+                                                    int32_t keep, int64_t n, const int32_t *boff,
+                                                    int32_t *rows) {
   __shared__ int32_t ws[4];
   const int64_t lo = (int64_t)blockIdx.x * kListBlock, hi = min(n, lo + kListBlock);
   const int wave = threadIdx.x >> 6;
   int32_t pos = boff[blockIdx.x];
   for (int64_t b0 = lo; b0 < hi; b0 += 256) {
     const int64_t i = b0 + threadIdx.x;
-    const bool sel = i < hi && list_sel(a_prev, changed, i);
+    const bool sel = i < hi && list_sel(a_prev, changed, i, keep);
     const uint64_t m = __ballot(sel);
     if (lane_id() == 0) ws[wave] = __popcll(m);
     __syncthreads();
@@ -539,16 +549,16 @@ hipError_t index_build_rest(const IndexBuild &ib, hipStream_t s) {
 int64_t index_rows_work(int64_t n) { return std::max<int64_t>(1, (n + kListBlock - 1) / kListBlock); }
 
 hipError_t index_rows(const int32_t *a_prev, const uint8_t *changed, int64_t n, int32_t *rows,
-                      int32_t *count, int32_t *work, hipStream_t s) {
+                      int32_t *count, int32_t *work, hipStream_t s, int32_t keep) {
   const int64_t nblk = (n + kListBlock - 1) / kListBlock;
   if (nblk > 0) {
-    hipLaunchKernelGGL(k_list_count, dim3((unsigned)nblk), dim3(256), 0, s, a_prev, changed, n,
-                       work);
+    hipLaunchKernelGGL(k_list_count, dim3((unsigned)nblk), dim3(256), 0, s, a_prev, changed, keep,
+                       n, work);
   }
   hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, s, work, nblk, count);
   if (nblk > 0) {
-    hipLaunchKernelGGL(k_list_write, dim3((unsigned)nblk), dim3(256), 0, s, a_prev, changed, n,
-                       work, rows);
+    hipLaunchKernelGGL(k_list_write, dim3((unsigned)nblk), dim3(256), 0, s, a_prev, changed, keep,
+                       n, work, rows);
   }
   return hipGetLastError();
 }
