@@ -157,7 +157,8 @@ typedef struct {
   float ms_index;             /* index query + exact candidate scoring (assign),
                                  index build (update) */
   int32_t head_terms;         /* terms this assignment scored on the matrix cores
-                                 (0 = none; the head is not used for NCC rows) */
+                                 (0 = none; NCC rows scored against at most 64
+                                 changed centroids do not use it) */
   float ms_head;              /* device time of the head products (part of ms_score) */
   int32_t score_launches;     /* launches of the sparse scoring kernel */
   double sparse_products;     /* scored_products restricted to the terms scored on

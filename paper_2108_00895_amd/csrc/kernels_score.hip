@@ -543,9 +543,11 @@ __global__ __launch_bounds__(256) void k_finalize(ScoreArgs a, const Partial *__
     n_cols = (unsigned long long)pl.ncols;
     n_prod = (unsigned long long)pl.ncols * (unsigned long long)n;
     n_ncc = pl.ncc ? 1ull : 0ull;
-    if (a.head_H > 0)
+    if (a.head_H > 0)   // narrow NCC rows (no head product) scored every term
       n_sp = (unsigned long long)pl.ncols *
-             (unsigned long long)(a.sc_indptr[row + 1] - a.sc_indptr[row]);
+             (unsigned long long)(pl.ncc && pl.ncols <= kNarrowMax
+                                      ? n
+                                      : a.sc_indptr[row + 1] - a.sc_indptr[row]);
     if (certain || a.no_exact) {
       a.a_out[row] = win;
       a.lo_out[row] = wlo;
