@@ -281,15 +281,24 @@ skm_status skm_set_schedule(skm_ctx *c, const skm_tune_trial *shape);
 
 /* Diagnostic: the low-precision scores of the context's own rows
  * [row0, row0 + n_rows) as an assignment step with the head computes them
- * (head product plus the rows' other terms), before any exact tier:
- * out[i * k + j], host, n_rows * k floats.  SKM_E_STATE when the head is off;
- * SKM_E_INVALID for a range outside the rows or above one head batch. */
-skm_status skm_score_head(skm_ctx *c, int64_t row0, int64_t n_rows, float *out);
+ * (head product and the rows' other terms summed apart, then added), before
+ * any exact tier: out[i * k + j], host, n_rows * k floats; out_head (host,
+ * same layout, may be NULL) receives the head parts alone.  SKM_E_STATE when
+ * the head is off; SKM_E_INVALID for a range outside the rows or above one
+ * head batch. */
+skm_status skm_score_head(skm_ctx *c, int64_t row0, int64_t n_rows, float *out,
+                          float *out_head);
 
-/* The certified bound for such head scores (Sec. 2 scores with the row values
- * of head terms rounded to BF16 and matrix-core accumulation); -1 when the
- * head is off. */
+/* The certified bound for such head scores as a function of the score alone
+ * (Sec. 2 scores with the row values of head terms rounded to BF16 and
+ * matrix-core accumulation); -1 when the head is off. */
 double skm_error_bound_head(const skm_ctx *c, double s, int64_t nnz, double l1);
+
+/* FP8 contexts with a head: the bound the assignment step uses, from the head
+ * part hs (BF16 head codes rounded from the FP64 centroids) and the part rs
+ * of the n_rest other terms (FP8 codes), both >= 0 and in score units:
+ * |s^ - s| <= kh hs + ks rs + 2^-24 (hs + rs) + A.  -1 for other contexts. */
+double skm_error_bound_split(const skm_ctx *c, double hs, double rs, int64_t n_rest, double l1);
 
 /* Index of threshold level `level` (Sec. 3.2), after an update with SKM_INDEX:
  * term-major lists.  offsets [n_cols + 1] (host int64), entries (host) of

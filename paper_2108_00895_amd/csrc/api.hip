@@ -257,8 +257,8 @@ skm_status rebuild_tiles(skm_ctx *c, const uint8_t *changed,
                              c->stream));
   ST_TRY(build_tail(c, 0, c->tile, c->k, changed ? chunks : nullptr));
   if (c->head_H > 0)
-    HIP_TRY(c, launch_head_codes(c->tile, c->D, c->k, c->prec, c->head_terms, c->head_H, c->k_pad,
-                                 c->ch_head, c->stream));
+    HIP_TRY(c, launch_head_codes(c->tile, c->master, c->scale, c->D, c->k, c->prec, c->head_terms,
+                                 c->head_H, c->k_pad, c->ch_head, c->stream));
   return SKM_OK;
 }
 
@@ -1467,16 +1467,19 @@ skm_status skm_score_dense(skm_ctx *c, const skm_csr *docs, float *out) {
 
 int32_t skm_head_terms(const skm_ctx *c) { return c ? c->head_H : 0; }
 
-skm_status skm_score_head(skm_ctx *c, int64_t row0, int64_t n_rows, float *out) {
+skm_status skm_score_head(skm_ctx *c, int64_t row0, int64_t n_rows, float *out,
+                          float *out_head) {
   ST_TRY(check_ctx(c));
   if (!out) return fail(SKM_E_INVALID, "out is NULL");
   if (c->head_H <= 0) return fail(SKM_E_STATE, "this context scores no head terms");
   if (row0 < 0 || n_rows < 0 || row0 + n_rows > c->N || n_rows * c->k_pad > c->hs_cap)
     return fail(SKM_E_INVALID, "row range outside the context or larger than one head batch");
   if (n_rows == 0) return SKM_OK;
-  float *d_out = nullptr;
-  if (hipMalloc(&d_out, sizeof(float) * n_rows * c->k) != hipSuccess) {
+  float *d_out = nullptr, *d_head = nullptr;
+  const size_t bytes = sizeof(float) * n_rows * c->k;
+  if (hipMalloc(&d_out, bytes) != hipSuccess || (out_head && hipMalloc(&d_head, bytes) != hipSuccess)) {
     (void)hipGetLastError();
+    if (d_out) (void)hipFree(d_out);
     return fail(SKM_E_NOMEM, "temporary device allocation failed");
   }
   // all centroid columns of these rows at once (the batch buffer holds them)
@@ -1485,11 +1488,13 @@ skm_status skm_score_head(skm_ctx *c, int64_t row0, int64_t n_rows, float *out) 
   if (e == hipSuccess)
     e = launch_score_dense(c->r_indptr + row0, c->r_indices, c->r_values, n_rows, c->tile, c->D,
                            c->k, c->scale, tail_view(c, 0), c->prec, c->hs, c->k_pad, d_out,
-                           c->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(out, d_out, sizeof(float) * n_rows * c->k, hipMemcpyDeviceToHost, c->stream);
+                           c->stream, d_head);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, d_out, bytes, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess && out_head)
+    e = hipMemcpyAsync(out_head, d_head, bytes, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   (void)hipFree(d_out);
+  if (d_head) (void)hipFree(d_head);
   if (e != hipSuccess) return device_fail(c, "score_head", e);
   return SKM_OK;
 }
@@ -1498,6 +1503,12 @@ double skm_error_bound_head(const skm_ctx *c, double s, int64_t nnz, double l1) 
   if (!c || c->head_H <= 0) return -1.0;
   return bound_kappa_head(nnz, c->head_H, c->uq) * s + bound_abs(nnz, l1, c->abs_coef) +
          bound_abs_head(c->head_H, l1, c->abs_coef);
+}
+
+double skm_error_bound_split(const skm_ctx *c, double hs, double rs, int64_t n_rest, double l1) {
+  if (!c || c->head_H <= 0 || c->prec != SKM_FP8_E4M3) return -1.0;
+  const double A = bound_abs(n_rest, l1, c->abs_coef) + (double)c->head_H * 0x1p-120;
+  return bound_split(hs, rs, bound_kappa_head_bf16(c->head_H), bound_kappa(n_rest, c->uq), A);
 }
 
 double skm_error_bound(const skm_ctx *c, double s, int64_t nnz, double l1) {

@@ -69,40 +69,49 @@ __device__ inline void wave_top2(float &b1, int &j1, float &b2) {
   }
 }
 
-// Inserts (s, j) into a list of four kept best first (better(): higher score,
-// then lower index), dropping the fifth.
-__device__ inline void top4_insert(float s, int j, float ts[4], int tj[4]) {
-  if (!better(s, j, ts[3], tj[3])) return;
-  ts[3] = s;
-  tj[3] = j;
+// FP8 chunk summaries kept as certified bounds: the column with the best
+// lower bound (ties: lower index) with its upper bound, and the two largest
+// upper bounds (ties: lower index) with their columns.
+__device__ inline void ub_insert(float u, int j, float &u1, int &j1, float &u2, int &j2) {
+  // selects only (branches on the references make the compiler spill them)
+  const bool f = better(u, j, u1, j1), g = better(u, j, u2, j2);
+  const float nu2 = f ? u1 : (g ? u : u2);
+  const int nj2 = f ? j1 : (g ? j : j2);
+  u1 = f ? u : u1;
+  j1 = f ? j : j1;
+  u2 = nu2;
+  j2 = nj2;
+}
+
+// Butterfly merge of bound summaries (the two halves hold disjoint columns);
+// every lane ends with the wave's summary.
+__device__ inline void wave_bound_summary(float &lb, int &jl, float &ubl, float &u1, int &j1,
+                                          float &u2, int &j2) {
 #pragma unroll
-  for (int q = 3; q > 0; --q) {
-    if (better(ts[q], tj[q], ts[q - 1], tj[q - 1])) {
-      const float x = ts[q];
-      ts[q] = ts[q - 1];
-      ts[q - 1] = x;
-      const int y = tj[q];
-      tj[q] = tj[q - 1];
-      tj[q - 1] = y;
+  for (int m = 1; m < kWave; m <<= 1) {
+    const float olb = __shfl_xor(lb, m, kWave), oubl = __shfl_xor(ubl, m, kWave);
+    const int ojl = __shfl_xor(jl, m, kWave);
+    const float ou1 = __shfl_xor(u1, m, kWave), ou2 = __shfl_xor(u2, m, kWave);
+    const int oj1 = __shfl_xor(j1, m, kWave), oj2 = __shfl_xor(j2, m, kWave);
+    if (better(olb, ojl, lb, jl)) {
+      lb = olb;
+      jl = ojl;
+      ubl = oubl;
     }
+    ub_insert(ou1, oj1, u1, j1, u2, j2);
+    ub_insert(ou2, oj2, u1, j1, u2, j2);
   }
 }
 
-// Top four over the wavefront (butterfly: the two halves merged at each step
-// hold disjoint columns); every lane ends with the result.
-__device__ inline void wave_top4(float ts[4], int tj[4]) {
-#pragma unroll
-  for (int m = 1; m < kWave; m <<= 1) {
-    float os[4];
-    int oj[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      os[q] = __shfl_xor(ts[q], m, kWave);
-      oj[q] = __shfl_xor(tj[q], m, kWave);
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) top4_insert(os[q], oj[q], ts, tj);
-  }
+// Float bounds that keep a double bound's direction: the largest float <= x,
+// the smallest float >= x.
+__device__ inline float f_down(double x) {
+  const float f = (float)x;
+  return (double)f > x ? nextafterf(f, -INFINITY) : f;
+}
+__device__ inline float f_up(double x) {
+  const float f = (float)x;
+  return (double)f < x ? nextafterf(f, INFINITY) : f;
 }
 
 __device__ inline void wave_best_d(double &s, int &j) {
@@ -216,6 +225,28 @@ __host__ __device__ inline double bound_kappa_head(int64_t n, int64_t H, double 
   double g = nn * u / (1.0 - nn * u);
   double k = (g + up / (1.0 - up)) / (1.0 - g);
   return k * (1.0 + 0x1p-20) + 0x1p-60;
+}
+
+// Relative bound of a head sum alone when the head codes are BF16 roundings of
+// the FP64 master (FP8 scoring copies): H products of BF16 row values and
+// BF16 codes (combined unit 2^-8 + 2^-8 + 2^-16), each accumulation step on the
+// matrix cores counted as two roundings.
+__host__ __device__ inline double bound_kappa_head_bf16(int64_t H) {
+  const double u = 0x1p-24, up = 0x1p-8 + 0x1p-8 + 0x1p-16;
+  double nn = 2.0 * (double)(H > 0 ? H : 1) + 4.0;
+  double g = nn * u / (1.0 - nn * u);
+  double k = (g + up / (1.0 - up)) / (1.0 - g);
+  return k * (1.0 + 0x1p-20) + 0x1p-60;
+}
+
+// Bound on an FP8 score whose head part hs and sparse part rs (both >= 0, in
+// score units) were summed separately and added once:
+//   |s^ - s| <= kh hs + ks rs + 2^-24 (hs + rs) + A,
+// kh from bound_kappa_head_bf16, ks and A those of the n_s sparse terms, plus
+// the matrix cores' flush term.
+__host__ __device__ inline double bound_split(double hs, double rs, double kh, double ks,
+                                              double A) {
+  return (kh * hs + ks * rs + 0x1p-24 * (hs + rs)) * (1.0 + 0x1p-20) + A;
 }
 
 // Absolute part for head scores: the encoding term grows with the rounded row

@@ -53,7 +53,7 @@ struct ScoreArgs {
   int32_t ncc_only;           // 1: rows whose previous centroid changed are left out
                               // (a second launch over their list scores them)
   int32_t head_H;             // head terms in the partial scores' bound (0: none)
-  int32_t top;                // entries kept per (row, chunk) partial: 2 or 4
+  int32_t top;                // partial format: 2 = scores, kTop = certified bounds (FP8)
   // scoring copy, chunk-blocked term-major (see tile_index)
   const uint8_t *tile;
   int64_t D;
@@ -90,13 +90,13 @@ struct ScoreArgs {
                               // [3] products, [8] products of the sparse pass (head on)
 };
 
-// Best scores of one row against one 512-centroid chunk, best first (higher
-// score, then lower centroid index); -inf where the chunk has fewer columns.
-// With top = 4 (FP8 scoring, whose wide bound makes large bands) all four
-// entries are kept and the exact tier takes a chunk's band members from them
-// without rescoring the chunk when the fourth cannot reach the row's bound;
-// with top = 2 only e[0] and the score of e[1] are kept.  The merge certifies
-// from the first two.
+// Summary of one row against one 512-centroid chunk; -inf where the chunk has
+// fewer columns.  top = 2 (FP32 / BF16): e[0] = best score (higher score,
+// then lower centroid index) and the score of the second best in e[1].s; the
+// merge derives both bounds from the scores.  top = kTop (FP8, whose head and
+// sparse parts carry different bounds): certified bounds per column, e[0] =
+// the best lower bound and its column, e[1].s = that column's upper bound,
+// e[2], e[3] = the two largest upper bounds and their columns.
 constexpr int kTop = 4;
 struct __align__(16) Partial {
   struct {
@@ -344,7 +344,8 @@ hipError_t launch_exact(const ExactArgs &a, int prec, hipStream_t s);
 hipError_t launch_score_dense(const int64_t *indptr, const int32_t *indices, const float *values,
                               int64_t n_rows, const uint8_t *tile, int64_t D, int32_t k,
                               const float *scale, const TailView &tv, int prec, const float *hs,
-                              int64_t hs_ld, float *out, hipStream_t s);
+                              int64_t hs_ld, float *out, hipStream_t s,
+                              float *out_head = nullptr);
 hipError_t launch_exact_scores(const int64_t *indptr, const int32_t *indices, const float *values,
                                int64_t n_rows, const int32_t *a, const double *master, int64_t D,
                                double *out, hipStream_t s, const int64_t *n_dev = nullptr);
@@ -432,9 +433,9 @@ hipError_t launch_head_split(const int64_t *indptr, const int32_t *indices, cons
                              int64_t n_rows, const int32_t *slot, int32_t H, int64_t *cnt,
                              int64_t *scan_work, int64_t *r_indptr, int32_t *r_indices,
                              float *r_values, uint16_t *xh, hipStream_t s);
-hipError_t launch_head_codes(const uint8_t *tile, int64_t D, int32_t k, int prec,
-                             const int32_t *terms, int32_t H, int32_t k_pad, uint16_t *ch,
-                             hipStream_t s);
+hipError_t launch_head_codes(const uint8_t *tile, const double *master, const float *scale,
+                             int64_t D, int32_t k, int prec, const int32_t *terms, int32_t H,
+                             int32_t k_pad, uint16_t *ch, hipStream_t s);
 // hs[r][j] = sum_h xh[x_r][h] * ch[col0 + j][h], r < nb, j < ncols, where
 // x_r = row0 + r, or rows[row0 + r] when rows is given (ncols a multiple of
 // 256, col0 + ncols <= rows of ch).

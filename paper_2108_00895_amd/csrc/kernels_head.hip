@@ -88,12 +88,15 @@ __global__ __launch_bounds__(256) void k_head_split(const int64_t *indptr, const
   for (int i = lane; i < H / 8; i += kWave) dst[i] = src[i];
 }
 
-// C_head[j][h] = the scoring code of centroid j at head term h, as BF16 (BF16
-// codes copied; FP8 codes decoded, without the centroid's scale, which is
-// exact in BF16).  Rows j >= k are zero.  A 64 x 64 block is transposed
-// through LDS so that both the code reads and the C_head writes are coalesced.
+// C_head[j][h] = centroid j at head term h as BF16: for BF16 scoring the code
+// itself; for FP8 scoring the BF16 rounding of the FP64 master value divided
+// by the centroid's power-of-two scale (the head part of an FP8 score thus
+// carries BF16 accuracy; the scale is applied with the rest of the score).
+// Rows j >= k are zero.  A 64 x 64 block is transposed through LDS so that the
+// C_head writes are coalesced.
 template <int P>
-__global__ __launch_bounds__(256) void k_head_codes(const uint8_t *tile, int64_t D, int32_t k,
+__global__ __launch_bounds__(256) void k_head_codes(const uint8_t *tile, const double *master,
+                                                    const float *scale, int64_t D, int32_t k,
                                                     const int32_t *terms, int32_t H,
                                                     int32_t k_pad, uint16_t *ch) {
   __shared__ uint16_t t_sh[64][65];
@@ -103,11 +106,10 @@ __global__ __launch_bounds__(256) void k_head_codes(const uint8_t *tile, int64_t
     const int h = h0 + r, j = j0 + tx;
     uint16_t v = 0;
     if (h < H && j < k) {
-      const int64_t at = tile_index(terms[h], j, D);
       if (P == SKM_BF16) {
-        v = reinterpret_cast<const uint16_t *>(tile)[at];
+        v = reinterpret_cast<const uint16_t *>(tile)[tile_index(terms[h], j, D)];
       } else {
-        v = bf16_rne(__builtin_amdgcn_cvt_pk_f32_fp8((int)tile[at], false)[0]);
+        v = encode_bf16(ldexp(master[(int64_t)j * D + terms[h]], -ilogbf(scale[j])));
       }
     }
     t_sh[r][tx] = v;
@@ -351,16 +353,19 @@ int64_t head_split_scan_blocks(int64_t n_rows) {
   return (n_rows + (int64_t)kScanBlock * kScanPer - 1) / ((int64_t)kScanBlock * kScanPer) + 1;
 }
 
-hipError_t launch_head_codes(const uint8_t *tile, int64_t D, int32_t k, int prec,
-                             const int32_t *terms, int32_t H, int32_t k_pad, uint16_t *ch,
-                             hipStream_t s) {
+hipError_t launch_head_codes(const uint8_t *tile, const double *master, const float *scale,
+                             int64_t D, int32_t k, int prec, const int32_t *terms, int32_t H,
+                             int32_t k_pad, uint16_t *ch, hipStream_t s) {
   const dim3 g((unsigned)((k_pad + 63) / 64), (unsigned)((H + 63) / 64)), b(256);
   switch (prec) {
     case SKM_BF16:
-      hipLaunchKernelGGL(k_head_codes<SKM_BF16>, g, b, 0, s, tile, D, k, terms, H, k_pad, ch);
+      hipLaunchKernelGGL(k_head_codes<SKM_BF16>, g, b, 0, s, tile, master, scale, D, k, terms, H,
+                         k_pad, ch);
       break;
     case SKM_FP8_E4M3:
-      hipLaunchKernelGGL(k_head_codes<SKM_FP8_E4M3>, g, b, 0, s, tile, D, k, terms, H, k_pad, ch);
+      if (!master || !scale) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(k_head_codes<SKM_FP8_E4M3>, g, b, 0, s, tile, master, scale, D, k, terms,
+                         H, k_pad, ch);
       break;
     default: return hipErrorInvalidValue;
   }

@@ -327,45 +327,66 @@ __global__ __launch_bounds__(256) void k_score_part(ScoreArgs a, Partial *__rest
     if (c0 >= pl.ncols) continue;
     const int64_t b = uniform64(a.sc_indptr[row]);
     const int64_t e = uniform64(a.sc_indptr[row + 1]);
+    // FP32 / BF16: the sparse terms are added onto the head scores of these 8
+    // columns (kernels_head.hip).  FP8: the head part (BF16 head codes) and
+    // the sparse part (FP8 codes) are summed apart and added once, so that
+    // each part keeps its own bound.
+    constexpr bool kSplit = P == SKM_FP8_E4M3;
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (a.hs) {
-      // start from the head scores of these 8 columns (kernels_head.hip)
+    float hh[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    auto load_head = [&](float *dst) {
       const float4 *h = reinterpret_cast<const float4 *>(a.hs + r * a.hs_ld + ci * kChunk +
                                                          lane * kColsPerLane);
       const float4 h0 = h[0], h1 = h[1];
-      acc[0] = h0.x;
-      acc[1] = h0.y;
-      acc[2] = h0.z;
-      acc[3] = h0.w;
-      acc[4] = h1.x;
-      acc[5] = h1.y;
-      acc[6] = h1.z;
-      acc[7] = h1.w;
-    }
+      dst[0] = h0.x;
+      dst[1] = h0.y;
+      dst[2] = h0.z;
+      dst[3] = h0.w;
+      dst[4] = h1.x;
+      dst[5] = h1.y;
+      dst[6] = h1.z;
+      dst[7] = h1.w;
+    };
+    if (!kSplit && a.hs) load_head(acc);
     score_chunk<P>(b, e, a.sc_indices, a.sc_values, pl.tile, a.D, c0, pl.ncols - c0, acc, *pl.tv,
                    lacc);
-    if (a.top == kTop) {
-      float ts[kTop] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
-      int tj[kTop] = {0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF};
+    if (kSplit && a.hs) load_head(hh);   // read after the sparse loop: no registers held
+    if constexpr (kSplit) {
+      // certified bounds per column (float arithmetic, inflated so that every
+      // rounding leaves them conservative): E = kh h + ks r + 2^-24 (h + r) + A,
+      // then lb = s - E - M and ub = s + E + M with M = 2^-21 (s + E)
+      const int64_t n_s = e - b;
+      const float ks = f_up(bound_kappa(n_s, a.uq));
+      const float kh = a.hs ? f_up(bound_kappa_head_bf16(a.head_H)) : 0.f;
+      const float A = f_up((bound_abs(n_s, a.xl1[row], a.abs_coef) +
+                            (a.hs ? (double)a.head_H * 0x1p-120 : 0.0)) * (1.0 + 0x1p-20));
+      float lb = -INFINITY, ubl = -INFINITY, u1 = -INFINITY, u2 = -INFINITY;
+      int jl = 0x7FFFFFFF, j1 = 0x7FFFFFFF, j2 = 0x7FFFFFFF;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int64_t col = c0 + lane * kColsPerLane + q;
         if (col < pl.ncols) {
           const int j = pl.colmap ? pl.colmap[col] : (int)col;
-          float s = acc[q];
-          if (a.scale) s *= a.scale[j];
-          top4_insert(s, j, ts, tj);
+          const float sc = a.scale[j];
+          const float hq = hh[q] * sc, rq = acc[q] * sc;
+          const float sf = (hh[q] + acc[q]) * sc;
+          float E = fmaf(kh, hq, fmaf(ks, rq, 0x1p-24f * (hq + rq)));
+          E = fmaf(E, 1.0f + 0x1p-20f, A);
+          const float M = 0x1p-21f * (sf + E);
+          const float lq = sf - E - M, uq = sf + E + M;
+          if (better(lq, j, lb, jl)) {
+            lb = lq;
+            jl = j;
+            ubl = uq;
+          }
+          ub_insert(uq, j, u1, j1, u2, j2);
         }
       }
-      wave_top4(ts, tj);
+      wave_bound_summary(lb, jl, ubl, u1, j1, u2, j2);
       if (lane == 0) {
-        Partial p;
-#pragma unroll
-        for (int q = 0; q < kTop; ++q) {
-          p.e[q].s = ts[q];
-          p.e[q].j = tj[q];
-        }
-        part[c * a.n_rows + row] = p;
+        float4 *dst = reinterpret_cast<float4 *>(&part[c * a.n_rows + row]);
+        dst[0] = make_float4(lb, __int_as_float(jl), ubl, __int_as_float(jl));
+        dst[1] = make_float4(u1, __int_as_float(j1), u2, __int_as_float(j2));
       }
     } else {
       float b1 = -INFINITY, b2 = -INFINITY;
@@ -438,23 +459,36 @@ __global__ __launch_bounds__(256) void k_score_narrow(ScoreArgs a, Partial *__re
   if (lane != 0) return;
   const int n_ch = a.n_ch;
   if (a.top == kTop) {
-    float ts[kTop] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
-    int tj[kTop] = {0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF};
+    // FP8 bound summary (every term from the FP8 codes)
+    const int64_t n = e - b;
+    const double ks = bound_kappa(n, a.uq), A = bound_abs(n, a.xl1[row], a.abs_coef);
+    float lb = -INFINITY, ubl = -INFINITY, u1 = -INFINITY, u2 = -INFINITY;
+    int jl = 0x7FFFFFFF, j1 = 0x7FFFFFFF, j2 = 0x7FFFFFFF;
 #pragma unroll
     for (int c = 0; c < NG * 8; ++c) {
       if (c < n_ch) {
         const int j = a.ch_ids[c];
-        float s = acc[c];
-        if (a.scale) s *= a.scale[j];
-        top4_insert(s, j, ts, tj);
+        const float sc = a.scale ? a.scale[j] : 1.f;
+        const float sf = acc[c] * sc;
+        const double E = bound_split(0.0, (double)sf, 0.0, ks, A);
+        const float lq = f_down((double)sf - E), uq = f_up((double)sf + E);
+        if (better(lq, j, lb, jl)) {
+          lb = lq;
+          jl = j;
+          ubl = uq;
+        }
+        ub_insert(uq, j, u1, j1, u2, j2);
       }
     }
     Partial p;
-#pragma unroll
-    for (int q = 0; q < kTop; ++q) {
-      p.e[q].s = ts[q];
-      p.e[q].j = tj[q];
-    }
+    p.e[0].s = lb;
+    p.e[0].j = jl;
+    p.e[1].s = ubl;
+    p.e[1].j = jl;
+    p.e[2].s = u1;
+    p.e[2].j = j1;
+    p.e[3].s = u2;
+    p.e[3].j = j2;
     part[row] = p;
   } else {
     float b1 = -INFINITY, b2 = -INFINITY;
@@ -491,53 +525,100 @@ __global__ __launch_bounds__(256) void k_finalize(ScoreArgs a, const Partial *__
   const RowPlan pl = row < n_rows ? plan_row(a, row, true) : RowPlan{};
   if (row < n_rows && !pl.done) {
     const int64_t b = a.indptr[row], e = a.indptr[row + 1];
-    float b1 = -INFINITY, b2 = -INFINITY;
-    int j1 = 0x7FFFFFFF;
-    const int64_t nch = (pl.ncols + kChunk - 1) / kChunk;
-    for (int64_t c = 0; c < nch; ++c) {
-      const Partial p = part[c * a.n_rows + row];
-      if (better(p.e[0].s, p.e[0].j, b1, j1)) {
-        b2 = fmaxf(b1, p.e[1].s);
-        b1 = p.e[0].s;
-        j1 = p.e[0].j;
-      } else {
-        b2 = fmaxf(b2, p.e[0].s);
-      }
-    }
     const int64_t n = e - b;
-    double kap, A;
-    part_bound(a, row, n, kap, A);
-    auto lo_of = [&](float s) { return s == -INFINITY ? -INFINITY : (double)s - (kap * (double)s + A); };
-    auto hi_of = [&](float s) { return s == -INFINITY ? -INFINITY : (double)s + (kap * (double)s + A); };
+    const int64_t nch = (pl.ncols + kChunk - 1) / kChunk;
     int win;
     double wlo, whi, L;
     bool certain;
-    if (!pl.ncc) {
-      win = j1;
-      wlo = lo_of(b1);
-      whi = hi_of(b1);
-      certain = wlo > hi_of(b2);
-      L = wlo;
-    } else {
-      const double plo = a.prev_lo[row], phi = a.prev_hi[row];
-      if (b1 == -INFINITY) {
-        win = pl.ap;
-        wlo = plo;
-        whi = phi;
-        certain = true;
-        L = plo;
-      } else if (plo >= lo_of(b1)) {
-        win = pl.ap;
-        wlo = plo;
-        whi = phi;
-        certain = plo > hi_of(b1);
-        L = plo;
+    if (a.top == kTop) {
+      // FP8: the chunk summaries hold certified bounds.  The winner is the
+      // column with the best lower bound; it is certain when that bound
+      // exceeds every other column's upper bound.
+      float lbw = -INFINITY, ubw = -INFINITY, g1 = -INFINITY, g2 = -INFINITY;
+      int jw = 0x7FFFFFFF, gj1 = 0x7FFFFFFF, gj2 = 0x7FFFFFFF;
+      for (int64_t c = 0; c < nch; ++c) {
+        const Partial p = part[c * a.n_rows + row];
+        if (better(p.e[0].s, p.e[0].j, lbw, jw)) {
+          lbw = p.e[0].s;
+          jw = p.e[0].j;
+          ubw = p.e[1].s;
+        }
+        ub_insert(p.e[2].s, p.e[2].j, g1, gj1, g2, gj2);
+        ub_insert(p.e[3].s, p.e[3].j, g1, gj1, g2, gj2);
+      }
+      const double other = gj1 != jw ? (double)g1 : (double)g2;   // best other upper bound
+      if (!pl.ncc) {
+        win = jw;
+        wlo = lbw;
+        whi = ubw;
+        certain = (double)lbw > other;
+        L = lbw;
       } else {
+        const double plo = a.prev_lo[row], phi = a.prev_hi[row];
+        if (nch == 0) {
+          win = pl.ap;
+          wlo = plo;
+          whi = phi;
+          certain = true;
+          L = plo;
+        } else if (plo >= (double)lbw) {
+          win = pl.ap;
+          wlo = plo;
+          whi = phi;
+          certain = plo > (double)g1;
+          L = plo;
+        } else {
+          win = jw;
+          wlo = lbw;
+          whi = ubw;
+          certain = (double)lbw > fmax(phi, other);
+          L = lbw;
+        }
+      }
+    } else {
+      float b1 = -INFINITY, b2 = -INFINITY;
+      int j1 = 0x7FFFFFFF;
+      for (int64_t c = 0; c < nch; ++c) {
+        const Partial p = part[c * a.n_rows + row];
+        if (better(p.e[0].s, p.e[0].j, b1, j1)) {
+          b2 = fmaxf(b1, p.e[1].s);
+          b1 = p.e[0].s;
+          j1 = p.e[0].j;
+        } else {
+          b2 = fmaxf(b2, p.e[0].s);
+        }
+      }
+      double kap, A;
+      part_bound(a, row, n, kap, A);
+      auto lo_of = [&](float s) { return s == -INFINITY ? -INFINITY : (double)s - (kap * (double)s + A); };
+      auto hi_of = [&](float s) { return s == -INFINITY ? -INFINITY : (double)s + (kap * (double)s + A); };
+      if (!pl.ncc) {
         win = j1;
         wlo = lo_of(b1);
         whi = hi_of(b1);
-        certain = wlo > fmax(phi, hi_of(b2));
+        certain = wlo > hi_of(b2);
         L = wlo;
+      } else {
+        const double plo = a.prev_lo[row], phi = a.prev_hi[row];
+        if (b1 == -INFINITY) {
+          win = pl.ap;
+          wlo = plo;
+          whi = phi;
+          certain = true;
+          L = plo;
+        } else if (plo >= lo_of(b1)) {
+          win = pl.ap;
+          wlo = plo;
+          whi = phi;
+          certain = plo > hi_of(b1);
+          L = plo;
+        } else {
+          win = j1;
+          wlo = lo_of(b1);
+          whi = hi_of(b1);
+          certain = wlo > fmax(phi, hi_of(b2));
+          L = wlo;
+        }
       }
     }
     n_cols = (unsigned long long)pl.ncols;
@@ -682,17 +763,24 @@ __global__ __launch_bounds__(256) void k_exact(ExactArgs x) {
     };
     for (int64_t c0 = 0; c0 < pl.ncols; c0 += kChunk) {
       if (nb + kChunk > kBandCap) flush();
-      // A chunk whose last kept score cannot reach L contributes only kept
-      // entries (its best one when two are kept, whose second then misses
-      // L): take them without rescoring the chunk.
+      // A chunk whose kept entries show that at most one column can reach L
+      // contributes that column without being rescored: with two kept
+      // scores, when the second one's upper bound misses L; with FP8 bound
+      // summaries, when the second largest upper bound misses L (every
+      // column but the one with the largest lies at or below it).
       const Partial p = x.part[(c0 / kChunk) * a.n_rows + row];
-      const int kept = a.top == kTop ? kTop : 2;
-      if (phi_of(p.e[kept - 1].s) < L) {
-        for (int q = 0; q < kept - 1; ++q) {
-          if (phi_of(p.e[q].s) >= L) {
-            if (lane == 0) band[nb] = p.e[q].j;
+      if (a.top == kTop) {
+        if ((double)p.e[3].s < L) {
+          if ((double)p.e[2].s >= L) {
+            if (lane == 0) band[nb] = p.e[2].j;
             nb += 1;
           }
+          continue;
+        }
+      } else if (phi_of(p.e[1].s) < L) {
+        if (phi_of(p.e[0].s) >= L) {
+          if (lane == 0) band[nb] = p.e[0].j;
+          nb += 1;
         }
         continue;
       }
@@ -733,7 +821,8 @@ __global__ __launch_bounds__(256) void k_score_dense(const int64_t *indptr, cons
                                                      const float *values, int64_t n_rows,
                                                      const uint8_t *tile, int64_t D, int32_t k,
                                                      const float *scale, TailView tv,
-                                                     const float *hs, int64_t hs_ld, float *out) {
+                                                     const float *hs, int64_t hs_ld, float *out,
+                                                     float *out_head) {
   __shared__ float lacc_all[4][kChunk];
   const int wave = uniform32(threadIdx.x >> 6);
   const int64_t row = (int64_t)blockIdx.x * 4 + wave;
@@ -744,15 +833,28 @@ __global__ __launch_bounds__(256) void k_score_dense(const int64_t *indptr, cons
   const int64_t b = uniform64(indptr[row]);
   const int64_t e = uniform64(indptr[row + 1]);
   for (int64_t c0 = 0; c0 < k; c0 += kChunk) {
+    // the head scores and the sparse terms combined as the scoring kernel
+    // does: added onto the head scores (FP32 / BF16), or summed apart and
+    // added once (FP8)
+    constexpr bool kSplit = P == SKM_FP8_E4M3;
     float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    float hh[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (hs) {
 #pragma unroll
-      for (int c = 0; c < 8; ++c) acc[c] = hs[row * hs_ld + c0 + lane * kColsPerLane + c];
+      for (int c = 0; c < 8; ++c) hh[c] = hs[row * hs_ld + c0 + lane * kColsPerLane + c];
+      if constexpr (!kSplit) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[c] = hh[c];
+      }
     }
     score_chunk<P>(b, e, indices, values, tile, D, c0, k - c0, acc, tv, lacc);
     for (int c = 0; c < 8; ++c) {
       const int64_t col = c0 + lane * kColsPerLane + c;
-      if (col < k) out[row * k + col] = scale ? acc[c] * scale[col] : acc[c];
+      if (col < k) {
+        const float sc = scale ? scale[col] : 1.f;
+        out[row * k + col] = (kSplit ? hh[c] + acc[c] : acc[c]) * sc;
+        if (out_head) out_head[row * k + col] = hh[c] * sc;
+      }
     }
   }
 }
@@ -885,21 +987,21 @@ hipError_t launch_exact(const ExactArgs &x, int prec, hipStream_t s) {
 hipError_t launch_score_dense(const int64_t *indptr, const int32_t *indices, const float *values,
                               int64_t n_rows, const uint8_t *tile, int64_t D, int32_t k,
                               const float *scale, const TailView &tv, int prec, const float *hs,
-                              int64_t hs_ld, float *out, hipStream_t s) {
+                              int64_t hs_ld, float *out, hipStream_t s, float *out_head) {
   if (n_rows <= 0) return hipSuccess;
   const dim3 g((unsigned)((n_rows + 3) / 4)), blk(256);
   switch (prec) {
     case SKM_FP32:
       hipLaunchKernelGGL(k_score_dense<SKM_FP32>, g, blk, 0, s, indptr, indices, values, n_rows, tile,
-                         D, k, nullptr, tv, hs, hs_ld, out);
+                         D, k, nullptr, tv, hs, hs_ld, out, out_head);
       break;
     case SKM_BF16:
       hipLaunchKernelGGL(k_score_dense<SKM_BF16>, g, blk, 0, s, indptr, indices, values, n_rows, tile,
-                         D, k, nullptr, tv, hs, hs_ld, out);
+                         D, k, nullptr, tv, hs, hs_ld, out, out_head);
       break;
     case SKM_FP8_E4M3:
       hipLaunchKernelGGL(k_score_dense<SKM_FP8_E4M3>, g, blk, 0, s, indptr, indices, values, n_rows,
-                         tile, D, k, scale, tv, hs, hs_ld, out);
+                         tile, D, k, scale, tv, hs, hs_ld, out, out_head);
       break;
     default: return hipErrorInvalidValue;
   }

@@ -29,7 +29,7 @@ EXPORTED = [
     "skm_assign_new", "skm_get_assignments", "skm_get_centroids", "skm_get_centroid_columns",
     "skm_get_centroid_rows", "skm_set_centroids",
     "skm_get_tile", "skm_get_changed", "skm_score_dense", "skm_error_bound", "skm_head_terms",
-    "skm_score_head", "skm_error_bound_head", "skm_autotune", "skm_set_schedule", "skm_get_index",
+    "skm_score_head", "skm_error_bound_head", "skm_error_bound_split", "skm_autotune", "skm_set_schedule", "skm_get_index",
     "skm_index_query", "skm_server_config_default", "skm_server_start", "skm_server_submit",
     "skm_server_wait", "skm_server_get_stats", "skm_server_stop",
     "skm_hbm_bytes", "skm_last_error", "skm_destroy",
@@ -161,10 +161,12 @@ def load():
     lib.skm_set_schedule.restype = st
     lib.skm_head_terms.argtypes = [vp]
     lib.skm_head_terms.restype = ctypes.c_int32
-    lib.skm_score_head.argtypes = [vp, i64, i64, vp]
+    lib.skm_score_head.argtypes = [vp, i64, i64, vp, vp]
     lib.skm_score_head.restype = st
     lib.skm_error_bound_head.argtypes = [vp, ctypes.c_double, i64, ctypes.c_double]
     lib.skm_error_bound_head.restype = ctypes.c_double
+    lib.skm_error_bound_split.argtypes = [vp, ctypes.c_double, ctypes.c_double, i64, ctypes.c_double]
+    lib.skm_error_bound_split.restype = ctypes.c_double
     lib.skm_get_index.argtypes = [vp, i32, vp, vp, P(i64)]
     lib.skm_get_index.restype = st
     lib.skm_index_query.argtypes = [vp, P(Csr), i32, vp, vp, i64]
@@ -414,14 +416,20 @@ class Context:
         """Terms scored on the matrix cores (0 = head off)."""
         return int(load().skm_head_terms(self._h))
 
-    def score_head(self, row0, n_rows):
-        """Head-path low-precision scores of rows [row0, row0 + n_rows)."""
+    def score_head(self, row0, n_rows, parts=False):
+        """Head-path low-precision scores of rows [row0, row0 + n_rows); with
+        parts=True also the head parts alone: (scores, head_parts)."""
         out = np.empty((n_rows, self.k), dtype=np.float32)
-        _check(load().skm_score_head(self._h, int(row0), int(n_rows), out.ctypes.data))
-        return out
+        head = np.empty((n_rows, self.k), dtype=np.float32) if parts else None
+        _check(load().skm_score_head(self._h, int(row0), int(n_rows), out.ctypes.data,
+                                     head.ctypes.data if parts else None))
+        return (out, head) if parts else out
 
     def error_bound_head(self, s, nnz, l1):
         return load().skm_error_bound_head(self._h, float(s), int(nnz), float(l1))
+
+    def error_bound_split(self, hs, rs, n_rest, l1):
+        return load().skm_error_bound_split(self._h, float(hs), float(rs), int(n_rest), float(l1))
 
     def index_level(self, level):
         lib = load()

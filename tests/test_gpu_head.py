@@ -3,7 +3,8 @@
 The most frequent terms are scored as a BF16 block on the matrix cores and
 the rest on the sparse path.  Checked against the oracle:
   * every head-path score of a (row, centroid) pair lies within the certified
-    head bound of the FP64 score (oracle centroids fed in);
+    head bound of the FP64 score (oracle centroids fed in), and for FP8 within
+    the split bound of its head and sparse parts;
   * assignments with the head forced on equal the oracle's, for the first
     step, for whole trajectories, and across chunk groups with a ragged last
     group and a ragged last centroid chunk;
@@ -84,6 +85,50 @@ def test_head_bound_holds_for_every_pair(prec, H, mid):
     np.testing.assert_array_equal(Sg2, Sg[100:150])
     say("  max |s^-s|/E =", worst)
     ctx.close()
+
+
+@pytest.mark.parametrize("H", [64, 640])
+def test_split_bound_holds_for_every_pair(H, mid):
+    """FP8 with the head: the head part of a score comes from BF16 head codes
+    rounded from the FP64 centroids, the rest from the FP8 codes, and the
+    assignment step bounds each pair by the two parts' own bounds.  Checked
+    on every (row, centroid) pair against the oracle's FP64 scores.  The
+    library returns the total and the head part; the rest is taken as their
+    difference, which differs from the kernel's own rest by at most one
+    rounding of the total (2^-24 of it), covered by an extra 2^-22 * score."""
+    csr, c, rows = mid
+    say("case: split bound", H)
+    ref = oracle.run(csr, c.n_terms, 300, rows[:300], max_iter=2, stop_rule="fixed")
+    C = ref.C
+    ctx = Context(csr, c.n_terms, 300, init_centroids=C, precision="fp8", head_max_terms=H,
+                  head_min_df=0.0)
+    assert ctx.head_terms() == H
+    n = 500
+    S, Hp = ctx.score_head(0, n, parts=True)
+    S, Hp = S.astype(np.float64), Hp.astype(np.float64)
+    Sr = oracle.scores(csr, C, np.arange(n))
+    ip, ix, v = csr
+    df = np.bincount(ix, minlength=c.n_terms)
+    head = np.zeros(c.n_terms, dtype=bool)
+    head[np.argsort(-df, kind="stable")[:H]] = True      # the selection rule, restated
+    l1 = np.add.reduceat(v.astype(np.float64), ip[:-1])[:n]
+    worst, ratio = 0.0, []
+    for i in range(n):
+        n_rest = int(np.count_nonzero(~head[ix[ip[i]:ip[i + 1]]]))
+        R = np.maximum(S[i] - Hp[i], 0.0)
+        E = np.array([ctx.error_bound_split(h, r, n_rest, l1[i]) for h, r in zip(Hp[i], R)])
+        E += 2.0 ** -22 * S[i]
+        worst = max(worst, float(np.max(np.abs(S[i] - Sr[i]) / E)))
+        E1 = np.array([ctx.error_bound_head(s, ip[i + 1] - ip[i], l1[i]) for s in S[i]])
+        ratio.append(float(np.sum(E) / np.sum(E1)))
+    assert worst <= 1.0, worst
+    assert ctx.error_bound_split(1.0, 1.0, 10, 1.0) > 0
+    say(f"  max |s^-s|/E = {worst:.3f}; split bound / single bound = {np.mean(ratio):.3f}")
+    ctx.close()
+    bf = Context(csr, c.n_terms, 300, init_centroids=C, precision="bf16", head_max_terms=H,
+                 head_min_df=0.0)
+    assert bf.error_bound_split(1.0, 1.0, 10, 1.0) == -1.0
+    bf.close()
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
