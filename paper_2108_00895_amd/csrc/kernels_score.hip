@@ -1,5 +1,6 @@
 // Assignment kernels: low-precision gather-FMA scoring with a fused top-two
-// argmax and certification (paper Sec. 2, Sec. 3.1), and the exact FP64 tier.
+// argmax (FP8: a fused summary of certified bounds) and certification (paper
+// Sec. 2, Sec. 3.1), and the exact FP64 tier.
 //
 // Layout: the scoring copy of the centroids is term-major, codes[t * ld + j],
 // so one term's codes for 512 consecutive centroids are contiguous: a wavefront
@@ -300,7 +301,8 @@ __device__ inline void part_bound(const ScoreArgs &a, int64_t row, int64_t n, do
   }
 }
 
-// Per-(row, chunk) top-two of the low-precision scores.  The grid is
+// Per-(row, chunk) top-two of the low-precision scores (FP8: bound summary,
+// see Partial).  The grid is
 // persistent and walks items chunk-major (item = chunk * n_rows + row), so all
 // wavefronts sweep the same 512-centroid slice of the codes at the same time
 // and its hot term rows stay in L2 / the Infinity Cache instead of being
