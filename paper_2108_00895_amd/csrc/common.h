@@ -126,6 +126,23 @@ __device__ inline void wave_best_d(double &s, int &j) {
   }
 }
 
+// FP64 dot product of a row with one centroid row, by one lane: eight
+// interleaved partial sums (fixed order) so that eight gathers are in flight.
+__device__ inline double dot64(int64_t b, int64_t e, const int32_t *__restrict__ indices,
+                               const float *__restrict__ values, const double *__restrict__ crow) {
+  double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int64_t q = b;
+  for (; q + 8 <= e; q += 8) {
+    double c[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c[u] = crow[indices[q + u]];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] = fma((double)values[q + u], c[u], s[u]);
+  }
+  for (; q < e; ++q) s[0] = fma((double)values[q], crow[indices[q]], s[0]);
+  return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
 __device__ inline double wave_sum_d(double v) {
 #pragma unroll
   for (int m = 1; m < kWave; m <<= 1) v += shfl_xor_d(v, m);

@@ -427,8 +427,7 @@ __global__ __launch_bounds__(256) void k_index_score(IndexArgs x, int64_t n_slot
   for (int i = lane; i <= nc; i += kWave) {
     const int j = i < nc ? x.cand[slot * x.cap + i] : ap;
     const double *c = x.master + (int64_t)j * x.D;
-    double s = 0.0;
-    for (int64_t q = b; q < e; ++q) s = fma((double)x.values[q], c[x.indices[q]], s);
+    const double s = dot64(b, e, x.indices, x.values, c);
     if (better_d(s, j, bs, bj)) {
       bs = s;
       bj = j;
