@@ -150,13 +150,18 @@ def test_head_trajectory_equals_oracle(prec, mid):
     ctx.close()
 
 
-def test_head_on_and_off_give_the_same_assignments(mid):
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_head_on_and_off_give_the_same_assignments(prec, mid):
+    """Head off is the plain sparse path (for FP8 with bound summaries from the
+    FP8 bound on every term); head on uses the head product (for FP8 the split
+    bound).  Both are exact, so the assignments agree."""
     csr, c, rows = mid
-    say("case: head on/off")
+    say("case: head on/off", prec)
     got = []
     for mx in [0, 4096]:
-        ctx = Context(csr, c.n_terms, len(rows), init_rows=rows, precision="bf16", ncc=True,
+        ctx = Context(csr, c.n_terms, len(rows), init_rows=rows, precision=prec, ncc=True,
                       head_max_terms=mx, stop_rule="fixed", max_iter=4)
+        assert (ctx.head_terms() > 0) == (mx > 0)
         seq = []
         for _ in range(4):
             ctx.assign()
