@@ -434,7 +434,7 @@ ScoreArgs base_args(skm_ctx *c) {
 int exact_waves() { return 4096; }
 
 constexpr int64_t kSegRows = 256;       // members per summation segment
-constexpr int64_t kWorkBytes = 8ll << 30;  // partial-row workspace cap
+constexpr int64_t kWorkBytes = 16ll << 30;  // partial-row workspace cap
 
 // FP64 member sums of the n_ids changed clusters (ids in c->ch_ids): clusters
 // with at most kSegRows members are summed by one workgroup each; larger ones
@@ -455,7 +455,15 @@ skm_status sum_changed(skm_ctx *c, int32_t n_ids, std::vector<int32_t> &ids) {
   int64_t n_full = 0;   // rows of the changed clusters: they score every centroid next time
   for (int32_t j : ids) n_full += counts[j];
   c->full_frac = c->N > 0 ? (double)n_full / (double)c->N : 0.0;
-  const int64_t max_slots = std::max<int64_t>(1, kWorkBytes / (8 * c->D));
+  // workspace rows: at most kWorkBytes, and within the HBM budget when one is
+  // set (one slot means every cluster is summed by a single workgroup)
+  int64_t work_cap = kWorkBytes;
+  if (c->cfg.hbm_budget_bytes) {
+    const int64_t held = c->work ? (int64_t)round_up(c->work_slots * 8 * c->D, 256) : 0;
+    work_cap = std::min<int64_t>(work_cap, std::max<int64_t>(
+                   0, (int64_t)c->cfg.hbm_budget_bytes - c->hbm_bytes + held));
+  }
+  const int64_t max_slots = std::max<int64_t>(1, work_cap / (8 * c->D));
   size_t pos = 0;
   std::vector<int4> tasks, groups;
   std::vector<int64_t> r0s;
