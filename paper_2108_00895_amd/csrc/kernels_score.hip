@@ -19,6 +19,7 @@ template <int P>
 struct Codes;
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 typedef int v2i __attribute__((ext_vector_type(2)));
 
 // Raw buffer loads: the resource (slab base and size) lives in scalar
@@ -153,8 +154,9 @@ __device__ inline void score_chunk(int64_t b, int64_t e, const int32_t *__restri
     float my_x = 0.f;
     bool my_tail = false;
     if (lane < cnt) {
-      my_t = indices[q0 + lane];
-      my_x = values[q0 + lane];
+      // streamed once per (row, chunk): non-temporal, to leave L2 to the codes
+      my_t = __builtin_nontemporal_load(indices + q0 + lane);
+      my_x = __builtin_nontemporal_load(values + q0 + lane);
       my_tail = ttail && ttail[my_t];
     }
     uint64_t dmask = __ballot(lane < cnt && !my_tail);
@@ -339,7 +341,9 @@ __global__ __launch_bounds__(256) void k_score_part(ScoreArgs a, Partial *__rest
     auto load_head = [&](float *dst) {
       const float4 *h = reinterpret_cast<const float4 *>(a.hs + r * a.hs_ld + ci * kChunk +
                                                          lane * kColsPerLane);
-      const float4 h0 = h[0], h1 = h[1];
+      // streamed once: non-temporal loads, to leave L2 to the codes
+      const v4f h0 = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(h));
+      const v4f h1 = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(h) + 1);
       dst[0] = h0.x;
       dst[1] = h0.y;
       dst[2] = h0.z;
