@@ -247,9 +247,10 @@ __global__ __launch_bounds__(512) void k_head_gemm(const uint16_t *__restrict__ 
         const int64_t r = r_base + wm * 64 + mb * 32 + 8 * g + 4 * kg + e;
         if (r < nb) {
           float *o = hs + r * ldh + c_base + wn * 128 + li;
-#pragma unroll
           // written once, read by the sparse kernel much later: non-temporal
-          for (int n4 = 0; n4 < 4; ++n4) __builtin_nontemporal_store(acc[mb][n4][4 * g + e], o + n4 * 32);
+#pragma unroll
+          for (int n4 = 0; n4 < 4; ++n4)
+            __builtin_nontemporal_store(acc[mb][n4][4 * g + e], o + n4 * 32);
         }
       }
 }
