@@ -16,6 +16,9 @@ constexpr int64_t kBucketBlock = 8192;   // rows per counting-sort block
 __device__ inline int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 __device__ inline int64_t gstride() { return (int64_t)gridDim.x * blockDim.x; }
 
+// The update streams dense FP64 rows through once: their loads and stores are
+// non-temporal so that they do not evict the lines the scatter-adds reuse.
+typedef double v2d __attribute__((ext_vector_type(2)));
 unsigned grid_for(int64_t n, int threads, int64_t cap = 65536) {
   int64_t g = (n + threads - 1) / threads;
   if (g < 1) g = 1;
@@ -171,7 +174,7 @@ __global__ __launch_bounds__(256) void k_quantize(const double *master, int32_t 
     if (j < k) {
       const double *row = master + j * D;
       if (vec) {
-        const double2 v = *reinterpret_cast<const double2 *>(row + t);
+        const v2d v = __builtin_nontemporal_load(reinterpret_cast<const v2d *>(row + t));
         c0 = v.x;
         c1 = v.y;
       } else {
@@ -374,8 +377,9 @@ __global__ __launch_bounds__(256) void k_sum_tasks(const int64_t *indptr, const 
   double *dst = tk.z < 0 ? S + (int64_t)tk.x * D : work + (int64_t)tk.z * D;
   const int tid = threadIdx.x;
   if (D % 2 == 0) {
-    double2 *d2 = reinterpret_cast<double2 *>(dst);
-    for (int64_t t = tid; t < D / 2; t += 256) d2[t] = make_double2(0.0, 0.0);
+    v2d *d2 = reinterpret_cast<v2d *>(dst);
+    const v2d z = {0.0, 0.0};
+    for (int64_t t = tid; t < D / 2; t += 256) __builtin_nontemporal_store(z, d2 + t);
   } else {
     for (int64_t t = tid; t < D; t += 256) dst[t] = 0.0;
   }
@@ -470,17 +474,20 @@ __global__ __launch_bounds__(256) void k_renorm(const double *S, const int32_t *
   }
   const int tid = threadIdx.x;
   const int64_t D2 = (D % 2 == 0) ? D / 2 : 0;
-  const double2 *S2 = reinterpret_cast<const double2 *>(Sj);
-  double2 *M2 = reinterpret_cast<double2 *>(Mj);
+  const v2d *S2 = reinterpret_cast<const v2d *>(Sj);
+  v2d *M2 = reinterpret_cast<v2d *>(Mj);
   double ss = 0.0;
   int64_t i = tid;
   for (; i + 768 < D2; i += 1024) {
-    const double2 a0 = S2[i], a1 = S2[i + 256], a2 = S2[i + 512], a3 = S2[i + 768];
+    const v2d a0 = __builtin_nontemporal_load(S2 + i);
+    const v2d a1 = __builtin_nontemporal_load(S2 + i + 256);
+    const v2d a2 = __builtin_nontemporal_load(S2 + i + 512);
+    const v2d a3 = __builtin_nontemporal_load(S2 + i + 768);
     ss += a0.x * a0.x + a0.y * a0.y + a1.x * a1.x + a1.y * a1.y;
     ss += a2.x * a2.x + a2.y * a2.y + a3.x * a3.x + a3.y * a3.y;
   }
   for (; i < D2; i += 256) {
-    const double2 a0 = S2[i];
+    const v2d a0 = __builtin_nontemporal_load(S2 + i);
     ss += a0.x * a0.x + a0.y * a0.y;
   }
   for (int64_t t = 2 * D2 + tid; t < D; t += 256) ss += Sj[t] * Sj[t];
@@ -495,22 +502,25 @@ __global__ __launch_bounds__(256) void k_renorm(const double *S, const int32_t *
   };
   i = tid;
   for (; i + 256 < D2; i += 512) {
-    const double2 a0 = S2[i], a1 = S2[i + 256];
-    const double2 o0 = M2[i], o1 = M2[i + 256];
-    double2 c0, c1;
+    const v2d a0 = __builtin_nontemporal_load(S2 + i);
+    const v2d a1 = __builtin_nontemporal_load(S2 + i + 256);
+    const v2d o0 = __builtin_nontemporal_load(M2 + i);
+    const v2d o1 = __builtin_nontemporal_load(M2 + i + 256);
+    v2d c0, c1;
     c0.x = one(a0.x, o0.x);
     c0.y = one(a0.y, o0.y);
     c1.x = one(a1.x, o1.x);
     c1.y = one(a1.y, o1.y);
-    M2[i] = c0;
-    M2[i + 256] = c1;
+    __builtin_nontemporal_store(c0, M2 + i);
+    __builtin_nontemporal_store(c1, M2 + i + 256);
   }
   for (; i < D2; i += 256) {
-    const double2 a0 = S2[i], o0 = M2[i];
-    double2 c0;
+    const v2d a0 = __builtin_nontemporal_load(S2 + i);
+    const v2d o0 = __builtin_nontemporal_load(M2 + i);
+    v2d c0;
     c0.x = one(a0.x, o0.x);
     c0.y = one(a0.y, o0.y);
-    M2[i] = c0;
+    __builtin_nontemporal_store(c0, M2 + i);
   }
   for (int64_t t = 2 * D2 + tid; t < D; t += 256) Mj[t] = one(Sj[t], Mj[t]);
   sh2 = block_sum_256(sh2, sh);
