@@ -447,9 +447,21 @@ __global__ __launch_bounds__(256) void k_combine(const int4 *groups, int64_t D, 
   const int4 g = groups[blockIdx.x / tblk];   // x = cluster, y = first slot, z = segments
   const int64_t t0 = (blockIdx.x % tblk) * 4096;
   for (int64_t t = t0 + threadIdx.x; t < min(D, t0 + 4096); t += 256) {
+    const double *w = work + (int64_t)g.y * D + t;
     double s = 0.0;
-    for (int p = 0; p < g.z; ++p) s += work[(int64_t)(g.y + p) * D + t];
-    S[(int64_t)g.x * D + t] = s;
+    int p = 0;
+    for (; p + 4 <= g.z; p += 4) {   // four loads in flight, added in segment order
+      const double w0 = __builtin_nontemporal_load(w + (int64_t)p * D);
+      const double w1 = __builtin_nontemporal_load(w + (int64_t)(p + 1) * D);
+      const double w2 = __builtin_nontemporal_load(w + (int64_t)(p + 2) * D);
+      const double w3 = __builtin_nontemporal_load(w + (int64_t)(p + 3) * D);
+      s += w0;
+      s += w1;
+      s += w2;
+      s += w3;
+    }
+    for (; p < g.z; ++p) s += __builtin_nontemporal_load(w + (int64_t)p * D);
+    __builtin_nontemporal_store(s, S + (int64_t)g.x * D + t);
   }
 }
 
