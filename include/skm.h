@@ -116,7 +116,10 @@ typedef struct {
                                    init_rows is NULL (rows must be unit length,
                                    non-negative) */
   size_t hbm_budget_bytes;    /* 0 = no limit; counts every device allocation
-                                 the context makes */
+                                 the context makes.  Without a budget skm_init
+                                 also allocates the update's largest workspace
+                                 (at most 16 GiB) so that no iteration
+                                 allocates it; under one it grows on demand */
   void *stream;               /* hipStream_t to enqueue on; NULL = own stream */
   int32_t validate;           /* 1 = check the CSR conventions above at init */
   int32_t head_max_terms;     /* BF16 / FP8 scoring: at most this many of the most

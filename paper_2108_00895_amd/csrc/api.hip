@@ -436,6 +436,14 @@ int exact_waves() { return 4096; }
 constexpr int64_t kSegRows = 256;       // members per summation segment
 constexpr int64_t kWorkBytes = 16ll << 30;  // partial-row workspace cap
 
+// Workspace rows any update can need: the segments of the clusters with more
+// than kSegRows members number at most N / 128 + 1 (each such cluster has at
+// most count / kSegRows + 1 of them), within kWorkBytes.
+int64_t work_slots_bound(const skm_ctx *c) {
+  const int64_t max_slots = std::max<int64_t>(1, kWorkBytes / (8 * c->D));
+  return std::min<int64_t>(max_slots, c->N / (kSegRows / 2) + 2);
+}
+
 // FP64 member sums of the n_ids changed clusters (ids in c->ch_ids): clusters
 // with at most kSegRows members are summed by one workgroup each; larger ones
 // are split into segments summed in parallel into workspace rows and combined
@@ -505,11 +513,16 @@ skm_status sum_changed(skm_ctx *c, int32_t n_ids, std::vector<int32_t> &ids) {
       c->task_cap = cap;
     }
     if (slots > c->work_slots) {
+      // Only under an HBM budget (without one, skm_init allocates the bound).
+      // A multi-GB hipMalloc can take seconds: grow to the bound at once
+      // unless the budget leaves less.
+      const int64_t want = std::max<int64_t>(slots, std::min<int64_t>(max_slots,
+                                                                    work_slots_bound(c)));
       if (c->work) dfree(c, c->work, c->work_slots * 8 * c->D);
       c->work = nullptr;
       c->work_slots = 0;
-      ST_TRY(dalloc(c, &c->work, (size_t)(slots * c->D)));
-      c->work_slots = slots;
+      ST_TRY(dalloc(c, &c->work, (size_t)(want * c->D)));
+      c->work_slots = want;
     }
     if (!c->groups) ST_TRY(dalloc(c, &c->groups, (size_t)c->k));
     HIP_TRY(c, hipMemcpyAsync(c->tasks, tasks.data(), sizeof(int4) * tasks.size(),
@@ -837,6 +850,12 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
     A_(c->idx_cand, N * (int64_t)c->idx_cap);
     A_(c->idx_ncand, N);
     A_(c->idx_level, N);
+  }
+  if (!cfg->hbm_budget_bytes) {
+    // the update's partial-sum rows, once for the context's lifetime: a
+    // multi-GB hipMalloc inside an iteration can take seconds
+    c->work_slots = work_slots_bound(c);
+    A_(c->work, c->work_slots * c->D);
   }
 #undef A_
 
