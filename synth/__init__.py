@@ -206,6 +206,16 @@ FP8_8M = Workload(
 
 WORKLOADS = {w.name: w for w in (SMALL, PLAIN_1M, PRUNED_BF16_2M, FP8_8M)}
 
+# Stand-ins shaped like the paper's two evaluation corpora (Sec. 4.1): one million
+# tweets over 783,304 terms with 10 non-zeros on average, and 200,000 abstracts
+# over 325,556 terms with 58.  Length spreads and clipping are not given: short
+# texts vary little in length (sigma 0.5 / 0.35), every row keeps at least one
+# term (rows of stop words only were dropped there).
+TWEETS_1M = Corpus(1_000_000, 783_304, 10.0, 0.5, 1, 40, 1.1, seed=7)
+ABSTRACTS_200K = Corpus(200_000, 325_556, 58.0, 0.35, 5, 300, 1.1, seed=8)
+PAPER_CORPORA = {"tweets-1m": TWEETS_1M, "abstracts-200k": ABSTRACTS_200K}
+PAPER_KS = (50, 500, 5000)
+
 
 def scaled(c: Corpus, n_docs: int, n_terms: int | None = None, seed: int | None = None) -> Corpus:
     """The same generator at a smaller size (for tests)."""

@@ -4,6 +4,7 @@ Assignments must equal the oracle's bit for bit except rows whose FP64 top-two
 gap is below 1e-12; centroids and objectives must agree within relative 1e-5.
 Sizes span several 512-centroid chunks with a ragged tail.
 """
+import functools
 import math
 
 import numpy as np
@@ -147,6 +148,43 @@ def test_trajectory_equals_oracle(prec, ncc, mid):
     assert rel_centroid_err(ctx.centroids(), ref.C) < 1e-9
     if ncc and len(stats) > 3:
         assert stats[-1]["ncc_rows"] > 0
+    ctx.close()
+
+
+@functools.lru_cache(maxsize=None)
+def _tweets():
+    c = synth.scaled(synth.TWEETS_1M, 6000)
+    csr = synth.generate(c)
+    rows = synth.seed_rows(c.n_docs, 64, 11)
+    return csr, c, rows, oracle.run(csr, c.n_terms, 64, rows, max_iter=40)
+
+
+@pytest.mark.parametrize("prec,ncc,index", [("fp32", False, False), ("fp32", True, False),
+                                            ("fp32", True, True), ("bf16", True, True)])
+def test_tweet_shaped_trajectory_equals_oracle(prec, ncc, index):
+    """Rows shaped like the paper's tweets (10 of 783,304 terms on average, one
+    512-wide slab of codes much taller than the rows are long).  Many rows share
+    no term with any seed: all their scores are 0 and they go to centroid 0
+    (lowest index among equal maxima).  Every mode of the paper's ablation
+    (plain, NCC, NCC + INDEX) follows the oracle's trajectory exactly."""
+    csr, c, rows, ref = _tweets()
+    say("case: tweet-shaped trajectory", prec, ncc, index)
+    ip, ix, _ = csr
+    seed_terms = np.zeros(c.n_terms, dtype=bool)
+    for r in rows:
+        seed_terms[ix[ip[r]:ip[r + 1]]] = True
+    hit = np.add.reduceat(seed_terms[ix].astype(np.int64), ip[:-1])
+    assert np.count_nonzero(hit == 0) > 20         # the degenerate rows are there
+    ctx = Context(to_device(csr), c.n_terms, len(rows), init_rows=rows, precision=prec, ncc=ncc,
+                  index=index, max_iter=40)
+    stats, conv = ctx.iterate()
+    assert conv == ref.converged and len(stats) == len(ref.records)
+    for st, rec in zip(stats, ref.records):
+        assert st["moved"] == rec.moved, (st["iter"], st["moved"], rec.moved)
+        if rec.updated:
+            assert math.isclose(st["objective_update"], rec.J_U, rel_tol=1e-9)
+    assert np.array_equal(ctx.assignments(), ref.a)
+    assert rel_centroid_err(ctx.centroids(), ref.C) < 1e-9
     ctx.close()
 
 

@@ -42,3 +42,19 @@ def test_seed_rows_distinct():
     assert sorted(r.tolist()) == list(range(1000))
     r2 = synth.seed_rows(10**6, 50, 7)
     assert len(set(r2.tolist())) == 50 and np.array_equal(r2, synth.seed_rows(10**6, 50, 7))
+
+
+def test_paper_shaped_corpora():
+    """The stand-ins of the paper's corpora (Sec. 4.1) keep its vocabulary sizes
+    and mean row lengths (10 and 58 non-zeros); checked on a row sample of the
+    same generator, which draws every row independently."""
+    for c, mean in ((synth.TWEETS_1M, 10.0), (synth.ABSTRACTS_200K, 58.0)):
+        s = synth.scaled(c, 20000)
+        ip, ix, v = synth.generate(s)
+        lens = np.diff(ip)
+        assert s.n_terms == c.n_terms
+        assert abs(lens.mean() - mean) < 0.03 * mean, (c, lens.mean())
+        assert lens.min() >= c.nnz_min and lens.max() <= c.nnz_max
+        assert ix.max() < c.n_terms and np.all(v > 0)
+    assert synth.TWEETS_1M.n_terms == 783_304 and synth.ABSTRACTS_200K.n_terms == 325_556
+    assert synth.TWEETS_1M.n_docs == 1_000_000 and synth.ABSTRACTS_200K.n_docs == 200_000
