@@ -7,7 +7,8 @@ module both sides use is ``synth`` (seeded input generation).
 
 Contents:
   * ``oracle.c`` (built to ``liboracle.so``): plain FP64 assignment, update and
-    seeding, the definition of the method's result (paper Sec. 2).
+    seeding, the definition of the method's result (paper Sec. 2), and
+    k-means++ seeding (the initialisation Sec. 2 names) with exact integer draws.
   * ``run``: the Lloyd loop with the paper's stopping rule (Sec. 2, Sec. 4.1).
   * ``index``: the dot-product index of Sec. 3.2 (G, P_lambda, query), pure Python.
   * ``quant``: BF16 and FP8-E4M3 rounding from the format definitions, exact.
@@ -61,6 +62,8 @@ def _load():
     lib.orc_scores.argtypes = [i64, i32, vp, vp, vp, i32, vp, vp, i64, vp]
     lib.orc_update.restype = ctypes.c_int
     lib.orc_update.argtypes = [i64, i32, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    lib.orc_kmeanspp.restype = ctypes.c_int
+    lib.orc_kmeanspp.argtypes = [i64, i32, vp, vp, vp, i32, vp, vp]
     lib.orc_centroid_rows.restype = ctypes.c_int
     lib.orc_centroid_rows.argtypes = [i64, i32, vp, vp, vp, i32, vp, vp, i32, vp, vp]
     _lib = lib
@@ -85,6 +88,21 @@ def seed(csr, n_terms: int, rows) -> np.ndarray:
     if rc != 0:
         raise ValueError("seed row out of range")
     return C
+
+
+def kmeanspp(csr, n_terms: int, k: int, draws) -> np.ndarray:
+    """k-means++ seed rows from the caller's 64-bit draws (one per seed); the
+    rules are in ``orc_kmeanspp`` (oracle.c)."""
+    ip, ix, v = _csr(csr)
+    draws = np.ascontiguousarray(draws, dtype=np.uint64)
+    if len(draws) < k:
+        raise ValueError("need one draw per seed")
+    out = np.empty(k, dtype=np.int32)
+    rc = _load().orc_kmeanspp(len(ip) - 1, n_terms, ip.ctypes.data, ix.ctypes.data, v.ctypes.data,
+                              k, draws.ctypes.data, out.ctypes.data)
+    if rc != 0:
+        raise ValueError("k must be in [1, n_rows]" if rc == -1 else "out of memory")
+    return out
 
 
 def assign(csr, C: np.ndarray, docs=None, nthreads: int = 0):

@@ -248,3 +248,80 @@ int orc_centroid_rows(int64_t n_docs, int32_t D, const int64_t *indptr, const in
   free(slot);
   return 0;
 }
+
+/*
+ * k-means++ seeding (the initialisation named in Sec. 2; D^2 sampling of
+ * Arthur and Vassilvitskii, 2007).  For unit vectors the squared Euclidean
+ * distance to the nearest chosen seed is 2 (1 - s) with s the highest cosine,
+ * so a row is drawn with probability proportional to 1 - s.  Readings:
+ *   - the caller supplies one 64-bit uniform draw per seed; the first seed is
+ *     row draws[0] mod n;
+ *   - s_i = max over chosen seeds r of (x_i . x_r) / ||x_r||: the dot runs over
+ *     the row's terms in ascending order as a chain of fused multiply-adds, the
+ *     squared norm likewise over the seed's terms, then one sqrt and one divide;
+ *   - the weight is the integer floor(2^32 max(0, 1 - s_i)), 0 for rows already
+ *     chosen, so the draw is decided in exact integer arithmetic: with
+ *     W = sum of weights > 0, seed m is the row whose cumulative weight
+ *     interval [prefix, prefix + w_i) holds draws[m] mod W; with W = 0 (every
+ *     row left points exactly like a seed) it is the lowest row not chosen.
+ * Needs 1 <= k <= n_docs.  rows_out[k].
+ */
+int orc_kmeanspp(int64_t n_docs, int32_t D, const int64_t *indptr, const int32_t *indices,
+                 const float *values, int32_t k, const uint64_t *draws, int32_t *rows_out) {
+  if (k < 1 || (int64_t)k > n_docs) return -1;
+  double *best = (double *)malloc(sizeof(double) * (size_t)n_docs);
+  double *seed_row = (double *)calloc((size_t)D, sizeof(double));
+  uint64_t *w = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n_docs);
+  unsigned char *chosen = (unsigned char *)calloc((size_t)n_docs, 1);
+  if (!best || !seed_row || !w || !chosen) {
+    free(best); free(seed_row); free(w); free(chosen);
+    return -2;
+  }
+  for (int64_t i = 0; i < n_docs; ++i) best[i] = 0.0;
+  int64_t r = (int64_t)(draws[0] % (uint64_t)n_docs);
+  rows_out[0] = (int32_t)r;
+  chosen[r] = 1;
+  for (int32_t m = 1; m < k; ++m) {
+    /* the previous seed as a dense row, and its length */
+    double ss = 0.0;
+    for (int64_t q = indptr[r]; q < indptr[r + 1]; ++q) {
+      const double v = (double)values[q];
+      seed_row[indices[q]] = v;
+      ss = fma(v, v, ss);
+    }
+    const double nrm = sqrt(ss);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n_docs; ++i) {
+      double acc = 0.0;
+      for (int64_t q = indptr[i]; q < indptr[i + 1]; ++q)
+        acc = fma((double)values[q], seed_row[indices[q]], acc);
+      const double s = acc / nrm;
+      if (s > best[i]) best[i] = s;
+      const double gap = 1.0 - best[i];
+      w[i] = chosen[i] ? 0 : (uint64_t)floor(ldexp(gap > 0.0 ? gap : 0.0, 32));
+    }
+    for (int64_t q = indptr[r]; q < indptr[r + 1]; ++q) seed_row[indices[q]] = 0.0;
+    uint64_t W = 0;
+    for (int64_t i = 0; i < n_docs; ++i) W += w[i];
+    int64_t pick = -1;
+    if (W == 0) {
+      for (int64_t i = 0; i < n_docs && pick < 0; ++i)
+        if (!chosen[i]) pick = i;
+    } else {
+      const uint64_t t = draws[m] % W;
+      uint64_t prefix = 0;
+      for (int64_t i = 0; i < n_docs; ++i) {
+        if (t < prefix + w[i]) {
+          pick = i;
+          break;
+        }
+        prefix += w[i];
+      }
+    }
+    r = pick;
+    rows_out[m] = (int32_t)r;
+    chosen[r] = 1;
+  }
+  free(best); free(seed_row); free(w); free(chosen);
+  return 0;
+}

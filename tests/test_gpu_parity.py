@@ -422,6 +422,37 @@ def test_index_trajectory_equals_oracle(prec):
     ctx.close()
 
 
+def test_index_enabled_dynamically():
+    """Sec. 4.3's suggestion: use the index only while more than a threshold of
+    centroids changed.  Iterations at or below it decide no row by the index,
+    and the trajectory is the oracle's either way."""
+    say("case: dynamic index enabling")
+    csr, tc = _topic(4000, seed=13)
+    k = 48
+    rows = synth.seed_rows(tc.n_docs, k, 6)
+    ref = oracle.run(csr, tc.n_terms, k, rows, max_iter=20)
+    # a threshold that splits the run: the changed counts the assignments of
+    # iterations 1.. see are the oracle's membership changes one step earlier
+    seen = sorted({len(r.changed) for r in ref.records[:-1] if r.changed is not None})
+    assert len(seen) >= 2
+    thr = seen[len(seen) // 2 - 1]
+    ctx = Context(to_device(csr), tc.n_terms, k, init_rows=rows, precision="bf16", ncc=True,
+                  index=True, index_min_changed=thr, max_iter=20)
+    stats, conv = ctx.iterate()
+    assert conv == ref.converged and len(stats) == len(ref.records)
+    for st, rec in zip(stats, ref.records):
+        assert st["moved"] == rec.moved, (st["iter"], st["moved"], rec.moved)
+    assert np.array_equal(ctx.assignments(), ref.a)
+    changed = [s["changed_centroids"] for s in stats]
+    say("  changed per iteration:", changed)
+    say("  index rows per iteration:", [s["index_rows"] for s in stats])
+    assert any(c > thr for c in changed[1:]) and any(c <= thr for c in changed[1:])
+    for s in stats:
+        if s["changed_centroids"] <= thr:
+            assert s["index_rows"] == 0, s
+    ctx.close()
+
+
 def test_index_only_without_ncc():
     say("case: index without ncc")
     csr, tc = _topic(2500, seed=17)
