@@ -188,6 +188,25 @@ typedef struct {
  * at most 4096 terms with document frequency >= 1/128. */
 void skm_config_default(skm_config *cfg);
 
+/* k-means++ seed rows (the initialisation Sec. 2 names; D^2 sampling, where
+ * the squared distance of unit rows to the nearest seed is 2 (1 - s) with s
+ * the highest cosine), for cfg->init_rows.  docs as for skm_init (host or
+ * device, checked the same way; not kept).  draws: host, k uniform 64-bit
+ * values supplied by the caller.  Seed 0 is row draws[0] mod n_rows; seed m
+ * weighs row i by floor(2^32 max(0, 1 - s_i)), 0 if already a seed, and takes
+ * the row whose cumulative weight interval holds draws[m] mod (total weight),
+ * or the lowest row not yet a seed when the total is 0.  s_i is the row's FP64
+ * dot product with the seed's values (ascending terms, fused multiply-adds)
+ * divided by the seed's length, so the result depends only on the inputs and
+ * the draws.  out_rows: host, k distinct row ids.  stream: hipStream_t or NULL
+ * for a stream of the call's own; the call returns when the seeds are ready.
+ * Work: k passes over the rows.  SKM_E_INVALID for bad arguments (k outside
+ * [1, n_rows]) or rows that break the CSR conventions, SKM_E_NOMEM when the
+ * device cannot hold its temporaries (about 25 bytes per row plus 8 per
+ * column). */
+skm_status skm_kmeanspp(const skm_csr *docs, int32_t k, const uint64_t *draws, int32_t *out_rows,
+                        void *stream);
+
 /* Creates a context: copies the rows into HBM, seeds the centroids (FP64) and
  * builds their scoring copies.  *out is owned by the caller and released with
  * skm_destroy.  SKM_E_INVALID for a malformed CSR or config, SKM_E_NOMEM when

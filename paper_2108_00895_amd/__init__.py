@@ -4,4 +4,4 @@ The hot path lives in HIP kernels behind the C ABI of ``include/skm.h``
 (``libskm.so``); ``skm`` is its ctypes binding.
 """
 from . import skm  # noqa: F401
-from .skm import Context, SkmError, load  # noqa: F401
+from .skm import Context, SkmError, kmeanspp, load  # noqa: F401

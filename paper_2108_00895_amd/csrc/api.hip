@@ -1492,6 +1492,86 @@ skm_status skm_score_dense(skm_ctx *c, const skm_csr *docs, float *out) {
   return SKM_OK;
 }
 
+skm_status skm_kmeanspp(const skm_csr *docs, int32_t k, const uint64_t *draws, int32_t *out_rows,
+                        void *stream) {
+  ST_TRY(check_csr_header(docs, 0));
+  if (!draws || !out_rows) return fail(SKM_E_INVALID, "draws or out_rows is NULL");
+  const int64_t n = docs->n_rows, D = docs->n_cols;
+  if (k < 1 || (int64_t)k > n) return fail(SKM_E_INVALID, "k must be in [1, n_rows]");
+  // a scratch context carries this call's device, stream and error state
+  skm_ctx *c = new (std::nothrow) skm_ctx();
+  if (!c) return fail(SKM_E_NOMEM, "host allocation failed");
+  std::vector<void *> tmp;
+  auto finish = [&](skm_status st) {
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (void *q : tmp) (void)hipFree(q);
+    skm_destroy(c);
+    return st;
+  };
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) return finish(device_fail(nullptr, "hipGetDevice", e));
+  if (stream) {
+    c->stream = static_cast<hipStream_t>(stream);
+  } else {
+    e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return finish(device_fail(nullptr, "hipStreamCreate", e));
+    c->own_stream = true;
+  }
+  hipStream_t s = c->stream;
+  auto talloc = [&](auto **p, size_t bytes) -> skm_status {
+    void *q = nullptr;
+    if (hipMalloc(&q, std::max<size_t>(bytes, 1)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SKM_E_NOMEM, "temporary device allocation failed");
+    }
+    tmp.push_back(q);
+    *p = static_cast<std::remove_reference_t<decltype(*p)>>(q);
+    return SKM_OK;
+  };
+  DevRows r;
+  skm_status st = upload_rows(c, docs, D, true, s, talloc, &r);
+  const int64_t nb = (n + 255) / 256;
+  double *best = nullptr, *dense = nullptr, *nrm2 = nullptr;
+  uint64_t *w = nullptr, *bsum = nullptr;
+  uint8_t *chosen = nullptr;
+  int32_t *rows = nullptr;
+  if (st == SKM_OK) st = talloc(&best, sizeof(double) * n);
+  if (st == SKM_OK) st = talloc(&dense, sizeof(double) * D);
+  if (st == SKM_OK) st = talloc(&nrm2, sizeof(double));
+  if (st == SKM_OK) st = talloc(&w, sizeof(uint64_t) * n);
+  if (st == SKM_OK) st = talloc(&bsum, sizeof(uint64_t) * nb);
+  if (st == SKM_OK) st = talloc(&chosen, (size_t)n);
+  if (st == SKM_OK) st = talloc(&rows, sizeof(int32_t) * k);
+  if (st != SKM_OK) return finish(st);
+  const int32_t r0 = (int32_t)(draws[0] % (uint64_t)n);
+  e = launch_fill_f64(best, 0.0, n, s);
+  if (e == hipSuccess) e = launch_fill_f64(dense, 0.0, D, s);
+  if (e == hipSuccess) e = launch_fill_u8(chosen, 0, n, s);
+  if (e == hipSuccess) e = launch_fill_u8(chosen + r0, 1, 1, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(rows, &r0, sizeof(int32_t), hipMemcpyHostToDevice, s);
+  for (int32_t m = 1; m < k && e == hipSuccess; ++m) {
+    double h_nrm2 = 0.0;
+    e = pp_place(r.indptr, r.indices, r.values, n, rows, m, dense, nrm2, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h_nrm2, nrm2, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) break;
+    if (!(h_nrm2 > 0.0)) return finish(fail(SKM_E_DEVICE, "k-means++ lost its seed row"));
+    // the length on the host: one correctly rounded square root
+    e = pp_weights(r.indptr, r.indices, r.values, n, dense, std::sqrt(h_nrm2), best, chosen, w, bsum,
+                   s);
+    if (e == hipSuccess) e = pp_select(bsum, w, n, draws[m], chosen, rows, m, s);
+  }
+  std::vector<int32_t> h(k);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h.data(), rows, sizeof(int32_t) * k, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return finish(device_fail(nullptr, "kmeanspp", e));
+  for (int32_t m = 0; m < k; ++m)
+    if (h[m] < 0 || h[m] >= n) return finish(fail(SKM_E_DEVICE, "k-means++ drew no row"));
+  std::memcpy(out_rows, h.data(), sizeof(int32_t) * k);
+  return finish(SKM_OK);
+}
+
 int32_t skm_head_terms(const skm_ctx *c) { return c ? c->head_H : 0; }
 
 skm_status skm_score_head(skm_ctx *c, int64_t row0, int64_t n_rows, float *out,

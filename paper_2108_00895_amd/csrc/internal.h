@@ -369,6 +369,15 @@ hipError_t tail_fill(const uint8_t *tile, int64_t D, int32_t ncols, int prec,
                      const uint32_t *off, int64_t stride, uint32_t *ent, hipStream_t s);
 hipError_t tail_bases(uint64_t *base, int32_t nch, int64_t stride, hipStream_t s);
 
+// k-means++ seeding (kernels_seed.hip), one seed per place/weights/select.
+hipError_t pp_place(const int64_t *indptr, const int32_t *indices, const float *values, int64_t n,
+                    const int32_t *rows, int32_t m, double *dense, double *nrm2, hipStream_t s);
+hipError_t pp_weights(const int64_t *indptr, const int32_t *indices, const float *values,
+                      int64_t n, const double *dense, double nrm, double *best,
+                      const uint8_t *chosen, uint64_t *w, uint64_t *bsum, hipStream_t s);
+hipError_t pp_select(const uint64_t *bsum, const uint64_t *w, int64_t n, uint64_t draw,
+                     uint8_t *chosen, int32_t *rows, int32_t m, hipStream_t s);
+
 // kernels_index.hip
 hipError_t index_build_counts(const double *master, int32_t k, int64_t D, int32_t *cnt,
                               int64_t *eoff, hipStream_t s);

@@ -25,7 +25,7 @@ PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3}
 CODE_BYTES = {FP32: 4, BF16: 2, FP8_E4M3: 1}
 
 EXPORTED = [
-    "skm_config_default", "skm_init", "skm_assign", "skm_update", "skm_iterate",
+    "skm_config_default", "skm_kmeanspp", "skm_init", "skm_assign", "skm_update", "skm_iterate",
     "skm_assign_new", "skm_get_assignments", "skm_get_centroids", "skm_get_centroid_columns",
     "skm_get_centroid_rows", "skm_set_centroids",
     "skm_get_tile", "skm_get_changed", "skm_score_dense", "skm_error_bound", "skm_head_terms",
@@ -147,6 +147,8 @@ def load():
     lib.skm_get_tile.restype = st
     lib.skm_get_changed.argtypes = [vp, vp]
     lib.skm_get_changed.restype = st
+    lib.skm_kmeanspp.argtypes = [P(Csr), i32, vp, vp, vp]
+    lib.skm_kmeanspp.restype = st
     lib.skm_score_dense.argtypes = [vp, P(Csr), vp]
     lib.skm_score_dense.restype = st
     lib.skm_error_bound.argtypes = [vp, ctypes.c_double, i64, ctypes.c_double]
@@ -220,6 +222,17 @@ def make_csr(indptr, indices, values, n_cols):
     c = Csr(len(indptr) - 1, n_cols, len(indices), indptr.ctypes.data, indices.ctypes.data,
             values.ctypes.data, 0)
     return c, (indptr, indices, values)
+
+
+def kmeanspp(csr, n_cols, k, draws, stream=None):
+    """k-means++ seed rows (skm_kmeanspp) from k caller-supplied 64-bit draws."""
+    c, hold = make_csr(*csr, n_cols)
+    d = np.ascontiguousarray(draws, dtype=np.uint64)
+    if len(d) < k:
+        raise ValueError("need one draw per seed")
+    out = np.empty(k, dtype=np.int32)
+    _check(load().skm_kmeanspp(ctypes.byref(c), k, d.ctypes.data, out.ctypes.data, stream))
+    return out
 
 
 @dataclass

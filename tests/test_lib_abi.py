@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2108_00895_amd import skm
@@ -58,4 +59,15 @@ def test_null_arguments_rejected_without_device():
     assert lib.skm_init(None, None, ctypes.byref(h)) == skm.SKM_E_INVALID
     assert b"NULL" in lib.skm_last_error()
     assert lib.skm_assign(None, None) == skm.SKM_E_INVALID
+    assert lib.skm_kmeanspp(None, 1, None, None, None) == skm.SKM_E_INVALID
+    # k outside [1, n_rows] is refused before any device call
+    ip = np.array([0, 1], dtype=np.int64)
+    ix = np.array([0], dtype=np.int32)
+    v = np.array([1.0], dtype=np.float32)
+    c = skm.Csr(1, 1, 1, ip.ctypes.data, ix.ctypes.data, v.ctypes.data, 0)
+    out = np.zeros(2, dtype=np.int32)
+    draws = np.zeros(2, dtype=np.uint64)
+    assert lib.skm_kmeanspp(ctypes.byref(c), 2, draws.ctypes.data, out.ctypes.data,
+                            None) == skm.SKM_E_INVALID
+    assert b"k must be" in lib.skm_last_error()
     lib.skm_destroy(None)
