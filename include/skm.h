@@ -271,6 +271,28 @@ skm_status skm_get_tile(const skm_ctx *c, void *codes, size_t codes_bytes, float
  * host array of k bytes. */
 skm_status skm_get_changed(const skm_ctx *c, uint8_t *out);
 
+/* Checkpoint (resume after a stop or a lost process).  Taken after
+ * skm_update and before the next skm_assign (SKM_E_STATE otherwise): writes to
+ * the host file path the assignment that made the current centroids, the
+ * certified score intervals of the rows' centroids, the changed-centroid flags,
+ * the run's counters, and the centroids of the clusters without members
+ * (sparse).  Every other centroid is the normalised sum of its members in
+ * ascending row order, a function of the assignment, so it is not stored.
+ * Size: 20 bytes per row, 1 per centroid, 12 per stored non-zero.
+ * SKM_E_INVALID when the file cannot be written. */
+skm_status skm_save(const skm_ctx *c, const char *path);
+
+/* Resumes a run from skm_save's file: a new context (*out, released with
+ * skm_destroy) over docs, which must be the rows the run used (same shape is
+ * checked), with cfg's k, precision and SKM_NCC / SKM_INDEX / SKM_NO_EXACT /
+ * SKM_DENSE_ONLY flags equal to the saved run's; cfg's other fields (stream,
+ * budget, stop rule, limits) apply from here on, and cfg's init fields are
+ * ignored.  The centroids are recomputed from the saved assignment, so the
+ * resumed run continues bit for bit as the saved one would have.
+ * SKM_E_INVALID for a missing, truncated or mismatched file (checked before
+ * any device work); otherwise as skm_init. */
+skm_status skm_load(skm_ctx **out, const skm_csr *docs, const char *path, const skm_config *cfg);
+
 /* Low-precision scores of the rows in docs against every centroid, before any
  * exact tier: out[i * k + j], host, n_rows * k floats.  Diagnostic for checking
  * the error bound; small inputs only. */

@@ -1422,6 +1422,216 @@ skm_status skm_set_centroids(skm_ctx *c, const double *centroids) {
   return SKM_OK;
 }
 
+// Checkpoint file: header, then a_prev int32[N], lo_prev and hi_prev double[N],
+// changed uint8[k], and the centroids of the clusters with no members (their
+// ids int32[n_empty], row offsets int64[n_empty + 1], terms int32[] and values
+// double[] of their non-zeros).  Every other centroid is the normalised sum of
+// its members in ascending row order, so it is recomputed on load and comes
+// out bit for bit the same.
+struct CkptHeader {
+  char magic[8];
+  uint32_t version;
+  int32_t k;
+  int64_t n_rows, n_cols, nnz;
+  int32_t precision;
+  uint32_t flags;
+  int32_t iter, last_changed;
+  int64_t last_moved;
+  int32_t idx_skip, idx_backoff;
+  int32_t index_ready, reserved;
+  double full_frac;
+  int64_t n_empty, empty_nnz;
+};
+constexpr char kCkptMagic[8] = {'S', 'K', 'M', 'C', 'K', 'P', 'T', '1'};
+constexpr uint32_t kStateFlags = SKM_NCC | SKM_INDEX | SKM_NO_EXACT | SKM_DENSE_ONLY;
+
+skm_status skm_save(const skm_ctx *cc, const char *path) {
+  ST_TRY(check_ctx(cc));
+  skm_ctx *c = const_cast<skm_ctx *>(cc);
+  if (!path) return fail(SKM_E_INVALID, "path is NULL");
+  if (c->assigned || !c->have_prev)
+    return fail(SKM_E_STATE, "a checkpoint is taken after skm_update and before the next skm_assign");
+  hipStream_t s = c->stream;
+  const int64_t N = c->N, D = c->D;
+  const int32_t k = c->k;
+  std::vector<int32_t> a(N);
+  std::vector<double> lo(N), hi(N);
+  std::vector<uint8_t> ch(k);
+  HIP_TRY(c, hipMemcpyAsync(a.data(), c->a_prev, sizeof(int32_t) * N, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipMemcpyAsync(lo.data(), c->lo_prev, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipMemcpyAsync(hi.data(), c->hi_prev, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipMemcpyAsync(ch.data(), c->changed, k, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  std::vector<int64_t> count(k, 0);
+  for (int32_t j : a) {
+    if (j < 0 || j >= k) return fail(SKM_E_STATE, "the assignment holds an invalid centroid id");
+    count[j] += 1;
+  }
+  std::vector<int32_t> e_ids, e_terms;
+  std::vector<int64_t> e_off(1, 0);
+  std::vector<double> e_vals, row(D);
+  for (int32_t j = 0; j < k; ++j) {
+    if (count[j] != 0) continue;
+    HIP_TRY(c, hipMemcpyAsync(row.data(), c->master + (size_t)j * D, sizeof(double) * D,
+                              hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    e_ids.push_back(j);
+    for (int64_t t = 0; t < D; ++t)
+      if (row[t] != 0.0) {
+        e_terms.push_back((int32_t)t);
+        e_vals.push_back(row[t]);
+      }
+    e_off.push_back((int64_t)e_terms.size());
+  }
+  CkptHeader h{};
+  std::memcpy(h.magic, kCkptMagic, 8);
+  h.version = 1;
+  h.k = k;
+  h.n_rows = N;
+  h.n_cols = D;
+  h.nnz = c->Z;
+  h.precision = c->prec;
+  h.flags = c->cfg.flags & kStateFlags;
+  h.iter = c->iter;
+  h.last_changed = c->last_changed;
+  h.last_moved = c->last_moved;
+  h.idx_skip = c->idx_skip;
+  h.idx_backoff = c->idx_backoff;
+  h.index_ready = c->index_ready ? 1 : 0;
+  h.full_frac = c->full_frac;
+  h.n_empty = (int64_t)e_ids.size();
+  h.empty_nnz = (int64_t)e_terms.size();
+  FILE *f = std::fopen(path, "wb");
+  if (!f) return fail(SKM_E_INVALID, std::string("cannot open ") + path + " for writing");
+  bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1;
+  auto put = [&](const void *p, size_t bytes) {
+    if (ok && bytes) ok = std::fwrite(p, 1, bytes, f) == bytes;
+  };
+  put(a.data(), sizeof(int32_t) * N);
+  put(lo.data(), sizeof(double) * N);
+  put(hi.data(), sizeof(double) * N);
+  put(ch.data(), (size_t)k);
+  put(e_ids.data(), sizeof(int32_t) * e_ids.size());
+  put(e_off.data(), sizeof(int64_t) * e_off.size());
+  put(e_terms.data(), sizeof(int32_t) * e_terms.size());
+  put(e_vals.data(), sizeof(double) * e_vals.size());
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) return fail(SKM_E_INVALID, std::string("writing ") + path + " failed");
+  return SKM_OK;
+}
+
+skm_status skm_load(skm_ctx **out, const skm_csr *docs, const char *path, const skm_config *cfg) {
+  if (!out) return fail(SKM_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!cfg || !path) return fail(SKM_E_INVALID, "cfg or path is NULL");
+  ST_TRY(check_csr_header(docs, 0));
+  // the whole file is read and checked before any device work
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return fail(SKM_E_INVALID, std::string("cannot open ") + path);
+  CkptHeader h{};
+  bool ok = std::fread(&h, sizeof(h), 1, f) == 1;
+  auto bad = [&](const char *why) {
+    std::fclose(f);
+    return fail(SKM_E_INVALID, std::string("checkpoint ") + path + ": " + why);
+  };
+  if (!ok || std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != 1)
+    return bad("not a checkpoint of this library");
+  if (h.n_rows != docs->n_rows || h.n_cols != docs->n_cols || h.nnz != docs->nnz)
+    return bad("taken on rows of another shape");
+  if (h.k != cfg->k || h.precision != cfg->precision || h.flags != (cfg->flags & kStateFlags))
+    return bad("k, precision or flags differ from cfg");
+  const int64_t N = h.n_rows, D = h.n_cols;
+  const int32_t k = h.k;
+  if (k < 1 || k > N || h.n_empty < 0 || h.n_empty > k || h.empty_nnz < 0 ||
+      h.empty_nnz > h.n_empty * D || h.iter < 1)
+    return bad("inconsistent header");
+  std::vector<int32_t> a(N), e_ids(h.n_empty), e_terms(h.empty_nnz);
+  std::vector<double> lo(N), hi(N), e_vals(h.empty_nnz);
+  std::vector<uint8_t> ch(k);
+  std::vector<int64_t> e_off(h.n_empty + 1);
+  auto get = [&](void *p, size_t bytes) {
+    if (ok && bytes) ok = std::fread(p, 1, bytes, f) == bytes;
+  };
+  get(a.data(), sizeof(int32_t) * N);
+  get(lo.data(), sizeof(double) * N);
+  get(hi.data(), sizeof(double) * N);
+  get(ch.data(), (size_t)k);
+  get(e_ids.data(), sizeof(int32_t) * e_ids.size());
+  get(e_off.data(), sizeof(int64_t) * e_off.size());
+  get(e_terms.data(), sizeof(int32_t) * e_terms.size());
+  get(e_vals.data(), sizeof(double) * e_vals.size());
+  if (!ok) return bad("truncated");
+  std::vector<int64_t> count(k, 0);
+  for (int32_t j : a) {
+    if (j < 0 || j >= k) return bad("assignment out of range");
+    count[j] += 1;
+  }
+  if (e_off[0] != 0 || e_off[h.n_empty] != h.empty_nnz) return bad("bad row offsets");
+  for (int64_t q = 0; q < h.n_empty; ++q) {
+    if (e_ids[q] < 0 || e_ids[q] >= k || count[e_ids[q]] != 0 || (q > 0 && e_ids[q] <= e_ids[q - 1]))
+      return bad("bad empty-cluster ids");
+    if (e_off[q + 1] < e_off[q]) return bad("bad row offsets");
+    for (int64_t p = e_off[q]; p < e_off[q + 1]; ++p)
+      if (e_terms[p] < 0 || e_terms[p] >= D) return bad("term out of range");
+  }
+  int64_t n_empty_a = 0;
+  for (int32_t j = 0; j < k; ++j) n_empty_a += count[j] == 0;
+  if (n_empty_a != h.n_empty) return bad("empty clusters do not match the assignment");
+  std::fclose(f);
+
+  // A context seeded from stand-in rows; then the saved state replaces it.
+  std::vector<int32_t> rows(k);
+  for (int32_t j = 0; j < k; ++j) rows[j] = j;
+  skm_config c2 = *cfg;
+  c2.init_rows = rows.data();
+  c2.init_centroids = nullptr;
+  skm_ctx *c = nullptr;
+  ST_TRY(skm_init(docs, &c2, &c));
+  auto cleanup = [&](skm_status st) {
+    skm_destroy(c);
+    return st;
+  };
+  hipStream_t s = c->stream;
+  hipError_t e = hipSuccess;
+  {
+    // clusters without members keep the saved centroid through the update
+    std::vector<double> row(D);
+    for (int64_t q = 0; q < h.n_empty && e == hipSuccess; ++q) {
+      std::fill(row.begin(), row.end(), 0.0);
+      for (int64_t p = e_off[q]; p < e_off[q + 1]; ++p) row[e_terms[p]] = e_vals[p];
+      e = hipMemcpyAsync(c->master + (size_t)e_ids[q] * D, row.data(), sizeof(double) * D,
+                         hipMemcpyHostToDevice, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(c->a, a.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->lo, lo.data(), sizeof(double) * N, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->hi, hi.data(), sizeof(double) * N, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return cleanup(device_fail(c, "checkpoint upload", e));
+  // every centroid from the saved assignment (the update swaps a, lo, hi into
+  // their _prev slots), then the counters of the saved run
+  c->assigned = true;
+  c->force_all = true;
+  c->have_prev = false;
+  c->idx_skip = 0;
+  skm_iter_stats st{};
+  skm_status rs = skm_update(c, &st);
+  if (rs != SKM_OK) return cleanup(rs);
+  e = hipMemcpyAsync(c->changed, ch.data(), (size_t)k, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return cleanup(device_fail(c, "checkpoint upload", e));
+  c->iter = h.iter;
+  c->last_changed = h.last_changed;
+  c->last_moved = h.last_moved;
+  c->idx_skip = h.idx_skip;
+  c->idx_backoff = h.idx_backoff;
+  c->index_ready = c->index_ready && h.index_ready;
+  c->full_frac = h.full_frac;
+  *out = c;
+  return SKM_OK;
+}
+
 skm_status skm_get_tile(const skm_ctx *c, void *codes, size_t codes_bytes, float *scales,
                         int64_t *ld) {
   ST_TRY(check_ctx(c));

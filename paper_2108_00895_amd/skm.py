@@ -28,7 +28,7 @@ EXPORTED = [
     "skm_config_default", "skm_kmeanspp", "skm_init", "skm_assign", "skm_update", "skm_iterate",
     "skm_assign_new", "skm_get_assignments", "skm_get_centroids", "skm_get_centroid_columns",
     "skm_get_centroid_rows", "skm_set_centroids",
-    "skm_get_tile", "skm_get_changed", "skm_score_dense", "skm_error_bound", "skm_head_terms",
+    "skm_save", "skm_load", "skm_get_tile", "skm_get_changed", "skm_score_dense", "skm_error_bound", "skm_head_terms",
     "skm_score_head", "skm_error_bound_head", "skm_error_bound_split", "skm_autotune", "skm_set_schedule", "skm_get_index",
     "skm_index_query", "skm_server_config_default", "skm_server_start", "skm_server_submit",
     "skm_server_wait", "skm_server_get_stats", "skm_server_stop",
@@ -147,6 +147,10 @@ def load():
     lib.skm_get_tile.restype = st
     lib.skm_get_changed.argtypes = [vp, vp]
     lib.skm_get_changed.restype = st
+    lib.skm_save.argtypes = [vp, ctypes.c_char_p]
+    lib.skm_save.restype = st
+    lib.skm_load.argtypes = [P(vp), P(Csr), ctypes.c_char_p, P(Config)]
+    lib.skm_load.restype = st
     lib.skm_kmeanspp.argtypes = [P(Csr), i32, vp, vp, vp]
     lib.skm_kmeanspp.restype = st
     lib.skm_score_dense.argtypes = [vp, P(Csr), vp]
@@ -254,6 +258,42 @@ class Options:
     head_min_df: float | None = None    # None: the library default (1/128)
 
 
+def _config(lib, k, o, init_rows, init_centroids, stream):
+    """skm_config from Options (+ the arrays it points to, to keep alive)."""
+    cfg = Config()
+    lib.skm_config_default(ctypes.byref(cfg))
+    cfg.k = k
+    cfg.precision = PRECISIONS[o.precision]
+    cfg.flags = ((NCC if o.ncc else 0) | (INDEX if o.index else 0) |
+                 (NO_EXACT if o.no_exact else 0) | (DENSE_ONLY if o.dense_only else 0))
+    cfg.n_lambda = len(o.lambdas)
+    for i, lam in enumerate(o.lambdas):
+        cfg.lambda_[i] = lam
+    cfg.index_min_changed = o.index_min_changed
+    cfg.stop_rule = STOP_PAPER if o.stop_rule == "paper" else STOP_FIXED
+    cfg.max_iter = o.max_iter
+    cfg.min_moved_frac = o.min_moved_frac
+    cfg.max_shift_sq = o.max_shift_sq
+    cfg.hbm_budget_bytes = o.hbm_budget_bytes
+    cfg.validate = 1 if o.validate else 0
+    if o.head_max_terms is not None:
+        cfg.head_max_terms = o.head_max_terms
+    if o.head_min_df is not None:
+        cfg.head_min_df = o.head_min_df
+    keep = []
+    if init_rows is not None:
+        r = np.ascontiguousarray(init_rows, dtype=np.int32)
+        keep.append(r)
+        cfg.init_rows = r.ctypes.data
+    if init_centroids is not None:
+        C = np.ascontiguousarray(init_centroids, dtype=np.float64)
+        keep.append(C)
+        cfg.init_centroids = C.ctypes.data
+    if stream is not None:
+        cfg.stream = stream
+    return cfg, keep
+
+
 class Context:
     """One clustering problem resident on the GPU (wraps skm_ctx)."""
 
@@ -261,37 +301,7 @@ class Context:
                  **opts):
         lib = load()
         o = Options(**opts)
-        cfg = Config()
-        lib.skm_config_default(ctypes.byref(cfg))
-        cfg.k = k
-        cfg.precision = PRECISIONS[o.precision]
-        cfg.flags = ((NCC if o.ncc else 0) | (INDEX if o.index else 0) |
-                     (NO_EXACT if o.no_exact else 0) | (DENSE_ONLY if o.dense_only else 0))
-        cfg.n_lambda = len(o.lambdas)
-        for i, lam in enumerate(o.lambdas):
-            cfg.lambda_[i] = lam
-        cfg.index_min_changed = o.index_min_changed
-        cfg.stop_rule = STOP_PAPER if o.stop_rule == "paper" else STOP_FIXED
-        cfg.max_iter = o.max_iter
-        cfg.min_moved_frac = o.min_moved_frac
-        cfg.max_shift_sq = o.max_shift_sq
-        cfg.hbm_budget_bytes = o.hbm_budget_bytes
-        cfg.validate = 1 if o.validate else 0
-        if o.head_max_terms is not None:
-            cfg.head_max_terms = o.head_max_terms
-        if o.head_min_df is not None:
-            cfg.head_min_df = o.head_min_df
-        keep = []
-        if init_rows is not None:
-            r = np.ascontiguousarray(init_rows, dtype=np.int32)
-            keep.append(r)
-            cfg.init_rows = r.ctypes.data
-        if init_centroids is not None:
-            C = np.ascontiguousarray(init_centroids, dtype=np.float64)
-            keep.append(C)
-            cfg.init_centroids = C.ctypes.data
-        if stream is not None:
-            cfg.stream = stream
+        cfg, keep = _config(lib, k, o, init_rows, init_centroids, stream)
         c, hold = make_csr(*csr, n_cols)
         h = ctypes.c_void_p()
         _check(lib.skm_init(ctypes.byref(c), ctypes.byref(cfg), ctypes.byref(h)))
@@ -299,6 +309,29 @@ class Context:
         self.k, self.n_cols, self.n_rows = k, n_cols, c.n_rows
         self.precision = cfg.precision
         self.opts = o
+
+    @classmethod
+    def from_checkpoint(cls, path, csr, n_cols, k, stream=None, **opts):
+        """A context resumed from skm_save's file (skm_load): the same rows,
+        k and options (precision, ncc, index, no_exact, dense_only) as the run
+        that saved it."""
+        lib = load()
+        o = Options(**opts)
+        cfg, _ = _config(lib, k, o, None, None, stream)
+        c, hold = make_csr(*csr, n_cols)
+        h = ctypes.c_void_p()
+        _check(lib.skm_load(ctypes.byref(h), ctypes.byref(c), os.fsencode(path), ctypes.byref(cfg)))
+        self = cls.__new__(cls)
+        self._h = h
+        self.k, self.n_cols, self.n_rows = k, n_cols, c.n_rows
+        self.precision = cfg.precision
+        self.opts = o
+        return self
+
+    def save(self, path):
+        """Checkpoint after an update (skm_save)."""
+        _check(load().skm_save(self._h, os.fsencode(path)))
+
 
     # -- lifecycle
     def close(self):

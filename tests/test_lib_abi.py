@@ -71,3 +71,36 @@ def test_null_arguments_rejected_without_device():
                             None) == skm.SKM_E_INVALID
     assert b"k must be" in lib.skm_last_error()
     lib.skm_destroy(None)
+
+
+def test_checkpoint_files_checked_without_device(tmp_path):
+    """skm_load reads and checks the whole file before any device work: a
+    missing file, a foreign file and a checkpoint of other rows are refused."""
+    lib = skm.load()
+    assert lib.skm_save(None, b"x") == skm.SKM_E_INVALID
+    ip = np.array([0, 1, 2], dtype=np.int64)
+    ix = np.array([0, 1], dtype=np.int32)
+    v = np.array([1.0, 1.0], dtype=np.float32)
+    c = skm.Csr(2, 2, 2, ip.ctypes.data, ix.ctypes.data, v.ctypes.data, 0)
+    cfg = skm.Config()
+    lib.skm_config_default(ctypes.byref(cfg))
+    cfg.k = 1
+    h = ctypes.c_void_p()
+    missing = str(tmp_path / "missing.ckpt").encode()
+    assert lib.skm_load(ctypes.byref(h), ctypes.byref(c), missing, ctypes.byref(cfg)) == \
+        skm.SKM_E_INVALID
+    foreign = tmp_path / "foreign.ckpt"
+    foreign.write_bytes(b"not a checkpoint" * 16)
+    assert lib.skm_load(ctypes.byref(h), ctypes.byref(c), str(foreign).encode(),
+                        ctypes.byref(cfg)) == skm.SKM_E_INVALID
+    assert b"not a checkpoint" in lib.skm_last_error()
+    # a well-formed header for 3 rows does not fit these 2 rows
+    import struct
+    hdr = struct.pack("<8sIiqqqiIiiqiiiidqq", b"SKMCKPT1", 1, 1, 3, 2, 3, 0, 0, 1, 1, 0, 0, 8,
+                      1, 0, 1.0, 0, 0)
+    other = tmp_path / "other.ckpt"
+    other.write_bytes(hdr)
+    assert lib.skm_load(ctypes.byref(h), ctypes.byref(c), str(other).encode(),
+                        ctypes.byref(cfg)) == skm.SKM_E_INVALID
+    assert b"another shape" in lib.skm_last_error()
+    assert not h.value
