@@ -69,8 +69,12 @@ enum {
   SKM_NO_EXACT = 1u << 2,  /* skip the exact tier: the argmax is taken on the
                               low-precision scores alone (timing comparator only;
                               results are then NOT those of an FP64 run) */
-  SKM_DENSE_ONLY = 1u << 3 /* score every term from the dense code slabs (no
+  SKM_DENSE_ONLY = 1u << 3, /* score every term from the dense code slabs (no
                               per-term lists of non-zero codes) */
+  SKM_BORROW_DEVICE = 1u << 4 /* skm_init / skm_load with device rows: use the
+                              caller's three arrays in place instead of copying
+                              them; the caller keeps them alive and unchanged
+                              until skm_destroy (host rows are still copied) */
 };
 
 typedef enum {
@@ -81,7 +85,8 @@ typedef enum {
 } skm_stop_rule;
 
 /*
- * A CSR matrix of rows (documents).  Borrowed for the duration of the call.
+ * A CSR matrix of rows (documents).  Borrowed for the duration of the call
+ * (for the context's lifetime with SKM_BORROW_DEVICE).
  *   indptr  [n_rows + 1], indptr[0] = 0, non-decreasing, indptr[n_rows] = nnz
  *   indices [nnz], strictly ascending within a row, in [0, n_cols)
  *   values  [nnz], finite and > 0; each row's L2 norm within 1e-5 of 1

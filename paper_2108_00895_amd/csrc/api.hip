@@ -122,7 +122,7 @@ struct DevRows {
 // and computes per-row norms; checks the CSR conventions on the device.
 template <typename Alloc>
 skm_status upload_rows(skm_ctx *c, const skm_csr *d, int64_t D, bool validate, hipStream_t s,
-                       Alloc alloc, DevRows *out) {
+                       Alloc alloc, DevRows *out, bool borrow = false) {
   const int64_t n = d->n_rows, z = d->nnz;
   std::vector<int64_t> ip_host;
   const int64_t *ip = d->indptr;
@@ -134,17 +134,24 @@ skm_status upload_rows(skm_ctx *c, const skm_csr *d, int64_t D, bool validate, h
     ip = ip_host.data();
   }
   ST_TRY(check_indptr(ip, n, z));
-  ST_TRY(alloc(&out->indptr, (size_t)(n + 1) * sizeof(int64_t)));
-  ST_TRY(alloc(&out->indices, (size_t)std::max<int64_t>(z, 1) * sizeof(int32_t)));
-  ST_TRY(alloc(&out->values, (size_t)std::max<int64_t>(z, 1) * sizeof(float)));
+  if (borrow && d->on_device) {
+    // the caller's device arrays are used in place (read only)
+    out->indptr = const_cast<int64_t *>(d->indptr);
+    out->indices = const_cast<int32_t *>(d->indices);
+    out->values = const_cast<float *>(d->values);
+  } else {
+    ST_TRY(alloc(&out->indptr, (size_t)(n + 1) * sizeof(int64_t)));
+    ST_TRY(alloc(&out->indices, (size_t)std::max<int64_t>(z, 1) * sizeof(int32_t)));
+    ST_TRY(alloc(&out->values, (size_t)std::max<int64_t>(z, 1) * sizeof(float)));
+    const hipMemcpyKind kind = d->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIP_TRY(c, hipMemcpyAsync(out->indptr, d->indptr, sizeof(int64_t) * (n + 1), kind, s));
+    if (z > 0) {
+      HIP_TRY(c, hipMemcpyAsync(out->indices, d->indices, sizeof(int32_t) * z, kind, s));
+      HIP_TRY(c, hipMemcpyAsync(out->values, d->values, sizeof(float) * z, kind, s));
+    }
+  }
   ST_TRY(alloc(&out->xl1, (size_t)std::max<int64_t>(n, 1) * sizeof(double)));
   ST_TRY(alloc(&out->xl2, (size_t)std::max<int64_t>(n, 1) * sizeof(double)));
-  const hipMemcpyKind kind = d->on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-  HIP_TRY(c, hipMemcpyAsync(out->indptr, d->indptr, sizeof(int64_t) * (n + 1), kind, s));
-  if (z > 0) {
-    HIP_TRY(c, hipMemcpyAsync(out->indices, d->indices, sizeof(int32_t) * z, kind, s));
-    HIP_TRY(c, hipMemcpyAsync(out->values, d->values, sizeof(float) * z, kind, s));
-  }
   int32_t *bad = nullptr;
   ST_TRY(alloc(&bad, sizeof(int32_t)));
   HIP_TRY(c, launch_fill_i32(bad, 0, 1, s));
@@ -775,7 +782,8 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
     return dalloc(c, reinterpret_cast<T **>(p), (bytes + sizeof(T) - 1) / sizeof(T));
   };
   DevRows rows;
-  skm_status st = upload_rows(c, docs, c->D, cfg->validate != 0, c->stream, alloc, &rows);
+  skm_status st = upload_rows(c, docs, c->D, cfg->validate != 0, c->stream, alloc, &rows,
+                              (cfg->flags & SKM_BORROW_DEVICE) != 0);
   if (st != SKM_OK) return cleanup(st);
   c->indptr = rows.indptr;
   c->indices = rows.indices;

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libskm.so")
 (SKM_OK, SKM_E_INVALID, SKM_E_NOMEM, SKM_E_DEVICE, SKM_E_STATE, SKM_E_UNSUPPORTED, SKM_E_BUSY,
  SKM_E_TIMEOUT) = range(8)
 FP32, BF16, FP8_E4M3 = 0, 1, 2
-NCC, INDEX, NO_EXACT, DENSE_ONLY = 1, 2, 4, 8
+NCC, INDEX, NO_EXACT, DENSE_ONLY, BORROW_DEVICE = 1, 2, 4, 8, 16
 STOP_PAPER, STOP_FIXED = 0, 1
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3}
 CODE_BYTES = {FP32: 4, BF16: 2, FP8_E4M3: 1}
@@ -256,6 +256,7 @@ class Options:
     validate: bool = True
     head_max_terms: int | None = None   # None: the library default (4096); 0: off
     head_min_df: float | None = None    # None: the library default (1/128)
+    borrow: bool = False                # device rows used in place (SKM_BORROW_DEVICE)
 
 
 def _config(lib, k, o, init_rows, init_centroids, stream):
@@ -265,7 +266,8 @@ def _config(lib, k, o, init_rows, init_centroids, stream):
     cfg.k = k
     cfg.precision = PRECISIONS[o.precision]
     cfg.flags = ((NCC if o.ncc else 0) | (INDEX if o.index else 0) |
-                 (NO_EXACT if o.no_exact else 0) | (DENSE_ONLY if o.dense_only else 0))
+                 (NO_EXACT if o.no_exact else 0) | (DENSE_ONLY if o.dense_only else 0) |
+                 (BORROW_DEVICE if o.borrow else 0))
     cfg.n_lambda = len(o.lambdas)
     for i, lam in enumerate(o.lambdas):
         cfg.lambda_[i] = lam
@@ -306,6 +308,7 @@ class Context:
         h = ctypes.c_void_p()
         _check(lib.skm_init(ctypes.byref(c), ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
+        self._hold = hold if o.borrow else None   # borrowed rows live as long as the context
         self.k, self.n_cols, self.n_rows = k, n_cols, c.n_rows
         self.precision = cfg.precision
         self.opts = o
@@ -323,6 +326,7 @@ class Context:
         _check(lib.skm_load(ctypes.byref(h), ctypes.byref(c), os.fsencode(path), ctypes.byref(cfg)))
         self = cls.__new__(cls)
         self._h = h
+        self._hold = hold if o.borrow else None
         self.k, self.n_cols, self.n_rows = k, n_cols, c.n_rows
         self.precision = cfg.precision
         self.opts = o
@@ -338,6 +342,7 @@ class Context:
         if getattr(self, "_h", None):
             load().skm_destroy(self._h)
             self._h = None
+        self._hold = None
 
     def __del__(self):
         try:

@@ -188,6 +188,26 @@ def test_tweet_shaped_trajectory_equals_oracle(prec, ncc, index):
     ctx.close()
 
 
+def test_borrowed_device_rows(mid):
+    """SKM_BORROW_DEVICE: the context reads the caller's device arrays in place
+    (no copy: less HBM by their size) and runs exactly as with a copy."""
+    csr, c, rows = mid
+    say("case: borrowed device rows")
+    dev = to_device(csr)
+    runs = []
+    for borrow in (False, True):
+        ctx = Context(dev, c.n_terms, len(rows), init_rows=rows, precision="bf16", ncc=True,
+                      stop_rule="fixed", max_iter=6, borrow=borrow)
+        hbm = ctx.hbm_bytes()
+        stats, _ = ctx.iterate()
+        runs.append((hbm, [s["moved"] for s in stats], ctx.assignments(), ctx.centroids()))
+        ctx.close()
+    (h0, m0, a0, C0), (h1, m1, a1, C1) = runs
+    z = len(csr[1])
+    assert h0 - h1 >= 8 * (c.n_docs + 1) + 8 * z
+    assert m0 == m1 and np.array_equal(a0, a1) and np.array_equal(C0, C1)
+
+
 def test_small_workload_ten_iterations():
     w = synth.SMALL
     say("case: small workload", w.name)
