@@ -1,0 +1,30 @@
+"""The CPU oracle and the input generator under AddressSanitizer and
+UndefinedBehaviorSanitizer (host code only): tests/sanitize_driver.c runs a
+small end-to-end workload through both, built with gcc."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+def test_oracle_and_generator_under_sanitizers(tmp_path):
+    exe = str(tmp_path / "sanitize_driver")
+    cmd = ["gcc", "-O1", "-g", "-std=c11", "-fopenmp", "-fno-omit-frame-pointer",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           os.path.join(ROOT, "tests", "sanitize_driver.c"),
+           os.path.join(ROOT, "oracle", "oracle.c"),
+           os.path.join(ROOT, "synth", "synth.c"), "-o", exe, "-lm"]
+    b = subprocess.run(cmd, capture_output=True, text=True)
+    if b.returncode != 0 and "sanitize" in b.stderr:
+        pytest.skip("gcc without sanitizer runtimes: " + b.stderr[-300:])
+    assert b.returncode == 0, b.stderr[-2000:]
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
+               UBSAN_OPTIONS="print_stacktrace=1", OMP_NUM_THREADS="2")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
+    assert r.returncode == 0, (r.stdout[-1000:], r.stderr[-3000:])
+    assert "sanitized run ok" in r.stdout
+    assert "runtime error" not in r.stderr and "ERROR: AddressSanitizer" not in r.stderr
