@@ -16,7 +16,9 @@ Contents:
 Pins (``tests/test_oracle*.py``): brute force by dense numpy products, closed
 forms (k = 1, planted disjoint blocks, k = N), the unit-norm invariant, the
 monotone objective chain J_A(t) <= J_U(t) <= J_A(t+1), Lemma 3.1 and the
-index's superset property, and format values from the format definitions.
+index's superset property, format values from the format definitions, and for
+k-means++ an exact rational brute force plus closed forms (k = N gives every
+row; groups of identical rows on disjoint terms get one seed each).
 """
 from __future__ import annotations
 
