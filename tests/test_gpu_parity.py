@@ -208,6 +208,30 @@ def test_borrowed_device_rows(mid):
     assert m0 == m1 and np.array_equal(a0, a1) and np.array_equal(C0, C1)
 
 
+def test_unchanged_centroids_keep_their_bits(mid):
+    """Sec. 3.1 taken exactly: after each update the changed flags are the
+    oracle's membership-changed clusters, and every centroid not flagged keeps
+    its FP64 bits (so NCC may reuse its codes and cached scores)."""
+    csr, c, rows = mid
+    say("case: unchanged centroids keep their bits")
+    ref = oracle.run(csr, c.n_terms, len(rows), rows, max_iter=8, stop_rule="fixed")
+    ctx = Context(to_device(csr), c.n_terms, len(rows), init_rows=rows, precision="bf16",
+                  ncc=True, stop_rule="fixed", max_iter=8)
+    n_kept = 0
+    for rec in ref.records:
+        before = ctx.centroids()
+        ctx.assign()
+        ctx.update()
+        flags = ctx.changed().astype(bool)
+        assert np.array_equal(np.nonzero(flags)[0], np.sort(rec.changed)), rec.t
+        after = ctx.centroids()
+        assert np.array_equal(after[~flags], before[~flags]), rec.t
+        n_kept += int((~flags).sum())
+    say("  unchanged centroid-iterations:", n_kept)
+    assert n_kept > 0
+    ctx.close()
+
+
 def test_small_workload_ten_iterations():
     w = synth.SMALL
     say("case: small workload", w.name)
