@@ -283,8 +283,10 @@ skm_status skm_get_changed(const skm_ctx *c, uint8_t *out);
  * the run's counters, and the centroids of the clusters without members
  * (sparse).  Every other centroid is the normalised sum of its members in
  * ascending row order, a function of the assignment, so it is not stored.
- * Size: 20 bytes per row, 1 per centroid, 12 per stored non-zero.
- * SKM_E_INVALID when the file cannot be written. */
+ * Size: 20 bytes per row, 1 per centroid, 12 per stored non-zero.  The file
+ * is written as path + ".tmp" and renamed to path when complete, so an earlier
+ * checkpoint at path survives a crash while writing.  SKM_E_INVALID when the
+ * file cannot be written. */
 skm_status skm_save(const skm_ctx *c, const char *path);
 
 /* Resumes a run from skm_save's file: a new context (*out, released with

@@ -1509,8 +1509,11 @@ skm_status skm_save(const skm_ctx *cc, const char *path) {
   h.full_frac = c->full_frac;
   h.n_empty = (int64_t)e_ids.size();
   h.empty_nnz = (int64_t)e_terms.size();
-  FILE *f = std::fopen(path, "wb");
-  if (!f) return fail(SKM_E_INVALID, std::string("cannot open ") + path + " for writing");
+  // written beside the target and renamed over it, so that a crash while
+  // writing leaves the previous checkpoint intact
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE *f = std::fopen(tmp.c_str(), "wb");
+  if (!f) return fail(SKM_E_INVALID, "cannot open " + tmp + " for writing");
   bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1;
   auto put = [&](const void *p, size_t bytes) {
     if (ok && bytes) ok = std::fwrite(p, 1, bytes, f) == bytes;
@@ -1523,8 +1526,13 @@ skm_status skm_save(const skm_ctx *cc, const char *path) {
   put(e_off.data(), sizeof(int64_t) * e_off.size());
   put(e_terms.data(), sizeof(int32_t) * e_terms.size());
   put(e_vals.data(), sizeof(double) * e_vals.size());
+  ok = (std::fflush(f) == 0) && ok;
   ok = (std::fclose(f) == 0) && ok;
-  if (!ok) return fail(SKM_E_INVALID, std::string("writing ") + path + " failed");
+  if (ok) ok = std::rename(tmp.c_str(), path) == 0;
+  if (!ok) {
+    (void)std::remove(tmp.c_str());
+    return fail(SKM_E_INVALID, std::string("writing ") + path + " failed");
+  }
   return SKM_OK;
 }
 

@@ -76,6 +76,9 @@ def test_checkpoint_states_and_mismatches(tmp_path):
         ctx.save(path)
     ctx.update()
     ctx.save(path)
+    assert path.exists() and not (tmp_path / "x.ckpt.tmp").exists()
+    with pytest.raises(SkmError):          # an unwritable place
+        ctx.save(tmp_path / "no_such_dir" / "x.ckpt")
     with pytest.raises(SkmError):          # another k
         Context.from_checkpoint(path, csr, c.n_terms, 21, stop_rule="fixed")
     with pytest.raises(SkmError):          # another precision
