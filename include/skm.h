@@ -276,9 +276,12 @@ skm_status skm_get_tile(const skm_ctx *c, void *codes, size_t codes_bytes, float
  * host array of k bytes. */
 skm_status skm_get_changed(const skm_ctx *c, uint8_t *out);
 
-/* Checkpoint (resume after a stop or a lost process).  Taken after
- * skm_update and before the next skm_assign (SKM_E_STATE otherwise): writes to
- * the host file path the assignment that made the current centroids, the
+/* Checkpoint (resume after a stop or a lost process).  Taken any time after
+ * the first skm_update (SKM_E_STATE before); when an skm_assign is pending its
+ * skm_update (as after skm_iterate stops on an assignment that moved nothing),
+ * the file holds the state before that assignment, which a resumed run
+ * repeats with the same result.  Writes to the host file path the assignment
+ * that made the current centroids, the
  * certified score intervals of the rows' centroids, the changed-centroid flags,
  * the run's counters, and the centroids of the clusters without members
  * (sparse).  Every other centroid is the normalised sum of its members in

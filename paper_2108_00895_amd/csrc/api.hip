@@ -967,6 +967,8 @@ float head_ms(skm_ctx *c, size_t n_ev) {
 skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
   ST_TRY(check_ctx_writable(c));
   hipStream_t s = c->stream;
+  c->idx_skip_pre = c->idx_skip;       // a checkpoint taken before the update restores these
+  c->idx_backoff_pre = c->idx_backoff;
   ScoreArgs a = base_args(c);
   // Sec. 3.1 pays when the work it leaves, (1 - r) n_ch / k of the scores of
   // the rows keeping their centroid plus the share r of rows whose centroid
@@ -1457,8 +1459,10 @@ skm_status skm_save(const skm_ctx *cc, const char *path) {
   ST_TRY(check_ctx(cc));
   skm_ctx *c = const_cast<skm_ctx *>(cc);
   if (!path) return fail(SKM_E_INVALID, "path is NULL");
-  if (c->assigned || !c->have_prev)
-    return fail(SKM_E_STATE, "a checkpoint is taken after skm_update and before the next skm_assign");
+  if (!c->have_prev) return fail(SKM_E_STATE, "a checkpoint needs a completed skm_update");
+  // With an assignment pending (taken but not yet followed by its update) the
+  // checkpoint holds the state before it: the assignment leaves a_prev, the
+  // intervals, the flags and the master alone, and the resumed run repeats it.
   hipStream_t s = c->stream;
   const int64_t N = c->N, D = c->D;
   const int32_t k = c->k;
@@ -1503,8 +1507,8 @@ skm_status skm_save(const skm_ctx *cc, const char *path) {
   h.iter = c->iter;
   h.last_changed = c->last_changed;
   h.last_moved = c->last_moved;
-  h.idx_skip = c->idx_skip;
-  h.idx_backoff = c->idx_backoff;
+  h.idx_skip = c->assigned ? c->idx_skip_pre : c->idx_skip;
+  h.idx_backoff = c->assigned ? c->idx_backoff_pre : c->idx_backoff;
   h.index_ready = c->index_ready ? 1 : 0;
   h.full_frac = c->full_frac;
   h.n_empty = (int64_t)e_ids.size();

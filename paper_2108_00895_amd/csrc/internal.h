@@ -269,6 +269,7 @@ struct skm_ctx {
   // turns the index off for idx_backoff iterations (doubling up to 64)
   int32_t idx_skip = 0;
   int32_t idx_backoff = 8;
+  int32_t idx_skip_pre = 0, idx_backoff_pre = 8;  // the two above when the last assign began
   float ms_index_build = 0.f;
   int64_t idx_eligible = 0;
   int server_attached = 0;     // a request server reads this context

@@ -46,7 +46,15 @@ __global__ __launch_bounds__(256) void k_pp_place(const int64_t *__restrict__ in
   for (int64_t q = b + tid; q < e; q += 256) dense[indices[q]] = (double)values[q];
   if (tid == 0) {
     double ss = 0.0;
-    for (int64_t q = b; q < e; ++q) {
+    int64_t q = b;
+    for (; q + 8 <= e; q += 8) {   // fixed order, loads issued eight ahead
+      float x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = values[q + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) ss = fma((double)x[u], (double)x[u], ss);
+    }
+    for (; q < e; ++q) {
       const double v = (double)values[q];
       ss = fma(v, v, ss);
     }
@@ -64,9 +72,25 @@ __global__ __launch_bounds__(kPPRows) void k_pp_weights(
   const int64_t i = (int64_t)blockIdx.x * kPPRows + tid;
   uint64_t wi = 0;
   if (i < n) {
+    // the chain's order is fixed; its loads are issued eight terms ahead
     double acc = 0.0;
+    int64_t q = indptr[i];
     const int64_t e = indptr[i + 1];
-    for (int64_t q = indptr[i]; q < e; ++q) acc = fma((double)values[q], dense[indices[q]], acc);
+    for (; q + 8 <= e; q += 8) {
+      int32_t t[8];
+      float x[8];
+      double d[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        t[u] = indices[q + u];
+        x[u] = values[q + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) d[u] = dense[t[u]];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = fma((double)x[u], d[u], acc);
+    }
+    for (; q < e; ++q) acc = fma((double)values[q], dense[indices[q]], acc);
     const double s = acc / nrm;
     const double bi = fmax(best[i], s);
     best[i] = bi;

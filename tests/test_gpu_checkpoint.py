@@ -72,8 +72,17 @@ def test_checkpoint_states_and_mismatches(tmp_path):
     with pytest.raises(SkmError):          # nothing to save before the first update
         ctx.save(path)
     ctx.assign()
-    with pytest.raises(SkmError):          # an assignment is pending its update
-        ctx.save(path)
+    ctx.update()
+    # with an assignment pending its update the checkpoint is the state before
+    # it: the resumed run repeats that assignment with the same result
+    pend = ctx.assign()
+    a_pend = ctx.assignments()
+    ctx.save(path)
+    r0 = Context.from_checkpoint(path, csr, c.n_terms, 20, stop_rule="fixed", max_iter=5)
+    again = r0.assign()
+    assert again["moved"] == pend["moved"] and again["changed_centroids"] == pend["changed_centroids"]
+    assert np.array_equal(r0.assignments(), a_pend)
+    r0.close()
     ctx.update()
     ctx.save(path)
     assert path.exists() and not (tmp_path / "x.ckpt.tmp").exists()
