@@ -24,7 +24,10 @@
  *
  * Conventions for every call:
  *   - Returns an skm_status; no C++ exception crosses this interface.
- *   - On SKM_E_INVALID / SKM_E_NOMEM / SKM_E_STATE nothing was modified.
+ *   - On SKM_E_INVALID / SKM_E_STATE nothing was modified.  On SKM_E_NOMEM
+ *     the clustering state (assignments, centroids, counters) is unchanged
+ *     and the call may be repeated; derived scratch such as the changed
+ *     flags may have been recomputed.
  *   - On SKM_E_DEVICE the context is unusable; only skm_destroy is valid.
  *   - skm_last_error() returns a thread-local message for the last failure.
  *   - A context is used by one thread at a time.  Work is enqueued on the
