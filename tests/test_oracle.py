@@ -222,3 +222,49 @@ def test_assign_seeds_matches_dense_seeds():
     assert np.all((a == b) | (gap < 1e-12))
     np.testing.assert_allclose(t1, s1, rtol=1e-14, atol=1e-16)
     np.testing.assert_allclose(t2, s2, rtol=1e-14, atol=1e-16)
+
+
+def test_changed_set_is_the_clusters_whose_member_set_changed():
+    """records[t].changed (the reference for the GPU's NCC flags, Sec. 3.1)
+    against a brute-force comparison, cluster by cluster, of the member sets of
+    the assignments before and after step t; iteration 0 changes every cluster."""
+    c = synth.Corpus(800, 600, 20.0, 0.5, 3, 60, 1.1, seed=44)
+    csr = synth.generate(c)
+    k = 30
+    rows = synth.seed_rows(c.n_docs, k, 3)
+    ref = oracle.run(csr, c.n_terms, k, rows, max_iter=12, stop_rule="fixed")
+    prev = None
+    n_partial = 0
+    for rec in ref.records:
+        if not rec.updated:
+            continue
+        if prev is None:
+            want = list(range(k))
+        else:
+            want = [j for j in range(k)
+                    if set(np.nonzero(rec.a == j)[0].tolist()) !=
+                    set(np.nonzero(prev == j)[0].tolist())]
+        assert sorted(int(j) for j in rec.changed) == want, rec.t
+        n_partial += 0 < len(want) < k
+        prev = rec.a
+    assert n_partial >= 5   # the run passes through partial changed sets
+
+
+def test_trajectory_records_hold_each_iterations_own_assignment():
+    """Each record's assignment is the lowest-index argmax against the
+    centroids made from the previous record's assignment (dense numpy)."""
+    csr, c = _tiny(n=300, D=400, seed=43)
+    k = 9
+    rows = synth.seed_rows(c.n_docs, k, 4)
+    ref = oracle.run(csr, c.n_terms, k, rows, max_iter=6, stop_rule="fixed")
+    X = _dense(csr, c.n_terms)
+    C = X[rows] / np.linalg.norm(X[rows], axis=1, keepdims=True)
+    for rec in ref.records:
+        S = X @ C.T
+        gap = np.sort(S, axis=1)[:, -1] - np.sort(S, axis=1)[:, -2]
+        assert ((rec.a == _first_argmax(S)) | (gap < 1e-12)).all(), rec.t
+        for j in range(k):
+            m = rec.a == j
+            if m.any():
+                s = X[m].sum(axis=0)
+                C[j] = s / np.linalg.norm(s)
