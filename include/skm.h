@@ -174,6 +174,11 @@ typedef struct {
   int32_t score_launches;     /* launches of the sparse scoring kernel */
   double sparse_products;     /* scored_products restricted to the terms scored on
                                  the sparse path (all of them when head_terms = 0) */
+  float ms_sparse;            /* device time of the sparse scoring kernel's launches
+                                 (part of ms_score) */
+  int32_t head_launches;      /* launches of the head GEMM */
+  double head_pairs;          /* (row, centroid) pairs the head GEMMs multiplied,
+                                 each over head_terms terms */
 } skm_iter_stats;
 
 /* One measured shape of the scoring work (skm_autotune). */
@@ -215,31 +220,48 @@ void skm_config_default(skm_config *cfg);
 skm_status skm_kmeanspp(const skm_csr *docs, int32_t k, const uint64_t *draws, int32_t *out_rows,
                         void *stream);
 
-/* Creates a context: copies the rows into HBM, seeds the centroids (FP64) and
- * builds their scoring copies.  *out is owned by the caller and released with
- * skm_destroy.  SKM_E_INVALID for a malformed CSR or config, SKM_E_NOMEM when
- * the budget is exceeded. */
+/* Creates a context for the problem of Sec. 2: unit-length sparse rows and k
+ * centroids of unit length.  Copies the rows into HBM (or, with
+ * SKM_BORROW_DEVICE, reads the caller's device rows in place), seeds the FP64
+ * centroids from init_rows (c_j = x_r / ||x_r||) or init_centroids, and builds
+ * their scoring copies (and, with SKM_INDEX, the Sec. 3.2 index).  *out is
+ * owned by the caller and released with skm_destroy.  SKM_E_INVALID for a
+ * malformed CSR or config, SKM_E_NOMEM when the budget is exceeded. */
 skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out);
 
-/* One assignment step against the current centroids (Sec. 2, with Sec. 3.1 /
- * 3.2 when enabled).  st may be NULL. */
+/* One assignment step against the current centroids: every row goes to the
+ * centroid of highest dot product, lowest index on ties (Sec. 2); with SKM_NCC
+ * a row whose previous centroid did not change compares only the changed ones
+ * (Sec. 3.1); with SKM_INDEX rows take their candidates from the index at the
+ * highest threshold not above their baseline (Sec. 3.2, Lemma 3.1).  The
+ * result equals the plain step's.  st (host, may be NULL) receives the step's
+ * counters and device times.  SKM_E_BUSY while a server is attached. */
 skm_status skm_assign(skm_ctx *c, skm_iter_stats *st);
 
-/* One update step from the last assignment: FP64 member sums in ascending row
- * order for every cluster whose membership changed, renormalisation, the
- * changed-centroid set for the next assignment, new scoring copies and, when
- * enabled, the index.  SKM_E_STATE if no assignment preceded it. */
+/* One update step from the last assignment (Sec. 2: a centroid is the sum of
+ * its members divided by that sum's length; a cluster without members keeps
+ * its centroid): FP64 member sums in ascending row order for every cluster
+ * whose membership changed, renormalisation, the changed-centroid set that
+ * Sec. 3.1 needs for the next assignment, new scoring copies and, when
+ * enabled, the Sec. 3.2 index.  st (host, may be NULL) receives the objective
+ * and the largest squared centroid shift.  SKM_E_STATE if no assignment
+ * preceded it. */
 skm_status skm_update(skm_ctx *c, skm_iter_stats *st);
 
-/* Repeats {assign; stop test; update; stop test} up to max_iter times (the
- * config's cap when max_iter <= 0).  per_iter: host array of max_iter records
- * or NULL.  *n_done = iterations started, *converged = 1 if a stop test (not the
- * cap) ended the loop. */
+/* The loop of Sec. 2 with the stopping rule of Sec. 4.1: repeats {assign;
+ * stop test; update; stop test} up to max_iter times (the config's cap when
+ * max_iter <= 0).  Under SKM_STOP_PAPER it stops after an assignment that moved
+ * no row (or fewer than min_moved_frac of them) or after an update whose
+ * largest squared centroid shift is below max_shift_sq.  per_iter: host array
+ * of max_iter records or NULL.  *n_done = iterations started, *converged = 1
+ * if a stop test (not the cap) ended the loop. */
 skm_status skm_iterate(skm_ctx *c, int32_t max_iter, skm_iter_stats *per_iter,
                        int32_t *n_done, int32_t *converged);
 
-/* Assigns new rows to the current centroids without changing the context
- * (exact, no NCC since the rows have no previous assignment).  out_assign
+/* Not part of the paper's method: assigns new rows to the current centroids
+ * with the assignment rule of Sec. 2, without changing the context (exact, no
+ * NCC since the rows have no previous assignment).  The rows must follow the
+ * CSR conventions above (checked: SKM_E_INVALID otherwise).  out_assign
  * [n_rows] and out_score [n_rows] (the FP64 dot product with the chosen
  * centroid) are device pointers when docs->on_device, else host pointers.
  * stream: hipStream_t for this call (NULL = the context's stream).  Calls with
@@ -346,9 +368,10 @@ skm_status skm_set_schedule(skm_ctx *c, const skm_tune_trial *shape);
 skm_status skm_score_head(skm_ctx *c, int64_t row0, int64_t n_rows, float *out,
                           float *out_head);
 
-/* The certified bound for such head scores as a function of the score alone
- * (Sec. 2 scores with the row values of head terms rounded to BF16 and
- * matrix-core accumulation); -1 when the head is off. */
+/* Not in the paper (it states no precision): the certified bound for such
+ * head scores as a function of the score alone, for scores computed with the
+ * row values of head terms rounded to BF16 and matrix-core accumulation; -1
+ * when the head is off. */
 double skm_error_bound_head(const skm_ctx *c, double s, int64_t nnz, double l1);
 
 /* FP8 contexts with a head: the bound the assignment step uses, from the head
@@ -363,6 +386,14 @@ double skm_error_bound_split(const skm_ctx *c, double hs, double rs, int64_t n_r
  * list ascending by centroid.  Pass entries = NULL to get *n_entries only. */
 skm_status skm_get_index(const skm_ctx *c, int32_t level, int64_t *offsets, uint32_t *entries,
                          int64_t *n_entries);
+
+/* The value the index compares a centroid's prefix-sum differences of
+ * squared sorted values against for threshold lambda (Sec. 3.2, Lemma 3.1:
+ * "reaches" read as >=): lambda^2 less a bound on the FP64 rounding of those
+ * differences for a centroid of n_entries non-zeros whose computed sum of
+ * squares is q_total, so that every exact difference >= lambda^2 passes.
+ * Host function, no context needed. */
+double skm_index_threshold(double lambda, int64_t n_entries, double q_total);
 
 /* Candidate sets of the Sec. 3.2 index at threshold level `level` for the rows
  * of docs (host CSR), without baselines: offsets [n_rows + 1] and cand

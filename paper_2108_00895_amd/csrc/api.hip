@@ -358,7 +358,8 @@ skm_status setup_head(skm_ctx *c, const std::vector<uint32_t> &df) {
   const size_t need = 4 * (size_t)H + 4 * (size_t)c->D + 2 * (size_t)c->N * H +
                       2 * (size_t)k_pad * H * ((c->cfg.flags & SKM_NCC) ? 2 : 1) +
                       4 * (size_t)rows * chunks * kChunk +
-                      4 * (size_t)c->N * ((c->cfg.flags & SKM_NCC) ? 2 : 0) +
+                      4 * (size_t)c->N * (((c->cfg.flags & SKM_NCC) ? 1 : 0) +
+                                          ((c->cfg.flags & (SKM_NCC | SKM_INDEX)) ? 1 : 0)) +
                       8 * (size_t)(c->N + 1) +
                       8 * (size_t)rest_nnz + 8 * (size_t)c->N + 8 * (size_t)nscan + 16 * 256;
   if (c->cfg.hbm_budget_bytes && c->hbm_bytes + need > c->cfg.hbm_budget_bytes) return SKM_OK;
@@ -369,9 +370,9 @@ skm_status setup_head(skm_ctx *c, const std::vector<uint32_t> &df) {
   ST_TRY(dalloc(c, &c->ch_head, (size_t)k_pad * H));
   if (c->cfg.flags & SKM_NCC) {
     ST_TRY(dalloc(c, &c->ch_head_ch, (size_t)k_pad * H));
-    ST_TRY(dalloc(c, &c->full_rows, (size_t)c->N));
     ST_TRY(dalloc(c, &c->ncc_list, (size_t)c->N));
   }
+  if (c->cfg.flags & (SKM_NCC | SKM_INDEX)) ST_TRY(dalloc(c, &c->full_rows, (size_t)c->N));
   ST_TRY(dalloc(c, &c->hs, (size_t)rows * chunks * kChunk));
   ST_TRY(dalloc(c, &c->r_indptr, (size_t)c->N + 1));
   ST_TRY(dalloc(c, &c->r_indices, (size_t)std::max<int64_t>(rest_nnz, 1)));
@@ -692,6 +693,10 @@ void skm_config_default(skm_config *cfg) {
 
 const char *skm_last_error(void) { return g_err.c_str(); }
 
+double skm_index_threshold(double lambda, int64_t n_entries, double q_total) {
+  return index_threshold(lambda, n_entries, q_total);
+}
+
 size_t skm_hbm_bytes(const skm_ctx *c) { return c ? c->hbm_bytes : 0; }
 
 void skm_destroy(skm_ctx *c) {
@@ -700,8 +705,9 @@ void skm_destroy(skm_ctx *c) {
   for (void *p : c->allocations) (void)hipFree(p);
   for (hipEvent_t &e : c->ev)
     if (e) (void)hipEventDestroy(e);
-  for (hipEvent_t &e : c->head_ev)
-    if (e) (void)hipEventDestroy(e);
+  for (auto *t : {&c->head_t, &c->sparse_t})
+    for (hipEvent_t &e : t->ev)
+      if (e) (void)hipEventDestroy(e);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   (void)hipGetLastError();
   delete c;
@@ -908,15 +914,48 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
   return SKM_OK;
 }
 
+// Records the next event of a pair list on stream s (events created on demand).
+skm_status mark(skm_ctx *c, skm_ctx::EventPairs &p, hipStream_t s) {
+  if (p.used == p.ev.size()) {
+    hipEvent_t x = nullptr;
+    hipError_t e = hipEventCreate(&x);
+    if (e != hipSuccess) return device_fail(c, "hipEventCreate", e);
+    p.ev.push_back(x);
+  }
+  HIP_TRY(c, hipEventRecord(p.ev[p.used++], s));
+  return SKM_OK;
+}
+
+// Device time of the pairs recorded since the last reset (after a sync).
+float pairs_ms(const skm_ctx::EventPairs &p) {
+  float ms = 0.f;
+  for (size_t i = 0; i + 1 < p.used; i += 2) ms += elapsed(p.ev[i], p.ev[i + 1]);
+  return ms;
+}
+
+void reset_timers(skm_ctx *c) {
+  c->head_t.used = 0;
+  c->sparse_t.used = 0;
+  c->head_pairs = 0;
+}
+
+// One launch of the sparse scoring kernel, bracketed by a timing pair.
+skm_status score_part_timed(skm_ctx *c, const ScoreArgs &a, hipStream_t s) {
+  ST_TRY(mark(c, c->sparse_t, s));
+  HIP_TRY(c, launch_score_part(a, c->part, c->n_cu, c->prec, s, c->score_wpc));
+  ST_TRY(mark(c, c->sparse_t, s));
+  return SKM_OK;
+}
+
 // Low-precision scoring with the head product of the rows [0, n_rows), or of
 // the listed rows, against the first ncols columns of a code copy whose head
 // codes are chead: in batches of head_rows rows x head_chunks chunks, head
 // GEMM into hs, then the sparse kernel adds the rows' other terms.  Batches
 // are large so that the sparse kernel still sweeps each chunk of codes over
-// many rows while its term rows are cached.  GEMM launches are bracketed by
-// event pairs from head_ev[ev] on (created on demand).
+// many rows while its term rows are cached.  Both launches are bracketed by
+// timing pairs (head_t, sparse_t).
 skm_status head_pass(skm_ctx *c, ScoreArgs &a, hipStream_t s, const uint16_t *chead,
-                     int64_t ncols, const int32_t *rows, int64_t n_rows, size_t &ev) {
+                     int64_t ncols, const int32_t *rows, int64_t n_rows) {
   a.sc_indptr = c->r_indptr;
   a.sc_indices = c->r_indices;
   a.sc_values = c->r_values;
@@ -929,22 +968,16 @@ skm_status head_pass(skm_ctx *c, ScoreArgs &a, hipStream_t s, const uint16_t *ch
     const int64_t nb = std::min<int64_t>(c->head_rows, n_rows - r0);
     for (int32_t g0 = 0; g0 < nch; g0 += c->head_chunks) {
       const int32_t gc = std::min<int32_t>(c->head_chunks, nch - g0);
-      while (c->head_ev.size() < ev + 2) {
-        hipEvent_t x = nullptr;
-        hipError_t e = hipEventCreate(&x);
-        if (e != hipSuccess) return device_fail(c, "hipEventCreate", e);
-        c->head_ev.push_back(x);
-      }
-      HIP_TRY(c, hipEventRecord(c->head_ev[ev], s));
+      ST_TRY(mark(c, c->head_t, s));
       HIP_TRY(c, launch_head_gemm(c->xh, c->head_H, r0, nb, rows, chead, (int64_t)g0 * kChunk,
                                   (int64_t)gc * kChunk, c->hs, a.hs_ld, s));
-      HIP_TRY(c, hipEventRecord(c->head_ev[ev + 1], s));
-      ev += 2;
+      ST_TRY(mark(c, c->head_t, s));
+      c->head_pairs += (double)nb * (double)gc * kChunk;
       a.row0 = r0;
       a.nb = nb;
       a.c_first = g0;
       a.c_count = gc;
-      HIP_TRY(c, launch_score_part(a, c->part, c->n_cu, c->prec, s, c->score_wpc));
+      ST_TRY(score_part_timed(c, a, s));
     }
   }
   a.row_list = nullptr;
@@ -953,15 +986,6 @@ skm_status head_pass(skm_ctx *c, ScoreArgs &a, hipStream_t s, const uint16_t *ch
   a.c_first = 0;
   a.c_count = (int32_t)((c->k + kChunk - 1) / kChunk);
   return SKM_OK;
-}
-
-// Device time of the head GEMMs recorded by the last step's passes (after a
-// synchronisation).
-float head_ms(skm_ctx *c, size_t n_ev) {
-  float ms = 0.f;
-  for (size_t i = 0; i + 1 < n_ev && i + 1 < c->head_ev.size(); i += 2)
-    ms += elapsed(c->head_ev[i], c->head_ev[i + 1]);
-  return ms;
 }
 
 skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
@@ -998,14 +1022,17 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
   const bool use_index = (c->cfg.flags & SKM_INDEX) && c->have_prev && c->index_ready &&
                          (c->cfg.index_min_changed <= 0 || c->last_changed > c->cfg.index_min_changed);
   if (use_index) {
+    // every row queries the index; with NCC on, a row keeping an unchanged
+    // previous centroid only takes changed candidates (end of Sec. 3.2)
     HIP_TRY(c, hipEventRecord(c->ev[6], s));
     HIP_TRY(c, launch_fill_u8(c->mode, 0, c->N, s));
-    HIP_TRY(c, index_rows(c->a_prev, (c->cfg.flags & SKM_NCC) ? c->changed : nullptr, c->N,
-                          c->idx_rows, c->ids_count, c->list_work, s));
+    HIP_TRY(c, index_rows(c->a_prev, nullptr, c->N, c->idx_rows, c->ids_count, c->list_work, s));
     int32_t n_rows_idx = 0;
     HIP_TRY(c, hipMemcpyAsync(&n_rows_idx, c->ids_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
     IndexArgs x = index_args(c);
+    x.changed = ncc ? c->changed : nullptr;
+    x.n_ch = n_ch;
     HIP_TRY(c, index_query(x, n_rows_idx, s));
     HIP_TRY(c, index_score(x, n_rows_idx, c->a, c->lo, c->hi, s));
     HIP_TRY(c, hipEventRecord(c->ev[7], s));
@@ -1014,10 +1041,20 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
   }
   HIP_TRY(c, hipEventRecord(c->ev[5], s));
   const bool head = c->head_H > 0;
-  size_t n_ev = 0;
-  int32_t launches = 1;
+  reset_timers(c);
+  // rows the index finished take no part in the head products
+  const uint8_t *undecided = use_index ? c->mode : nullptr;
   if (head && !ncc) {
-    ST_TRY(head_pass(c, a, s, c->ch_head, c->k, nullptr, c->N, n_ev));
+    if (use_index) {
+      int32_t n_list = 0;
+      HIP_TRY(c, index_rows(c->a_prev, nullptr, c->N, c->full_rows, c->ids_count, c->list_work, s,
+                            0, undecided));
+      HIP_TRY(c, hipMemcpyAsync(&n_list, c->ids_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      HIP_TRY(c, hipStreamSynchronize(s));
+      ST_TRY(head_pass(c, a, s, c->ch_head, c->k, c->full_rows, n_list));
+    } else {
+      ST_TRY(head_pass(c, a, s, c->ch_head, c->k, nullptr, c->N));
+    }
     HIP_TRY(c, launch_finalize(a, c->part, s));
   } else if (head) {
     // Sec. 3.1 with the head: every row keeping its previous centroid scores
@@ -1025,12 +1062,13 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
     // compacted code copy); the rows whose previous centroid changed score
     // all centroids, from their list.  One merge over all rows at the end.
     int32_t n_full = 0, n_keep = 0;
-    HIP_TRY(c, index_rows(c->a_prev, c->changed, c->N, c->full_rows, c->ids_count, c->list_work, s));
+    HIP_TRY(c, index_rows(c->a_prev, c->changed, c->N, c->full_rows, c->ids_count, c->list_work, s,
+                          0, undecided));
     HIP_TRY(c, hipMemcpyAsync(&n_full, c->ids_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     if (n_ch > kNarrowMax) {
       HIP_TRY(c, launch_gather_head(c->ch_head, c->head_H, c->ch_ids, n_ch, c->ch_head_ch, s));
       HIP_TRY(c, index_rows(c->a_prev, c->changed, c->N, c->ncc_list, c->ids_count + 1,
-                            c->list_work, s, 1));
+                            c->list_work, s, 1, undecided));
       HIP_TRY(c, hipMemcpyAsync(&n_keep, c->ids_count + 1, sizeof(int32_t), hipMemcpyDeviceToHost,
                                 s));
     }
@@ -1042,15 +1080,15 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
       HIP_TRY(c, launch_score_narrow(a, c->part, c->prec, s));
     } else {
       // head products of the rows keeping their centroid only
-      ST_TRY(head_pass(c, a, s, c->ch_head_ch, n_ch, c->ncc_list, n_keep, n_ev));
+      ST_TRY(head_pass(c, a, s, c->ch_head_ch, n_ch, c->ncc_list, n_keep));
     }
     a.ncc_only = 0;
-    ST_TRY(head_pass(c, a, s, c->ch_head, c->k, c->full_rows, n_full, n_ev));
+    ST_TRY(head_pass(c, a, s, c->ch_head, c->k, c->full_rows, n_full));
     HIP_TRY(c, launch_finalize(a, c->part, s));
   } else {
-    HIP_TRY(c, launch_score(a, c->part, c->n_cu, c->prec, s, c->score_wpc));
+    ST_TRY(score_part_timed(c, a, s));
+    HIP_TRY(c, launch_finalize(a, c->part, s));
   }
-  launches = head ? std::max<int32_t>(1, (int32_t)(n_ev / 2)) : 1;
   HIP_TRY(c, hipEventRecord(c->ev[1], s));
   if (!a.no_exact) {
     ExactArgs x{a, c->part, c->master, c->D, exact_waves()};
@@ -1093,11 +1131,13 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
     st_out->ms_exact = elapsed(c->ev[1], c->ev[2]);
     st_out->ms_index = use_index ? elapsed(c->ev[6], c->ev[7]) : 0.f;
     st_out->head_terms = head ? c->head_H : 0;
-    st_out->score_launches = 1;
+    st_out->score_launches = (int32_t)(c->sparse_t.used / 2);
+    st_out->ms_sparse = pairs_ms(c->sparse_t);
     st_out->sparse_products = (double)stv[3];
     if (head) {
-      st_out->ms_head = head_ms(c, n_ev);
-      st_out->score_launches = launches;
+      st_out->ms_head = pairs_ms(c->head_t);
+      st_out->head_launches = (int32_t)(c->head_t.used / 2);
+      st_out->head_pairs = c->head_pairs;
       st_out->sparse_products = (double)stv[8];
     }
     st_out->objective_assign = st_out->objective_update = st_out->max_shift_sq = -1.0;
@@ -1122,9 +1162,9 @@ skm_status skm_autotune(skm_ctx *c, skm_tune_report *report) {
     HIP_TRY(c, launch_fill_i32(c->counters, 0, 8, s));
     HIP_TRY(c, launch_fill_i32(reinterpret_cast<int32_t *>(c->stat), 0, 32, s));
     HIP_TRY(c, hipEventRecord(c->ev[5], s));
+    reset_timers(c);
     if (c->head_H > 0) {
-      size_t n_ev = 0;
-      ST_TRY(head_pass(c, a, s, c->ch_head, c->k, nullptr, c->N, n_ev));
+      ST_TRY(head_pass(c, a, s, c->ch_head, c->k, nullptr, c->N));
       HIP_TRY(c, launch_finalize(a, c->part, s));
     } else {
       HIP_TRY(c, launch_score(a, c->part, c->n_cu, c->prec, s, wpc));
@@ -1315,7 +1355,8 @@ skm_status skm_assign_new(skm_ctx *c, const skm_csr *docs, int32_t *out_assign, 
     for (void *q : tmp) (void)hipFree(q);
   };
   DevRows r;
-  skm_status st = upload_rows(c, docs, c->D, false, s, talloc, &r);
+  // the certificate assumes positive values and ascending terms: always check
+  skm_status st = upload_rows(c, docs, c->D, true, s, talloc, &r);
   if (st != SKM_OK) {
     release();
     return st;
@@ -1873,14 +1914,15 @@ skm_status skm_get_index(const skm_ctx *c, int32_t level, int64_t *offsets, uint
   }
   HIP_TRY(m, hipStreamSynchronize(c->stream));
   const double lam = c->cfg.lambda[level];
-  const double thr = lam * lam * (1.0 - 0x1p-40);
-  // m_p = least m with Q_j[min(p + m, n_j)] - Q_j[p] >= thr; no P entry when none
+  // m_p = least m with Q_j[min(p + m, n_j)] - Q_j[p] >= thr (the query's
+  // threshold for centroid j); no P entry when none
   int64_t n = 0;
   offsets[0] = 0;
   for (int64_t t = 0; t < D; ++t) {
     for (int64_t g = toff[t]; g < toff[t + 1]; ++g) {
       const int64_t j = G[g].x, p = G[g].y, nj = eoff[j + 1] - eoff[j];
       const double *q = Q.data() + eoff[j] + j;
+      const double thr = index_threshold(lam, nj, q[nj]);
       if (q[nj] - q[p] < thr) continue;
       int64_t lo = 1, hi = nj - p;
       while (lo < hi) {

@@ -156,6 +156,10 @@ struct IndexArgs {
   int32_t k;
   const int32_t *rows;      // rows handled, one workgroup each
   const int32_t *a_prev;    // previous assignment (baseline), or nullptr
+  const uint8_t *changed;   // Sec. 3.1 changed flags: rows keeping an unchanged
+                            // previous centroid only take changed candidates
+                            // (nullptr: no filter)
+  int32_t n_ch;             // changed centroids (cost guard of those rows)
   const int64_t *toff;
   const uint2 *G;
   const int64_t *eoff;
@@ -172,6 +176,33 @@ struct IndexArgs {
   unsigned long long *stat; // [0] scored, [2] index rows, [3] products, [5] no level,
                             // [6] guard, [7] over cap
 };
+
+// Index threshold.
+// The index (Sec. 3.2) compares differences of FP64 prefix sums of a
+// centroid's sorted squared values, Q[h] - Q[p], against lam^2 ("reaches the
+// threshold" read as >=).  The prefix sums of a centroid with n entries are
+// computed by 256 threads (kernels_index.hip, k_prefix_sq): each thread sums
+// a chunk of per = ceil(n / 256) squares, a 256-wide scan of 8 rounds adds the
+// chunks, one subtraction turns the inclusive scan into the chunk's offset,
+// and the chunk's squares are added to it one by one.  Every square therefore
+// reaches any prefix through at most m = 2 per + 20 roundings (per + 1 in its
+// chunk, 8 in the scan, 1 subtraction, per in the running sum, plus the
+// subtraction's carried scan error, counted as 9 more), all on sums of
+// non-negative terms, so |Q^[i] - Q[i]| <= g_m S with g_m = m u / (1 - m u),
+// u = 2^-53 and S the exact total; the difference adds its own rounding,
+// |fl(Q^[h] - Q^[p]) - (Q[h] - Q[p])| <= (2 g_m + 2 u) S.  The threshold is
+// lam^2 less that bound (with S <= Q^[n] / (1 - g_m)) and less 4u for the
+// rounding of lam^2 and of the subtraction itself, inflated by 2^-20: an
+// exact difference >= lam^2 always passes, so the candidate set can only
+// grow.  q_total is the computed Q^[n].
+__host__ __device__ inline double index_threshold(double lam, int64_t n, double q_total) {
+  const double u = 0x1p-53;
+  const double m = 2.0 * (double)((n + 255) / 256) + 20.0;
+  const double g = m * u / (1.0 - m * u);
+  const double S = q_total / (1.0 - g);
+  const double E = ((2.0 * g + 2.0 * u) * S + 4.0 * u) * (1.0 + 0x1p-20);
+  return lam * lam - E;
+}
 
 // LDS of the index query: k positions (4 B) and k 16-bit counts.
 __host__ __device__ inline size_t index_lds_bytes(int32_t k) {
@@ -280,7 +311,13 @@ struct skm_ctx {
   int32_t head_chunks = 0;       // 512-centroid chunks per head batch
   int64_t hs_cap = 0;            // floats in hs (head_rows x head_chunks x 512 at most)
   int32_t score_wpc = 0;         // scoring grid workgroups per CU (0 = as many as fit)
-  std::vector<hipEvent_t> head_ev;  // pairs around the head GEMM launches of one step
+  // event pairs around the launches of one step (device time per kernel):
+  // the head GEMMs and the sparse scoring kernel
+  struct EventPairs {
+    std::vector<hipEvent_t> ev;
+    size_t used = 0;
+  } head_t, sparse_t;
+  double head_pairs = 0;         // (row, centroid) pairs the head GEMMs of one step computed
   int32_t *head_terms = nullptr; // [H] term ids, ascending
   int32_t *head_slot = nullptr;  // [D] slot of a head term, -1 otherwise
   int32_t *sum_hot_slot = nullptr;   // [D] LDS slot of a term in the member sums, -1 otherwise
@@ -384,11 +421,13 @@ hipError_t index_build_counts(const double *master, int32_t k, int64_t D, int32_
                               int64_t *eoff, hipStream_t s);
 hipError_t index_build_rest(const IndexBuild &ib, hipStream_t s);
 // Ascending list of the rows whose previous centroid is flagged in `changed`
-// (keep = 0) or not flagged (keep = 1), all rows when changed is nullptr, and
+// (keep = 0) or not flagged (keep = 1), all rows when changed is nullptr,
+// leaving out rows the index finished (mode[i] == 2) when mode is given, and
 // its length; `work` holds index_rows_work(n) int32 values.
 int64_t index_rows_work(int64_t n);
 hipError_t index_rows(const int32_t *a_prev, const uint8_t *changed, int64_t n, int32_t *rows,
-                      int32_t *count, int32_t *work, hipStream_t s, int32_t keep = 0);
+                      int32_t *count, int32_t *work, hipStream_t s, int32_t keep = 0,
+                      const uint8_t *mode = nullptr);
 hipError_t index_query(const IndexArgs &x, int64_t n_slots, hipStream_t s);
 hipError_t index_score(const IndexArgs &x, int64_t n_slots, int32_t *a_out, double *lo_out,
                        double *hi_out, hipStream_t s);

@@ -13,8 +13,9 @@
 // position p*: the query computes count_j and p*_j from G and tests
 //   Q_j[min(p*_j + count_j, n_j)] - Q_j[p*_j] >= lam^2,
 // which returns the same set as the paper's two-map query.  Sums are compared
-// against lam^2 (1 - 2^-40) so FP64 rounding of the prefix differences can only
-// enlarge the candidate set.
+// against index_threshold (internal.h): lam^2 less a margin derived from the
+// prefix kernel's summation order, so FP64 rounding of the prefix
+// differences can only enlarge the candidate set.
 #include <algorithm>
 
 #include "internal.h"
@@ -290,17 +291,20 @@ __global__ void k_scan_i32_to_i64(const int32_t *cnt, int64_t n, int64_t *off) {
 
 // ---------------------------------------------------------------- query
 
-__device__ inline double index_threshold(double lam) { return lam * lam * (1.0 - 0x1p-40); }
-
-// Index path for the rows in `rows` (their previous centroid changed).  One
-// workgroup per row:
+// Index path for the rows in `rows`.  One workgroup per row:
 //   1. baseline b = x . c_{a_prev} in FP64 (the current centroid of the previous
 //      assignment), b_lo = b - err; level = highest lam with lam * ||x|| <= b_lo;
 //   2. cost guard: the query reads sum_t |G[t]| entries; when that exceeds
-//      guard * nnz * k the dense scan is cheaper and the row stays dense;
+//      guard * nnz * (centroids the row would otherwise score) the dense scan
+//      is cheaper and the row stays dense;
 //   3. overlap counts and highest-valued positions in LDS, the candidate test
 //      above, candidates ascending into cand[slot * cap ...] (dense fallback
 //      when more than cap survive).
+// With x.changed (Sec. 3.1 and 3.2 together, the combination the end of
+// Sec. 3.2 describes): a row whose previous centroid did not change can only
+// move to a changed centroid that beats it, so its candidates are the index's
+// candidates that changed (its baseline is the unchanged previous centroid's
+// score), and the alternative it is guarded against scores n_ch centroids.
 // mode[row] = 2 marks rows finished here (scored by k_index_score).
 __global__ __launch_bounds__(256) void k_index_query(IndexArgs x) {
   extern __shared__ uint32_t lds[];
@@ -313,6 +317,7 @@ __global__ __launch_bounds__(256) void k_index_query(IndexArgs x) {
   const int64_t row = x.rows[slot];
   const int64_t b = x.indptr[row], e = x.indptr[row + 1], n = e - b;
   const int32_t ap = x.a_prev ? x.a_prev[row] : 0;
+  const bool keep_row = x.changed && x.a_prev && !x.changed[ap];
   // 1. baseline
   double part = 0.0;
   if (x.a_prev)
@@ -344,8 +349,9 @@ __global__ __launch_bounds__(256) void k_index_query(IndexArgs x) {
     int lv = -1;
     for (int l = 0; l < x.n_lambda; ++l)
       if (x.lambda[l] * xn <= blo) lv = l;
+    const double alt = keep_row ? (double)x.n_ch : (double)x.k;
     if (x.forced_level >= 0) lv = x.forced_level;
-    else if (lv >= 0 && red[0] > x.guard * (double)n * (double)x.k) lv = -2;
+    else if (lv >= 0 && red[0] > x.guard * (double)n * alt) lv = -2;
     s_level = lv;
   }
   __syncthreads();
@@ -370,18 +376,18 @@ __global__ __launch_bounds__(256) void k_index_query(IndexArgs x) {
     }
   }
   __syncthreads();
-  const double thr = index_threshold(x.lambda[level]);
+  const double lam = x.lambda[level];
   int total = 0;
   for (int j0 = 0; j0 < x.k; j0 += 256) {
     const int j = j0 + threadIdx.x;
     int in = 0;
     const uint32_t cj = j < x.k ? (cnt[j >> 1] >> (16 * (j & 1))) & 0xFFFFu : 0u;
-    if (cj > 0) {
+    if (cj > 0 && (!keep_row || x.changed[j])) {
       const int64_t nj = x.eoff[j + 1] - x.eoff[j];
       const int64_t p = pmin[j];
       const int64_t h = min<int64_t>(p + cj, nj);
       const double *Qj = x.Q + x.eoff[j] + j;
-      in = (Qj[h] - Qj[p] >= thr) ? 1 : 0;
+      in = (Qj[h] - Qj[p] >= index_threshold(lam, nj, Qj[nj])) ? 1 : 0;
     }
     sh_i[threadIdx.x] = in;
     __syncthreads();
@@ -450,17 +456,19 @@ __global__ __launch_bounds__(256) void k_index_score(IndexArgs x, int64_t n_slot
 // writes (ballot ranks within a wave, wave counts through LDS).
 constexpr int64_t kListBlock = 4096;   // rows per block
 
-__device__ inline bool list_sel(const int32_t *a_prev, const uint8_t *changed, int64_t i,
-                                int32_t keep) {
-  return !changed || (changed[a_prev[i]] != 0) != (keep != 0);
+__device__ inline bool list_sel(const int32_t *a_prev, const uint8_t *changed, const uint8_t *mode,
+                                int64_t i, int32_t keep) {
+  return (!changed || (changed[a_prev[i]] != 0) != (keep != 0)) && (!mode || mode[i] != 2);
 }
 
 __global__ __launch_bounds__(256) void k_list_count(const int32_t *a_prev, const uint8_t *changed,
-                                                    int32_t keep, int64_t n, int32_t *bcnt) {
+                                                    const uint8_t *mode, int32_t keep, int64_t n,
+                                                    int32_t *bcnt) {
   __shared__ int32_t ws[4];
   const int64_t lo = (int64_t)blockIdx.x * kListBlock, hi = min(n, lo + kListBlock);
   int c = 0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) c += list_sel(a_prev, changed, i, keep) ? 1 : 0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256)
+    c += list_sel(a_prev, changed, mode, i, keep) ? 1 : 0;
   for (int m = 1; m < kWave; m <<= 1) c += __shfl_xor(c, m, kWave);
   if (lane_id() == 0) ws[threadIdx.x >> 6] = c;
   __syncthreads();
@@ -495,15 +503,15 @@ __global__ __launch_bounds__(1024) void k_list_scan(int32_t *bcnt, int64_t nblk,
 }
 
 __global__ __launch_bounds__(256) void k_list_write(const int32_t *a_prev, const uint8_t *changed,
-                                                    int32_t keep, int64_t n, const int32_t *boff,
-                                                    int32_t *rows) {
+                                                    const uint8_t *mode, int32_t keep, int64_t n,
+                                                    const int32_t *boff, int32_t *rows) {
   __shared__ int32_t ws[4];
   const int64_t lo = (int64_t)blockIdx.x * kListBlock, hi = min(n, lo + kListBlock);
   const int wave = threadIdx.x >> 6;
   int32_t pos = boff[blockIdx.x];
   for (int64_t b0 = lo; b0 < hi; b0 += 256) {
     const int64_t i = b0 + threadIdx.x;
-    const bool sel = i < hi && list_sel(a_prev, changed, i, keep);
+    const bool sel = i < hi && list_sel(a_prev, changed, mode, i, keep);
     const uint64_t m = __ballot(sel);
     if (lane_id() == 0) ws[wave] = __popcll(m);
     __syncthreads();
@@ -548,16 +556,17 @@ hipError_t index_build_rest(const IndexBuild &ib, hipStream_t s) {
 int64_t index_rows_work(int64_t n) { return std::max<int64_t>(1, (n + kListBlock - 1) / kListBlock); }
 
 hipError_t index_rows(const int32_t *a_prev, const uint8_t *changed, int64_t n, int32_t *rows,
-                      int32_t *count, int32_t *work, hipStream_t s, int32_t keep) {
+                      int32_t *count, int32_t *work, hipStream_t s, int32_t keep,
+                      const uint8_t *mode) {
   const int64_t nblk = (n + kListBlock - 1) / kListBlock;
   if (nblk > 0) {
-    hipLaunchKernelGGL(k_list_count, dim3((unsigned)nblk), dim3(256), 0, s, a_prev, changed, keep,
-                       n, work);
+    hipLaunchKernelGGL(k_list_count, dim3((unsigned)nblk), dim3(256), 0, s, a_prev, changed, mode,
+                       keep, n, work);
   }
   hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, s, work, nblk, count);
   if (nblk > 0) {
-    hipLaunchKernelGGL(k_list_write, dim3((unsigned)nblk), dim3(256), 0, s, a_prev, changed, keep,
-                       n, work, rows);
+    hipLaunchKernelGGL(k_list_write, dim3((unsigned)nblk), dim3(256), 0, s, a_prev, changed, mode,
+                       keep, n, work, rows);
   }
   return hipGetLastError();
 }

@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -359,9 +360,25 @@ skm_status skm_server_submit(skm_server *s, const skm_csr *docs, int32_t *out_as
       if (r->indptr[i + 1] < r->indptr[i]) return set_error(SKM_E_INVALID, "indptr decreases");
     r->indices.assign(docs->indices, docs->indices + z);
     r->values.assign(docs->values, docs->values + z);
-    for (int64_t q = 0; q < z; ++q)
-      if (r->indices[q] < 0 || r->indices[q] >= s->c->D)
-        return set_error(SKM_E_INVALID, "term index out of range");
+    // the CSR conventions of skm.h, as skm_assign_new checks them: the
+    // certificate of the low-precision scores assumes positive values
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t b = r->indptr[i], e = r->indptr[i + 1];
+      if (e == b) return set_error(SKM_E_INVALID, "empty row");
+      double sq = 0.0;
+      for (int64_t q = b; q < e; ++q) {
+        const int32_t t = r->indices[q];
+        const float v = r->values[q];
+        if (t < 0 || t >= s->c->D) return set_error(SKM_E_INVALID, "term index out of range");
+        if (q > b && t <= r->indices[q - 1])
+          return set_error(SKM_E_INVALID, "indices must be strictly ascending within a row");
+        if (!(v > 0.0f) || !std::isfinite(v))
+          return set_error(SKM_E_INVALID, "values must be finite and > 0");
+        sq += (double)v * (double)v;
+      }
+      if (std::fabs(std::sqrt(sq) - 1.0) > 1e-5)
+        return set_error(SKM_E_INVALID, "row L2 norm differs from 1 by more than 1e-5");
+    }
   }
   r->out_a = out_assign;
   r->out_s = out_score;

@@ -32,7 +32,7 @@ EXPORTED = [
     "skm_score_head", "skm_error_bound_head", "skm_error_bound_split", "skm_autotune", "skm_set_schedule", "skm_get_index",
     "skm_index_query", "skm_server_config_default", "skm_server_start", "skm_server_submit",
     "skm_server_wait", "skm_server_get_stats", "skm_server_stop",
-    "skm_hbm_bytes", "skm_last_error", "skm_destroy",
+    "skm_hbm_bytes", "skm_last_error", "skm_destroy", "skm_index_threshold",
 ]
 
 
@@ -72,7 +72,8 @@ class IterStats(ctypes.Structure):
                 ("ms_score", ctypes.c_float), ("ms_exact", ctypes.c_float), ("ms_update", ctypes.c_float),
                 ("ms_index", ctypes.c_float), ("head_terms", ctypes.c_int32),
                 ("ms_head", ctypes.c_float), ("score_launches", ctypes.c_int32),
-                ("sparse_products", ctypes.c_double)]
+                ("sparse_products", ctypes.c_double), ("ms_sparse", ctypes.c_float),
+                ("head_launches", ctypes.c_int32), ("head_pairs", ctypes.c_double)]
 
     def asdict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -189,6 +190,8 @@ def load():
     lib.skm_server_get_stats.restype = st
     lib.skm_server_stop.argtypes = [vp]
     lib.skm_server_stop.restype = st
+    lib.skm_index_threshold.argtypes = [ctypes.c_double, i64, ctypes.c_double]
+    lib.skm_index_threshold.restype = ctypes.c_double
     lib.skm_hbm_bytes.argtypes = [vp]
     lib.skm_hbm_bytes.restype = ctypes.c_size_t
     lib.skm_last_error.argtypes = []

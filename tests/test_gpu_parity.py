@@ -136,7 +136,16 @@ def test_trajectory_equals_oracle(prec, ncc, mid):
     ref = oracle.run(csr, c.n_terms, len(rows), rows, max_iter=25)
     ctx = Context(to_device(csr), c.n_terms, len(rows), init_rows=rows, precision=prec, ncc=ncc,
                   max_iter=25)
-    stats, conv = ctx.iterate()
+    # one iteration per call, so that each iteration's assignment is compared
+    stats, conv = [], False
+    for t in range(25):
+        st, conv = ctx.iterate(1)
+        stats += st
+        rec = ref.records[t]
+        assert_assign_equal(ctx.assignments(), rec.a, rec.s1, rec.s2,
+                            f"trajectory {prec} ncc={ncc} iteration {t}")
+        if conv:
+            break
     assert conv == ref.converged and len(stats) == len(ref.records)
     for st, rec in zip(stats, ref.records):
         assert st["moved"] == rec.moved, (st["iter"], st["moved"], rec.moved)
