@@ -56,7 +56,9 @@ typedef enum {
   SKM_E_STATE = 4,       /* call made in the wrong order */
   SKM_E_UNSUPPORTED = 5, /* valid but outside what this build supports */
   SKM_E_BUSY = 6,        /* a request server is attached to the context */
-  SKM_E_TIMEOUT = 7      /* skm_server_wait ran out of time (request still queued) */
+  SKM_E_TIMEOUT = 7,     /* skm_server_wait ran out of time (request still queued) */
+  SKM_E_CANCELLED = 8    /* the request or job was cancelled (skm_server_cancel, or
+                            a job still pending when its server stopped) */
 } skm_status;
 
 typedef enum {
@@ -352,6 +354,36 @@ int32_t skm_head_terms(const skm_ctx *c);
  * trial. */
 skm_status skm_autotune(skm_ctx *c, skm_tune_report *report);
 
+/* Measured thresholds of the Sec. 3.2 index (skm_tune_lambda). */
+typedef struct {
+  int32_t n_sample;           /* rows measured */
+  int32_t n_grid;             /* thresholds measured */
+  double grid[20];            /* ascending */
+  double qualify[20];         /* share of the rows whose baseline reaches grid[g] ||x|| */
+  double mean_candidates[20]; /* centroids those rows would score at grid[g] */
+  int32_t n_before, n_after;
+  double before[8], after[8]; /* the set in use before and after the call */
+  double cost_before;         /* centroids scored per sampled row with `before` */
+  double cost_after;          /* the same with `after` */
+  int32_t applied;            /* 1 if the context now uses `after` */
+} skm_lambda_report;
+
+/* Tunes the index's threshold set (Sec. 3.2 builds several thresholds and uses
+ * the highest one a row's baseline reaches; Sec. 4.1 fixes {0.1, 0.25, 0.4,
+ * 0.6}) for this workload: on n_sample rows spread over the corpus, against
+ * the current centroids and with each row's previous centroid as baseline, it
+ * measures for every threshold of a fixed grid (0.05 .. 0.8, plus the set in
+ * use) which rows qualify and how many candidates the index returns, and
+ * takes the set of at most four grid values that minimises the centroids
+ * scored per row (a qualifying row scores its candidates plus its baseline
+ * centroid; another row scores every centroid, or with SKM_NCC the changed
+ * ones when its previous centroid did not change), when it is at least 5 %
+ * cheaper than the set in use.  Results are unaffected (every set gives the
+ * exact assignment).  Needs SKM_INDEX, a completed skm_update and no pending
+ * assignment (SKM_E_STATE).  report (host, may be NULL) receives the
+ * measurements. */
+skm_status skm_tune_lambda(skm_ctx *c, int32_t n_sample, skm_lambda_report *report);
+
 /* Applies a shape found by skm_autotune (for instance on another context of
  * the same workload): workgroups_per_cu, and head_chunks x head_rows when the
  * context scores a head (they must fit its head-score buffer, else
@@ -403,63 +435,128 @@ skm_status skm_index_query(skm_ctx *c, const skm_csr *docs, int32_t level, int64
                            int32_t *cand, int64_t cap);
 
 /* ---------------------------------------------------------------- serving
- * A request server keeps one context's centroids resident and answers
- * assign-new-rows requests (the exact assignment of skm_assign_new) from many
- * client threads.  A worker thread batches queued requests continuously: as
- * soon as one of its n_slots batch slots (each with its own stream and
- * preallocated device buffers) is free, it packs the requests at the head of
- * the queue that fit the slot's row and non-zero capacity and launches them;
- * requests that arrive while batches run join the next free slot, so
- * transfers and kernels of different batches overlap.  Admission is by memory:
- * the slots are sized up front and their total is held within
- * hbm_budget_bytes.  While a server is attached, calls that change the
- * context (assign, update, iterate, set_centroids) return SKM_E_BUSY. */
+ * Not part of the paper's method.  A request server keeps one context's
+ * centroids resident and answers assign-new-rows requests (the exact
+ * assignment of skm_assign_new) from many client threads, and runs small
+ * clustering jobs beside them.
+ *
+ * Requests: a worker thread batches queued requests continuously: as soon as
+ * one of its n_slots batch slots (each with its own stream and preallocated
+ * device buffers) is free, it packs the requests at the head of the queue that
+ * fit the slot's free rows and non-zeros and launches them; requests that
+ * arrive while batches run join the next free slot, so transfers and kernels
+ * of different batches overlap.  The slots are sized up front and their total
+ * is held within hbm_budget_bytes.
+ *
+ * Jobs: a clustering job (its own rows and configuration) is admitted by
+ * memory: it waits until the budget left by the slots and the running jobs
+ * holds skm_context_bytes for it (and fewer than max_jobs run); a job thread
+ * then runs the admitted jobs round robin, one iteration (assign, stop test,
+ * update, stop test, as skm_iterate) per turn, on their own streams, beside the
+ * request batches.  Each job's result is that of skm_init + skm_iterate on the
+ * same rows and configuration.
+ *
+ * Answers are written into the caller's buffers by skm_server_wait when it
+ * returns SKM_OK, never later.  While a server is attached, calls that change
+ * the context (assign, update, iterate, set_centroids) return SKM_E_BUSY. */
 typedef struct skm_server skm_server;
 
 typedef struct {
   int32_t n_slots;          /* batches in flight, default 4 */
   int32_t slot_rows;        /* rows per batch, default 16384 */
   int64_t slot_nnz;         /* non-zeros per batch, default 4 Mi */
-  size_t hbm_budget_bytes;  /* device memory cap for the slots; n_slots shrinks to fit (0 = none) */
+  size_t hbm_budget_bytes;  /* device memory cap for the slots and the jobs; n_slots
+                               shrinks to fit (0 = none) */
   int32_t max_wait_us;      /* a partly filled batch waits at most this long for more rows
                                when no batch is running, default 100 */
   int32_t use_graphs;       /* 1 = each slot replays its compute pipeline as one captured
                                HIP graph (default); 0 = launch the kernels one by one */
+  int32_t max_jobs;         /* clustering jobs run at once, default 2 (0 = none admitted) */
 } skm_server_config;
 
 typedef struct {
   int64_t requests_done;
   int64_t rows_done;
   int64_t batches;
-  double p50_ms, p99_ms, mean_ms, max_ms;  /* latency, submit to outputs written */
+  double p50_ms, p99_ms, mean_ms, max_ms;  /* request latency, submit to answers ready */
   double rows_per_s;        /* rows_done over first submit .. last completion */
   int32_t slots;            /* slots actually allocated */
   int32_t max_queue_depth;
-  size_t hbm_bytes;         /* device memory held by the server */
+  size_t hbm_bytes;         /* device memory held by the slots and the admitted jobs */
+  int64_t jobs_done;        /* jobs finished (any status) */
+  int64_t job_iterations;   /* iterations run by all jobs */
+  int32_t jobs_running;
+  int32_t jobs_queued;
 } skm_server_stats;
 
+/* Result counters of a clustering job. */
+typedef struct {
+  int32_t iterations;       /* iterations started, as skm_iterate's n_done */
+  int32_t converged;        /* 1 if a stop test ended the job, 0 if max_iter did */
+  double objective;         /* J_U = sum_j ||S_j|| after the last update */
+  size_t hbm_bytes;         /* device memory the job was admitted with */
+} skm_job_info;
+
 void skm_server_config_default(skm_server_config *cfg);
+
+/* Device memory skm_init and the following iterations may need for these rows
+ * and this configuration, in bytes (an upper bound, used to admit jobs); 0 for
+ * invalid arguments. */
+size_t skm_context_bytes(const skm_csr *docs, const skm_config *cfg);
 
 /* Starts a server on context c (which must outlive it). */
 skm_status skm_server_start(skm_ctx *c, const skm_server_config *cfg, skm_server **out);
 
-/* Queues the rows of docs (host CSR, copied before return) for assignment;
- * out_assign [n_rows] and out_score [n_rows] are host buffers the server fills
- * before skm_server_wait(ticket) returns SKM_OK.  Thread-safe.  SKM_E_INVALID
- * for a malformed CSR or one larger than a slot. */
+/* Queues the rows of docs (host CSR, copied and checked against the CSR
+ * conventions above before return) for assignment; out_assign [n_rows] and
+ * out_score [n_rows] are host buffers that skm_server_wait(ticket) fills when
+ * it returns SKM_OK.  Thread-safe.  SKM_E_INVALID for a malformed CSR or one
+ * larger than a slot. */
 skm_status skm_server_submit(skm_server *s, const skm_csr *docs, int32_t *out_assign,
                              double *out_score, int64_t *ticket);
 
-/* Blocks until the request is answered (SKM_OK, or the request's error), or
- * timeout_s seconds pass (SKM_E_TIMEOUT; the request stays queued; timeout_s
- * < 0 waits forever).  Each ticket is waited for at most once successfully. */
+/* Queues a clustering job: docs (host CSR, copied before return; checked when
+ * the job starts, as by skm_init) clustered with cfg (k, precision, flags,
+ * stop rule, max_iter >= 1, init_rows required and copied; stream and budget
+ * are ignored).  When skm_server_wait(ticket) returns SKM_OK it has written
+ * the final assignment to out_assign [n_rows] (host), the FP64 centroids to
+ * out_centroids [k * n_cols] (host, may be NULL) and the counters to *out_info
+ * (may be NULL).  SKM_E_NOMEM when the job alone needs more memory than the
+ * budget leaves beside the slots; errors of the job itself (SKM_E_INVALID for
+ * its rows, SKM_E_NOMEM, SKM_E_DEVICE) are returned by the wait. */
+skm_status skm_server_submit_job(skm_server *s, const skm_csr *docs, const skm_config *cfg,
+                                 int32_t *out_assign, double *out_centroids,
+                                 skm_job_info *out_info, int64_t *ticket);
+
+/* Blocks until the request or job is answered (SKM_OK, or its error), or
+ * timeout_s seconds pass (SKM_E_TIMEOUT; it stays queued and nothing is
+ * written; timeout_s < 0 waits forever).  Each ticket is collected at most
+ * once; SKM_E_CANCELLED for a cancelled one. */
 skm_status skm_server_wait(skm_server *s, int64_t ticket, double timeout_s);
+
+/* Cancels a request or job: a queued one is dropped, a batch in flight
+ * finishes but its answers are discarded, a running job ends at its next
+ * turn; nothing is written to the caller's buffers, and the request's rows
+ * and answers are released.  A waiter (present or later) gets
+ * SKM_E_CANCELLED, which collects the ticket.  SKM_E_INVALID for an unknown
+ * ticket. */
+skm_status skm_server_cancel(skm_server *s, int64_t ticket);
 
 /* Latency and throughput counters since start. */
 skm_status skm_server_get_stats(skm_server *s, skm_server_stats *out);
 
-/* Answers every queued request, stops the worker and frees the server. */
+/* Answers every queued request, ends queued and running jobs as cancelled,
+ * stops the worker threads, waits until every thread inside skm_server_wait
+ * has returned and frees the server. */
 skm_status skm_server_stop(skm_server *s);
+
+/* Test aid for the error path (not part of the method): after n_calls more
+ * checked HIP calls of this context (0 = the next one) one reports a launch
+ * failure instead of being made, so the call that reaches it returns
+ * SKM_E_DEVICE with the context poisoned, as after a real device error; no
+ * fault happens on the device.  n_calls < 0 disarms it.  SKM_E_DEVICE on a
+ * context that is already poisoned. */
+skm_status skm_debug_fail_after(skm_ctx *c, int32_t n_calls);
 
 /* Device memory the context currently holds, in bytes. */
 size_t skm_hbm_bytes(const skm_ctx *c);

@@ -21,6 +21,11 @@ def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
+def host_sources():
+    """Plain C++ (no HIP) parts of the library: built with the host compiler."""
+    return sorted(glob.glob(os.path.join(HERE, "csrc", "*.cpp")))
+
+
 def build(verbose: bool = False, jobs: int = 4) -> str:
     """Compile every csrc/*.hip into one shared library with hipcc."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -39,9 +44,17 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
             p, c = procs.pop(0)
             if p.wait() != 0:
                 raise RuntimeError("hipcc failed: " + " ".join(c))
+    for src in host_sources():
+        obj = os.path.join(HERE, "_build", os.path.basename(src) + ".o")
+        cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-c", "-I", os.path.join(ROOT, "include"),
+               src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((subprocess.Popen(cmd), cmd))
+        objs.append(obj)
     for p, c in procs:
         if p.wait() != 0:
-            raise RuntimeError("hipcc failed: " + " ".join(c))
+            raise RuntimeError("compile failed: " + " ".join(c))
     link = [hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(link), flush=True)

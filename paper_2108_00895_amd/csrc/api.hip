@@ -6,10 +6,12 @@
 #include <cstdio>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <string>
 #include <vector>
 
+#include "host_checks.h"
 #include "internal.h"
 
 using namespace skm;
@@ -29,10 +31,17 @@ skm_status device_fail(skm_ctx *c, const char *what, hipError_t e) {
   return SKM_E_DEVICE;
 }
 
-#define HIP_TRY(c, expr)                                   \
-  do {                                                     \
-    hipError_t _e = (expr);                                \
-    if (_e != hipSuccess) return device_fail(c, #expr, _e); \
+// Test aid (skm_debug_fail_after): the armed call reports a launch failure
+// instead of being made.
+bool injected(skm_ctx *c) {
+  if (!c || c->fail_after < 0) return false;
+  return c->fail_after-- == 0;
+}
+
+#define HIP_TRY(c, expr)                                                        \
+  do {                                                                          \
+    hipError_t _e = injected(c) ? hipErrorLaunchFailure : (expr);               \
+    if (_e != hipSuccess) return device_fail(c, #expr, _e);                     \
   } while (0)
 
 #define ST_TRY(expr)                \
@@ -90,24 +99,19 @@ double abs_coefficient(int prec) {
   return 0x1p-120;
 }
 
+// The shape and pointers of a CSR description (host_checks.cpp).
 skm_status check_csr_header(const skm_csr *d, int64_t max_cols) {
-  if (!d) return fail(SKM_E_INVALID, "docs is NULL");
-  if (d->n_rows < 0 || d->n_cols < 1 || d->nnz < 0) return fail(SKM_E_INVALID, "bad CSR sizes");
-  if (max_cols > 0 && d->n_cols > max_cols)
-    return fail(SKM_E_INVALID, "n_cols exceeds the context's vocabulary");
-  if (d->n_cols > INT32_MAX || d->n_rows > INT32_MAX)
-    return fail(SKM_E_UNSUPPORTED, "n_rows and n_cols must fit int32");
-  if (d->n_rows > 0 && (!d->indptr || (d->nnz > 0 && (!d->indices || !d->values))))
-    return fail(SKM_E_INVALID, "CSR array pointer is NULL");
+  std::string why;
+  bool unsupported = false;
+  if (!host::csr_header_ok(d, max_cols, &unsupported, &why))
+    return fail(unsupported ? SKM_E_UNSUPPORTED : SKM_E_INVALID, why);
   return SKM_OK;
 }
 
 // indptr must be checked before any kernel walks rows.
 skm_status check_indptr(const int64_t *ip, int64_t n, int64_t nnz) {
-  if (ip[0] != 0) return fail(SKM_E_INVALID, "indptr[0] != 0");
-  for (int64_t i = 0; i < n; ++i)
-    if (ip[i + 1] < ip[i]) return fail(SKM_E_INVALID, "indptr decreases at row " + std::to_string(i));
-  if (ip[n] != nnz) return fail(SKM_E_INVALID, "indptr[n_rows] != nnz");
+  std::string why;
+  if (!host::indptr_ok(ip, n, nnz, &why)) return fail(SKM_E_INVALID, why);
   return SKM_OK;
 }
 
@@ -693,6 +697,12 @@ void skm_config_default(skm_config *cfg) {
 
 const char *skm_last_error(void) { return g_err.c_str(); }
 
+skm_status skm_debug_fail_after(skm_ctx *c, int32_t n_calls) {
+  ST_TRY(check_ctx(c));
+  c->fail_after = n_calls < 0 ? -1 : n_calls;
+  return SKM_OK;
+}
+
 double skm_index_threshold(double lambda, int64_t n_entries, double q_total) {
   return index_threshold(lambda, n_entries, q_total);
 }
@@ -711,6 +721,50 @@ void skm_destroy(skm_ctx *c) {
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   (void)hipGetLastError();
   delete c;
+}
+
+size_t skm_context_bytes(const skm_csr *docs, const skm_config *cfg) {
+  if (!docs || !cfg || docs->n_rows < 1 || docs->n_cols < 1 || docs->nnz < 0 || cfg->k < 1 ||
+      cfg->precision < SKM_FP32 || cfg->precision > SKM_FP8_E4M3)
+    return 0;
+  // An upper bound of what skm_init allocates and what the iterations may
+  // grow to, for the allocations of this file (each rounded up to 256 bytes).
+  const double N = (double)docs->n_rows, D = (double)docs->n_cols, Z = (double)docs->nnz;
+  const double k = (double)cfg->k;
+  const double ld = (double)round_up(cfg->k, kChunk), nch = ld / kChunk;
+  const double esize = (double)code_bytes(cfg->precision);
+  const bool ncc = cfg->flags & SKM_NCC, index = cfg->flags & SKM_INDEX;
+  const bool borrow = (cfg->flags & SKM_BORROW_DEVICE) && docs->on_device;
+  double b = 0;
+  if (!borrow) b += 8 * (N + 1) + 8 * Z;                      // rows
+  b += 16 * N;                                                 // norms
+  b += 16 * k * D + D * ld * esize * (ncc ? 2 : 1);            // master, sums, codes
+  b += 4 * ld + 48 * k + 8 * (k + 1);                          // scales, per-centroid state
+  b += N * (4 + 4 + 8 * 4 + 4 + 8 + 1 + 4);                    // per-row state, members
+  b += 4 * std::ceil(N / 8192) * k + sizeof(Partial) * nch * N;  // histogram, partials
+  if (!(cfg->flags & SKM_DENSE_ONLY))                          // list offsets, flags, counts
+    b += (ncc ? 2 : 1) * nch * (9 * D + 16);
+  if (index) {
+    const double nb = std::ceil(k / 64);
+    b += N * (1 + 4 + 4 * 128 + 4 + 4) + 12 * (k + 1) + D * (12 * nb + 12);
+  }
+  // non-zeros of all centroids are at most min(Z, k D): index entries (40 B
+  // each, 25 % headroom) and code lists (8 B each, per-chunk stride headroom)
+  const double cnz = std::min(Z, k * D);
+  if (index) b += 1.25 * 40 * cnz;
+  if (!(cfg->flags & SKM_DENSE_ONLY)) b += (ncc ? 2 : 1) * 1.25 * 8 * std::min(cnz, nch * 512 * D);
+  // the dense head (BF16 / FP8): at most head_max_terms terms
+  if (cfg->precision != SKM_FP32 && cfg->head_max_terms >= 64) {
+    const double H = std::min<double>((double)(cfg->head_max_terms / 64) * 64, D);
+    const double rows = std::min<double>((double)(1 << 20), (double)round_up(docs->n_rows, 256));
+    b += 4 * H + 8 * D + 2 * N * H + 2 * ld * H * (ncc ? 2 : 1) + 4 * rows * 4 * kChunk +
+         4 * N * 2 + 8 * (N + 1) + 8 * Z + 16 * N;
+  }
+  // the update's workspace: the bound skm_init allocates without a budget
+  b += 8 * D * (double)std::min<int64_t>(std::max<int64_t>(1, kWorkBytes / (8 * docs->n_cols)),
+                                         docs->n_rows / (kSegRows / 2) + 2);
+  b += 8 * 1024 * 1024 + 64 * 256.0;   // task lists, small buffers, rounding
+  return (size_t)b;
 }
 
 skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
@@ -1145,6 +1199,142 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
   return SKM_OK;
 }
 
+skm_status skm_tune_lambda(skm_ctx *c, int32_t n_sample, skm_lambda_report *report) {
+  ST_TRY(check_ctx_writable(c));
+  if (!(c->cfg.flags & SKM_INDEX)) return fail(SKM_E_STATE, "skm_tune_lambda needs SKM_INDEX");
+  if (!c->have_prev || c->assigned)
+    return fail(SKM_E_STATE, "skm_tune_lambda needs a completed update and no pending assignment");
+  if (n_sample < 1) return fail(SKM_E_INVALID, "n_sample must be >= 1");
+  hipStream_t s = c->stream;
+  if (!c->index_ready) ST_TRY(build_index(c));
+  const int64_t n = std::min<int64_t>(n_sample, c->N);
+  // rows spread evenly over the corpus (deterministic)
+  std::vector<int32_t> rows(n);
+  for (int64_t q = 0; q < n; ++q) rows[q] = (int32_t)((q * c->N) / n);
+  HIP_TRY(c, hipMemcpyAsync(c->idx_rows, rows.data(), 4 * n, hipMemcpyHostToDevice, s));
+  // the thresholds measured: a fixed grid and the set in use
+  std::vector<double> grid = {0.05, 0.1, 0.15, 0.2, 0.25, 0.3, 0.35, 0.4, 0.5, 0.6, 0.7, 0.8};
+  for (int l = 0; l < c->cfg.n_lambda; ++l)
+    if (std::find(grid.begin(), grid.end(), c->cfg.lambda[l]) == grid.end())
+      grid.push_back(c->cfg.lambda[l]);
+  std::sort(grid.begin(), grid.end());
+  if (grid.size() > 20) grid.resize(20);
+  const int32_t G = (int32_t)grid.size();
+  // rows keeping an unchanged previous centroid only take changed candidates
+  // (and would otherwise score the n_ch changed centroids)
+  const bool ncc = (c->cfg.flags & SKM_NCC) != 0;
+  std::vector<uint8_t> ch(c->k);
+  std::vector<int32_t> ap(c->N);
+  std::vector<double> xn(c->N), blo(n);
+  HIP_TRY(c, hipMemcpyAsync(ch.data(), c->changed, c->k, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipMemcpyAsync(ap.data(), c->a_prev, 4 * c->N, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipMemcpyAsync(xn.data(), c->xl2, 8 * c->N, hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  int32_t n_ch = 0;
+  for (uint8_t f : ch) n_ch += f != 0;
+  std::vector<double> dense(n), ratio(n);
+  std::vector<int32_t> cand((size_t)G * n);
+  for (int32_t g = 0; g < G; ++g) {
+    IndexArgs x = index_args(c);
+    x.lambda[0] = grid[g];
+    x.n_lambda = 1;
+    x.forced_level = 0;
+    x.guard = 1e300;
+    x.mode = nullptr;
+    x.changed = ncc ? c->changed : nullptr;
+    x.n_ch = n_ch;
+    x.base_out = g == 0 ? c->flag_L : nullptr;
+    HIP_TRY(c, launch_fill_i32(reinterpret_cast<int32_t *>(c->stat), 0, 32, s));
+    HIP_TRY(c, index_query(x, n, s));
+    HIP_TRY(c, hipMemcpyAsync(cand.data() + (size_t)g * n, c->idx_ncand, 4 * n,
+                              hipMemcpyDeviceToHost, s));
+    if (g == 0) HIP_TRY(c, hipMemcpyAsync(blo.data(), c->flag_L, 8 * n, hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(c, hipStreamSynchronize(s));
+  for (int64_t q = 0; q < n; ++q) {
+    const int32_t r = rows[q];
+    const bool keep = ncc && !ch[ap[r]];
+    dense[q] = keep ? (double)n_ch + 1.0 : (double)c->k;
+    ratio[q] = blo[q] / (xn[r] * (1.0 + 0x1p-40));   // qualifies for lam <= ratio
+  }
+  // cost of a row at grid level g: candidates + 1 when its baseline reaches
+  // the threshold (and the list fits), else the dense scan
+  auto row_cost = [&](int64_t q, int32_t g) {
+    if (!(grid[g] <= ratio[q])) return dense[q];
+    const int32_t nc = cand[(size_t)g * n + q];
+    return nc >= 0 ? (double)nc + 1.0 : dense[q];
+  };
+  auto set_cost = [&](const std::vector<int32_t> &set) {   // set ascending
+    double sum = 0.0;
+    for (int64_t q = 0; q < n; ++q) {
+      double cst = dense[q];
+      for (int32_t i = (int32_t)set.size() - 1; i >= 0; --i)
+        if (grid[set[i]] <= ratio[q]) {
+          cst = row_cost(q, set[i]);
+          break;
+        }
+      sum += cst;
+    }
+    return sum / (double)n;
+  };
+  std::vector<int32_t> cur;
+  for (int l = 0; l < c->cfg.n_lambda; ++l)
+    cur.push_back((int32_t)(std::find(grid.begin(), grid.end(), c->cfg.lambda[l]) - grid.begin()));
+  std::sort(cur.begin(), cur.end());
+  const double cost_before = set_cost(cur);
+  // every set of at most four grid thresholds (the paper uses four levels)
+  std::vector<int32_t> best = cur, set;
+  double best_cost = cost_before;
+  std::function<void(int32_t)> walk = [&](int32_t from) {
+    if (!set.empty()) {
+      const double cst = set_cost(set);
+      if (cst < best_cost - 1e-12 || (cst <= best_cost + 1e-12 && set.size() < best.size())) {
+        best_cost = cst;
+        best = set;
+      }
+    }
+    if (set.size() == 4) return;
+    for (int32_t g = from; g < G; ++g) {
+      set.push_back(g);
+      walk(g + 1);
+      set.pop_back();
+    }
+  };
+  walk(0);
+  // a new set is taken only when it is clearly cheaper (5 %)
+  const bool apply = best != cur && best_cost < 0.95 * cost_before;
+  if (report) {
+    std::memset(report, 0, sizeof(*report));
+    report->n_sample = (int32_t)n;
+    report->n_grid = G;
+    for (int32_t g = 0; g < G; ++g) {
+      int64_t nq = 0;
+      double sc = 0.0;
+      for (int64_t q = 0; q < n; ++q)
+        if (grid[g] <= ratio[q]) {
+          ++nq;
+          sc += row_cost(q, g);
+        }
+      report->grid[g] = grid[g];
+      report->qualify[g] = (double)nq / (double)n;
+      report->mean_candidates[g] = nq ? sc / (double)nq : 0.0;
+    }
+    report->n_before = (int32_t)cur.size();
+    for (size_t i = 0; i < cur.size(); ++i) report->before[i] = grid[cur[i]];
+    report->cost_before = cost_before;
+    const std::vector<int32_t> &fin = apply ? best : cur;
+    report->n_after = (int32_t)fin.size();
+    for (size_t i = 0; i < fin.size(); ++i) report->after[i] = grid[fin[i]];
+    report->cost_after = apply ? best_cost : cost_before;
+    report->applied = apply ? 1 : 0;
+  }
+  if (apply) {
+    c->cfg.n_lambda = (int32_t)best.size();
+    for (size_t i = 0; i < best.size(); ++i) c->cfg.lambda[i] = grid[best[i]];
+  }
+  return SKM_OK;
+}
+
 skm_status skm_autotune(skm_ctx *c, skm_tune_report *report) {
   ST_TRY(check_ctx_writable(c));
   if (c->assigned)
@@ -1473,27 +1663,11 @@ skm_status skm_set_centroids(skm_ctx *c, const double *centroids) {
   return SKM_OK;
 }
 
-// Checkpoint file: header, then a_prev int32[N], lo_prev and hi_prev double[N],
-// changed uint8[k], and the centroids of the clusters with no members (their
-// ids int32[n_empty], row offsets int64[n_empty + 1], terms int32[] and values
-// double[] of their non-zeros).  Every other centroid is the normalised sum of
-// its members in ascending row order, so it is recomputed on load and comes
-// out bit for bit the same.
-struct CkptHeader {
-  char magic[8];
-  uint32_t version;
-  int32_t k;
-  int64_t n_rows, n_cols, nnz;
-  int32_t precision;
-  uint32_t flags;
-  int32_t iter, last_changed;
-  int64_t last_moved;
-  int32_t idx_skip, idx_backoff;
-  int32_t index_ready, reserved;
-  double full_frac;
-  int64_t n_empty, empty_nnz;
-};
-constexpr char kCkptMagic[8] = {'S', 'K', 'M', 'C', 'K', 'P', 'T', '1'};
+// Checkpoint (file format and checks in host_checks.cpp): the assignment that
+// made the centroids, the certified intervals, the changed flags, the run's
+// counters and the centroids of the clusters with no members.  Every other
+// centroid is the normalised sum of its members in ascending row order, so it
+// is recomputed on load and comes out bit for bit the same.
 constexpr uint32_t kStateFlags = SKM_NCC | SKM_INDEX | SKM_NO_EXACT | SKM_DENSE_ONLY;
 
 skm_status skm_save(const skm_ctx *cc, const char *path) {
@@ -1520,64 +1694,41 @@ skm_status skm_save(const skm_ctx *cc, const char *path) {
     if (j < 0 || j >= k) return fail(SKM_E_STATE, "the assignment holds an invalid centroid id");
     count[j] += 1;
   }
-  std::vector<int32_t> e_ids, e_terms;
-  std::vector<int64_t> e_off(1, 0);
-  std::vector<double> e_vals, row(D);
+  host::Checkpoint ck;
+  std::vector<double> row(D);
+  ck.e_off.push_back(0);
   for (int32_t j = 0; j < k; ++j) {
     if (count[j] != 0) continue;
     HIP_TRY(c, hipMemcpyAsync(row.data(), c->master + (size_t)j * D, sizeof(double) * D,
                               hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
-    e_ids.push_back(j);
+    ck.e_ids.push_back(j);
     for (int64_t t = 0; t < D; ++t)
       if (row[t] != 0.0) {
-        e_terms.push_back((int32_t)t);
-        e_vals.push_back(row[t]);
+        ck.e_terms.push_back((int32_t)t);
+        ck.e_vals.push_back(row[t]);
       }
-    e_off.push_back((int64_t)e_terms.size());
+    ck.e_off.push_back((int64_t)ck.e_terms.size());
   }
-  CkptHeader h{};
-  std::memcpy(h.magic, kCkptMagic, 8);
-  h.version = 1;
-  h.k = k;
-  h.n_rows = N;
-  h.n_cols = D;
-  h.nnz = c->Z;
-  h.precision = c->prec;
-  h.flags = c->cfg.flags & kStateFlags;
-  h.iter = c->iter;
-  h.last_changed = c->last_changed;
-  h.last_moved = c->last_moved;
-  h.idx_skip = c->assigned ? c->idx_skip_pre : c->idx_skip;
-  h.idx_backoff = c->assigned ? c->idx_backoff_pre : c->idx_backoff;
-  h.index_ready = c->index_ready ? 1 : 0;
-  h.full_frac = c->full_frac;
-  h.n_empty = (int64_t)e_ids.size();
-  h.empty_nnz = (int64_t)e_terms.size();
-  // written beside the target and renamed over it, so that a crash while
-  // writing leaves the previous checkpoint intact
-  const std::string tmp = std::string(path) + ".tmp";
-  FILE *f = std::fopen(tmp.c_str(), "wb");
-  if (!f) return fail(SKM_E_INVALID, "cannot open " + tmp + " for writing");
-  bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1;
-  auto put = [&](const void *p, size_t bytes) {
-    if (ok && bytes) ok = std::fwrite(p, 1, bytes, f) == bytes;
-  };
-  put(a.data(), sizeof(int32_t) * N);
-  put(lo.data(), sizeof(double) * N);
-  put(hi.data(), sizeof(double) * N);
-  put(ch.data(), (size_t)k);
-  put(e_ids.data(), sizeof(int32_t) * e_ids.size());
-  put(e_off.data(), sizeof(int64_t) * e_off.size());
-  put(e_terms.data(), sizeof(int32_t) * e_terms.size());
-  put(e_vals.data(), sizeof(double) * e_vals.size());
-  ok = (std::fflush(f) == 0) && ok;
-  ok = (std::fclose(f) == 0) && ok;
-  if (ok) ok = std::rename(tmp.c_str(), path) == 0;
-  if (!ok) {
-    (void)std::remove(tmp.c_str());
-    return fail(SKM_E_INVALID, std::string("writing ") + path + " failed");
-  }
+  ck.k = k;
+  ck.n_rows = N;
+  ck.n_cols = D;
+  ck.nnz = c->Z;
+  ck.precision = c->prec;
+  ck.flags = c->cfg.flags & kStateFlags;
+  ck.iter = c->iter;
+  ck.last_changed = c->last_changed;
+  ck.last_moved = c->last_moved;
+  ck.idx_skip = c->assigned ? c->idx_skip_pre : c->idx_skip;
+  ck.idx_backoff = c->assigned ? c->idx_backoff_pre : c->idx_backoff;
+  ck.index_ready = c->index_ready ? 1 : 0;
+  ck.full_frac = c->full_frac;
+  ck.a = std::move(a);
+  ck.lo = std::move(lo);
+  ck.hi = std::move(hi);
+  ck.changed = std::move(ch);
+  std::string why;
+  if (!host::write_checkpoint(path, ck, &why)) return fail(SKM_E_INVALID, why);
   return SKM_OK;
 }
 
@@ -1587,58 +1738,20 @@ skm_status skm_load(skm_ctx **out, const skm_csr *docs, const char *path, const 
   if (!cfg || !path) return fail(SKM_E_INVALID, "cfg or path is NULL");
   ST_TRY(check_csr_header(docs, 0));
   // the whole file is read and checked before any device work
-  FILE *f = std::fopen(path, "rb");
-  if (!f) return fail(SKM_E_INVALID, std::string("cannot open ") + path);
-  CkptHeader h{};
-  bool ok = std::fread(&h, sizeof(h), 1, f) == 1;
-  auto bad = [&](const char *why) {
-    std::fclose(f);
-    return fail(SKM_E_INVALID, std::string("checkpoint ") + path + ": " + why);
-  };
-  if (!ok || std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != 1)
-    return bad("not a checkpoint of this library");
-  if (h.n_rows != docs->n_rows || h.n_cols != docs->n_cols || h.nnz != docs->nnz)
-    return bad("taken on rows of another shape");
+  host::Checkpoint h;
+  std::string why;
+  if (!host::read_checkpoint(path, docs->n_rows, docs->n_cols, docs->nnz, &h, &why))
+    return fail(SKM_E_INVALID, why);
   if (h.k != cfg->k || h.precision != cfg->precision || h.flags != (cfg->flags & kStateFlags))
-    return bad("k, precision or flags differ from cfg");
+    return fail(SKM_E_INVALID, std::string("checkpoint ") + path +
+                                   ": k, precision or flags differ from cfg");
   const int64_t N = h.n_rows, D = h.n_cols;
   const int32_t k = h.k;
-  if (k < 1 || k > N || h.n_empty < 0 || h.n_empty > k || h.empty_nnz < 0 ||
-      h.empty_nnz > h.n_empty * D || h.iter < 1)
-    return bad("inconsistent header");
-  std::vector<int32_t> a(N), e_ids(h.n_empty), e_terms(h.empty_nnz);
-  std::vector<double> lo(N), hi(N), e_vals(h.empty_nnz);
-  std::vector<uint8_t> ch(k);
-  std::vector<int64_t> e_off(h.n_empty + 1);
-  auto get = [&](void *p, size_t bytes) {
-    if (ok && bytes) ok = std::fread(p, 1, bytes, f) == bytes;
-  };
-  get(a.data(), sizeof(int32_t) * N);
-  get(lo.data(), sizeof(double) * N);
-  get(hi.data(), sizeof(double) * N);
-  get(ch.data(), (size_t)k);
-  get(e_ids.data(), sizeof(int32_t) * e_ids.size());
-  get(e_off.data(), sizeof(int64_t) * e_off.size());
-  get(e_terms.data(), sizeof(int32_t) * e_terms.size());
-  get(e_vals.data(), sizeof(double) * e_vals.size());
-  if (!ok) return bad("truncated");
-  std::vector<int64_t> count(k, 0);
-  for (int32_t j : a) {
-    if (j < 0 || j >= k) return bad("assignment out of range");
-    count[j] += 1;
-  }
-  if (e_off[0] != 0 || e_off[h.n_empty] != h.empty_nnz) return bad("bad row offsets");
-  for (int64_t q = 0; q < h.n_empty; ++q) {
-    if (e_ids[q] < 0 || e_ids[q] >= k || count[e_ids[q]] != 0 || (q > 0 && e_ids[q] <= e_ids[q - 1]))
-      return bad("bad empty-cluster ids");
-    if (e_off[q + 1] < e_off[q]) return bad("bad row offsets");
-    for (int64_t p = e_off[q]; p < e_off[q + 1]; ++p)
-      if (e_terms[p] < 0 || e_terms[p] >= D) return bad("term out of range");
-  }
-  int64_t n_empty_a = 0;
-  for (int32_t j = 0; j < k; ++j) n_empty_a += count[j] == 0;
-  if (n_empty_a != h.n_empty) return bad("empty clusters do not match the assignment");
-  std::fclose(f);
+  const int64_t n_empty = (int64_t)h.e_ids.size();
+  const std::vector<int32_t> &a = h.a, &e_ids = h.e_ids, &e_terms = h.e_terms;
+  const std::vector<double> &lo = h.lo, &hi = h.hi, &e_vals = h.e_vals;
+  const std::vector<int64_t> &e_off = h.e_off;
+  const std::vector<uint8_t> &ch = h.changed;
 
   // A context seeded from stand-in rows; then the saved state replaces it.
   std::vector<int32_t> rows(k);
@@ -1657,7 +1770,7 @@ skm_status skm_load(skm_ctx **out, const skm_csr *docs, const char *path, const 
   {
     // clusters without members keep the saved centroid through the update
     std::vector<double> row(D);
-    for (int64_t q = 0; q < h.n_empty && e == hipSuccess; ++q) {
+    for (int64_t q = 0; q < n_empty && e == hipSuccess; ++q) {
       std::fill(row.begin(), row.end(), 0.0);
       for (int64_t p = e_off[q]; p < e_off[q + 1]; ++p) row[e_terms[p]] = e_vals[p];
       e = hipMemcpyAsync(c->master + (size_t)e_ids[q] * D, row.data(), sizeof(double) * D,

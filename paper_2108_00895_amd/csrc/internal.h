@@ -175,6 +175,7 @@ struct IndexArgs {
   uint8_t *mode;            // [n_rows] 2 = finished by the index path, or nullptr
   unsigned long long *stat; // [0] scored, [2] index rows, [3] products, [5] no level,
                             // [6] guard, [7] over cap
+  double *base_out;         // [slots] certified lower bound of the baseline, or nullptr
 };
 
 // Index threshold.
@@ -216,6 +217,7 @@ struct skm_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   bool poisoned = false;
+  int32_t fail_after = -1;     // test aid: checked HIP calls left before an injected failure
   skm_config cfg{};
 
   int64_t N = 0, D = 0, Z = 0;

@@ -331,6 +331,7 @@ __global__ __launch_bounds__(256) void k_index_query(IndexArgs x) {
   }
   const double base = red[0];
   const double blo = base - exact_err(n, base);
+  if (x.base_out && threadIdx.x == 0) x.base_out[slot] = blo;
   const double xn = x.xl2[row] * (1.0 + 0x1p-40);
   // 2. cost guard
   double gsum = 0.0;

@@ -1,18 +1,32 @@
 // Request server of libskm: continuous batching of assign-new-rows requests
-// against one resident context (declared in include/skm.h).
+// against one resident context, and small clustering jobs run beside them
+// (declared in include/skm.h).
 //
-// Client threads submit host CSR requests; a worker thread owns n_slots batch
-// slots, each a HIP stream with pinned staging buffers and device buffers
-// sized for slot_rows rows and slot_nnz non-zeros.  Whenever a slot is free
-// the worker packs the requests at the head of the queue into it (in arrival
-// order, as many as fit), copies them in on the slot's stream, runs the exact
-// new-row pipeline (low-precision scoring + certification + FP64 tier + FP64
-// scores) and copies the answers back; a completed slot's answers are
-// scattered to the requests' output buffers and their waiters are woken.
-// Different slots run on different streams, so batches overlap on the device.
-// With use_graphs, each slot's compute pipeline is captured once into a HIP
-// graph sized for the slot's capacity; a batch then costs the copies plus one
-// graph launch, and the kernels read the batch's row count from the device.
+// Requests.  Client threads submit host CSR requests; a worker thread owns
+// n_slots batch slots, each a HIP stream with pinned staging buffers and device
+// buffers sized for slot_rows rows and slot_nnz non-zeros.  Whenever a slot is
+// free the worker packs the requests at the head of the queue into it (in
+// arrival order, as many as fit its rows and non-zeros), copies them in on the
+// slot's stream, runs the exact new-row pipeline (low-precision scoring +
+// certification + FP64 tier + FP64 scores) and copies the answers back; a
+// completed slot's answers are stored in the requests themselves and their
+// waiters are woken.  Different slots run on different streams, so batches
+// overlap on the device.  With use_graphs, each slot's compute pipeline is
+// captured once into a HIP graph sized for the slot's capacity; a batch then
+// costs the copies plus one graph launch, and the kernels read the batch's row
+// count from the device.
+//
+// Jobs.  A clustering job (rows, a configuration) waits in a queue until the
+// server's memory budget, less the slots, holds its estimated device memory
+// (skm_context_bytes); a job thread then builds its context (own stream) and
+// runs the admitted jobs round robin, one iteration (assign, stop test, update,
+// stop test) per turn, so that jobs of any size share the device with each
+// other and with the request batches.  A finished job's assignment (and, when
+// asked for, its FP64 centroids) is copied into the job and its context freed,
+// which admits the next job.
+//
+// Answers are copied into the caller's buffers by skm_server_wait itself, so
+// nothing is written to them after a time-out or a cancellation.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,6 +42,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "host_checks.h"
 #include "internal.h"
 
 using namespace skm;
@@ -38,14 +53,28 @@ using Clock = std::chrono::steady_clock;
 
 struct Request {
   int64_t id = 0;
-  int64_t n_rows = 0, nnz = 0;
+  bool is_job = false;
+  int64_t n_rows = 0, nnz = 0, n_cols = 0;
   std::vector<int64_t> indptr;
   std::vector<int32_t> indices;
   std::vector<float> values;
+  // caller's buffers, written only by skm_server_wait
   int32_t *out_a = nullptr;
-  double *out_s = nullptr;
+  double *out_s = nullptr;           // request: scores; job: centroids (may be null)
+  skm_job_info *out_info = nullptr;  // job only (may be null)
+  // answers, owned by the request until the wait copies them out
+  std::vector<int32_t> res_a;
+  std::vector<double> res_s;
+  // job
+  skm_config cfg{};
+  std::vector<int32_t> init_rows;
+  size_t need = 0;                   // admitted device bytes
+  skm_ctx *ctx = nullptr;
+  skm_job_info info{};
   Clock::time_point t_submit;
   bool done = false;
+  bool cancelled = false;
+  int waiters = 0;
   skm_status status = SKM_OK;
 };
 
@@ -77,6 +106,17 @@ size_t slot_device_bytes(const skm_ctx *c, int64_t rows, int64_t nnz) {
          (size_t)nch * rows * sizeof(Partial) + (size_t)rows * (4 + 8 + 8 + 4 + 8 + 1 + 8) + 32 + 128;
 }
 
+// The CSR conventions of skm.h on a host copy (host_checks.cpp; the
+// certificate of the low-precision scores assumes positive values and
+// ascending terms).
+skm_status check_host_rows(const std::vector<int64_t> &ip, const std::vector<int32_t> &ix,
+                           const std::vector<float> &v, int64_t n, int64_t z, int64_t D) {
+  std::string why;
+  if (!host::rows_ok(ip.data(), ix.data(), v.data(), n, z, D, &why))
+    return set_error(SKM_E_INVALID, why);
+  return SKM_OK;
+}
+
 }  // namespace
 
 struct skm_server {
@@ -84,17 +124,22 @@ struct skm_server {
   skm_server_config cfg{};
   std::vector<Slot> slots;
   std::vector<void *> dev_allocs, host_allocs;
-  size_t hbm = 0;
+  size_t hbm = 0;                    // slots
+  size_t job_hbm = 0;                // admitted jobs
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
+  std::condition_variable cv_work, cv_done, cv_jobs;
   std::deque<std::shared_ptr<Request>> queue;
+  std::deque<std::shared_ptr<Request>> job_queue;
+  std::vector<std::shared_ptr<Request>> running;
   std::unordered_map<int64_t, std::shared_ptr<Request>> live;
   int64_t next_id = 1;
   bool stopping = false;
-  std::thread worker;
+  int n_waiters = 0;                 // threads inside skm_server_wait
+  std::thread worker, job_worker;
   // statistics
   std::vector<double> lat_ms;
   int64_t rows_done = 0, batches = 0;
+  int64_t jobs_done = 0, job_iterations = 0;
   int32_t max_depth = 0;
   bool any_submit = false;
   Clock::time_point t_first, t_last;
@@ -221,14 +266,27 @@ void launch_slot(skm_server *s, Slot &sl) {
   s->batches += 1;
 }
 
-// Scatters a finished slot's answers to its requests (lock held).
+// A cancelled request keeps only its ticket (for the wait that reports the
+// cancellation): its rows and answers are released.
+void drop_payload(skm_server *, const std::shared_ptr<Request> &r) {
+  if (!r->cancelled) return;
+  std::vector<int64_t>().swap(r->indptr);
+  std::vector<int32_t>().swap(r->indices);
+  std::vector<float>().swap(r->values);
+  std::vector<int32_t>().swap(r->res_a);
+  std::vector<double>().swap(r->res_s);
+}
+
+// Stores a finished slot's answers in its requests (lock held).
 void finish_slot(skm_server *s, Slot &sl, hipError_t e) {
   int64_t row = 0;
   const auto now = Clock::now();
   for (auto &r : sl.reqs) {
-    if (e == hipSuccess) {
-      std::memcpy(r->out_a, sl.h_a + row, sizeof(int32_t) * r->n_rows);
-      std::memcpy(r->out_s, sl.h_s + row, sizeof(double) * r->n_rows);
+    if (r->cancelled) {
+      r->status = SKM_E_CANCELLED;   // answers dropped
+    } else if (e == hipSuccess) {
+      r->res_a.assign(sl.h_a + row, sl.h_a + row + r->n_rows);
+      r->res_s.assign(sl.h_s + row, sl.h_s + row + r->n_rows);
       r->status = SKM_OK;
     } else {
       r->status = SKM_E_DEVICE;
@@ -237,6 +295,7 @@ void finish_slot(skm_server *s, Slot &sl, hipError_t e) {
     r->done = true;
     s->lat_ms.push_back(std::chrono::duration<double, std::milli>(now - r->t_submit).count());
     s->rows_done += r->n_rows;
+    drop_payload(s, r);
   }
   s->t_last = now;
   sl.reqs.clear();
@@ -291,6 +350,148 @@ void worker_loop(skm_server *s) {
   }
 }
 
+// Device bytes the server may give to jobs (0 = no limit).
+size_t job_budget(const skm_server *s) {
+  if (!s->cfg.hbm_budget_bytes) return 0;
+  return s->cfg.hbm_budget_bytes > s->hbm ? s->cfg.hbm_budget_bytes - s->hbm : 1;
+}
+
+// A finished job's answers, fetched without the server lock (they wait on
+// the job's own stream); the context is freed.
+struct JobResult {
+  skm_status status = SKM_OK;
+  std::vector<int32_t> a;
+  std::vector<double> c;
+};
+
+JobResult collect_job(skm_ctx *ctx, int64_t n_rows, int64_t k, int64_t n_cols, bool centroids,
+                      skm_status st, bool fetch) {
+  JobResult out;
+  out.status = st;
+  if (ctx && fetch && st == SKM_OK) {
+    out.a.resize(n_rows);
+    out.status = skm_get_assignments(ctx, out.a.data(), 0);
+    if (out.status == SKM_OK && centroids) {
+      out.c.resize((size_t)k * (size_t)n_cols);
+      out.status = skm_get_centroids(ctx, out.c.data(), 0);
+    }
+  }
+  if (ctx) skm_destroy(ctx);
+  return out;
+}
+
+// Completes a job (lock held): its answers or status into the request, its
+// memory returned to the budget, its waiters woken.  The context must be
+// freed already (r->ctx null), except when the server stops.
+void finish_job(skm_server *s, const std::shared_ptr<Request> &r, JobResult res) {
+  if (r->ctx) {
+    skm_destroy(r->ctx);
+    r->ctx = nullptr;
+  }
+  s->job_hbm -= r->need;
+  r->info.hbm_bytes = r->need;
+  r->need = 0;
+  if (r->cancelled) {
+    r->status = SKM_E_CANCELLED;
+  } else {
+    r->status = res.status;
+    r->res_a = std::move(res.a);
+    r->res_s = std::move(res.c);
+  }
+  r->done = true;
+  s->jobs_done += 1;
+  s->running.erase(std::remove(s->running.begin(), s->running.end(), r), s->running.end());
+  drop_payload(s, r);
+  s->cv_done.notify_all();
+  s->cv_jobs.notify_all();
+}
+
+JobResult status_only(skm_status st) {
+  JobResult r;
+  r.status = st;
+  return r;
+}
+
+void job_loop(skm_server *s) {
+  (void)hipSetDevice(s->c->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  size_t turn = 0;
+  for (;;) {
+    // admission: jobs in arrival order while their memory fits the budget
+    while (!s->job_queue.empty() && !s->stopping &&
+           (int32_t)s->running.size() < s->cfg.max_jobs) {
+      auto r = s->job_queue.front();
+      const size_t cap = job_budget(s);
+      if (cap && s->job_hbm + r->need > cap) break;
+      s->job_queue.pop_front();
+      s->job_hbm += r->need;
+      s->running.push_back(r);
+      // the context is built outside the lock (it copies the rows to HBM)
+      skm_csr d{r->n_rows, r->n_cols, r->nnz, r->indptr.data(), r->indices.data(),
+                r->values.data(), 0};
+      skm_config cf = r->cfg;
+      cf.init_rows = r->init_rows.data();
+      cf.init_centroids = nullptr;
+      cf.stream = nullptr;
+      cf.hbm_budget_bytes = 0;
+      lk.unlock();
+      skm_ctx *ctx = nullptr;
+      const skm_status st = skm_init(&d, &cf, &ctx);
+      lk.lock();
+      r->ctx = ctx;
+      if (st != SKM_OK) finish_job(s, r, status_only(st));
+    }
+    if (s->stopping) {
+      // queued and running jobs end as cancelled
+      while (!s->job_queue.empty()) {
+        auto r = s->job_queue.front();
+        s->job_queue.pop_front();
+        r->cancelled = true;
+        s->job_hbm += r->need;   // finish_job gives it back
+        finish_job(s, r, status_only(SKM_E_CANCELLED));
+      }
+      while (!s->running.empty()) {
+        auto r = s->running.front();
+        r->cancelled = true;
+        finish_job(s, r, status_only(SKM_E_CANCELLED));
+      }
+      break;
+    }
+    if (s->running.empty()) {
+      s->cv_jobs.wait(lk);
+      continue;
+    }
+    // one iteration of the next running job, outside the lock
+    auto r = s->running[turn++ % s->running.size()];
+    const bool cancel = r->cancelled;
+    skm_ctx *ctx = r->ctx;
+    r->ctx = nullptr;   // owned by this turn; collect_job frees it when the job ends
+    lk.unlock();
+    skm_iter_stats st{};
+    int32_t n = 0, conv = 0;
+    skm_status rc = SKM_OK;
+    bool end = cancel;
+    if (!cancel) {
+      rc = skm_iterate(ctx, 1, &st, &n, &conv);
+      end = rc != SKM_OK || conv || r->info.iterations + n >= r->cfg.max_iter;
+    }
+    JobResult res;
+    if (end) {
+      res = collect_job(ctx, r->n_rows, r->cfg.k, r->n_cols, r->out_s != nullptr, rc, !cancel);
+      ctx = nullptr;
+    }
+    lk.lock();
+    r->ctx = ctx;
+    s->job_iterations += n;
+    r->info.iterations += n;
+    if (st.objective_update >= 0.0) r->info.objective = st.objective_update;
+    if (end) {
+      r->info.converged = conv;
+      finish_job(s, r, std::move(res));
+    }
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -303,6 +504,7 @@ void skm_server_config_default(skm_server_config *cfg) {
   cfg->hbm_budget_bytes = 0;
   cfg->max_wait_us = 100;
   cfg->use_graphs = 1;
+  cfg->max_jobs = 2;
 }
 
 skm_status skm_server_start(skm_ctx *c, const skm_server_config *cfg, skm_server **out) {
@@ -313,7 +515,8 @@ skm_status skm_server_start(skm_ctx *c, const skm_server_config *cfg, skm_server
   skm_server_config cf;
   skm_server_config_default(&cf);
   if (cfg) cf = *cfg;
-  if (cf.n_slots < 1 || cf.slot_rows < 1 || cf.slot_nnz < 1 || cf.max_wait_us < 0)
+  if (cf.n_slots < 1 || cf.slot_rows < 1 || cf.slot_nnz < 1 || cf.max_wait_us < 0 ||
+      cf.max_jobs < 0)
     return set_error(SKM_E_INVALID, "bad server config");
   const size_t per = slot_device_bytes(c, cf.slot_rows, cf.slot_nnz);
   if (cf.hbm_budget_bytes) {
@@ -335,6 +538,7 @@ skm_status skm_server_start(skm_ctx *c, const skm_server_config *cfg, skm_server
   }
   c->server_attached = 1;
   s->worker = std::thread(worker_loop, s);
+  s->job_worker = std::thread(job_loop, s);
   *out = s;
   return SKM_OK;
 }
@@ -355,30 +559,10 @@ skm_status skm_server_submit(skm_server *s, const skm_csr *docs, int32_t *out_as
   r->nnz = z;
   if (n > 0) {
     r->indptr.assign(docs->indptr, docs->indptr + n + 1);
-    if (r->indptr[0] != 0 || r->indptr[n] != z) return set_error(SKM_E_INVALID, "bad indptr");
-    for (int64_t i = 0; i < n; ++i)
-      if (r->indptr[i + 1] < r->indptr[i]) return set_error(SKM_E_INVALID, "indptr decreases");
     r->indices.assign(docs->indices, docs->indices + z);
     r->values.assign(docs->values, docs->values + z);
-    // the CSR conventions of skm.h, as skm_assign_new checks them: the
-    // certificate of the low-precision scores assumes positive values
-    for (int64_t i = 0; i < n; ++i) {
-      const int64_t b = r->indptr[i], e = r->indptr[i + 1];
-      if (e == b) return set_error(SKM_E_INVALID, "empty row");
-      double sq = 0.0;
-      for (int64_t q = b; q < e; ++q) {
-        const int32_t t = r->indices[q];
-        const float v = r->values[q];
-        if (t < 0 || t >= s->c->D) return set_error(SKM_E_INVALID, "term index out of range");
-        if (q > b && t <= r->indices[q - 1])
-          return set_error(SKM_E_INVALID, "indices must be strictly ascending within a row");
-        if (!(v > 0.0f) || !std::isfinite(v))
-          return set_error(SKM_E_INVALID, "values must be finite and > 0");
-        sq += (double)v * (double)v;
-      }
-      if (std::fabs(std::sqrt(sq) - 1.0) > 1e-5)
-        return set_error(SKM_E_INVALID, "row L2 norm differs from 1 by more than 1e-5");
-    }
+    const skm_status st = check_host_rows(r->indptr, r->indices, r->values, n, z, s->c->D);
+    if (st != SKM_OK) return st;
   }
   r->out_a = out_assign;
   r->out_s = out_score;
@@ -404,6 +588,53 @@ skm_status skm_server_submit(skm_server *s, const skm_csr *docs, int32_t *out_as
   return SKM_OK;
 }
 
+skm_status skm_server_submit_job(skm_server *s, const skm_csr *docs, const skm_config *cfg,
+                                 int32_t *out_assign, double *out_centroids,
+                                 skm_job_info *out_info, int64_t *ticket) {
+  if (!s || !docs || !cfg || !ticket || !out_assign) return set_error(SKM_E_INVALID, "NULL argument");
+  if (docs->on_device) return set_error(SKM_E_INVALID, "jobs are host CSR");
+  const int64_t n = docs->n_rows, z = docs->nnz;
+  if (n < 1 || z < 0 || docs->n_cols < 1 || !docs->indptr || (z > 0 && (!docs->indices || !docs->values)))
+    return set_error(SKM_E_INVALID, "bad CSR");
+  if (!cfg->init_rows) return set_error(SKM_E_INVALID, "a job needs init_rows");
+  if (cfg->k < 1 || cfg->k > n) return set_error(SKM_E_INVALID, "k must be in [1, n_rows]");
+  if (cfg->max_iter < 1) return set_error(SKM_E_INVALID, "a job needs max_iter >= 1");
+  auto r = std::make_shared<Request>();
+  r->is_job = true;
+  r->n_rows = n;
+  r->nnz = z;
+  r->n_cols = docs->n_cols;
+  r->indptr.assign(docs->indptr, docs->indptr + n + 1);
+  if (r->indptr[0] != 0 || r->indptr[n] != z) return set_error(SKM_E_INVALID, "bad indptr");
+  for (int64_t i = 0; i < n; ++i)
+    if (r->indptr[i + 1] < r->indptr[i]) return set_error(SKM_E_INVALID, "indptr decreases");
+  r->indices.assign(docs->indices, docs->indices + z);
+  r->values.assign(docs->values, docs->values + z);
+  r->cfg = *cfg;
+  r->init_rows.assign(cfg->init_rows, cfg->init_rows + cfg->k);
+  r->need = skm_context_bytes(docs, cfg);
+  if (r->need == 0) return set_error(SKM_E_INVALID, "bad job configuration");
+  r->out_a = out_assign;
+  r->out_s = out_centroids;
+  r->out_info = out_info;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stopping) return set_error(SKM_E_STATE, "server is stopping");
+    const size_t cap = job_budget(s);
+    if (cap && r->need > cap)
+      return set_error(SKM_E_NOMEM, "job needs " + std::to_string(r->need) +
+                                        " device bytes, more than the server's budget leaves (" +
+                                        std::to_string(cap) + ")");
+    r->id = s->next_id++;
+    r->t_submit = Clock::now();
+    s->job_queue.push_back(r);
+    s->live[r->id] = r;
+    *ticket = r->id;
+  }
+  s->cv_jobs.notify_all();
+  return SKM_OK;
+}
+
 skm_status skm_server_wait(skm_server *s, int64_t ticket, double timeout_s) {
   if (!s) return set_error(SKM_E_INVALID, "server is NULL");
   std::unique_lock<std::mutex> lk(s->mu);
@@ -411,13 +642,62 @@ skm_status skm_server_wait(skm_server *s, int64_t ticket, double timeout_s) {
   if (it == s->live.end()) return set_error(SKM_E_INVALID, "unknown ticket");
   auto r = it->second;
   auto ready = [&] { return r->done; };
+  r->waiters += 1;
+  s->n_waiters += 1;
+  bool ok = true;
   if (timeout_s < 0) {
     s->cv_done.wait(lk, ready);
-  } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready)) {
+  } else {
+    ok = s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready);
+  }
+  r->waiters -= 1;
+  s->n_waiters -= 1;
+  if (!ok) {
+    s->cv_done.notify_all();   // a stopping server may wait for waiters to leave
     return set_error(SKM_E_TIMEOUT, "request not answered yet");
   }
   s->live.erase(ticket);
-  if (r->status != SKM_OK) return set_error(r->status, "device error while serving");
+  const skm_status st = r->status;
+  if (st == SKM_OK) {
+    // the answers are copied out here, by the waiting caller
+    if (!r->res_a.empty()) std::memcpy(r->out_a, r->res_a.data(), sizeof(int32_t) * r->res_a.size());
+    if (r->out_s && !r->res_s.empty())
+      std::memcpy(r->out_s, r->res_s.data(), sizeof(double) * r->res_s.size());
+    if (r->is_job && r->out_info) *r->out_info = r->info;
+  }
+  s->cv_done.notify_all();
+  if (st == SKM_E_CANCELLED) return set_error(st, "request was cancelled");
+  if (st != SKM_OK) return set_error(st, r->is_job ? "clustering job failed" : "device error while serving");
+  return SKM_OK;
+}
+
+skm_status skm_server_cancel(skm_server *s, int64_t ticket) {
+  if (!s) return set_error(SKM_E_INVALID, "server is NULL");
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->live.find(ticket);
+    if (it == s->live.end()) return set_error(SKM_E_INVALID, "unknown ticket");
+    auto r = it->second;
+    r->cancelled = true;
+    r->res_a.clear();   // answers not collected yet are dropped
+    r->res_s.clear();
+    auto drop = [&](std::deque<std::shared_ptr<Request>> &q) {
+      auto p = std::find(q.begin(), q.end(), r);
+      if (p == q.end()) return false;
+      q.erase(p);
+      return true;
+    };
+    // still queued or already answered: complete as cancelled now; in a
+    // running batch, finish_slot completes it without answers; a running job
+    // is ended by the job thread at its next turn
+    if ((r->is_job ? drop(s->job_queue) : drop(s->queue)) || r->done) {
+      r->done = true;
+      r->status = SKM_E_CANCELLED;
+      drop_payload(s, r);
+    }
+  }
+  s->cv_done.notify_all();
+  s->cv_jobs.notify_all();
   return SKM_OK;
 }
 
@@ -430,7 +710,11 @@ skm_status skm_server_get_stats(skm_server *s, skm_server_stats *out) {
   out->batches = s->batches;
   out->slots = (int32_t)s->slots.size();
   out->max_queue_depth = s->max_depth;
-  out->hbm_bytes = s->hbm;
+  out->hbm_bytes = s->hbm + s->job_hbm;
+  out->jobs_done = s->jobs_done;
+  out->job_iterations = s->job_iterations;
+  out->jobs_running = (int32_t)s->running.size();
+  out->jobs_queued = (int32_t)s->job_queue.size();
   if (!s->lat_ms.empty()) {
     std::vector<double> v = s->lat_ms;
     std::sort(v.begin(), v.end());
@@ -457,7 +741,16 @@ skm_status skm_server_stop(skm_server *s) {
     s->stopping = true;
   }
   s->cv_work.notify_all();
+  s->cv_jobs.notify_all();
   if (s->worker.joinable()) s->worker.join();
+  if (s->job_worker.joinable()) s->job_worker.join();
+  {
+    // every request is answered now; threads still inside skm_server_wait
+    // leave before the server is freed
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv_done.notify_all();
+    s->cv_done.wait(lk, [&] { return s->n_waiters == 0; });
+  }
   const bool dev_err = s->dev_error != hipSuccess;
   s->c->server_attached = 0;
   if (dev_err) s->c->poisoned = true;

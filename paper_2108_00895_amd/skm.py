@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libskm.so")
 
 (SKM_OK, SKM_E_INVALID, SKM_E_NOMEM, SKM_E_DEVICE, SKM_E_STATE, SKM_E_UNSUPPORTED, SKM_E_BUSY,
- SKM_E_TIMEOUT) = range(8)
+ SKM_E_TIMEOUT, SKM_E_CANCELLED) = range(9)
 FP32, BF16, FP8_E4M3 = 0, 1, 2
 NCC, INDEX, NO_EXACT, DENSE_ONLY, BORROW_DEVICE = 1, 2, 4, 8, 16
 STOP_PAPER, STOP_FIXED = 0, 1
@@ -31,7 +31,8 @@ EXPORTED = [
     "skm_save", "skm_load", "skm_get_tile", "skm_get_changed", "skm_score_dense", "skm_error_bound", "skm_head_terms",
     "skm_score_head", "skm_error_bound_head", "skm_error_bound_split", "skm_autotune", "skm_set_schedule", "skm_get_index",
     "skm_index_query", "skm_server_config_default", "skm_server_start", "skm_server_submit",
-    "skm_server_wait", "skm_server_get_stats", "skm_server_stop",
+    "skm_server_wait", "skm_server_get_stats", "skm_server_stop", "skm_server_submit_job",
+    "skm_server_cancel", "skm_context_bytes", "skm_tune_lambda", "skm_debug_fail_after",
     "skm_hbm_bytes", "skm_last_error", "skm_destroy", "skm_index_threshold",
 ]
 
@@ -89,10 +90,20 @@ class TuneReport(ctypes.Structure):
                 ("trials", TuneTrial * 16)]
 
 
+class LambdaReport(ctypes.Structure):
+    _fields_ = [("n_sample", ctypes.c_int32), ("n_grid", ctypes.c_int32),
+                ("grid", ctypes.c_double * 20), ("qualify", ctypes.c_double * 20),
+                ("mean_candidates", ctypes.c_double * 20), ("n_before", ctypes.c_int32),
+                ("n_after", ctypes.c_int32), ("before", ctypes.c_double * 8),
+                ("after", ctypes.c_double * 8), ("cost_before", ctypes.c_double),
+                ("cost_after", ctypes.c_double), ("applied", ctypes.c_int32)]
+
+
 class ServerConfig(ctypes.Structure):
     _fields_ = [("n_slots", ctypes.c_int32), ("slot_rows", ctypes.c_int32),
                 ("slot_nnz", ctypes.c_int64), ("hbm_budget_bytes", ctypes.c_size_t),
-                ("max_wait_us", ctypes.c_int32), ("use_graphs", ctypes.c_int32)]
+                ("max_wait_us", ctypes.c_int32), ("use_graphs", ctypes.c_int32),
+                ("max_jobs", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -101,7 +112,17 @@ class ServerStats(ctypes.Structure):
                 ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
                 ("max_ms", ctypes.c_double), ("rows_per_s", ctypes.c_double),
                 ("slots", ctypes.c_int32), ("max_queue_depth", ctypes.c_int32),
-                ("hbm_bytes", ctypes.c_size_t)]
+                ("hbm_bytes", ctypes.c_size_t), ("jobs_done", ctypes.c_int64),
+                ("job_iterations", ctypes.c_int64), ("jobs_running", ctypes.c_int32),
+                ("jobs_queued", ctypes.c_int32)]
+
+    def asdict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class JobInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("objective", ctypes.c_double), ("hbm_bytes", ctypes.c_size_t)]
 
     def asdict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -190,6 +211,16 @@ def load():
     lib.skm_server_get_stats.restype = st
     lib.skm_server_stop.argtypes = [vp]
     lib.skm_server_stop.restype = st
+    lib.skm_server_submit_job.argtypes = [vp, P(Csr), P(Config), vp, vp, P(JobInfo), P(i64)]
+    lib.skm_server_submit_job.restype = st
+    lib.skm_server_cancel.argtypes = [vp, i64]
+    lib.skm_server_cancel.restype = st
+    lib.skm_debug_fail_after.argtypes = [vp, i32]
+    lib.skm_debug_fail_after.restype = st
+    lib.skm_tune_lambda.argtypes = [vp, i32, P(LambdaReport)]
+    lib.skm_tune_lambda.restype = st
+    lib.skm_context_bytes.argtypes = [P(Csr), P(Config)]
+    lib.skm_context_bytes.restype = ctypes.c_size_t
     lib.skm_index_threshold.argtypes = [ctypes.c_double, i64, ctypes.c_double]
     lib.skm_index_threshold.restype = ctypes.c_double
     lib.skm_hbm_bytes.argtypes = [vp]
@@ -450,6 +481,22 @@ class Context:
         _check(load().skm_get_centroid_columns(self._h, t.ctypes.data, len(t), out.ctypes.data))
         return out
 
+    def debug_fail_after(self, n_calls):
+        """Test aid: the (n_calls + 1)-th checked HIP call reports a failure."""
+        _check(load().skm_debug_fail_after(self._h, n_calls))
+
+    def tune_lambda(self, n_sample=4096):
+        """Tunes the index's threshold set on a row sample (skm_tune_lambda);
+        returns the report as a dict."""
+        rep = LambdaReport()
+        _check(load().skm_tune_lambda(self._h, n_sample, ctypes.byref(rep)))
+        g = rep.n_grid
+        return {"n_sample": rep.n_sample, "grid": list(rep.grid[:g]),
+                "qualify": list(rep.qualify[:g]), "mean_candidates": list(rep.mean_candidates[:g]),
+                "before": list(rep.before[:rep.n_before]), "after": list(rep.after[:rep.n_after]),
+                "cost_before": rep.cost_before, "cost_after": rep.cost_after,
+                "applied": bool(rep.applied)}
+
     def autotune(self):
         """Times candidate shapes of the scoring work and keeps the fastest;
         returns {"best": {...}, "trials": [{...}, ...]}."""
@@ -514,13 +561,14 @@ class Server:
     wait(ticket) returns (assignments, scores)."""
 
     def __init__(self, ctx: Context, n_slots=4, slot_rows=16384, slot_nnz=4 * 1024 * 1024,
-                 hbm_budget_bytes=0, max_wait_us=100, use_graphs=True):
+                 hbm_budget_bytes=0, max_wait_us=100, use_graphs=True, max_jobs=2):
         lib = load()
         cfg = ServerConfig()
         lib.skm_server_config_default(ctypes.byref(cfg))
         cfg.n_slots, cfg.slot_rows, cfg.slot_nnz = n_slots, slot_rows, slot_nnz
         cfg.hbm_budget_bytes, cfg.max_wait_us = hbm_budget_bytes, max_wait_us
         cfg.use_graphs = 1 if use_graphs else 0
+        cfg.max_jobs = max_jobs
         h = ctypes.c_void_p()
         _check(lib.skm_server_start(ctx._h, ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
@@ -538,13 +586,45 @@ class Server:
         _check(load().skm_server_submit(self._h, ctypes.byref(c), a.ctypes.data, s.ctypes.data,
                                         ctypes.byref(t)))
         with self._lock:
-            self._out[t.value] = (a, s)
+            self._out[t.value] = ("rows", a, s)
+        return t.value
+
+    def submit_job(self, csr, n_cols, k, init_rows, centroids=False, **opts):
+        """Queues a clustering job (skm_server_submit_job) with the same options
+        as Context; wait(ticket) returns (assignments, centroids or None, info)."""
+        lib = load()
+        o = Options(**opts)
+        cfg, keep = _config(lib, k, o, init_rows, None, None)
+        c, hold = make_csr(*csr, n_cols)
+        a = np.empty(c.n_rows, dtype=np.int32)
+        C = np.empty((k, n_cols), dtype=np.float64) if centroids else None
+        info = JobInfo()
+        t = ctypes.c_int64()
+        _check(lib.skm_server_submit_job(self._h, ctypes.byref(c), ctypes.byref(cfg), a.ctypes.data,
+                                         C.ctypes.data if C is not None else None,
+                                         ctypes.byref(info), ctypes.byref(t)))
+        with self._lock:
+            self._out[t.value] = ("job", a, C, info)
         return t.value
 
     def wait(self, ticket, timeout_s=-1.0):
-        _check(load().skm_server_wait(self._h, ticket, float(timeout_s)))
+        """(assignments, scores) for a request; (assignments, centroids or
+        None, info dict) for a job."""
+        try:
+            _check(load().skm_server_wait(self._h, ticket, float(timeout_s)))
+        except SkmError as e:
+            if e.status != SKM_E_TIMEOUT:
+                with self._lock:
+                    self._out.pop(ticket, None)
+            raise
         with self._lock:
-            return self._out.pop(ticket)
+            out = self._out.pop(ticket)
+        if out[0] == "job":
+            return out[1], out[2], out[3].asdict()
+        return out[1], out[2]
+
+    def cancel(self, ticket):
+        _check(load().skm_server_cancel(self._h, ticket))
 
     def stats(self):
         st = ServerStats()

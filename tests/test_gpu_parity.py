@@ -387,6 +387,39 @@ def test_error_paths():
     assert e.value.status == skm.SKM_E_INVALID
 
 
+def test_device_error_poisons_the_context():
+    """A device error (injected on the host: the armed HIP call reports a
+    launch failure instead of being made, so nothing faults on the GPU) makes
+    the call return SKM_E_DEVICE and poisons the context: every later call
+    except skm_destroy returns SKM_E_DEVICE; other contexts are unaffected."""
+    say("case: injected device error")
+    csr, c = corpus(400, 2000, nnz_mean=20.0, nnz_max=60, seed=12)
+    rows = synth.seed_rows(c.n_docs, 40, 3)
+    for n_calls in (0, 2, 7, 15, 40):
+        ctx = Context(csr, c.n_terms, 40, init_rows=rows, precision="bf16", ncc=True,
+                      index=True, stop_rule="fixed", max_iter=6)
+        ctx.assign()
+        ctx.update()
+        ctx.debug_fail_after(n_calls)
+        with pytest.raises(SkmError) as e:
+            ctx.iterate(6)
+        assert e.value.status == skm.SKM_E_DEVICE, n_calls
+        for call in (ctx.assign, ctx.update, ctx.assignments, ctx.centroids,
+                     lambda: ctx.assign_new(synth.subset(*csr, np.arange(5))),
+                     lambda: ctx.debug_fail_after(-1)):
+            with pytest.raises(SkmError) as e:
+                call()
+            assert e.value.status == skm.SKM_E_DEVICE, n_calls
+        ctx.close()
+    # a fresh context works as before
+    ref = oracle.run(csr, c.n_terms, 40, rows, max_iter=3, stop_rule="fixed")
+    ctx = Context(csr, c.n_terms, 40, init_rows=rows, precision="bf16", stop_rule="fixed",
+                  max_iter=3)
+    ctx.iterate()
+    assert np.array_equal(ctx.assignments(), ref.a)
+    ctx.close()
+
+
 # ------------------------------------------------------------------ index (Sec. 3.2)
 
 def _sparse_rows(C):
@@ -517,4 +550,36 @@ def test_index_only_without_ncc():
     stats, _ = ctx.iterate()
     assert np.array_equal(ctx.assignments(), ref.a)
     assert sum(s["index_rows"] for s in stats) > 0
+    ctx.close()
+
+
+def test_lambda_tuning_keeps_the_trajectory():
+    """Tuning the index's thresholds per workload (skm_tune_lambda) on the
+    topic-structured rows: the measured cost of the chosen set is at most the
+    paper's set's, the report is consistent, and the run continues on the
+    oracle's trajectory (any threshold set gives the exact assignment)."""
+    say("case: lambda tuning")
+    csr, tc = _topic(4000, seed=13)
+    k = 48
+    rows = synth.seed_rows(tc.n_docs, k, 6)
+    ref = oracle.run(csr, tc.n_terms, k, rows, max_iter=20)
+    ctx = Context(to_device(csr), tc.n_terms, k, init_rows=rows, precision="bf16", ncc=True,
+                  index=True, max_iter=20)
+    stats, conv = ctx.iterate(2)
+    rep = ctx.tune_lambda(2048)
+    say("  before", rep["before"], round(rep["cost_before"], 2), "after", rep["after"],
+        round(rep["cost_after"], 2), "applied", rep["applied"])
+    assert rep["n_sample"] == 2048 and rep["before"] == [0.1, 0.25, 0.4, 0.6]
+    assert rep["cost_after"] <= rep["cost_before"]
+    assert 1 <= len(rep["after"]) <= 4 and rep["after"] == sorted(rep["after"])
+    # qualifying shares fall as the threshold rises
+    q = rep["qualify"]
+    assert all(x >= y for x, y in zip(q, q[1:]))
+    more, conv = ctx.iterate(18)
+    stats += more
+    assert conv == ref.converged and len(stats) == len(ref.records)
+    for st, rec in zip(stats, ref.records):
+        assert st["moved"] == rec.moved, (st["iter"], st["moved"], rec.moved)
+    assert np.array_equal(ctx.assignments(), ref.a)
+    assert sum(s["index_rows"] for s in more) > 0
     ctx.close()

@@ -1,6 +1,7 @@
-"""The CPU oracle and the input generator under AddressSanitizer and
-UndefinedBehaviorSanitizer (host code only): tests/sanitize_driver.c runs a
-small end-to-end workload through both, built with gcc."""
+"""Host code under AddressSanitizer and UndefinedBehaviorSanitizer: the CPU
+oracle and the input generator (tests/sanitize_driver.c runs a small
+end-to-end workload through both, built with gcc), and the library's host-side
+checks of caller data (tests/sanitize_host_checks.cpp, built with g++)."""
 import os
 import shutil
 import subprocess
@@ -27,4 +28,29 @@ def test_oracle_and_generator_under_sanitizers(tmp_path):
     r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
     assert r.returncode == 0, (r.stdout[-1000:], r.stderr[-3000:])
     assert "sanitized run ok" in r.stdout
+    assert "runtime error" not in r.stderr and "ERROR: AddressSanitizer" not in r.stderr
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="needs g++")
+def test_library_input_checks_under_sanitizers(tmp_path):
+    """The library's host-side parsers of caller data (CSR conventions, the
+    checkpoint file: host_checks.cpp, the code skm_init / skm_load /
+    skm_assign_new and the server run before any device work) under
+    AddressSanitizer and UBSan, fed malformed rows and truncated or corrupted
+    checkpoints (tests/sanitize_host_checks.cpp)."""
+    exe = str(tmp_path / "sanitize_host_checks")
+    cmd = ["g++", "-O1", "-g", "-std=c++17", "-fno-omit-frame-pointer",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-I", os.path.join(ROOT, "include"),
+           os.path.join(ROOT, "paper_2108_00895_amd", "csrc", "host_checks.cpp"),
+           os.path.join(ROOT, "tests", "sanitize_host_checks.cpp"), "-o", exe]
+    b = subprocess.run(cmd, capture_output=True, text=True)
+    if b.returncode != 0 and "sanitize" in b.stderr:
+        pytest.skip("g++ without sanitizer runtimes: " + b.stderr[-300:])
+    assert b.returncode == 0, b.stderr[-2000:]
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
+               UBSAN_OPTIONS="print_stacktrace=1")
+    r = subprocess.run([exe, str(tmp_path)], capture_output=True, text=True, env=env, timeout=300)
+    assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-3000:])
+    assert "host checks ok" in r.stdout
     assert "runtime error" not in r.stderr and "ERROR: AddressSanitizer" not in r.stderr

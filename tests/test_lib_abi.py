@@ -45,11 +45,13 @@ def test_tune_structs():
 
 
 def test_server_structs():
-    assert ctypes.sizeof(skm.ServerConfig) == 4 + 4 + 8 + 8 + 4 + 4
+    assert ctypes.sizeof(skm.ServerConfig) == 4 + 4 + 8 + 8 + 4 + 4 + 4 + 4
+    assert ctypes.sizeof(skm.ServerStats) == 3 * 8 + 5 * 8 + 4 + 4 + 8 + 8 + 8 + 4 + 4
+    assert ctypes.sizeof(skm.JobInfo) == 4 + 4 + 8 + 8
     cfg = skm.ServerConfig()
     skm.load().skm_server_config_default(ctypes.byref(cfg))
     assert cfg.n_slots == 4 and cfg.slot_rows == 16384 and cfg.max_wait_us == 100
-    assert cfg.use_graphs == 1
+    assert cfg.use_graphs == 1 and cfg.max_jobs == 2
     assert skm.load().skm_server_start(None, None, ctypes.byref(ctypes.c_void_p())) == skm.SKM_E_INVALID
 
 
@@ -104,3 +106,25 @@ def test_checkpoint_files_checked_without_device(tmp_path):
                         ctypes.byref(cfg)) == skm.SKM_E_INVALID
     assert b"another shape" in lib.skm_last_error()
     assert not h.value
+
+
+def test_context_bytes_estimate():
+    """skm_context_bytes (job admission) bounds the allocations of skm_init from
+    the sizes alone, grows with every size and is 0 for bad arguments."""
+    lib = skm.load()
+    cfg = skm.Config()
+    lib.skm_config_default(ctypes.byref(cfg))
+    cfg.k = 100
+    c = skm.Csr(10_000, 50_000, 1_000_000, None, None, None, 0)
+    base = lib.skm_context_bytes(ctypes.byref(c), ctypes.byref(cfg))
+    # at least the FP64 centroids and sums and the rows themselves
+    assert base >= 2 * 8 * 100 * 50_000 + 8 * 1_000_000
+    for field, val in (("n_rows", 20_000), ("n_cols", 90_000), ("nnz", 3_000_000)):
+        c2 = skm.Csr(10_000, 50_000, 1_000_000, None, None, None, 0)
+        setattr(c2, field, val)
+        assert lib.skm_context_bytes(ctypes.byref(c2), ctypes.byref(cfg)) > base, field
+    cfg.flags = skm.NCC | skm.INDEX
+    assert lib.skm_context_bytes(ctypes.byref(c), ctypes.byref(cfg)) > base
+    cfg.k = 0
+    assert lib.skm_context_bytes(ctypes.byref(c), ctypes.byref(cfg)) == 0
+    assert lib.skm_context_bytes(None, None) == 0
