@@ -272,6 +272,29 @@ skm_status skm_iterate(skm_ctx *c, int32_t max_iter, skm_iter_stats *per_iter,
 skm_status skm_assign_new(skm_ctx *c, const skm_csr *docs, int32_t *out_assign,
                           double *out_score, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): skm_assign_new for
+ * device rows without any device allocation.  docs must be device pointers
+ * (on_device = 1) and is read in place; out_assign [n_rows] (int32) and
+ * out_score [n_rows] (FP64 dot product with the chosen centroid) are device
+ * pointers written directly.  The call's temporaries live in one static
+ * device array of the library, skm_static_scratch_bytes() bytes (64 MiB) on
+ * each GPU the library runs on, held until the process ends; at most
+ * skm_static_max_rows(c) rows fit (about 64 MiB / (32 B x ceil(k / 512) + 45 B)),
+ * more gives SKM_E_INVALID with nothing written.  The array is shared by every
+ * call on that GPU and keeps the last call's contents: calls that overlap on
+ * one GPU (different streams or threads) race and must be serialised by the
+ * caller.  Same checks, results and errors as skm_assign_new otherwise; the
+ * call synchronises `stream` (NULL = the context's stream) before returning. */
+skm_status skm_assign_new_static(skm_ctx *c, const skm_csr *docs, int32_t *out_assign,
+                                 double *out_score, void *stream);
+
+/* Size of skm_assign_new_static's static workspace per GPU, in bytes. */
+size_t skm_static_scratch_bytes(void);
+
+/* Rows one skm_assign_new_static call on context c can take. */
+int64_t skm_static_max_rows(const skm_ctx *c);
+
 /* Current assignment (after skm_assign) into out[n_rows]. */
 skm_status skm_get_assignments(const skm_ctx *c, int32_t *out, int32_t on_device);
 

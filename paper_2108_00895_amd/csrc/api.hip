@@ -819,6 +819,10 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
   };
   hipError_t e = hipGetDevice(&c->device);
   if (e != hipSuccess) return cleanup(device_fail(nullptr, "hipGetDevice", e));
+  {
+    const skm_status sn = noalloc_setup(c->device);
+    if (sn != SKM_OK) return cleanup(sn);
+  }
   if (cfg->stream) {
     c->stream = static_cast<hipStream_t>(cfg->stream);
   } else {

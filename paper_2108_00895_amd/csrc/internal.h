@@ -397,6 +397,10 @@ hipError_t launch_new_rows(skm_ctx *c, const NewRows &b, int64_t n, hipStream_t 
                            const int64_t *n_dev = nullptr);
 skm_status set_error(skm_status st, const std::string &msg);  // thread-local last error
 
+// noalloc.hip: looks up the static workspace's device address on `device`
+// (the current device), once per device.
+skm_status noalloc_setup(int device);
+
 // kernels_tail.hip
 // Chunks chunks[0 .. n_list) of a copy with ncols columns: classification,
 // counts and per-chunk offsets (totals[q] = entries of chunks[q]); then the

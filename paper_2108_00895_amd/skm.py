@@ -34,6 +34,7 @@ EXPORTED = [
     "skm_server_wait", "skm_server_get_stats", "skm_server_stop", "skm_server_submit_job",
     "skm_server_cancel", "skm_context_bytes", "skm_tune_lambda", "skm_debug_fail_after",
     "skm_hbm_bytes", "skm_last_error", "skm_destroy", "skm_index_threshold",
+    "skm_assign_new_static", "skm_static_scratch_bytes", "skm_static_max_rows",
 ]
 
 
@@ -159,6 +160,12 @@ def load():
     lib.skm_iterate.restype = st
     lib.skm_assign_new.argtypes = [vp, P(Csr), vp, vp, vp]
     lib.skm_assign_new.restype = st
+    lib.skm_assign_new_static.argtypes = [vp, P(Csr), vp, vp, vp]
+    lib.skm_assign_new_static.restype = st
+    lib.skm_static_scratch_bytes.argtypes = []
+    lib.skm_static_scratch_bytes.restype = ctypes.c_size_t
+    lib.skm_static_max_rows.argtypes = [vp]
+    lib.skm_static_max_rows.restype = i64
     lib.skm_get_assignments.argtypes = [vp, vp, i32]
     lib.skm_get_assignments.restype = st
     lib.skm_get_centroids.argtypes = [vp, vp, i32]
@@ -425,6 +432,17 @@ class Context:
         _check(load().skm_assign_new(self._h, ctypes.byref(c), a.ctypes.data, s.ctypes.data,
                                      stream))
         return a, s
+
+    def assign_new_static(self, csr, out_assign, out_score, stream=None):
+        """skm_assign_new_static: device rows (torch tensors) in, answers written
+        into the caller's device tensors out_assign (int32) and out_score
+        (float64); no device memory is allocated by the call."""
+        c, hold = make_csr(*csr, self.n_cols)
+        _check(load().skm_assign_new_static(self._h, ctypes.byref(c), out_assign.data_ptr(),
+                                            out_score.data_ptr(), stream))
+
+    def static_max_rows(self):
+        return int(load().skm_static_max_rows(self._h))
 
     # -- getters
     def assignments(self):
