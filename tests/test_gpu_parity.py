@@ -197,6 +197,42 @@ def test_tweet_shaped_trajectory_equals_oracle(prec, ncc, index):
     ctx.close()
 
 
+@functools.lru_cache(maxsize=None)
+def _abstracts(k):
+    c = synth.scaled(synth.ABSTRACTS_200K, 20_000)
+    csr = synth.generate(c)
+    rows = synth.seed_rows(c.n_docs, k, 12)
+    return csr, c, rows, oracle.run(csr, c.n_terms, k, rows, max_iter=40)
+
+
+@pytest.mark.parametrize("k,prec,ncc,index", [(50, "fp32", False, False), (50, "fp32", True, False),
+                                              (50, "bf16", True, True), (50, "fp8", True, True),
+                                              (600, "bf16", True, True)])
+def test_abstract_shaped_trajectory_equals_oracle(k, prec, ncc, index):
+    """Rows shaped like the paper's abstracts (58 of 325,556 terms on average,
+    20,000 rows): at k = 50 (35 iterations) and k = 600 (two 512-wide chunks,
+    the second ragged) every mode of the paper's ablation follows the oracle's
+    trajectory: each iteration's assignment and moved count, the final
+    centroids."""
+    csr, c, rows, ref = _abstracts(k)
+    say("case: abstract-shaped trajectory", k, prec, ncc, index)
+    ctx = Context(to_device(csr), c.n_terms, len(rows), init_rows=rows, precision=prec, ncc=ncc,
+                  index=index, max_iter=40)
+    stats, conv = [], False
+    for t in range(40):
+        st, conv = ctx.iterate(1)
+        stats += st
+        rec = ref.records[t]
+        assert_assign_equal(ctx.assignments(), rec.a, rec.s1, rec.s2, f"abstracts iteration {t}")
+        assert st[-1]["moved"] == rec.moved, (t, st[-1]["moved"], rec.moved)
+        if conv:
+            break
+    assert conv == ref.converged and len(stats) == len(ref.records)
+    assert np.array_equal(ctx.assignments(), ref.a)
+    assert rel_centroid_err(ctx.centroids(), ref.C) < 1e-9
+    ctx.close()
+
+
 def test_borrowed_device_rows(mid):
     """SKM_BORROW_DEVICE: the context reads the caller's device arrays in place
     (no copy: less HBM by their size) and runs exactly as with a copy."""
