@@ -445,21 +445,40 @@ ScoreArgs base_args(skm_ctx *c) {
 
 int exact_waves() { return 4096; }
 
-constexpr int64_t kSegRows = 256;       // members per summation segment
+constexpr int64_t kSegRows = 256;       // least members per summation segment
 constexpr int64_t kWorkBytes = 16ll << 30;  // partial-row workspace cap
 
+// Rows shorter than this on average are summed several rows per step.
+constexpr int64_t kShortRow = 64;
+
+bool short_rows(int64_t N, int64_t Z) { return Z <= kShortRow * N; }
+
+// Members per summation segment: kSegRows, or for corpora of short rows
+// (summed several rows per step) as many rows as make about 256 steps of 256
+// entries, so that a segment's own adds stay comparable to the D-entry
+// workspace row it clears and the combine reads back (with a large
+// vocabulary and short rows that row would otherwise cost hundreds of times
+// the adds).  A function of the corpus shape alone, so a cluster's segments
+// (and its FP64 sum) depend only on its member set.
+int64_t seg_rows_for(int64_t N, int64_t D, int64_t Z) {
+  (void)D;
+  if (!short_rows(N, Z) || Z <= 0) return kSegRows;
+  return std::max<int64_t>(kSegRows, (int64_t(1) << 16) * N / Z);
+}
+
 // Workspace rows any update can need: the segments of the clusters with more
-// than kSegRows members number at most N / 128 + 1 (each such cluster has at
-// most count / kSegRows + 1 of them), within kWorkBytes.
+// than seg members number at most N / (seg / 2) + 1 (each such cluster has at
+// most count / seg + 1 of them), within kWorkBytes.
 int64_t work_slots_bound(const skm_ctx *c) {
   const int64_t max_slots = std::max<int64_t>(1, kWorkBytes / (8 * c->D));
-  return std::min<int64_t>(max_slots, c->N / (kSegRows / 2) + 2);
+  const int64_t seg = seg_rows_for(c->N, c->D, c->Z);
+  return std::min<int64_t>(max_slots, c->N / (seg / 2) + 2);
 }
 
 // FP64 member sums of the n_ids changed clusters (ids in c->ch_ids): clusters
-// with at most kSegRows members are summed by one workgroup each; larger ones
-// are split into segments summed in parallel into workspace rows and combined
-// in segment order.  Rounds keep the workspace within kWorkBytes.
+// with at most seg_rows_for members are summed by one workgroup each; larger
+// ones are split into segments summed in parallel into workspace rows and
+// combined in segment order.  Rounds keep the workspace within kWorkBytes.
 skm_status sum_changed(skm_ctx *c, int32_t n_ids, std::vector<int32_t> &ids) {
   ids.clear();
   c->full_frac = 0.0;
@@ -484,6 +503,7 @@ skm_status sum_changed(skm_ctx *c, int32_t n_ids, std::vector<int32_t> &ids) {
                    0, (int64_t)c->cfg.hbm_budget_bytes - c->hbm_bytes + held));
   }
   const int64_t max_slots = std::max<int64_t>(1, work_cap / (8 * c->D));
+  const int64_t seg_rows = seg_rows_for(c->N, c->D, c->Z);
   size_t pos = 0;
   std::vector<int4> tasks, groups;
   std::vector<int64_t> r0s;
@@ -496,7 +516,7 @@ skm_status sum_changed(skm_ctx *c, int32_t n_ids, std::vector<int32_t> &ids) {
       const int32_t j = ids[pos];
       const int64_t cnt = counts[j];
       const int64_t nseg =
-          std::min<int64_t>(max_slots, std::max<int64_t>(1, (cnt + kSegRows - 1) / kSegRows));
+          std::min<int64_t>(max_slots, std::max<int64_t>(1, (cnt + seg_rows - 1) / seg_rows));
       const int64_t seg = nseg > 0 ? (cnt + nseg - 1) / nseg : cnt;
       if (nseg == 1) {
         tasks.push_back(make_int4(j, (int)cnt, -1, 0));
@@ -545,7 +565,7 @@ skm_status sum_changed(skm_ctx *c, int32_t n_ids, std::vector<int32_t> &ids) {
                                 hipMemcpyHostToDevice, s));
     HIP_TRY(c, launch_sum_tasks(c->indptr, c->indices, c->values, c->members, c->tasks, c->task_r0,
                                 (int32_t)tasks.size(), c->D, c->S, c->work, c->sum_hot_slot,
-                                c->sum_hot_terms, c->n_sum_hot, s));
+                                c->sum_hot_terms, c->n_sum_hot, s, short_rows(c->N, c->Z)));
     HIP_TRY(c, launch_combine(c->groups, (int32_t)groups.size(), c->D, c->work, c->S, s));
     // the host vectors are reused next round: wait for the copies to finish
     HIP_TRY(c, hipStreamSynchronize(s));
@@ -553,8 +573,36 @@ skm_status sum_changed(skm_ctx *c, int32_t n_ids, std::vector<int32_t> &ids) {
   return SKM_OK;
 }
 
+// Entry-sized buffers of the index (keys and terms twice for the sort, prefix
+// sums, G): 40 bytes per entry (plus 8 per centroid).
+skm_status alloc_index_entries(skm_ctx *c, int64_t cap) {
+  const int64_t old = c->idx_cap_entries;
+  dfree(c, c->idx_key0, old * 8);
+  dfree(c, c->idx_key1, old * 8);
+  dfree(c, c->idx_term0, old * 4);
+  dfree(c, c->idx_term1, old * 4);
+  dfree(c, c->idx_Q, (old + c->k) * 8);
+  dfree(c, c->idx_G, old * 8);
+  c->idx_key0 = c->idx_key1 = nullptr;
+  c->idx_term0 = c->idx_term1 = nullptr;
+  c->idx_Q = nullptr;
+  c->idx_G = nullptr;
+  c->idx_cap_entries = 0;
+  c->index_ready = false;
+  ST_TRY(dalloc(c, &c->idx_key0, (size_t)cap));
+  ST_TRY(dalloc(c, &c->idx_key1, (size_t)cap));
+  ST_TRY(dalloc(c, &c->idx_term0, (size_t)cap));
+  ST_TRY(dalloc(c, &c->idx_term1, (size_t)cap));
+  ST_TRY(dalloc(c, &c->idx_Q, (size_t)(cap + c->k)));
+  ST_TRY(dalloc(c, &c->idx_G, (size_t)cap));
+  c->idx_cap_entries = cap;
+  return SKM_OK;
+}
+
 // Sec. 3.2 index from the current master: entries per centroid, sorted, prefix
-// sums of squares, term-major G.  Entry-sized buffers grow on demand.
+// sums of squares, term-major G.  Entry-sized buffers grow on demand (by half
+// again, so that a growing run reallocates only a few times); without an HBM
+// budget skm_init reserves min(nnz, k D) entries up to 16 GiB at once.
 skm_status build_index(skm_ctx *c) {
   hipStream_t s = c->stream;
   HIP_TRY(c, hipEventRecord(c->ev[6], s));
@@ -563,27 +611,9 @@ skm_status build_index(skm_ctx *c) {
   HIP_TRY(c, hipMemcpyAsync(&total, c->idx_eoff + c->k, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
   if (total > c->idx_cap_entries) {
-    const int64_t cap = std::max<int64_t>(total + total / 4, 1024);
-    const int64_t old = c->idx_cap_entries;
-    dfree(c, c->idx_key0, old * 8);
-    dfree(c, c->idx_key1, old * 8);
-    dfree(c, c->idx_term0, old * 4);
-    dfree(c, c->idx_term1, old * 4);
-    dfree(c, c->idx_Q, (old + c->k) * 8);
-    dfree(c, c->idx_G, old * 8);
-    c->idx_key0 = c->idx_key1 = nullptr;
-    c->idx_term0 = c->idx_term1 = nullptr;
-    c->idx_Q = nullptr;
-    c->idx_G = nullptr;
-    c->idx_cap_entries = 0;
-    c->index_ready = false;
-    ST_TRY(dalloc(c, &c->idx_key0, (size_t)cap));
-    ST_TRY(dalloc(c, &c->idx_key1, (size_t)cap));
-    ST_TRY(dalloc(c, &c->idx_term0, (size_t)cap));
-    ST_TRY(dalloc(c, &c->idx_term1, (size_t)cap));
-    ST_TRY(dalloc(c, &c->idx_Q, (size_t)(cap + c->k)));
-    ST_TRY(dalloc(c, &c->idx_G, (size_t)cap));
-    c->idx_cap_entries = cap;
+    const int64_t bound = std::min<int64_t>(c->Z, (int64_t)c->k * c->D);
+    const int64_t cap = std::max<int64_t>(std::min<int64_t>(total + total / 2, bound), total);
+    ST_TRY(alloc_index_entries(c, std::max<int64_t>(cap, 1024)));
   }
   IndexBuild ib{c->master, c->k, c->D, c->idx_eoff, c->idx_key0, c->idx_key1, c->idx_term0,
                 c->idx_term1, c->idx_Q, c->idx_mask, c->idx_blkpre, c->idx_tcnt, c->idx_toff,
@@ -761,8 +791,9 @@ size_t skm_context_bytes(const skm_csr *docs, const skm_config *cfg) {
          4 * N * 2 + 8 * (N + 1) + 8 * Z + 16 * N;
   }
   // the update's workspace: the bound skm_init allocates without a budget
-  b += 8 * D * (double)std::min<int64_t>(std::max<int64_t>(1, kWorkBytes / (8 * docs->n_cols)),
-                                         docs->n_rows / (kSegRows / 2) + 2);
+  b += 8 * D * (double)std::min<int64_t>(
+                   std::max<int64_t>(1, kWorkBytes / (8 * docs->n_cols)),
+                   docs->n_rows / (seg_rows_for(docs->n_rows, docs->n_cols, docs->nnz) / 2) + 2);
   b += 8 * 1024 * 1024 + 64 * 256.0;   // task lists, small buffers, rounding
   return (size_t)b;
 }
@@ -928,6 +959,13 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
     // multi-GB hipMalloc inside an iteration can take seconds
     c->work_slots = work_slots_bound(c);
     A_(c->work, c->work_slots * c->D);
+    if (c->cfg.flags & SKM_INDEX) {
+      // the index's entries: every centroid's non-zeros, at most min(nnz, k D)
+      // (the members' terms), reserved up to 16 GiB
+      const int64_t bound = std::min<int64_t>(c->Z, (int64_t)c->k * c->D);
+      const int64_t cap = std::max<int64_t>(1024, std::min<int64_t>(bound, (16ll << 30) / 40));
+      if ((st = alloc_index_entries(c, cap)) != SKM_OK) return cleanup(st);
+    }
   }
 #undef A_
 
@@ -1061,9 +1099,9 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
   int32_t n_ch = c->k;
   HIP_TRY(c, hipEventRecord(c->ev[0], s));
   if (ncc) {
+    // the flags are those of the last update, which counted them
+    n_ch = c->last_changed;
     HIP_TRY(c, launch_compact_changed(c->changed, c->k, c->ch_ids, c->ids_count, s));
-    HIP_TRY(c, hipMemcpyAsync(&n_ch, c->ids_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(c, hipStreamSynchronize(s));
     HIP_TRY(c, launch_gather_tile(c->tile, c->D, c->esize, c->ch_ids, n_ch, c->tile_ch, s));
     ST_TRY(build_tail(c, 1, c->tile_ch, n_ch, nullptr));
     a.a_prev = c->a_prev;
@@ -1084,11 +1122,9 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
     // previous centroid only takes changed candidates (end of Sec. 3.2)
     HIP_TRY(c, hipEventRecord(c->ev[6], s));
     HIP_TRY(c, launch_fill_u8(c->mode, 0, c->N, s));
-    HIP_TRY(c, index_rows(c->a_prev, nullptr, c->N, c->idx_rows, c->ids_count, c->list_work, s));
-    int32_t n_rows_idx = 0;
-    HIP_TRY(c, hipMemcpyAsync(&n_rows_idx, c->ids_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(c, hipStreamSynchronize(s));
+    const int64_t n_rows_idx = c->N;
     IndexArgs x = index_args(c);
+    x.rows = nullptr;   // every row, slot = row
     x.changed = ncc ? c->changed : nullptr;
     x.n_ch = n_ch;
     HIP_TRY(c, index_query(x, n_rows_idx, s));

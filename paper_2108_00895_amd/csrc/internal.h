@@ -154,7 +154,7 @@ struct IndexArgs {
   const double *master;
   int64_t D;
   int32_t k;
-  const int32_t *rows;      // rows handled, one workgroup each
+  const int32_t *rows;      // rows handled, one workgroup each (nullptr: slot = row)
   const int32_t *a_prev;    // previous assignment (baseline), or nullptr
   const uint8_t *changed;   // Sec. 3.1 changed flags: rows keeping an unchanged
                             // previous centroid only take changed candidates
@@ -467,12 +467,13 @@ hipError_t launch_centroid_columns(const double *master, int32_t k, int64_t D, c
 hipError_t launch_bucket(const int32_t *a, int64_t n, int32_t k, int64_t nblk, int32_t *hist,
                          int32_t *counts, int64_t *offsets, int32_t *members, hipStream_t s);
 // Member sums of the tasks; terms with hot_slot[t] >= 0 (n_hot <= kSumHot of
-// them, hot_terms[slot] = t) are summed in LDS.
+// them, hot_terms[slot] = t) are summed in LDS.  short_rows: the corpus has
+// short rows, summed several rows per step (when D < 2^24).
 hipError_t launch_sum_tasks(const int64_t *indptr, const int32_t *indices, const float *values,
                             const int32_t *members, const int4 *tasks, const int64_t *task_r0,
                             int32_t n_tasks, int64_t D, double *S, double *work,
                             const int32_t *hot_slot, const int32_t *hot_terms, int32_t n_hot,
-                            hipStream_t s);
+                            hipStream_t s, bool short_rows);
 hipError_t launch_combine(const int4 *groups, int32_t n_groups, int64_t D, const double *work,
                           double *S, hipStream_t s);
 hipError_t launch_renorm(const double *S, const int32_t *counts, const int32_t *ids, int32_t n_ids,

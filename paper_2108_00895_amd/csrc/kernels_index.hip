@@ -314,7 +314,7 @@ __global__ __launch_bounds__(256) void k_index_query(IndexArgs x) {
   __shared__ int32_t sh_i[256];
   __shared__ int s_level;
   const int64_t slot = blockIdx.x;
-  const int64_t row = x.rows[slot];
+  const int64_t row = x.rows ? (int64_t)x.rows[slot] : slot;
   const int64_t b = x.indptr[row], e = x.indptr[row + 1], n = e - b;
   const int32_t ap = x.a_prev ? x.a_prev[row] : 0;
   const bool keep_row = x.changed && x.a_prev && !x.changed[ap];
@@ -426,7 +426,7 @@ __global__ __launch_bounds__(256) void k_index_score(IndexArgs x, int64_t n_slot
   if (slot >= n_slots) return;
   const int32_t nc = x.ncand[slot];
   if (nc < 0) return;
-  const int64_t row = x.rows[slot];
+  const int64_t row = x.rows ? (int64_t)x.rows[slot] : slot;
   const int64_t b = x.indptr[row], e = x.indptr[row + 1];
   const int32_t ap = x.a_prev[row];
   double bs = -INFINITY;

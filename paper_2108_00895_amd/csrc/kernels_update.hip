@@ -441,6 +441,123 @@ __global__ __launch_bounds__(256) void k_sum_tasks(const int64_t *indptr, const 
   for (int h = tid; h < n_hot; h += 256) dst[hot_terms[h]] = hot[h];
 }
 
+// The same sums for corpora of short rows (a few dozen terms or fewer).  A
+// step takes as many consecutive member rows as fit in 256 entries, one entry
+// per thread; the step's (term, row) keys are sorted in LDS (bitonic) so that
+// each term's values form one run in row order, the run's head adds them in
+// that order and adds the run's sum to the term's accumulator once.  Terms
+// are distinct across runs, so the adds of a step are race-free, and steps
+// follow the member order: the sum is a fixed function of the member list.
+// Rows of more than 256 entries take a step of their own (their terms are
+// distinct).  Requires D < 2^24 (keys pack the term above an 8-bit row index).
+__global__ __launch_bounds__(256) void k_sum_tasks_short(const int64_t *indptr,
+                                                         const int32_t *indices,
+                                                         const float *values,
+                                                         const int32_t *members,
+                                                         const int4 *tasks, const int64_t *task_r0,
+                                                         int64_t D, double *S, double *work,
+                                                         const int32_t *hot_slot,
+                                                         const int32_t *hot_terms, int32_t n_hot) {
+  __shared__ double hot[kSumHot];
+  __shared__ int64_t rb[256];
+  __shared__ int32_t plen[257];          // inclusive prefix of the group's row lengths
+  __shared__ uint32_t key[256];
+  __shared__ double val[256];
+  const int4 tk = tasks[blockIdx.x];   // x = cluster, y = count, z = dest slot (-1: S_j)
+  double *dst = tk.z < 0 ? S + (int64_t)tk.x * D : work + (int64_t)tk.z * D;
+  const int tid = threadIdx.x;
+  if (D % 2 == 0) {
+    v2d *d2 = reinterpret_cast<v2d *>(dst);
+    const v2d z = {0.0, 0.0};
+    for (int64_t t = tid; t < D / 2; t += 256) __builtin_nontemporal_store(z, d2 + t);
+  } else {
+    for (int64_t t = tid; t < D; t += 256) dst[t] = 0.0;
+  }
+  for (int h = tid; h < n_hot; h += 256) hot[h] = 0.0;
+  auto add = [&](int32_t t, double v) {
+    const int32_t h = hot_slot ? hot_slot[t] : -1;
+    if (h >= 0) {
+      hot[h] += v;
+    } else {
+      dst[t] += v;
+    }
+  };
+  const int64_t r0 = task_r0[blockIdx.x], r1 = r0 + tk.y;
+  for (int64_t g0 = r0; g0 < r1; g0 += 256) {
+    const int nr = (int)min<int64_t>(256, r1 - g0);
+    __syncthreads();   // the zeroing, or the previous group's steps, are done
+    int32_t len = 0;
+    if (tid < nr) {
+      const int64_t i = members[g0 + tid];
+      rb[tid] = indptr[i];
+      len = (int32_t)(indptr[i + 1] - rb[tid]);
+    }
+    // inclusive scan of the lengths (capped: a long row is a step of its own)
+    plen[tid + 1] = len;
+    if (tid == 0) plen[0] = 0;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const int32_t v = tid + 1 > off ? plen[tid + 1 - off] : 0;
+      __syncthreads();
+      plen[tid + 1] += v;
+      __syncthreads();
+    }
+    int q0 = 0;
+    while (q0 < nr) {
+      // rows q0 .. q1 - 1: as many as fit in 256 entries (at least one)
+      int q1 = q0 + 1;
+      while (q1 < nr && plen[q1 + 1] - plen[q0] <= 256) ++q1;
+      const int32_t n_ent = plen[q1] - plen[q0];
+      if (q1 - q0 == 1) {
+        // one row: its terms are distinct, every thread adds its entries
+        for (int32_t e = tid; e < n_ent; e += 256)
+          add(indices[rb[q0] + e], (double)values[rb[q0] + e]);
+      } else {
+        // several rows: sort the step's entries by (term, row)
+        uint32_t kk = 0xFFFFFFFFu;
+        double vv = 0.0;
+        if (tid < n_ent) {
+          int q = q0;   // the row holding entry tid of the step
+          while (plen[q + 1] - plen[q0] <= tid) ++q;
+          const int64_t p = rb[q] + (tid - (plen[q] - plen[q0]));
+          kk = ((uint32_t)indices[p] << 8) | (uint32_t)(q - q0);
+          vv = (double)values[p];
+        }
+        key[tid] = kk;
+        val[tid] = vv;
+        __syncthreads();
+        for (int size = 2; size <= 256; size <<= 1) {
+          for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const int partner = tid ^ stride;
+            if (partner > tid) {
+              const bool up = (tid & size) == 0;
+              const uint32_t a = key[tid], b = key[partner];
+              if ((a > b) == up) {
+                key[tid] = b;
+                key[partner] = a;
+                const double x = val[tid];
+                val[tid] = val[partner];
+                val[partner] = x;
+              }
+            }
+            __syncthreads();
+          }
+        }
+        if (tid < n_ent && (tid == 0 || (key[tid] >> 8) != (key[tid - 1] >> 8))) {
+          const uint32_t term = key[tid] >> 8;
+          double run = val[tid];
+          for (int e = tid + 1; e < n_ent && (key[e] >> 8) == term; ++e) run += val[e];
+          add((int32_t)term, run);
+        }
+      }
+      __syncthreads();
+      q0 = q1;
+    }
+  }
+  __syncthreads();
+  for (int h = tid; h < n_hot; h += 256) dst[hot_terms[h]] = hot[h];
+}
+
 // S_j = sum of its segment partials, in segment order.  Block (group, term block).
 __global__ __launch_bounds__(256) void k_combine(const int4 *groups, int64_t D, int64_t tblk,
                                                  const double *work, double *S) {
@@ -721,12 +838,18 @@ hipError_t launch_sum_tasks(const int64_t *indptr, const int32_t *indices, const
                             const int32_t *members, const int4 *tasks, const int64_t *task_r0,
                             int32_t n_tasks, int64_t D, double *S, double *work,
                             const int32_t *hot_slot, const int32_t *hot_terms, int32_t n_hot,
-                            hipStream_t s) {
+                            hipStream_t s, bool short_rows) {
   if (n_tasks <= 0) return hipSuccess;
   if (n_hot > kSumHot || (n_hot > 0 && (!hot_slot || !hot_terms))) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_sum_tasks, dim3((unsigned)n_tasks), dim3(256), 0, s, indptr, indices, values,
-                     members, tasks, task_r0, D, S, work, n_hot > 0 ? hot_slot : nullptr, hot_terms,
-                     n_hot);
+  if (short_rows && D < (int64_t(1) << 24)) {
+    hipLaunchKernelGGL(k_sum_tasks_short, dim3((unsigned)n_tasks), dim3(256), 0, s, indptr, indices,
+                       values, members, tasks, task_r0, D, S, work,
+                       n_hot > 0 ? hot_slot : nullptr, hot_terms, n_hot);
+  } else {
+    hipLaunchKernelGGL(k_sum_tasks, dim3((unsigned)n_tasks), dim3(256), 0, s, indptr, indices,
+                       values, members, tasks, task_r0, D, S, work,
+                       n_hot > 0 ? hot_slot : nullptr, hot_terms, n_hot);
+  }
   return hipGetLastError();
 }
 
