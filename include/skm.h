@@ -138,6 +138,12 @@ typedef struct {
                                  below 64 = off.  Default 4096. */
   double head_min_df;         /* a term joins that head when at least this fraction
                                  of the rows contain it.  Default 1/128. */
+  int32_t ncc_adaptive;       /* SKM_NCC: 0 (default) = use Sec. 3.1 whenever its
+                                 estimated scoring work is at most 0.9 of a full
+                                 pass; 1 = also only when the scoring it saves
+                                 (measured on the last full pass) exceeds the cost of
+                                 building its compacted copy (measured at its last
+                                 use).  Results are the same either way. */
 } skm_config;
 
 typedef struct {

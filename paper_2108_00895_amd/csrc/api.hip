@@ -1095,7 +1095,15 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
   // changed (all of theirs), is clearly below a full pass; otherwise every
   // row scores the full copy.
   const double ncc_cost = (1.0 - c->full_frac) * (double)c->last_changed / (double)c->k + c->full_frac;
-  const bool ncc = (c->cfg.flags & SKM_NCC) && c->have_prev && ncc_cost <= kNccMaxCost;
+  bool ncc = (c->cfg.flags & SKM_NCC) && c->have_prev && ncc_cost <= kNccMaxCost;
+  if (ncc && c->cfg.ncc_adaptive && c->ms_full_score >= 0.f) {
+    // the scoring NCC saves, against what building its compacted copy costs
+    // (measured at its last use, else estimated from the bytes it moves)
+    const double prep = c->ms_ncc_prep >= 0.f
+                            ? (double)c->ms_ncc_prep
+                            : 3.0 * (double)c->D * c->last_changed * c->esize / 2e9;
+    if ((1.0 - ncc_cost) * (double)c->ms_full_score <= prep) ncc = false;
+  }
   int32_t n_ch = c->k;
   HIP_TRY(c, hipEventRecord(c->ev[0], s));
   if (ncc) {
@@ -1104,6 +1112,7 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
     HIP_TRY(c, launch_compact_changed(c->changed, c->k, c->ch_ids, c->ids_count, s));
     HIP_TRY(c, launch_gather_tile(c->tile, c->D, c->esize, c->ch_ids, n_ch, c->tile_ch, s));
     ST_TRY(build_tail(c, 1, c->tile_ch, n_ch, nullptr));
+    HIP_TRY(c, hipEventRecord(c->ev[8], s));
     a.a_prev = c->a_prev;
     a.changed = c->changed;
     a.tile_ch = c->tile_ch;
@@ -1195,6 +1204,10 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
   HIP_TRY(c, hipMemcpyAsync(cnt, c->counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipMemcpyAsync(stv, c->stat, sizeof(stv), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
+  if (ncc)
+    c->ms_ncc_prep = elapsed(c->ev[0], c->ev[8]);
+  else
+    c->ms_full_score = elapsed(c->ev[5], c->ev[1]);
   c->assigned = true;
   c->last_moved = c->have_prev ? (int64_t)stv[4] : c->N;
   if (use_index) {

@@ -354,7 +354,9 @@ struct skm_ctx {
   int32_t last_changed = 0;    // changed centroids before the last assignment
   int64_t last_moved = 0;
 
-  hipEvent_t ev[8] = {};
+  hipEvent_t ev[10] = {};
+  float ms_full_score = -1.f;  // device time of the last scoring pass over every centroid
+  float ms_ncc_prep = -1.f;    // device time of the last Sec. 3.1 preparation (compacted copy)
 };
 
 namespace skm {

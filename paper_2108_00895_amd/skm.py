@@ -58,7 +58,8 @@ class Config(ctypes.Structure):
                 ("max_shift_sq", ctypes.c_double), ("init_rows", ctypes.c_void_p),
                 ("init_centroids", ctypes.c_void_p), ("hbm_budget_bytes", ctypes.c_size_t),
                 ("stream", ctypes.c_void_p), ("validate", ctypes.c_int32),
-                ("head_max_terms", ctypes.c_int32), ("head_min_df", ctypes.c_double)]
+                ("head_max_terms", ctypes.c_int32), ("head_min_df", ctypes.c_double),
+                ("ncc_adaptive", ctypes.c_int32)]
 
 
 class IterStats(ctypes.Structure):
@@ -298,6 +299,7 @@ class Options:
     head_max_terms: int | None = None   # None: the library default (4096); 0: off
     head_min_df: float | None = None    # None: the library default (1/128)
     borrow: bool = False                # device rows used in place (SKM_BORROW_DEVICE)
+    ncc_adaptive: bool = False          # NCC only when its measured saving beats its preparation
 
 
 def _config(lib, k, o, init_rows, init_centroids, stream):
@@ -319,6 +321,7 @@ def _config(lib, k, o, init_rows, init_centroids, stream):
     cfg.max_shift_sq = o.max_shift_sq
     cfg.hbm_budget_bytes = o.hbm_budget_bytes
     cfg.validate = 1 if o.validate else 0
+    cfg.ncc_adaptive = 1 if o.ncc_adaptive else 0
     if o.head_max_terms is not None:
         cfg.head_max_terms = o.head_max_terms
     if o.head_min_df is not None:

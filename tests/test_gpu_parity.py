@@ -168,16 +168,20 @@ def _tweets():
     return csr, c, rows, oracle.run(csr, c.n_terms, 64, rows, max_iter=40)
 
 
-@pytest.mark.parametrize("prec,ncc,index", [("fp32", False, False), ("fp32", True, False),
-                                            ("fp32", True, True), ("bf16", True, True)])
-def test_tweet_shaped_trajectory_equals_oracle(prec, ncc, index):
+@pytest.mark.parametrize("prec,ncc,index,adaptive", [("fp32", False, False, False),
+                                                     ("fp32", True, False, False),
+                                                     ("fp32", True, False, True),
+                                                     ("fp32", True, True, False),
+                                                     ("bf16", True, True, True)])
+def test_tweet_shaped_trajectory_equals_oracle(prec, ncc, index, adaptive):
     """Rows shaped like the paper's tweets (10 of 783,304 terms on average, one
     512-wide slab of codes much taller than the rows are long).  Many rows share
     no term with any seed: all their scores are 0 and they go to centroid 0
     (lowest index among equal maxima).  Every mode of the paper's ablation
-    (plain, NCC, NCC + INDEX) follows the oracle's trajectory exactly."""
+    (plain, NCC, NCC + INDEX) follows the oracle's trajectory exactly, also with
+    NCC applied only where its measured saving beats its preparation."""
     csr, c, rows, ref = _tweets()
-    say("case: tweet-shaped trajectory", prec, ncc, index)
+    say("case: tweet-shaped trajectory", prec, ncc, index, adaptive)
     ip, ix, _ = csr
     seed_terms = np.zeros(c.n_terms, dtype=bool)
     for r in rows:
@@ -185,7 +189,7 @@ def test_tweet_shaped_trajectory_equals_oracle(prec, ncc, index):
     hit = np.add.reduceat(seed_terms[ix].astype(np.int64), ip[:-1])
     assert np.count_nonzero(hit == 0) > 20         # the degenerate rows are there
     ctx = Context(to_device(csr), c.n_terms, len(rows), init_rows=rows, precision=prec, ncc=ncc,
-                  index=index, max_iter=40)
+                  index=index, max_iter=40, ncc_adaptive=adaptive)
     stats, conv = ctx.iterate()
     assert conv == ref.converged and len(stats) == len(ref.records)
     for st, rec in zip(stats, ref.records):
