@@ -449,7 +449,7 @@ constexpr int64_t kSegRows = 256;       // least members per summation segment
 constexpr int64_t kWorkBytes = 16ll << 30;  // partial-row workspace cap
 
 // Rows shorter than this on average are summed several rows per step.
-constexpr int64_t kShortRow = 64;
+constexpr int64_t kShortRow = 32;
 
 bool short_rows(int64_t N, int64_t Z) { return Z <= kShortRow * N; }
 

@@ -16,6 +16,7 @@ namespace {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 
 __device__ inline uint16_t bf16_rne(float x) {
   uint32_t u = __float_as_uint(x);
@@ -131,66 +132,98 @@ __global__ __launch_bounds__(256) void k_gather_head(const uint16_t *ch, int32_t
 
 // ------------------------------------------------------------------ GEMM
 // hs[r][j] = sum_h xh[row0 + r][h] * ch[j][h] for r < nb, j < ncp (ch already
-// offset to the first column).  Consecutive workgroups take consecutive column
-// tiles of one row tile: the workgroups are dealt to the XCDs round-robin, so
-// with 8 column tiles each XCD keeps one B tile in its L2 while the row tiles
-// stream past.
-// Workgroup tile 256 rows x 256 centroids, K step 64 through LDS (two stages,
-// 144 KiB; rows padded to 144 bytes so that the 16-byte operand reads of 8
-// consecutive rows fall on distinct banks).  Eight wavefronts as 4 (rows) x 2
-// (centroids); each computes 64 x 128 with 2 x 4 MFMA 32x32x16 blocks.
-// Lane layout of v_mfma_f32_32x32x16_bf16: A operand lane l holds row l%32,
-// k = 8*(l/32) .. +8; B operand lane l holds column l%32, same k; the FP32
-// result element (8g + 4*(l/32) + e, l%32) sits in accumulator 4g + e.
-constexpr int kGM = 256, kGN = 256, kGK = 64;
-constexpr int kGRow = kGK * 2 + 16;   // LDS bytes per tile row
-constexpr int kGTile = kGM * kGRow;   // bytes per operand tile
+// offset to the first column).
+// Workgroup tile (64 WM) rows x 256 centroids, K step GK through LDS in two
+// stages; WM x 2 wavefronts, each computing 64 x 128 with 2 x 4 MFMA 32x32x16
+// blocks.  The launch uses WM = 4, GK = 64 (144 KiB of LDS, one workgroup per
+// CU); WM = 2, GK = 32 (60 KiB, two workgroups per CU, so that one's first
+// loads and final stores overlap the other's products) measured 10 % slower
+// on the head batches of a 2e6-row corpus.  Operand rows are padded by 16
+// bytes so that the 16-byte operand reads of consecutive rows fall on distinct
+// banks.  Lane layout of v_mfma_f32_32x32x16_bf16: A operand lane l
+// holds row l%32, k = 8*(l/32) .. +8; B operand lane l holds column l%32, same
+// k; the FP32 result element (8g + 4*(l/32) + e, l%32) sits in accumulator
+// 4g + e.
+constexpr int kGN = 256;
+constexpr int64_t kXcdCols = 2;   // column tiles (of 256) per XCD
 
-__global__ __launch_bounds__(512) void k_head_gemm(const uint16_t *__restrict__ xh, int32_t H,
-                                                   int64_t row0, int64_t nb,
-                                                   const int32_t *__restrict__ rows,
-                                                   const uint16_t *__restrict__ ch, int64_t ncp,
-                                                   float *__restrict__ hs, int64_t ldh) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[2][2][kGTile];
+// Column-tile counts the XCD-aware placement covers: a power of two that
+// splits into at most 8 groups of kXcdCols (or fewer) tiles.
+__host__ __device__ inline bool xcd_placement(int64_t ncb) {
+  return ncb >= 1 && ncb <= 8 * kXcdCols && (ncb & (ncb - 1)) == 0;
+}
+
+// Workgroups of one head product launch with row tiles of gm rows.
+inline int64_t gemm_blocks(int64_t nb, int64_t ncb, int64_t gm) {
+  const int64_t nrb = (nb + gm - 1) / gm;
+  if (!xcd_placement(ncb)) return nrb * ncb;
+  const int64_t cpx = ncb < kXcdCols ? ncb : kXcdCols;
+  const int64_t gr = 8 / (ncb / cpx);
+  return 8 * ((nrb + gr - 1) / gr) * cpx;
+}
+
+template <int GK, int WM>
+__global__ __launch_bounds__(WM * 128) void k_head_gemm(const uint16_t *__restrict__ xh, int32_t H,
+                                                        int64_t row0, int64_t nb,
+                                                        const int32_t *__restrict__ rows,
+                                                        const uint16_t *__restrict__ ch,
+                                                        int64_t ncp, float *__restrict__ hs,
+                                                        int64_t ldh) {
+  constexpr int kT = WM * 128;           // threads
+  constexpr int kGM = WM * 64;           // rows of the tile
+  constexpr int kRow = GK * 2 + 16;      // LDS bytes per tile row
+  constexpr int kPPR = GK / 8;           // 16-byte pieces per tile row
+  constexpr int kRPP = kT / kPPR;        // tile rows moved per pass of the workgroup
+  constexpr int kNA = kGM / kRPP;        // passes per A tile
+  constexpr int kNB = kGN / kRPP;        // passes per B tile
+  static_assert(kNA >= 1 && kNB >= 1 && kGM % kRPP == 0 && kGN % kRPP == 0, "tile shape");
+  __shared__ __attribute__((aligned(16))) uint8_t lds_a[2][kGM * kRow];
+  __shared__ __attribute__((aligned(16))) uint8_t lds_b[2][kGN * kRow];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int li = lane & 31, kg = lane >> 5;
-  const int wm = wave & 3, wn = wave >> 2;
+  const int wm = wave % WM, wn = wave / WM;
   const int64_t ncb = ncp / kGN;
-  const int64_t rb = blockIdx.x / ncb, cb = blockIdx.x - rb * ncb;
+  int64_t rb, cb;
+  if (xcd_placement(ncb)) {
+    // XCD-aware placement: workgroups are dealt to the 8 XCDs round-robin;
+    // XCD x takes kXcdCols column tiles (their B tiles stay in its L2) and
+    // every (8 / groups)-th row tile, the column tiles of one row tile on
+    // consecutive slots so that its A tile is fetched into that L2 once.
+    const int64_t cpx = ncb < kXcdCols ? ncb : kXcdCols;
+    const int64_t gc = ncb / cpx, gr = 8 / gc;
+    const int64_t x = blockIdx.x % 8, slot = blockIdx.x / 8;
+    cb = (x % gc) * cpx + slot % cpx;
+    rb = (slot / cpx) * gr + x / gc;
+    if (rb * kGM >= nb) return;
+  } else {
+    rb = blockIdx.x / ncb;
+    cb = blockIdx.x - rb * ncb;
+  }
   const int64_t r_base = rb * kGM, c_base = cb * kGN;
 
-  // global -> register staging, 4 x 16 B of A and of B per thread and K step:
-  // thread t moves pieces t + 512 u (u < 4) of a 256 x 64 tile, piece id ->
-  // row id / 8, k offset 8 * (id % 8)
-  const int pr = tid >> 3, kq = tid & 7;
-  const int so = pr * kGRow + kq * 16;   // LDS offset of piece u: so + 64 u rows
+  // global -> register staging: thread t moves piece (row pr + kRPP u, k
+  // offset 8 kq) of the A tile (u < kNA) and of the B tile (u < kNB)
+  const int pr = tid / kPPR, kq = tid % kPPR;
+  const int so = pr * kRow + kq * 16;   // LDS offset of piece u: so + kRPP u rows
   // Rows at or past nb read row nb - 1 instead: their results are never
   // stored, and every output row depends on its own A row only.
-  const uint4 *xv = reinterpret_cast<const uint4 *>(xh);
-  const uint4 *cv = reinterpret_cast<const uint4 *>(ch);
+  const v4u *xv = reinterpret_cast<const v4u *>(xh);
+  const v4u *cv = reinterpret_cast<const v4u *>(ch);
   const int64_t h8 = H / 8;
-#define SKM_AROW(u)                                                   \
-  (rows ? (int64_t)rows[row0 + min<int64_t>(r_base + pr + 64 * (u), nb - 1)] \
-        : row0 + min<int64_t>(r_base + pr + 64 * (u), nb - 1))
-  const int64_t oa0 = SKM_AROW(0) * h8 + kq, oa1 = SKM_AROW(1) * h8 + kq;
-  const int64_t oa2 = SKM_AROW(2) * h8 + kq, oa3 = SKM_AROW(3) * h8 + kq;
-#undef SKM_AROW
-  const int64_t ob0 = (c_base + pr) * h8 + kq, ob1 = ob0 + 64 * h8;
-  const int64_t ob2 = ob1 + 64 * h8, ob3 = ob2 + 64 * h8;
-  uint4 ra0 = xv[oa0], ra1 = xv[oa1], ra2 = xv[oa2], ra3 = xv[oa3];
-  uint4 rb0 = cv[ob0], rb1 = cv[ob1], rb2 = cv[ob2], rb3 = cv[ob3];
-#define SKM_HEAD_STORE(buf)                                                      \
-  do {                                                                           \
-    *reinterpret_cast<uint4 *>(&lds[buf][0][so]) = ra0;                          \
-    *reinterpret_cast<uint4 *>(&lds[buf][0][so + 64 * kGRow]) = ra1;             \
-    *reinterpret_cast<uint4 *>(&lds[buf][0][so + 128 * kGRow]) = ra2;            \
-    *reinterpret_cast<uint4 *>(&lds[buf][0][so + 192 * kGRow]) = ra3;            \
-    *reinterpret_cast<uint4 *>(&lds[buf][1][so]) = rb0;                          \
-    *reinterpret_cast<uint4 *>(&lds[buf][1][so + 64 * kGRow]) = rb1;             \
-    *reinterpret_cast<uint4 *>(&lds[buf][1][so + 128 * kGRow]) = rb2;            \
-    *reinterpret_cast<uint4 *>(&lds[buf][1][so + 192 * kGRow]) = rb3;            \
-  } while (0)
+  int64_t oa[kNA], ob[kNB];
+#pragma unroll
+  for (int u = 0; u < kNA; ++u) {
+    const int64_t r = row0 + min<int64_t>(r_base + pr + kRPP * u, nb - 1);
+    oa[u] = (rows ? (int64_t)rows[r] : r) * h8 + kq;
+  }
+#pragma unroll
+  for (int u = 0; u < kNB; ++u) ob[u] = (c_base + pr + kRPP * u) * h8 + kq;
+  v4u ra[kNA], rbv[kNB];
+#pragma unroll
+  for (int u = 0; u < kNA; ++u) ra[u] = xv[oa[u]];
+#pragma unroll
+  for (int u = 0; u < kNB; ++u) rbv[u] = cv[ob[u]];
 
   f32x16_t acc[2][4];
 #pragma unroll
@@ -200,43 +233,48 @@ __global__ __launch_bounds__(512) void k_head_gemm(const uint16_t *__restrict__ 
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[mb][n4][i] = 0.f;
 
-  const int nk = H / kGK;
-  SKM_HEAD_STORE(0);
+  const int nk = H / GK;
+#pragma unroll
+  for (int u = 0; u < kNA; ++u) *reinterpret_cast<v4u *>(&lds_a[0][so + kRPP * u * kRow]) = ra[u];
+#pragma unroll
+  for (int u = 0; u < kNB; ++u) *reinterpret_cast<v4u *>(&lds_b[0][so + kRPP * u * kRow]) = rbv[u];
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < nk) {
-      const int q = (kt + 1) * (kGK / 8);
-      ra0 = xv[oa0 + q];
-      ra1 = xv[oa1 + q];
-      ra2 = xv[oa2 + q];
-      ra3 = xv[oa3 + q];
-      rb0 = cv[ob0 + q];
-      rb1 = cv[ob1 + q];
-      rb2 = cv[ob2 + q];
-      rb3 = cv[ob3 + q];
+      const int q = (kt + 1) * kPPR;
+#pragma unroll
+      for (int u = 0; u < kNA; ++u) ra[u] = xv[oa[u] + q];
+#pragma unroll
+      for (int u = 0; u < kNB; ++u) rbv[u] = cv[ob[u] + q];
     }
 #pragma unroll
-    for (int ks = 0; ks < kGK / 16; ++ks) {
+    for (int ks = 0; ks < GK / 16; ++ks) {
       bf16x8_t a[2], b[4];
 #pragma unroll
       for (int mb = 0; mb < 2; ++mb)
         a[mb] = *reinterpret_cast<const bf16x8_t *>(
-            &lds[cur][0][(wm * 64 + mb * 32 + li) * kGRow + ks * 32 + kg * 16]);
+            &lds_a[cur][(wm * 64 + mb * 32 + li) * kRow + ks * 32 + kg * 16]);
 #pragma unroll
       for (int n4 = 0; n4 < 4; ++n4)
         b[n4] = *reinterpret_cast<const bf16x8_t *>(
-            &lds[cur][1][(wn * 128 + n4 * 32 + li) * kGRow + ks * 32 + kg * 16]);
+            &lds_b[cur][(wn * 128 + n4 * 32 + li) * kRow + ks * 32 + kg * 16]);
 #pragma unroll
       for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
         for (int n4 = 0; n4 < 4; ++n4)
           acc[mb][n4] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mb], b[n4], acc[mb][n4], 0, 0, 0);
     }
-    if (kt + 1 < nk) SKM_HEAD_STORE(cur ^ 1);
+    if (kt + 1 < nk) {
+#pragma unroll
+      for (int u = 0; u < kNA; ++u)
+        *reinterpret_cast<v4u *>(&lds_a[cur ^ 1][so + kRPP * u * kRow]) = ra[u];
+#pragma unroll
+      for (int u = 0; u < kNB; ++u)
+        *reinterpret_cast<v4u *>(&lds_b[cur ^ 1][so + kRPP * u * kRow]) = rbv[u];
+    }
     __syncthreads();
   }
-#undef SKM_HEAD_STORE
 
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
@@ -254,6 +292,10 @@ __global__ __launch_bounds__(512) void k_head_gemm(const uint16_t *__restrict__ 
         }
       }
 }
+
+// Shape of the head product: K step (H is a multiple of 64, so of either
+// step) and wavefront rows.
+constexpr int kHeadGK = 64, kHeadWM = 4;
 
 // ------------------------------------------------------------------ scan
 // Exclusive prefix sum of n int64 values into out[0..n] (out[n] = total):
@@ -378,10 +420,10 @@ hipError_t launch_head_gemm(const uint16_t *xh, int32_t H, int64_t row0, int64_t
                             const int32_t *rows, const uint16_t *ch, int64_t col0, int64_t ncols,
                             float *hs, int64_t ldh, hipStream_t s) {
   if (nb <= 0) return hipSuccess;
-  if (H % kGK != 0 || ncols % kGN != 0 || ldh < ncols) return hipErrorInvalidValue;
-  const int64_t blocks = ((nb + kGM - 1) / kGM) * (ncols / kGN);
-  hipLaunchKernelGGL(k_head_gemm, dim3((unsigned)blocks), dim3(512), 0, s, xh, H, row0, nb, rows,
-                     ch + col0 * (int64_t)H, ncols, hs, ldh);
+  if (H % 64 != 0 || ncols % kGN != 0 || ldh < ncols) return hipErrorInvalidValue;
+  const int64_t blocks = gemm_blocks(nb, ncols / kGN, 64 * kHeadWM);
+  hipLaunchKernelGGL((k_head_gemm<kHeadGK, kHeadWM>), dim3((unsigned)blocks), dim3(128 * kHeadWM),
+                     0, s, xh, H, row0, nb, rows, ch + col0 * (int64_t)H, ncols, hs, ldh);
   return hipGetLastError();
 }
 
