@@ -144,6 +144,9 @@ typedef struct {
                                  (measured on the last full pass) exceeds the cost of
                                  building its compacted copy (measured at its last
                                  use).  Results are the same either way. */
+  int32_t index_always;       /* SKM_INDEX: 1 = query and rebuild the index after
+                                 every update even when it decides few rows (no
+                                 back-off); 0 (default) = back off (Sec. 4.3) */
 } skm_config;
 
 typedef struct {
@@ -187,6 +190,10 @@ typedef struct {
   int32_t head_launches;      /* launches of the head GEMM */
   double head_pairs;          /* (row, centroid) pairs the head GEMMs multiplied,
                                  each over head_terms terms */
+  float ms_index_build;       /* device time of the index build (part of ms_index) */
+  int32_t index_build;        /* index build of this update: 0 none, 1 full,
+                                 2 only the changed centroids (Sec. 3.2 entries of
+                                 the others kept) */
 } skm_iter_stats;
 
 /* One measured shape of the scoring work (skm_autotune). */

@@ -574,54 +574,130 @@ skm_status sum_changed(skm_ctx *c, int32_t n_ids, std::vector<int32_t> &ids) {
 }
 
 // Entry-sized buffers of the index (keys and terms twice for the sort, prefix
-// sums, G): 40 bytes per entry (plus 8 per centroid).
+// sums, G, and G2 for a quarter of them): 42 bytes per entry (plus 16 per
+// centroid).
 skm_status alloc_index_entries(skm_ctx *c, int64_t cap) {
   const int64_t old = c->idx_cap_entries;
   dfree(c, c->idx_key0, old * 8);
   dfree(c, c->idx_key1, old * 8);
   dfree(c, c->idx_term0, old * 4);
   dfree(c, c->idx_term1, old * 4);
-  dfree(c, c->idx_Q, (old + c->k) * 8);
+  dfree(c, c->idx_Q, (old + 2 * (int64_t)c->k) * 8);
   dfree(c, c->idx_G, old * 8);
+  dfree(c, c->idx_G2, (old / 4 + 1024) * 8);
   c->idx_key0 = c->idx_key1 = nullptr;
   c->idx_term0 = c->idx_term1 = nullptr;
   c->idx_Q = nullptr;
-  c->idx_G = nullptr;
+  c->idx_G = c->idx_G2 = nullptr;
   c->idx_cap_entries = 0;
   c->index_ready = false;
   ST_TRY(dalloc(c, &c->idx_key0, (size_t)cap));
   ST_TRY(dalloc(c, &c->idx_key1, (size_t)cap));
   ST_TRY(dalloc(c, &c->idx_term0, (size_t)cap));
   ST_TRY(dalloc(c, &c->idx_term1, (size_t)cap));
-  ST_TRY(dalloc(c, &c->idx_Q, (size_t)(cap + c->k)));
+  ST_TRY(dalloc(c, &c->idx_Q, (size_t)(cap + 2 * (int64_t)c->k)));
   ST_TRY(dalloc(c, &c->idx_G, (size_t)cap));
+  ST_TRY(dalloc(c, &c->idx_G2, (size_t)(cap / 4 + 1024)));
   c->idx_cap_entries = cap;
   return SKM_OK;
 }
 
-// Sec. 3.2 index from the current master: entries per centroid, sorted, prefix
-// sums of squares, term-major G.  Entry-sized buffers grow on demand (by half
-// again, so that a growing run reallocates only a few times); without an HBM
-// budget skm_init reserves min(nnz, k D) entries up to 16 GiB at once.
-skm_status build_index(skm_ctx *c) {
+IndexBuild index_build_args(skm_ctx *c) {
+  return IndexBuild{c->master,     c->k,         c->D,         c->idx_sstart, c->idx_cnt,
+                    c->idx_qstart, c->idx_key0,  c->idx_key1,  c->idx_term0,  c->idx_term1,
+                    c->idx_Q,      c->idx_mask,  c->idx_blkpre, c->idx_tcnt,  c->idx_toff,
+                    c->idx_G};
+}
+
+// Sec. 3.2 index from the current master.  With the changed centroids of the
+// last update (ids, ascending, device and host copies) and an index that was
+// valid before it, only those centroids are rebuilt (segments appended, G2
+// over every centroid rebuilt since the last full build); otherwise, or when
+// the rebuilt centroids hold more than a quarter of all entries or the
+// buffers are full, everything is rebuilt and compacted.  Entry-sized buffers
+// grow on demand (by half again, so that a growing run reallocates only a
+// few times); without an HBM budget skm_init reserves min(nnz, k D) entries
+// up to 16 GiB at once.
+skm_status build_index(skm_ctx *c, const int32_t *ids_dev = nullptr,
+                       const std::vector<int32_t> *ids = nullptr) {
   hipStream_t s = c->stream;
+  const int32_t k = c->k;
   HIP_TRY(c, hipEventRecord(c->ev[6], s));
-  HIP_TRY(c, index_build_counts(c->master, c->k, c->D, c->idx_cnt, c->idx_eoff, s));
-  int64_t total = 0;
-  HIP_TRY(c, hipMemcpyAsync(&total, c->idx_eoff + c->k, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  HIP_TRY(c, hipStreamSynchronize(s));
-  if (total > c->idx_cap_entries) {
-    const int64_t bound = std::min<int64_t>(c->Z, (int64_t)c->k * c->D);
-    const int64_t cap = std::max<int64_t>(std::min<int64_t>(total + total / 2, bound), total);
-    ST_TRY(alloc_index_entries(c, std::max<int64_t>(cap, 1024)));
+  c->idx_h_cnt.resize(k, 0);
+  c->idx_h_dirty.resize(k, 0);
+  const bool can_delta = ids && ids_dev && c->index_ready && c->idx_cap_entries > 0 &&
+                         4 * (int64_t)ids->size() <= (int64_t)k;
+  c->index_ready = false;
+  bool full = !can_delta;
+  if (!full) {
+    const int32_t n = (int32_t)ids->size();
+    if (n > 0) {
+      HIP_TRY(c, index_counts(c->master, k, c->D, ids_dev, n, c->idx_cnt, s));
+      HIP_TRY(c, index_place(ids_dev, n, c->idx_cnt, c->idx_used_e, c->idx_used_q, c->idx_sstart,
+                             c->idx_qstart, c->idx_tot, s));
+      int64_t tot[2] = {0, 0};
+      HIP_TRY(c, hipMemcpyAsync(tot, c->idx_tot, sizeof(tot), hipMemcpyDeviceToHost, s));
+      HIP_TRY(c, hipMemcpyAsync(c->idx_h_cnt.data(), c->idx_cnt, sizeof(int32_t) * k,
+                                hipMemcpyDeviceToHost, s));
+      HIP_TRY(c, hipStreamSynchronize(s));
+      for (int32_t j : *ids)
+        if (!c->idx_h_dirty[j]) {
+          c->idx_h_dirty[j] = 1;
+          c->idx_h_dids.push_back(j);
+        }
+      int64_t live = 0, dirty = 0;
+      for (int32_t j = 0; j < k; ++j) live += c->idx_h_cnt[j];
+      for (int32_t j : c->idx_h_dids) dirty += c->idx_h_cnt[j];
+      if (c->idx_used_e + tot[0] > c->idx_cap_entries ||
+          c->idx_used_q + tot[1] > c->idx_cap_entries + 2 * (int64_t)k || 4 * dirty > live) {
+        full = true;
+      } else {
+        const IndexBuild ib = index_build_args(c);
+        HIP_TRY(c, index_segments(ib, ids_dev, n, s));
+        c->idx_used_e += tot[0];
+        c->idx_used_q += tot[1];
+        c->idx_entries = live;
+        std::sort(c->idx_h_dids.begin(), c->idx_h_dids.end());
+        const int32_t nd = (int32_t)c->idx_h_dids.size();
+        HIP_TRY(c, hipMemcpyAsync(c->idx_dids, c->idx_h_dids.data(), sizeof(int32_t) * nd,
+                                  hipMemcpyHostToDevice, s));
+        HIP_TRY(c, hipMemcpyAsync(c->idx_dirty, c->idx_h_dirty.data(), k, hipMemcpyHostToDevice, s));
+        HIP_TRY(c, index_delta(ib, c->idx_dids, nd, c->idx_dirty, c->idx_tcnt2, c->idx_cur2,
+                               c->idx_toff2, c->idx_G2, c->idx_dbits, s));
+        c->idx_last_build = 2;
+      }
+    } else {
+      c->idx_last_build = 2;
+    }
   }
-  IndexBuild ib{c->master, c->k, c->D, c->idx_eoff, c->idx_key0, c->idx_key1, c->idx_term0,
-                c->idx_term1, c->idx_Q, c->idx_mask, c->idx_blkpre, c->idx_tcnt, c->idx_toff,
-                c->idx_G};
-  HIP_TRY(c, index_build_rest(ib, s));
+  if (full) {
+    HIP_TRY(c, index_counts(c->master, k, c->D, nullptr, k, c->idx_cnt, s));
+    HIP_TRY(c, index_place(nullptr, k, c->idx_cnt, 0, 0, c->idx_sstart, c->idx_qstart, c->idx_tot,
+                           s));
+    int64_t tot[2] = {0, 0};
+    HIP_TRY(c, hipMemcpyAsync(tot, c->idx_tot, sizeof(tot), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipMemcpyAsync(c->idx_h_cnt.data(), c->idx_cnt, sizeof(int32_t) * k,
+                              hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    const int64_t total = tot[0];
+    if (total > c->idx_cap_entries) {
+      const int64_t bound = std::min<int64_t>(c->Z, (int64_t)k * c->D);
+      const int64_t cap = std::max<int64_t>(std::min<int64_t>(total + total / 2, bound), total);
+      ST_TRY(alloc_index_entries(c, std::max<int64_t>(cap, 1024)));
+    }
+    const IndexBuild ib = index_build_args(c);
+    HIP_TRY(c, index_segments(ib, nullptr, k, s));
+    HIP_TRY(c, index_terms(ib, s));
+    std::fill(c->idx_h_dirty.begin(), c->idx_h_dirty.end(), 0);
+    c->idx_h_dids.clear();
+    c->idx_used_e = total;
+    c->idx_used_q = tot[1];
+    c->idx_entries = total;
+    c->idx_g_entries = total;
+    c->idx_last_build = 1;
+  }
   HIP_TRY(c, hipEventRecord(c->ev[7], s));
   HIP_TRY(c, hipStreamSynchronize(s));
-  c->idx_entries = total;
   c->index_ready = true;
   c->ms_index_build = elapsed(c->ev[6], c->ev[7]);
   return SKM_OK;
@@ -640,8 +716,13 @@ IndexArgs index_args(skm_ctx *c) {
   x.a_prev = c->a_prev;
   x.toff = c->idx_toff;
   x.G = c->idx_G;
-  x.eoff = c->idx_eoff;
+  x.cnt = c->idx_cnt;
+  x.qstart = c->idx_qstart;
   x.Q = c->idx_Q;
+  x.n_dirty = (int32_t)c->idx_h_dids.size();
+  x.dbits = c->idx_dbits;
+  x.toff2 = c->idx_toff2;
+  x.G2 = c->idx_G2;
   for (int i = 0; i < 8; ++i) x.lambda[i] = c->cfg.lambda[i];
   x.n_lambda = c->cfg.n_lambda;
   x.forced_level = -1;
@@ -776,12 +857,12 @@ size_t skm_context_bytes(const skm_csr *docs, const skm_config *cfg) {
     b += (ncc ? 2 : 1) * nch * (9 * D + 16);
   if (index) {
     const double nb = std::ceil(k / 64);
-    b += N * (1 + 4 + 4 * 128 + 4 + 4) + 12 * (k + 1) + D * (12 * nb + 12);
+    b += N * (1 + 4 + 4 * 128 + 4 + 4) + 56 * (k + 1) + D * (12 * nb + 28);
   }
-  // non-zeros of all centroids are at most min(Z, k D): index entries (40 B
+  // non-zeros of all centroids are at most min(Z, k D): index entries (42 B
   // each, 25 % headroom) and code lists (8 B each, per-chunk stride headroom)
   const double cnz = std::min(Z, k * D);
-  if (index) b += 1.25 * 40 * cnz;
+  if (index) b += 1.25 * 42 * cnz;
   if (!(cfg->flags & SKM_DENSE_ONLY)) b += (ncc ? 2 : 1) * 1.25 * 8 * std::min(cnz, nch * 512 * D);
   // the dense head (BF16 / FP8): at most head_max_terms terms
   if (cfg->precision != SKM_FP32 && cfg->head_max_terms >= 64) {
@@ -944,11 +1025,19 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
     const int64_t nb = (k + 63) / 64;
     A_(c->mode, N);
     A_(c->idx_cnt, k);
-    A_(c->idx_eoff, k + 1);
+    A_(c->idx_sstart, k);
+    A_(c->idx_qstart, k);
+    A_(c->idx_tot, 2);
     A_(c->idx_mask, c->D * nb);
     A_(c->idx_blkpre, c->D * nb);
     A_(c->idx_tcnt, c->D);
     A_(c->idx_toff, c->D + 1);
+    A_(c->idx_dirty, k);
+    A_(c->idx_dids, k);
+    A_(c->idx_dbits, (k + 31) / 32);
+    A_(c->idx_tcnt2, c->D);
+    A_(c->idx_cur2, c->D);
+    A_(c->idx_toff2, c->D + 1);
     A_(c->idx_rows, N);
     A_(c->idx_cand, N * (int64_t)c->idx_cap);
     A_(c->idx_ncand, N);
@@ -1210,7 +1299,7 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
     c->ms_full_score = elapsed(c->ev[5], c->ev[1]);
   c->assigned = true;
   c->last_moved = c->have_prev ? (int64_t)stv[4] : c->N;
-  if (use_index) {
+  if (use_index && !c->cfg.index_always) {
     // Sec. 4.3: the index only pays when it decides rows; back off otherwise
     if ((double)stv[2] < 0.05 * (double)std::max<int64_t>(c->idx_eligible, 1)) {
       c->idx_skip = c->idx_backoff;
@@ -1516,12 +1605,16 @@ skm_status skm_update(skm_ctx *c, skm_iter_stats *st_out) {
   ST_TRY(rebuild_tiles(c, c->changed, &chunks));
   HIP_TRY(c, hipEventRecord(c->ev[4], s));
   c->ms_index_build = 0.f;
+  c->idx_last_build = 0;
+  const bool index_was_ready = c->index_ready;
   c->index_ready = false;
   if (c->cfg.flags & SKM_INDEX) {
     if (c->idx_skip > 0) {
-      c->idx_skip -= 1;   // index off for this iteration: no rebuild
+      c->idx_skip -= 1;   // index off for this iteration: no rebuild (the next is full)
     } else {
-      ST_TRY(build_index(c));
+      // valid for the previous centroids: rebuild the changed ones
+      c->index_ready = index_was_ready;
+      ST_TRY(build_index(c, c->ch_ids, &ids));
     }
   }
   double red[3];
@@ -1541,6 +1634,8 @@ skm_status skm_update(skm_ctx *c, skm_iter_stats *st_out) {
     st_out->max_shift_sq = red[2];
     st_out->ms_update = elapsed(c->ev[3], c->ev[4]);
     if (c->cfg.flags & SKM_INDEX) st_out->ms_index += c->ms_index_build;
+    st_out->ms_index_build = c->ms_index_build;
+    st_out->index_build = c->idx_last_build;
   }
   return SKM_OK;
 }
@@ -2068,26 +2163,45 @@ skm_status skm_get_index(const skm_ctx *c, int32_t level, int64_t *offsets, uint
   if (level < 0 || level >= c->cfg.n_lambda) return fail(SKM_E_INVALID, "level out of range");
   if (!offsets || !n_entries) return fail(SKM_E_INVALID, "offsets / n_entries is NULL");
   skm_ctx *m = const_cast<skm_ctx *>(c);
-  const int64_t E = c->idx_entries, D = c->D, k = c->k;
-  std::vector<int64_t> toff(D + 1), eoff(k + 1);
-  std::vector<uint2> G(std::max<int64_t>(E, 1));
-  std::vector<double> Q(E + k);
+  const int64_t D = c->D, k = c->k, EG = c->idx_g_entries;
+  const int64_t nd = (int64_t)c->idx_h_dids.size();
+  std::vector<int64_t> toff(D + 1), toff2(D + 1, 0), qstart(k);
+  std::vector<int32_t> cnt(k);
+  std::vector<uint2> G(std::max<int64_t>(EG, 1));
+  std::vector<double> Q(std::max<int64_t>(c->idx_used_q, 1));
   HIP_TRY(m, hipMemcpyAsync(toff.data(), c->idx_toff, 8 * (D + 1), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(m, hipMemcpyAsync(eoff.data(), c->idx_eoff, 8 * (k + 1), hipMemcpyDeviceToHost, c->stream));
-  if (E > 0) {
-    HIP_TRY(m, hipMemcpyAsync(G.data(), c->idx_G, 8 * E, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(m, hipMemcpyAsync(Q.data(), c->idx_Q, 8 * (E + k), hipMemcpyDeviceToHost, c->stream));
-  }
+  HIP_TRY(m, hipMemcpyAsync(cnt.data(), c->idx_cnt, 4 * k, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(m, hipMemcpyAsync(qstart.data(), c->idx_qstart, 8 * k, hipMemcpyDeviceToHost, c->stream));
+  if (EG > 0) HIP_TRY(m, hipMemcpyAsync(G.data(), c->idx_G, 8 * EG, hipMemcpyDeviceToHost, c->stream));
+  if (c->idx_used_q > 0)
+    HIP_TRY(m, hipMemcpyAsync(Q.data(), c->idx_Q, 8 * c->idx_used_q, hipMemcpyDeviceToHost,
+                              c->stream));
+  if (nd > 0)
+    HIP_TRY(m, hipMemcpyAsync(toff2.data(), c->idx_toff2, 8 * (D + 1), hipMemcpyDeviceToHost,
+                              c->stream));
   HIP_TRY(m, hipStreamSynchronize(c->stream));
+  std::vector<uint2> G2(std::max<int64_t>(toff2[D], 1));
+  if (toff2[D] > 0) {
+    HIP_TRY(m, hipMemcpyAsync(G2.data(), c->idx_G2, 8 * toff2[D], hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(m, hipStreamSynchronize(c->stream));
+  }
   const double lam = c->cfg.lambda[level];
   // m_p = least m with Q_j[min(p + m, n_j)] - Q_j[p] >= thr (the query's
-  // threshold for centroid j); no P entry when none
+  // threshold for centroid j); no P entry when none.  A term's (centroid,
+  // position) pairs: those of G of centroids not rebuilt since the last full
+  // build, and those of G2, ascending by centroid.
   int64_t n = 0;
   offsets[0] = 0;
+  std::vector<uint2> pairs;
   for (int64_t t = 0; t < D; ++t) {
-    for (int64_t g = toff[t]; g < toff[t + 1]; ++g) {
-      const int64_t j = G[g].x, p = G[g].y, nj = eoff[j + 1] - eoff[j];
-      const double *q = Q.data() + eoff[j] + j;
+    pairs.clear();
+    for (int64_t g = toff[t]; g < toff[t + 1]; ++g)
+      if (nd == 0 || !c->idx_h_dirty[G[g].x]) pairs.push_back(G[g]);
+    for (int64_t g = toff2[t]; g < toff2[t + 1]; ++g) pairs.push_back(G2[g]);
+    std::sort(pairs.begin(), pairs.end(), [](const uint2 &x, const uint2 &y) { return x.x < y.x; });
+    for (const uint2 &pr : pairs) {
+      const int64_t j = pr.x, p = pr.y, nj = cnt[j];
+      const double *q = Q.data() + qstart[j];
       const double thr = index_threshold(lam, nj, q[nj]);
       if (q[nj] - q[p] < thr) continue;
       int64_t lo = 1, hi = nj - p;

@@ -135,10 +135,12 @@ struct IndexBuild {
   const double *master;
   int32_t k;
   int64_t D;
-  const int64_t *eoff;   // [k + 1] entry offsets per centroid
+  const int64_t *sstart; // [k] first entry of each centroid's segment
+  const int32_t *cnt;    // [k] entries (non-zeros) per centroid
+  const int64_t *qstart; // [k] first prefix sum of each centroid (cnt + 1 of them)
   uint64_t *key0, *key1; // sort keys (~bits of the value), ping-pong
   int32_t *term0, *term1;
-  double *Q;             // prefix sums of squares, centroid j at eoff[j] + j
+  double *Q;             // prefix sums of squares
   uint64_t *mask;        // [D][ceil(k/64)] non-zero masks
   int32_t *blkpre;       // [D][ceil(k/64)] per-term prefix of mask popcounts
   int32_t *tcnt;         // [D] centroids per term
@@ -162,8 +164,13 @@ struct IndexArgs {
   int32_t n_ch;             // changed centroids (cost guard of those rows)
   const int64_t *toff;
   const uint2 *G;
-  const int64_t *eoff;
+  const int32_t *cnt;       // entries per centroid
+  const int64_t *qstart;    // first prefix sum per centroid
   const double *Q;
+  int32_t n_dirty;          // centroids rebuilt since the last full build (0: no G2)
+  const uint32_t *dbits;    // [ceil(k / 32)] their bitmap
+  const int64_t *toff2;     // [D + 1] G2 offsets
+  const uint2 *G2;          // (centroid, position) of the dirty centroids, term-major
   double lambda[8];
   int32_t n_lambda;
   int32_t forced_level;     // >= 0: use this level, no baseline, no cost guard
@@ -207,7 +214,7 @@ __host__ __device__ inline double index_threshold(double lam, int64_t n, double 
 
 // LDS of the index query: k positions (4 B) and k 16-bit counts.
 __host__ __device__ inline size_t index_lds_bytes(int32_t k) {
-  return sizeof(uint32_t) * ((size_t)k + ((size_t)k + 1) / 2);
+  return sizeof(uint32_t) * ((size_t)k + ((size_t)k + 1) / 2 + ((size_t)k + 31) / 32);
 }
 
 }  // namespace skm
@@ -285,9 +292,12 @@ struct skm_ctx {
   // Sec. 3.2 index (built when SKM_INDEX is set)
   bool index_ready = false;
   int64_t idx_cap_entries = 0;   // capacity of the entry-sized buffers
-  int64_t idx_entries = 0;       // entries of the current build
-  int32_t *idx_cnt = nullptr;
-  int64_t *idx_eoff = nullptr;
+  int64_t idx_entries = 0;       // live entries (all centroids)
+  int64_t idx_g_entries = 0;     // entries of G (last full build)
+  int64_t idx_used_e = 0, idx_used_q = 0;  // entry / prefix-sum slots in use
+  int32_t *idx_cnt = nullptr;    // [k] entries per centroid
+  int64_t *idx_sstart = nullptr, *idx_qstart = nullptr;  // [k] segment, prefix-sum starts
+  int64_t *idx_tot = nullptr;    // [2] totals of the last placement
   uint64_t *idx_key0 = nullptr, *idx_key1 = nullptr;
   int32_t *idx_term0 = nullptr, *idx_term1 = nullptr;
   double *idx_Q = nullptr;
@@ -295,6 +305,17 @@ struct skm_ctx {
   uint64_t *idx_mask = nullptr;
   int32_t *idx_blkpre = nullptr, *idx_tcnt = nullptr;
   int64_t *idx_toff = nullptr;
+  // centroids rebuilt since the last full build ("dirty") and their G2
+  uint8_t *idx_dirty = nullptr;  // [k]
+  int32_t *idx_dids = nullptr;   // [k] dirty ids
+  uint32_t *idx_dbits = nullptr; // [ceil(k / 32)]
+  int32_t *idx_tcnt2 = nullptr, *idx_cur2 = nullptr;  // [D]
+  int64_t *idx_toff2 = nullptr;  // [D + 1]
+  uint2 *idx_G2 = nullptr;       // [idx_cap_entries / 4 + 1024]
+  std::vector<int32_t> idx_h_cnt;     // host copy of idx_cnt
+  std::vector<uint8_t> idx_h_dirty;   // host copy of idx_dirty
+  std::vector<int32_t> idx_h_dids;    // host copy of idx_dids
+  int32_t idx_last_build = 0;    // 0 none, 1 full, 2 changed centroids only
   int32_t *idx_rows = nullptr, *idx_cand = nullptr, *idx_ncand = nullptr, *idx_level = nullptr;
   int32_t idx_cap = 128;
   double idx_guard = 0.25;
@@ -425,9 +446,16 @@ hipError_t pp_select(const uint64_t *bsum, const uint64_t *w, int64_t n, uint64_
                      uint8_t *chosen, int32_t *rows, int32_t m, hipStream_t s);
 
 // kernels_index.hip
-hipError_t index_build_counts(const double *master, int32_t k, int64_t D, int32_t *cnt,
-                              int64_t *eoff, hipStream_t s);
-hipError_t index_build_rest(const IndexBuild &ib, hipStream_t s);
+hipError_t index_counts(const double *master, int32_t k, int64_t D, const int32_t *ids,
+                        int32_t n, int32_t *cnt, hipStream_t s);
+hipError_t index_place(const int32_t *ids, int32_t n, const int32_t *cnt, int64_t base_e,
+                       int64_t base_q, int64_t *sstart, int64_t *qstart, int64_t *tot,
+                       hipStream_t s);
+hipError_t index_segments(const IndexBuild &ib, const int32_t *ids, int32_t n, hipStream_t s);
+hipError_t index_terms(const IndexBuild &ib, hipStream_t s);
+hipError_t index_delta(const IndexBuild &ib, const int32_t *dirty_ids, int32_t n_dirty,
+                       const uint8_t *dirty, int32_t *tcnt2, int32_t *cur2, int64_t *toff2,
+                       uint2 *G2, uint32_t *dbits, hipStream_t s);
 // Ascending list of the rows whose previous centroid is flagged in `changed`
 // (keep = 0) or not flagged (keep = 1), all rows when changed is nullptr,
 // leaving out rows the index finished (mode[i] == 2) when mode is given, and

@@ -2,9 +2,16 @@
 //
 // Build (from the FP64 master):
 //   - every centroid's non-zero entries, sorted by value descending (equal
-//     values: ascending term), with the FP64 prefix sums Q_j of their squares;
+//     values: ascending term), with the FP64 prefix sums Q_j of their squares
+//     (a segment per centroid at sstart[j] with cnt[j] entries, its prefix
+//     sums at qstart[j]);
 //   - G: for every term t, the centroids with a non-zero at t, ascending, each
 //     with the term's position p in that centroid's sorted order.
+// After an update only the changed centroids are rebuilt: their new segments
+// are appended behind the others, they are marked dirty, their entries in G
+// are skipped, and G2 holds the (centroid, position) entries of every dirty
+// centroid, term-major.  A full build (when the dirty entries exceed a
+// quarter of all, or the buffers run out) compacts everything into G again.
 // The paper's minimum overlap count of position p for threshold lam is
 //   m_p = least m with Q_j[min(p + m, n_j)] - Q_j[p] >= lam^2,
 // and the positions entering P are those where such an m exists.  m_p is
@@ -29,10 +36,11 @@ __device__ inline bool key_less(uint64_t ka, int32_t ta, uint64_t kb, int32_t tb
   return ka < kb || (ka == kb && ta < tb);
 }
 
-// Non-zeros per centroid.
-__global__ __launch_bounds__(256) void k_centroid_nnz(const double *master, int64_t D, int32_t *cnt) {
+// Non-zeros per centroid (the listed ones, or all when ids is nullptr).
+__global__ __launch_bounds__(256) void k_centroid_nnz(const double *master, int64_t D,
+                                                      const int32_t *ids, int32_t *cnt) {
   __shared__ int32_t sh[256];
-  const int j = blockIdx.x;
+  const int j = ids ? ids[blockIdx.x] : blockIdx.x;
   int c = 0;
   for (int64_t t = threadIdx.x; t < D; t += 256) c += master[(int64_t)j * D + t] != 0.0;
   sh[threadIdx.x] = c;
@@ -44,17 +52,53 @@ __global__ __launch_bounds__(256) void k_centroid_nnz(const double *master, int6
   if (threadIdx.x == 0) cnt[j] = sh[0];
 }
 
+// Segments of the listed centroids (all when ids is nullptr), in list order
+// from base_e (entries) and base_q (prefix sums, one more each):
+// sstart[j] = base_e + entries before j, qstart[j] = base_q + the same + i
+// for the i-th listed centroid; tot = {entries, prefix-sum slots}.  One
+// workgroup of 1024 threads, each scanning a contiguous piece of the list.
+__global__ __launch_bounds__(1024) void k_place(const int32_t *ids, int64_t n, const int32_t *cnt,
+                                                int64_t base_e, int64_t base_q, int64_t *sstart,
+                                                int64_t *qstart, int64_t *tot) {
+  __shared__ int64_t sh[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t lo = min<int64_t>(t * per, n), hi = min(n, lo + per);
+  int64_t c = 0;
+  for (int64_t i = lo; i < hi; ++i) c += cnt[ids ? ids[i] : i];
+  sh[t] = c;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int64_t v = t >= o ? sh[t - o] : 0;
+    __syncthreads();
+    sh[t] += v;
+    __syncthreads();
+  }
+  int64_t pos = sh[t] - c;
+  for (int64_t i = lo; i < hi; ++i) {
+    const int64_t j = ids ? ids[i] : i;
+    sstart[j] = base_e + pos;
+    qstart[j] = base_q + pos + i;
+    pos += cnt[j];
+  }
+  if (t == 1023) {
+    tot[0] = sh[1023];
+    tot[1] = sh[1023] + n;
+  }
+}
+
 // Entries of centroid j: key = ~bits(value) (ascending key = descending
 // value, values are positive), term.  Coalesced sweeps of the FP64 row, each
 // wavefront appending its non-zeros by ballot at a workgroup counter; the
 // order within the segment is arbitrary, since k_sort_segments orders the
 // (key, term) pairs, which are unique, completely.
-__global__ __launch_bounds__(256) void k_extract(const double *master, int64_t D, const int64_t *eoff,
-                                                 uint64_t *key, int32_t *term) {
+__global__ __launch_bounds__(256) void k_extract(const double *master, int64_t D, const int32_t *ids,
+                                                 const int64_t *sstart, uint64_t *key,
+                                                 int32_t *term) {
   __shared__ int32_t fill;
-  const int j = blockIdx.x;
+  const int j = ids ? ids[blockIdx.x] : blockIdx.x;
   const double *row = master + (int64_t)j * D;
-  const int64_t base = eoff[j];
+  const int64_t base = sstart[j];
   const int lane = lane_id();
   if (threadIdx.x == 0) fill = 0;
   __syncthreads();
@@ -99,13 +143,14 @@ __device__ inline int64_t corank(int64_t o, const uint64_t *ka, const int32_t *t
 // Sorts each centroid's segment ascending by (key, term): bitonic runs of
 // 2048 in LDS, then merge passes between the two buffers.  The result ends in
 // (key0, term0).
-__global__ __launch_bounds__(256) void k_sort_segments(const int64_t *eoff, uint64_t *key0,
+__global__ __launch_bounds__(256) void k_sort_segments(const int32_t *ids, const int64_t *sstart,
+                                                       const int32_t *cnt, uint64_t *key0,
                                                        int32_t *term0, uint64_t *key1,
                                                        int32_t *term1) {
   __shared__ uint64_t sk[kRun];
   __shared__ int32_t st[kRun];
-  const int j = blockIdx.x;
-  const int64_t s0 = eoff[j], s1 = eoff[j + 1], n = s1 - s0;
+  const int j = ids ? ids[blockIdx.x] : blockIdx.x;
+  const int64_t s0 = sstart[j], n = cnt[j];
   if (n <= 1) return;
   for (int64_t r0 = 0; r0 < n; r0 += kRun) {
     const int64_t m = min<int64_t>(kRun, n - r0);
@@ -185,13 +230,14 @@ __global__ __launch_bounds__(256) void k_sort_segments(const int64_t *eoff, uint
 }
 
 // Q_j[0] = 0, Q_j[p + 1] = Q_j[p] + v_p^2 over the sorted entries (fixed
-// per-thread pieces + block scan: deterministic).  Q_j starts at qoff = eoff[j] + j.
-__global__ __launch_bounds__(256) void k_prefix_sq(const int64_t *eoff, const uint64_t *key,
-                                                   double *Q) {
+// per-thread pieces + block scan: deterministic).  Q_j starts at qstart[j].
+__global__ __launch_bounds__(256) void k_prefix_sq(const int32_t *ids, const int64_t *sstart,
+                                                   const int32_t *cnt, const int64_t *qstart,
+                                                   const uint64_t *key, double *Q) {
   __shared__ double sh[256];
-  const int j = blockIdx.x;
-  const int64_t s0 = eoff[j], n = eoff[j + 1] - s0;
-  double *q = Q + s0 + j;
+  const int j = ids ? ids[blockIdx.x] : blockIdx.x;
+  const int64_t s0 = sstart[j], n = cnt[j];
+  double *q = Q + qstart[j];
   const int64_t per = (n + 255) / 256;
   const int64_t lo = min<int64_t>((int64_t)threadIdx.x * per, n), hi = min(n, lo + per);
   double c = 0.0;
@@ -251,11 +297,12 @@ __global__ void k_term_prefix(const uint64_t *mask, int64_t D, int64_t nb, int32
 }
 
 // G entries: (centroid, position) at term t's slot ordered by centroid.
-__global__ __launch_bounds__(256) void k_fill_G(const int64_t *eoff, const int32_t *term,
-                                                const uint64_t *mask, const int32_t *blkpre,
-                                                const int64_t *toff, int64_t nb, uint2 *G) {
+__global__ __launch_bounds__(256) void k_fill_G(const int64_t *sstart, const int32_t *cnt,
+                                                const int32_t *term, const uint64_t *mask,
+                                                const int32_t *blkpre, const int64_t *toff,
+                                                int64_t nb, uint2 *G) {
   const int j = blockIdx.x;
-  const int64_t s0 = eoff[j], n = eoff[j + 1] - s0;
+  const int64_t s0 = sstart[j], n = cnt[j];
   const int64_t b = j >> 6;
   const uint64_t below = (j & 63) ? (~0ull >> (64 - (j & 63))) : 0ull;
   for (int64_t p = threadIdx.x; p < n; p += 256) {
@@ -263,6 +310,37 @@ __global__ __launch_bounds__(256) void k_fill_G(const int64_t *eoff, const int32
     const int64_t pos = toff[t] + blkpre[t * nb + b] + __popcll(mask[t * nb + b] & below);
     G[pos] = make_uint2((uint32_t)j, (uint32_t)p);
   }
+}
+
+// G2 over the dirty centroids ids[0 .. n): per-term counts, then the entries
+// at per-term cursors (their order within a term is immaterial to the query,
+// whose counts and best positions are order-free).
+__global__ __launch_bounds__(256) void k_g2_count(const int32_t *ids, const int64_t *sstart,
+                                                  const int32_t *cnt, const int32_t *term,
+                                                  int32_t *tcnt2) {
+  const int j = ids[blockIdx.x];
+  const int64_t s0 = sstart[j], n = cnt[j];
+  for (int64_t p = threadIdx.x; p < n; p += 256) atomicAdd(&tcnt2[term[s0 + p]], 1);
+}
+
+__global__ __launch_bounds__(256) void k_g2_fill(const int32_t *ids, const int64_t *sstart,
+                                                 const int32_t *cnt, const int32_t *term,
+                                                 const int64_t *toff2, int32_t *cur2, uint2 *G2) {
+  const int j = ids[blockIdx.x];
+  const int64_t s0 = sstart[j], n = cnt[j];
+  for (int64_t p = threadIdx.x; p < n; p += 256) {
+    const int32_t t = term[s0 + p];
+    G2[toff2[t] + atomicAdd(&cur2[t], 1)] = make_uint2((uint32_t)j, (uint32_t)p);
+  }
+}
+
+// Bit j of bits[j / 32] = dirty[j].
+__global__ void k_dirty_bits(const uint8_t *dirty, int32_t k, uint32_t *bits) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w * 32 >= k) return;
+  uint32_t m = 0;
+  for (int i = 0; i < 32 && w * 32 + i < k; ++i) m |= (dirty[w * 32 + i] ? 1u : 0u) << i;
+  bits[w] = m;
 }
 
 __global__ void k_scan_i32_to_i64(const int32_t *cnt, int64_t n, int64_t *off) {
@@ -306,10 +384,13 @@ __global__ void k_scan_i32_to_i64(const int32_t *cnt, int64_t n, int64_t *off) {
 // candidates that changed (its baseline is the unchanged previous centroid's
 // score), and the alternative it is guarded against scores n_ch centroids.
 // mode[row] = 2 marks rows finished here (scored by k_index_score).
+// Dirty centroids (rebuilt since the last full build) are taken from G2, their
+// stale entries in G skipped by a bitmap in LDS.
 __global__ __launch_bounds__(256) void k_index_query(IndexArgs x) {
   extern __shared__ uint32_t lds[];
   uint32_t *pmin = lds;                        // k positions
   uint32_t *cnt = lds + x.k;                   // k counts, two 16-bit counts per word
+  uint32_t *dbits = cnt + (x.k + 1) / 2;       // dirty bitmap, k bits
   __shared__ double red[256];
   __shared__ int32_t sh_i[256];
   __shared__ int s_level;
@@ -338,6 +419,7 @@ __global__ __launch_bounds__(256) void k_index_query(IndexArgs x) {
   for (int64_t q = b + threadIdx.x; q < e; q += 256) {
     const int32_t t = x.indices[q];
     gsum += (double)(x.toff[t + 1] - x.toff[t]);
+    if (x.n_dirty > 0) gsum += (double)(x.toff2[t + 1] - x.toff2[t]);
   }
   __syncthreads();
   red[threadIdx.x] = gsum;
@@ -367,13 +449,24 @@ __global__ __launch_bounds__(256) void k_index_query(IndexArgs x) {
   // 3. counts and best positions
   for (int j = threadIdx.x; j < x.k; j += 256) pmin[j] = 0xFFFFFFFFu;
   for (int j = threadIdx.x; j < (x.k + 1) / 2; j += 256) cnt[j] = 0;
+  const bool delta = x.n_dirty > 0;
+  if (delta)
+    for (int w = threadIdx.x; w < (x.k + 31) / 32; w += 256) dbits[w] = x.dbits[w];
   __syncthreads();
   for (int64_t q = b; q < e; ++q) {
     const int32_t t = x.indices[q];
     for (int64_t g = x.toff[t] + threadIdx.x; g < x.toff[t + 1]; g += 256) {
       const uint2 ent = x.G[g];
+      if (delta && ((dbits[ent.x >> 5] >> (ent.x & 31)) & 1u)) continue;
       atomicAdd(&cnt[ent.x >> 1], 1u << (16 * (ent.x & 1)));
       atomicMin(&pmin[ent.x], ent.y);
+    }
+    if (delta) {
+      for (int64_t g = x.toff2[t] + threadIdx.x; g < x.toff2[t + 1]; g += 256) {
+        const uint2 ent = x.G2[g];
+        atomicAdd(&cnt[ent.x >> 1], 1u << (16 * (ent.x & 1)));
+        atomicMin(&pmin[ent.x], ent.y);
+      }
     }
   }
   __syncthreads();
@@ -384,10 +477,10 @@ __global__ __launch_bounds__(256) void k_index_query(IndexArgs x) {
     int in = 0;
     const uint32_t cj = j < x.k ? (cnt[j >> 1] >> (16 * (j & 1))) & 0xFFFFu : 0u;
     if (cj > 0 && (!keep_row || x.changed[j])) {
-      const int64_t nj = x.eoff[j + 1] - x.eoff[j];
+      const int64_t nj = x.cnt[j];
       const int64_t p = pmin[j];
       const int64_t h = min<int64_t>(p + cj, nj);
-      const double *Qj = x.Q + x.eoff[j] + j;
+      const double *Qj = x.Q + x.qstart[j];
       in = (Qj[h] - Qj[p] >= index_threshold(lam, nj, Qj[nj])) ? 1 : 0;
     }
     sh_i[threadIdx.x] = in;
@@ -529,28 +622,61 @@ __global__ __launch_bounds__(256) void k_list_write(const int32_t *a_prev, const
 
 }  // namespace
 
-hipError_t index_build_counts(const double *master, int32_t k, int64_t D, int32_t *cnt,
-                              int64_t *eoff, hipStream_t s) {
-  hipLaunchKernelGGL(k_centroid_nnz, dim3((unsigned)k), dim3(256), 0, s, master, D, cnt);
-  hipLaunchKernelGGL(k_scan_i32_to_i64, dim3(1), dim3(1024), 0, s, cnt, (int64_t)k, eoff);
+hipError_t index_counts(const double *master, int32_t k, int64_t D, const int32_t *ids,
+                        int32_t n, int32_t *cnt, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_centroid_nnz, dim3((unsigned)n), dim3(256), 0, s, master, D, ids, cnt);
   return hipGetLastError();
 }
 
-hipError_t index_build_rest(const IndexBuild &ib, hipStream_t s) {
+hipError_t index_place(const int32_t *ids, int32_t n, const int32_t *cnt, int64_t base_e,
+                       int64_t base_q, int64_t *sstart, int64_t *qstart, int64_t *tot,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_place, dim3(1), dim3(1024), 0, s, ids, (int64_t)n, cnt, base_e, base_q,
+                     sstart, qstart, tot);
+  return hipGetLastError();
+}
+
+hipError_t index_segments(const IndexBuild &ib, const int32_t *ids, int32_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_extract, dim3((unsigned)n), dim3(256), 0, s, ib.master, ib.D, ids, ib.sstart,
+                     ib.key0, ib.term0);
+  hipLaunchKernelGGL(k_sort_segments, dim3((unsigned)n), dim3(256), 0, s, ids, ib.sstart, ib.cnt,
+                     ib.key0, ib.term0, ib.key1, ib.term1);
+  hipLaunchKernelGGL(k_prefix_sq, dim3((unsigned)n), dim3(256), 0, s, ids, ib.sstart, ib.cnt,
+                     ib.qstart, ib.key0, ib.Q);
+  return hipGetLastError();
+}
+
+hipError_t index_terms(const IndexBuild &ib, hipStream_t s) {
   const int32_t k = ib.k;
   const int64_t D = ib.D, nb = (k + 63) / 64;
-  hipLaunchKernelGGL(k_extract, dim3((unsigned)k), dim3(256), 0, s, ib.master, D, ib.eoff, ib.key0,
-                     ib.term0);
-  hipLaunchKernelGGL(k_sort_segments, dim3((unsigned)k), dim3(256), 0, s, ib.eoff, ib.key0,
-                     ib.term0, ib.key1, ib.term1);
-  hipLaunchKernelGGL(k_prefix_sq, dim3((unsigned)k), dim3(256), 0, s, ib.eoff, ib.key0, ib.Q);
   hipLaunchKernelGGL(k_term_masks, dim3((unsigned)nb, (unsigned)((D + 63) / 64)), dim3(256), 0, s,
                      ib.master, k, D, nb, ib.mask);
   hipLaunchKernelGGL(k_term_prefix, dim3((unsigned)((D + 255) / 256)), dim3(256), 0, s, ib.mask, D,
                      nb, ib.blkpre, ib.tcnt);
   hipLaunchKernelGGL(k_scan_i32_to_i64, dim3(1), dim3(1024), 0, s, ib.tcnt, D, ib.toff);
-  hipLaunchKernelGGL(k_fill_G, dim3((unsigned)k), dim3(256), 0, s, ib.eoff, ib.term0, ib.mask,
-                     ib.blkpre, ib.toff, nb, ib.G);
+  hipLaunchKernelGGL(k_fill_G, dim3((unsigned)k), dim3(256), 0, s, ib.sstart, ib.cnt, ib.term0,
+                     ib.mask, ib.blkpre, ib.toff, nb, ib.G);
+  return hipGetLastError();
+}
+
+hipError_t index_delta(const IndexBuild &ib, const int32_t *dirty_ids, int32_t n_dirty,
+                       const uint8_t *dirty, int32_t *tcnt2, int32_t *cur2, int64_t *toff2,
+                       uint2 *G2, uint32_t *dbits, hipStream_t s) {
+  const int64_t D = ib.D;
+  hipError_t e = launch_fill_i32(tcnt2, 0, D, s);
+  if (e == hipSuccess) e = launch_fill_i32(cur2, 0, D, s);
+  if (e != hipSuccess) return e;
+  if (n_dirty > 0)
+    hipLaunchKernelGGL(k_g2_count, dim3((unsigned)n_dirty), dim3(256), 0, s, dirty_ids, ib.sstart,
+                       ib.cnt, ib.term0, tcnt2);
+  hipLaunchKernelGGL(k_scan_i32_to_i64, dim3(1), dim3(1024), 0, s, tcnt2, D, toff2);
+  if (n_dirty > 0)
+    hipLaunchKernelGGL(k_g2_fill, dim3((unsigned)n_dirty), dim3(256), 0, s, dirty_ids, ib.sstart,
+                       ib.cnt, ib.term0, toff2, cur2, G2);
+  hipLaunchKernelGGL(k_dirty_bits, dim3((unsigned)((ib.k + 32 * 256 - 1) / (32 * 256))), dim3(256),
+                     0, s, dirty, ib.k, dbits);
   return hipGetLastError();
 }
 

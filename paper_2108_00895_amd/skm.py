@@ -59,7 +59,7 @@ class Config(ctypes.Structure):
                 ("init_centroids", ctypes.c_void_p), ("hbm_budget_bytes", ctypes.c_size_t),
                 ("stream", ctypes.c_void_p), ("validate", ctypes.c_int32),
                 ("head_max_terms", ctypes.c_int32), ("head_min_df", ctypes.c_double),
-                ("ncc_adaptive", ctypes.c_int32)]
+                ("ncc_adaptive", ctypes.c_int32), ("index_always", ctypes.c_int32)]
 
 
 class IterStats(ctypes.Structure):
@@ -76,7 +76,8 @@ class IterStats(ctypes.Structure):
                 ("ms_index", ctypes.c_float), ("head_terms", ctypes.c_int32),
                 ("ms_head", ctypes.c_float), ("score_launches", ctypes.c_int32),
                 ("sparse_products", ctypes.c_double), ("ms_sparse", ctypes.c_float),
-                ("head_launches", ctypes.c_int32), ("head_pairs", ctypes.c_double)]
+                ("head_launches", ctypes.c_int32), ("head_pairs", ctypes.c_double),
+                ("ms_index_build", ctypes.c_float), ("index_build", ctypes.c_int32)]
 
     def asdict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -300,6 +301,7 @@ class Options:
     head_min_df: float | None = None    # None: the library default (1/128)
     borrow: bool = False                # device rows used in place (SKM_BORROW_DEVICE)
     ncc_adaptive: bool = False          # NCC only when its measured saving beats its preparation
+    index_always: bool = False          # no back-off of the index when it decides few rows
 
 
 def _config(lib, k, o, init_rows, init_centroids, stream):
@@ -322,6 +324,7 @@ def _config(lib, k, o, init_rows, init_centroids, stream):
     cfg.hbm_budget_bytes = o.hbm_budget_bytes
     cfg.validate = 1 if o.validate else 0
     cfg.ncc_adaptive = 1 if o.ncc_adaptive else 0
+    cfg.index_always = 1 if o.index_always else 0
     if o.head_max_terms is not None:
         cfg.head_max_terms = o.head_max_terms
     if o.head_min_df is not None:

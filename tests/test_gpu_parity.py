@@ -499,6 +499,49 @@ def test_index_build_equals_oracle(src):
     ctx.close()
 
 
+def test_incremental_index_equals_oracle():
+    """Updates that rebuild only the changed centroids' part of the index
+    (their segments appended, a second term-major list over every centroid
+    rebuilt since the last full build, their old entries skipped): after each
+    of them P_lambda equals the oracle's exact-arithmetic build of the
+    current centroids at all four levels, and the run follows the oracle's
+    trajectory."""
+    from oracle import index as oix
+
+    say("case: incremental index")
+    csr, tc = _topic(4000, seed=13)
+    k = 48
+    rows = synth.seed_rows(tc.n_docs, k, 6)
+    n_it = 14
+    ref = oracle.run(csr, tc.n_terms, k, rows, max_iter=n_it, stop_rule="fixed")
+    ctx = Context(to_device(csr), tc.n_terms, k, init_rows=rows, precision="bf16", ncc=True,
+                  index=True, stop_rule="fixed", max_iter=n_it, index_always=True)
+    kinds, checked = [], 0
+    for it in range(n_it):
+        sa = ctx.assign()
+        su = ctx.update()
+        assert sa["moved"] == ref.records[it].moved, (it, sa["moved"], ref.records[it].moved)
+        kinds.append(su["index_build"])
+        if su["index_build"] != 2:
+            continue
+        cents = _sparse_rows(ctx.centroids())
+        for level, lam in enumerate((0.1, 0.25, 0.4, 0.6)):
+            off, ent = ctx.index_level(level)
+            G, P = oix.build(cents, lam)
+            got = {}
+            for t in range(tc.n_terms):
+                e = ent[off[t]:off[t + 1]]
+                if len(e):
+                    got[t] = [(int(x >> 16), int(x & 0xFFFF)) for x in e]
+            want = {t: sorted(v) for t, v in P.items()}
+            assert got == want, (it, level)
+        checked += 1
+    say("  index builds per update (1 full, 2 changed only):", kinds)
+    assert checked >= 2
+    assert np.array_equal(ctx.assignments(), ref.a)
+    ctx.close()
+
+
 def test_index_query_equals_oracle():
     from oracle import index as oix
 

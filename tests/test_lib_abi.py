@@ -29,8 +29,8 @@ def test_every_declared_symbol_is_exported():
 def test_struct_layouts_match_header():
     # sizes follow the header's field order on x86-64
     assert ctypes.sizeof(skm.Csr) == 7 * 8
-    assert ctypes.sizeof(skm.IterStats) == 4 + 4 + 8 * 8 + 5 * 8 + 5 * 4 + 4 + 4 + 4 + 8 + 4 + 4 + 8
-    assert ctypes.sizeof(skm.Config) == 4 * 4 + 8 * 8 + 4 * 4 + 8 * 2 + 8 * 4 + 4 + 4 + 8 + 8
+    assert ctypes.sizeof(skm.IterStats) == 4 + 4 + 8 * 8 + 5 * 8 + 5 * 4 + 4 + 4 + 4 + 8 + 4 + 4 + 8 + 4 + 4
+    assert ctypes.sizeof(skm.Config) == 4 * 4 + 8 * 8 + 4 * 4 + 8 * 2 + 8 * 4 + 4 + 4 + 8 + 4 + 4
     cfg = skm.Config()
     skm.load().skm_config_default(ctypes.byref(cfg))
     assert cfg.n_lambda == 4 and list(cfg.lambda_[:4]) == [0.1, 0.25, 0.4, 0.6]
