@@ -585,6 +585,9 @@ skm_status alloc_index_entries(skm_ctx *c, int64_t cap) {
   dfree(c, c->idx_Q, (old + 2 * (int64_t)c->k) * 8);
   dfree(c, c->idx_G, old * 8);
   dfree(c, c->idx_G2, (old / 4 + 1024) * 8);
+  dfree(c, c->idx_runs, (old / index_run_len() + c->k + 1) * 8);
+  dfree(c, c->idx_tiles, (old / index_run_len() + c->k + 1) * 8);
+  c->idx_runs = c->idx_tiles = nullptr;
   c->idx_key0 = c->idx_key1 = nullptr;
   c->idx_term0 = c->idx_term1 = nullptr;
   c->idx_Q = nullptr;
@@ -598,6 +601,8 @@ skm_status alloc_index_entries(skm_ctx *c, int64_t cap) {
   ST_TRY(dalloc(c, &c->idx_Q, (size_t)(cap + 2 * (int64_t)c->k)));
   ST_TRY(dalloc(c, &c->idx_G, (size_t)cap));
   ST_TRY(dalloc(c, &c->idx_G2, (size_t)(cap / 4 + 1024)));
+  ST_TRY(dalloc(c, &c->idx_runs, (size_t)(cap / index_run_len() + c->k + 1)));
+  ST_TRY(dalloc(c, &c->idx_tiles, (size_t)(cap / index_run_len() + c->k + 1)));
   c->idx_cap_entries = cap;
   return SKM_OK;
 }
@@ -607,6 +612,42 @@ IndexBuild index_build_args(skm_ctx *c) {
                     c->idx_qstart, c->idx_key0,  c->idx_key1,  c->idx_term0,  c->idx_term1,
                     c->idx_Q,      c->idx_mask,  c->idx_blkpre, c->idx_tcnt,  c->idx_toff,
                     c->idx_G};
+}
+
+// Extracts, sorts and sums the segments of the listed centroids (all when ids
+// is nullptr), whose counts are in idx_h_cnt: the sort's work lists (runs of
+// every segment, merge tiles of the long ones) are built here.
+skm_status index_segments_of(skm_ctx *c, const int32_t *ids_dev, const std::vector<int32_t> *ids) {
+  const int32_t R = index_run_len();
+  std::vector<int2> &runs = c->idx_h_runs, &tiles = c->idx_h_tiles;
+  runs.clear();
+  tiles.clear();
+  int64_t max_len = 0;
+  auto add = [&](int32_t j) {
+    const int32_t n = c->idx_h_cnt[j];
+    if (n > 1)
+      for (int32_t y = 0; y < n; y += R) runs.push_back(make_int2(j, y));
+    if (n > R) {
+      for (int32_t y = 0; y < n; y += R) tiles.push_back(make_int2(j, y));
+      max_len = std::max<int64_t>(max_len, n);
+    }
+  };
+  if (ids) {
+    for (int32_t j : *ids) add(j);
+  } else {
+    for (int32_t j = 0; j < c->k; ++j) add(j);
+  }
+  hipStream_t s = c->stream;
+  if (!runs.empty())
+    HIP_TRY(c, hipMemcpyAsync(c->idx_runs, runs.data(), sizeof(int2) * runs.size(),
+                              hipMemcpyHostToDevice, s));
+  if (!tiles.empty())
+    HIP_TRY(c, hipMemcpyAsync(c->idx_tiles, tiles.data(), sizeof(int2) * tiles.size(),
+                              hipMemcpyHostToDevice, s));
+  const int32_t n = ids ? (int32_t)ids->size() : c->k;
+  HIP_TRY(c, index_segments(index_build_args(c), ids_dev, n, c->idx_runs, (int64_t)runs.size(),
+                            c->idx_tiles, (int64_t)tiles.size(), max_len, s));
+  return SKM_OK;
 }
 
 // Sec. 3.2 index from the current master.  With the changed centroids of the
@@ -653,7 +694,7 @@ skm_status build_index(skm_ctx *c, const int32_t *ids_dev = nullptr,
         full = true;
       } else {
         const IndexBuild ib = index_build_args(c);
-        HIP_TRY(c, index_segments(ib, ids_dev, n, s));
+        ST_TRY(index_segments_of(c, ids_dev, ids));
         c->idx_used_e += tot[0];
         c->idx_used_q += tot[1];
         c->idx_entries = live;
@@ -662,8 +703,8 @@ skm_status build_index(skm_ctx *c, const int32_t *ids_dev = nullptr,
         HIP_TRY(c, hipMemcpyAsync(c->idx_dids, c->idx_h_dids.data(), sizeof(int32_t) * nd,
                                   hipMemcpyHostToDevice, s));
         HIP_TRY(c, hipMemcpyAsync(c->idx_dirty, c->idx_h_dirty.data(), k, hipMemcpyHostToDevice, s));
-        HIP_TRY(c, index_delta(ib, c->idx_dids, nd, c->idx_dirty, c->idx_tcnt2, c->idx_cur2,
-                               c->idx_toff2, c->idx_G2, c->idx_dbits, s));
+        HIP_TRY(c, index_delta(ib, c->idx_dids, nd, c->idx_dirty, c->idx_toff2, c->idx_G2,
+                               c->idx_dbits, s));
         c->idx_last_build = 2;
       }
     } else {
@@ -686,7 +727,7 @@ skm_status build_index(skm_ctx *c, const int32_t *ids_dev = nullptr,
       ST_TRY(alloc_index_entries(c, std::max<int64_t>(cap, 1024)));
     }
     const IndexBuild ib = index_build_args(c);
-    HIP_TRY(c, index_segments(ib, nullptr, k, s));
+    ST_TRY(index_segments_of(c, nullptr, nullptr));
     HIP_TRY(c, index_terms(ib, s));
     std::fill(c->idx_h_dirty.begin(), c->idx_h_dirty.end(), 0);
     c->idx_h_dids.clear();
@@ -857,7 +898,7 @@ size_t skm_context_bytes(const skm_csr *docs, const skm_config *cfg) {
     b += (ncc ? 2 : 1) * nch * (9 * D + 16);
   if (index) {
     const double nb = std::ceil(k / 64);
-    b += N * (1 + 4 + 4 * 128 + 4 + 4) + 56 * (k + 1) + D * (12 * nb + 28);
+    b += N * (1 + 4 + 4 * 128 + 4 + 4) + 72 * (k + 1) + D * (12 * nb + 20);
   }
   // non-zeros of all centroids are at most min(Z, k D): index entries (42 B
   // each, 25 % headroom) and code lists (8 B each, per-chunk stride headroom)
@@ -1035,8 +1076,6 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
     A_(c->idx_dirty, k);
     A_(c->idx_dids, k);
     A_(c->idx_dbits, (k + 31) / 32);
-    A_(c->idx_tcnt2, c->D);
-    A_(c->idx_cur2, c->D);
     A_(c->idx_toff2, c->D + 1);
     A_(c->idx_rows, N);
     A_(c->idx_cand, N * (int64_t)c->idx_cap);

@@ -141,9 +141,9 @@ struct IndexBuild {
   uint64_t *key0, *key1; // sort keys (~bits of the value), ping-pong
   int32_t *term0, *term1;
   double *Q;             // prefix sums of squares
-  uint64_t *mask;        // [D][ceil(k/64)] non-zero masks
-  int32_t *blkpre;       // [D][ceil(k/64)] per-term prefix of mask popcounts
-  int32_t *tcnt;         // [D] centroids per term
+  uint64_t *mask;        // [D][ceil(k/64)] non-zero masks (build scratch)
+  int32_t *blkpre;       // [D][ceil(k/64)] per-term prefix of mask popcounts (scratch)
+  int32_t *tcnt;         // [D] centroids per term (scratch)
   int64_t *toff;         // [D + 1] G offsets
   uint2 *G;              // (centroid, position) per (term, centroid)
 };
@@ -309,9 +309,10 @@ struct skm_ctx {
   uint8_t *idx_dirty = nullptr;  // [k]
   int32_t *idx_dids = nullptr;   // [k] dirty ids
   uint32_t *idx_dbits = nullptr; // [ceil(k / 32)]
-  int32_t *idx_tcnt2 = nullptr, *idx_cur2 = nullptr;  // [D]
   int64_t *idx_toff2 = nullptr;  // [D + 1]
   uint2 *idx_G2 = nullptr;       // [idx_cap_entries / 4 + 1024]
+  int2 *idx_runs = nullptr, *idx_tiles = nullptr;  // sort work lists [cap / run + k]
+  std::vector<int2> idx_h_runs, idx_h_tiles;
   std::vector<int32_t> idx_h_cnt;     // host copy of idx_cnt
   std::vector<uint8_t> idx_h_dirty;   // host copy of idx_dirty
   std::vector<int32_t> idx_h_dids;    // host copy of idx_dids
@@ -451,11 +452,19 @@ hipError_t index_counts(const double *master, int32_t k, int64_t D, const int32_
 hipError_t index_place(const int32_t *ids, int32_t n, const int32_t *cnt, int64_t base_e,
                        int64_t base_q, int64_t *sstart, int64_t *qstart, int64_t *tot,
                        hipStream_t s);
-hipError_t index_segments(const IndexBuild &ib, const int32_t *ids, int32_t n, hipStream_t s);
+// Segments of the n listed centroids (all when ids is nullptr): extraction,
+// sort and prefix sums.  runs: (centroid, first entry) of every run of
+// index_run_len() entries of the listed segments with more than one entry;
+// tiles: the same for the segments longer than one run; max_len: their
+// longest segment.
+int32_t index_run_len();
+hipError_t index_segments(const IndexBuild &ib, const int32_t *ids, int32_t n, const int2 *runs,
+                          int64_t n_runs, const int2 *tiles, int64_t n_tiles, int64_t max_len,
+                          hipStream_t s);
 hipError_t index_terms(const IndexBuild &ib, hipStream_t s);
 hipError_t index_delta(const IndexBuild &ib, const int32_t *dirty_ids, int32_t n_dirty,
-                       const uint8_t *dirty, int32_t *tcnt2, int32_t *cur2, int64_t *toff2,
-                       uint2 *G2, uint32_t *dbits, hipStream_t s);
+                       const uint8_t *dirty, int64_t *toff2, uint2 *G2, uint32_t *dbits,
+                       hipStream_t s);
 // Ascending list of the rows whose previous centroid is flagged in `changed`
 // (keep = 0) or not flagged (keep = 1), all rows when changed is nullptr,
 // leaving out rows the index finished (mode[i] == 2) when mode is given, and

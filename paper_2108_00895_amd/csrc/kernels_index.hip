@@ -90,8 +90,8 @@ __global__ __launch_bounds__(1024) void k_place(const int32_t *ids, int64_t n, c
 // Entries of centroid j: key = ~bits(value) (ascending key = descending
 // value, values are positive), term.  Coalesced sweeps of the FP64 row, each
 // wavefront appending its non-zeros by ballot at a workgroup counter; the
-// order within the segment is arbitrary, since k_sort_segments orders the
-// (key, term) pairs, which are unique, completely.
+// order within the segment is arbitrary, since the sort orders the (key,
+// term) pairs, which are unique, completely.
 __global__ __launch_bounds__(256) void k_extract(const double *master, int64_t D, const int32_t *ids,
                                                  const int64_t *sstart, uint64_t *key,
                                                  int32_t *term) {
@@ -140,92 +140,95 @@ __device__ inline int64_t corank(int64_t o, const uint64_t *ka, const int32_t *t
   return lo;
 }
 
-// Sorts each centroid's segment ascending by (key, term): bitonic runs of
-// 2048 in LDS, then merge passes between the two buffers.  The result ends in
-// (key0, term0).
-__global__ __launch_bounds__(256) void k_sort_segments(const int32_t *ids, const int64_t *sstart,
-                                                       const int32_t *cnt, uint64_t *key0,
-                                                       int32_t *term0, uint64_t *key1,
-                                                       int32_t *term1) {
+// Segments are sorted ascending by (key, term) in two stages spread over the
+// whole GPU, so that one long centroid does not hold a build up: every run of
+// kRun entries is sorted by a workgroup in LDS (bitonic), then merge passes of
+// width w = kRun, 2 kRun, ... between the two buffers, each workgroup producing
+// one tile of kRun outputs of one merge (a tile never straddles two merges:
+// both are aligned to kRun and merges span 2w).  runs / tiles list (centroid,
+// first entry within its segment).
+
+__global__ __launch_bounds__(256) void k_sort_runs(const int2 *runs, const int64_t *sstart,
+                                                   const int32_t *cnt, uint64_t *key,
+                                                   int32_t *term) {
   __shared__ uint64_t sk[kRun];
   __shared__ int32_t st[kRun];
-  const int j = ids ? ids[blockIdx.x] : blockIdx.x;
-  const int64_t s0 = sstart[j], n = cnt[j];
-  if (n <= 1) return;
-  for (int64_t r0 = 0; r0 < n; r0 += kRun) {
-    const int64_t m = min<int64_t>(kRun, n - r0);
-    for (int i = threadIdx.x; i < kRun; i += 256) {
-      sk[i] = i < m ? key0[s0 + r0 + i] : ~0ull;
-      st[i] = i < m ? term0[s0 + r0 + i] : 0x7FFFFFFF;
-    }
-    __syncthreads();
-    for (int size = 2; size <= kRun; size <<= 1) {
-      for (int stride = size >> 1; stride > 0; stride >>= 1) {
-        for (int i = threadIdx.x; i < kRun / 2; i += 256) {
-          const int lo = 2 * i - (i & (stride - 1));
-          const int hi = lo + stride;
-          const bool up = (lo & size) == 0;
-          const bool gt = key_less(sk[hi], st[hi], sk[lo], st[lo]);
-          if (gt == up) {
-            const uint64_t k2 = sk[lo];
-            sk[lo] = sk[hi];
-            sk[hi] = k2;
-            const int32_t t2 = st[lo];
-            st[lo] = st[hi];
-            st[hi] = t2;
-          }
-        }
-        __syncthreads();
-      }
-    }
-    for (int i = threadIdx.x; i < m; i += 256) {
-      key0[s0 + r0 + i] = sk[i];
-      term0[s0 + r0 + i] = st[i];
-    }
-    __syncthreads();
+  const int2 rr = runs[blockIdx.x];
+  const int64_t s0 = sstart[rr.x] + rr.y;
+  const int64_t m = min<int64_t>(kRun, (int64_t)cnt[rr.x] - rr.y);
+  for (int i = threadIdx.x; i < kRun; i += 256) {
+    sk[i] = i < m ? key[s0 + i] : ~0ull;
+    st[i] = i < m ? term[s0 + i] : 0x7FFFFFFF;
   }
-  uint64_t *ka = key0 + s0, *kb = key1 + s0;
-  int32_t *ta = term0 + s0, *tb = term1 + s0;
-  int passes = 0;
-  for (int64_t w = kRun; w < n; w <<= 1) {
-    for (int64_t a = 0; a < n; a += 2 * w) {
-      const int64_t na = min(w, n - a);
-      const int64_t nb = max<int64_t>(0, min(w, n - a - w));
-      const int64_t len = na + nb;
-      const int64_t per = (len + 255) / 256;
-      const int64_t o0 = min<int64_t>((int64_t)threadIdx.x * per, len);
-      const int64_t o1 = min<int64_t>(o0 + per, len);
-      const uint64_t *KA = ka + a, *KB = ka + a + na;
-      const int32_t *TA = ta + a, *TB = ta + a + na;
-      int64_t i = corank(o0, KA, TA, na, KB, TB, nb);
-      int64_t jj = o0 - i;
-      for (int64_t o = o0; o < o1; ++o) {
-        const bool takeB = jj < nb && (i >= na || key_less(KB[jj], TB[jj], KA[i], TA[i]));
-        if (takeB) {
-          kb[a + o] = KB[jj];
-          tb[a + o] = TB[jj];
-          ++jj;
-        } else {
-          kb[a + o] = KA[i];
-          tb[a + o] = TA[i];
-          ++i;
+  __syncthreads();
+  for (int size = 2; size <= kRun; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < kRun / 2; i += 256) {
+        const int lo = 2 * i - (i & (stride - 1));
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const bool gt = key_less(sk[hi], st[hi], sk[lo], st[lo]);
+        if (gt == up) {
+          const uint64_t k2 = sk[lo];
+          sk[lo] = sk[hi];
+          sk[hi] = k2;
+          const int32_t t2 = st[lo];
+          st[lo] = st[hi];
+          st[hi] = t2;
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
-    uint64_t *kt = ka;
-    ka = kb;
-    kb = kt;
-    int32_t *tt = ta;
-    ta = tb;
-    tb = tt;
-    ++passes;
   }
-  if (passes & 1) {   // result is in the second buffer: copy back
-    for (int64_t i = threadIdx.x; i < n; i += 256) {
-      key0[s0 + i] = ka[i];
-      term0[s0 + i] = ta[i];
+  for (int i = threadIdx.x; i < m; i += 256) {
+    key[s0 + i] = sk[i];
+    term[s0 + i] = st[i];
+  }
+}
+
+// One merge pass of width w (src -> dst); a merge with one run copies it.
+// Each thread produces kRun / 256 consecutive outputs from its own co-rank.
+__global__ __launch_bounds__(256) void k_merge_pass(const int2 *tiles, const int64_t *sstart,
+                                                    const int32_t *cnt, int64_t w,
+                                                    const uint64_t *ks, const int32_t *ts,
+                                                    uint64_t *kd, int32_t *td) {
+  constexpr int kPer = kRun / 256;
+  const int2 tl = tiles[blockIdx.x];
+  const int64_t s0 = sstart[tl.x], n = cnt[tl.x];
+  const int64_t a = ((int64_t)tl.y / (2 * w)) * (2 * w);   // first entry of the merge
+  const int64_t na = min(w, n - a), nb = max<int64_t>(0, min(w, n - a - w));
+  const int64_t len = na + nb;
+  const uint64_t *KA = ks + s0 + a, *KB = KA + na;
+  const int32_t *TA = ts + s0 + a, *TB = TA + na;
+  const int64_t o0 = (int64_t)tl.y - a + (int64_t)threadIdx.x * kPer;
+  if (o0 >= len) return;
+  const int64_t o1 = min<int64_t>(o0 + kPer, len);
+  int64_t i = corank(o0, KA, TA, na, KB, TB, nb);
+  int64_t j = o0 - i;
+  for (int64_t o = o0; o < o1; ++o) {
+    const bool takeB = j < nb && (i >= na || key_less(KB[j], TB[j], KA[i], TA[i]));
+    if (takeB) {
+      kd[s0 + a + o] = KB[j];
+      td[s0 + a + o] = TB[j];
+      ++j;
+    } else {
+      kd[s0 + a + o] = KA[i];
+      td[s0 + a + o] = TA[i];
+      ++i;
     }
+  }
+}
+
+// Copies the listed tiles (kRun entries each) from src to dst.
+__global__ __launch_bounds__(256) void k_copy_tiles(const int2 *tiles, const int64_t *sstart,
+                                                    const int32_t *cnt, const uint64_t *ks,
+                                                    const int32_t *ts, uint64_t *kd, int32_t *td) {
+  const int2 tl = tiles[blockIdx.x];
+  const int64_t s0 = sstart[tl.x] + tl.y;
+  const int64_t m = min<int64_t>(kRun, (int64_t)cnt[tl.x] - tl.y);
+  for (int64_t i = threadIdx.x; i < m; i += 256) {
+    kd[s0 + i] = ks[s0 + i];
+    td[s0 + i] = ts[s0 + i];
   }
 }
 
@@ -262,15 +265,18 @@ __global__ __launch_bounds__(256) void k_prefix_sq(const int32_t *ids, const int
   }
 }
 
-// Non-zero masks, term-major: mask[t * nb + b] bit i = (c_{64b+i, t} != 0).
-__global__ __launch_bounds__(256) void k_term_masks(const double *master, int32_t k, int64_t D,
-                                                    int64_t nb, uint64_t *mask) {
+// Non-zero masks, term-major, over the listed centroids (all k when ids is
+// nullptr): mask[t * nb + b] bit i = (c_{ids[64b+i], t} != 0).
+__global__ __launch_bounds__(256) void k_term_masks(const double *master, const int32_t *ids,
+                                                    int32_t k, int64_t D, int64_t nb,
+                                                    uint64_t *mask) {
   __shared__ uint8_t nz[64][65];
   const int64_t j0 = (int64_t)blockIdx.x * 64, t0 = (int64_t)blockIdx.y * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   for (int jj = ty; jj < 64; jj += 4) {
-    const int64_t j = j0 + jj, t = t0 + tx;
-    nz[jj][tx] = (j < k && t < D) ? (master[j * D + t] != 0.0) : 0;
+    const int64_t i = j0 + jj, t = t0 + tx;
+    const int64_t j = i < k ? (ids ? (int64_t)ids[i] : i) : 0;
+    nz[jj][tx] = (i < k && t < D) ? (master[j * D + t] != 0.0) : 0;
   }
   __syncthreads();
   if (threadIdx.x < 64) {
@@ -297,40 +303,19 @@ __global__ void k_term_prefix(const uint64_t *mask, int64_t D, int64_t nb, int32
 }
 
 // G entries: (centroid, position) at term t's slot ordered by centroid.
-__global__ __launch_bounds__(256) void k_fill_G(const int64_t *sstart, const int32_t *cnt,
-                                                const int32_t *term, const uint64_t *mask,
-                                                const int32_t *blkpre, const int64_t *toff,
-                                                int64_t nb, uint2 *G) {
-  const int j = blockIdx.x;
+__global__ __launch_bounds__(256) void k_fill_G(const int32_t *ids, const int64_t *sstart,
+                                                const int32_t *cnt, const int32_t *term,
+                                                const uint64_t *mask, const int32_t *blkpre,
+                                                const int64_t *toff, int64_t nb, uint2 *G) {
+  const int i = blockIdx.x;                    // list index (column of the masks)
+  const int j = ids ? ids[i] : i;
   const int64_t s0 = sstart[j], n = cnt[j];
-  const int64_t b = j >> 6;
-  const uint64_t below = (j & 63) ? (~0ull >> (64 - (j & 63))) : 0ull;
+  const int64_t b = i >> 6;
+  const uint64_t below = (i & 63) ? (~0ull >> (64 - (i & 63))) : 0ull;
   for (int64_t p = threadIdx.x; p < n; p += 256) {
     const int64_t t = term[s0 + p];
     const int64_t pos = toff[t] + blkpre[t * nb + b] + __popcll(mask[t * nb + b] & below);
     G[pos] = make_uint2((uint32_t)j, (uint32_t)p);
-  }
-}
-
-// G2 over the dirty centroids ids[0 .. n): per-term counts, then the entries
-// at per-term cursors (their order within a term is immaterial to the query,
-// whose counts and best positions are order-free).
-__global__ __launch_bounds__(256) void k_g2_count(const int32_t *ids, const int64_t *sstart,
-                                                  const int32_t *cnt, const int32_t *term,
-                                                  int32_t *tcnt2) {
-  const int j = ids[blockIdx.x];
-  const int64_t s0 = sstart[j], n = cnt[j];
-  for (int64_t p = threadIdx.x; p < n; p += 256) atomicAdd(&tcnt2[term[s0 + p]], 1);
-}
-
-__global__ __launch_bounds__(256) void k_g2_fill(const int32_t *ids, const int64_t *sstart,
-                                                 const int32_t *cnt, const int32_t *term,
-                                                 const int64_t *toff2, int32_t *cur2, uint2 *G2) {
-  const int j = ids[blockIdx.x];
-  const int64_t s0 = sstart[j], n = cnt[j];
-  for (int64_t p = threadIdx.x; p < n; p += 256) {
-    const int32_t t = term[s0 + p];
-    G2[toff2[t] + atomicAdd(&cur2[t], 1)] = make_uint2((uint32_t)j, (uint32_t)p);
   }
 }
 
@@ -637,12 +622,29 @@ hipError_t index_place(const int32_t *ids, int32_t n, const int32_t *cnt, int64_
   return hipGetLastError();
 }
 
-hipError_t index_segments(const IndexBuild &ib, const int32_t *ids, int32_t n, hipStream_t s) {
+int32_t index_run_len() { return kRun; }
+
+hipError_t index_segments(const IndexBuild &ib, const int32_t *ids, int32_t n, const int2 *runs,
+                          int64_t n_runs, const int2 *tiles, int64_t n_tiles, int64_t max_len,
+                          hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_extract, dim3((unsigned)n), dim3(256), 0, s, ib.master, ib.D, ids, ib.sstart,
                      ib.key0, ib.term0);
-  hipLaunchKernelGGL(k_sort_segments, dim3((unsigned)n), dim3(256), 0, s, ids, ib.sstart, ib.cnt,
-                     ib.key0, ib.term0, ib.key1, ib.term1);
+  if (n_runs > 0)
+    hipLaunchKernelGGL(k_sort_runs, dim3((unsigned)n_runs), dim3(256), 0, s, runs, ib.sstart, ib.cnt,
+                       ib.key0, ib.term0);
+  bool in1 = false;   // the sorted entries are in (key1, term1)
+  if (n_tiles > 0) {
+    for (int64_t w = kRun; w < max_len; w *= 2) {
+      hipLaunchKernelGGL(k_merge_pass, dim3((unsigned)n_tiles), dim3(256), 0, s, tiles, ib.sstart,
+                         ib.cnt, w, in1 ? ib.key1 : ib.key0, in1 ? ib.term1 : ib.term0,
+                         in1 ? ib.key0 : ib.key1, in1 ? ib.term0 : ib.term1);
+      in1 = !in1;
+    }
+    if (in1)
+      hipLaunchKernelGGL(k_copy_tiles, dim3((unsigned)n_tiles), dim3(256), 0, s, tiles, ib.sstart,
+                         ib.cnt, ib.key1, ib.term1, ib.key0, ib.term0);
+  }
   hipLaunchKernelGGL(k_prefix_sq, dim3((unsigned)n), dim3(256), 0, s, ids, ib.sstart, ib.cnt,
                      ib.qstart, ib.key0, ib.Q);
   return hipGetLastError();
@@ -652,29 +654,32 @@ hipError_t index_terms(const IndexBuild &ib, hipStream_t s) {
   const int32_t k = ib.k;
   const int64_t D = ib.D, nb = (k + 63) / 64;
   hipLaunchKernelGGL(k_term_masks, dim3((unsigned)nb, (unsigned)((D + 63) / 64)), dim3(256), 0, s,
-                     ib.master, k, D, nb, ib.mask);
+                     ib.master, (const int32_t *)nullptr, k, D, nb, ib.mask);
   hipLaunchKernelGGL(k_term_prefix, dim3((unsigned)((D + 255) / 256)), dim3(256), 0, s, ib.mask, D,
                      nb, ib.blkpre, ib.tcnt);
   hipLaunchKernelGGL(k_scan_i32_to_i64, dim3(1), dim3(1024), 0, s, ib.tcnt, D, ib.toff);
-  hipLaunchKernelGGL(k_fill_G, dim3((unsigned)k), dim3(256), 0, s, ib.sstart, ib.cnt, ib.term0,
-                     ib.mask, ib.blkpre, ib.toff, nb, ib.G);
+  hipLaunchKernelGGL(k_fill_G, dim3((unsigned)k), dim3(256), 0, s, (const int32_t *)nullptr,
+                     ib.sstart, ib.cnt, ib.term0, ib.mask, ib.blkpre, ib.toff, nb, ib.G);
   return hipGetLastError();
 }
 
+// G2 over the dirty centroids ids[0 .. n) (ascending), built like G over that
+// list (the full build's masks and block prefixes are free again once G is
+// filled, and hold ceil(k / 64) >= ceil(n / 64) blocks per term): each term's
+// entries ascending by centroid, without atomics.
 hipError_t index_delta(const IndexBuild &ib, const int32_t *dirty_ids, int32_t n_dirty,
-                       const uint8_t *dirty, int32_t *tcnt2, int32_t *cur2, int64_t *toff2,
-                       uint2 *G2, uint32_t *dbits, hipStream_t s) {
-  const int64_t D = ib.D;
-  hipError_t e = launch_fill_i32(tcnt2, 0, D, s);
-  if (e == hipSuccess) e = launch_fill_i32(cur2, 0, D, s);
-  if (e != hipSuccess) return e;
-  if (n_dirty > 0)
-    hipLaunchKernelGGL(k_g2_count, dim3((unsigned)n_dirty), dim3(256), 0, s, dirty_ids, ib.sstart,
-                       ib.cnt, ib.term0, tcnt2);
-  hipLaunchKernelGGL(k_scan_i32_to_i64, dim3(1), dim3(1024), 0, s, tcnt2, D, toff2);
-  if (n_dirty > 0)
-    hipLaunchKernelGGL(k_g2_fill, dim3((unsigned)n_dirty), dim3(256), 0, s, dirty_ids, ib.sstart,
-                       ib.cnt, ib.term0, toff2, cur2, G2);
+                       const uint8_t *dirty, int64_t *toff2, uint2 *G2, uint32_t *dbits,
+                       hipStream_t s) {
+  const int64_t D = ib.D, nb2 = (n_dirty + 63) / 64;
+  if (n_dirty > 0) {
+    hipLaunchKernelGGL(k_term_masks, dim3((unsigned)nb2, (unsigned)((D + 63) / 64)), dim3(256), 0,
+                       s, ib.master, dirty_ids, n_dirty, D, nb2, ib.mask);
+    hipLaunchKernelGGL(k_term_prefix, dim3((unsigned)((D + 255) / 256)), dim3(256), 0, s, ib.mask,
+                       D, nb2, ib.blkpre, ib.tcnt);
+    hipLaunchKernelGGL(k_scan_i32_to_i64, dim3(1), dim3(1024), 0, s, ib.tcnt, D, toff2);
+    hipLaunchKernelGGL(k_fill_G, dim3((unsigned)n_dirty), dim3(256), 0, s, dirty_ids, ib.sstart,
+                       ib.cnt, ib.term0, ib.mask, ib.blkpre, toff2, nb2, G2);
+  }
   hipLaunchKernelGGL(k_dirty_bits, dim3((unsigned)((ib.k + 32 * 256 - 1) / (32 * 256))), dim3(256),
                      0, s, dirty, ib.k, dbits);
   return hipGetLastError();
