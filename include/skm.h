@@ -140,10 +140,11 @@ typedef struct {
                                  of the rows contain it.  Default 1/128. */
   int32_t ncc_adaptive;       /* SKM_NCC: 0 (default) = use Sec. 3.1 whenever its
                                  estimated scoring work is at most 0.9 of a full
-                                 pass; 1 = also only when the scoring it saves
-                                 (measured on the last full pass) exceeds the cost of
-                                 building its compacted copy (measured at its last
-                                 use).  Results are the same either way. */
+                                 pass; 1 = also only when its predicted assignment
+                                 time (its share of the last full pass's scoring
+                                 plus its own fixed cost, measured at its last use)
+                                 is below the last full assignment's.  Results are
+                                 the same either way. */
   int32_t index_always;       /* SKM_INDEX: 1 = query and rebuild the index after
                                  every update even when it decides few rows (no
                                  back-off); 0 (default) = back off (Sec. 4.3) */
@@ -284,6 +285,14 @@ skm_status skm_iterate(skm_ctx *c, int32_t max_iter, skm_iter_stats *per_iter,
  * overlap skm_assign/skm_update/skm_iterate on the same context. */
 skm_status skm_assign_new(skm_ctx *c, const skm_csr *docs, int32_t *out_assign,
                           double *out_score, void *stream);
+
+/* Rows of the last skm_assign_new to finish that the Sec. 3.2 index assigned (contexts
+ * with SKM_INDEX once the index is built; the others score every centroid).
+ * A new row's baseline is the certified FP64 score of a probe centroid: the
+ * best of the centroids that are largest at the row's three largest values'
+ * terms.  Not in the paper, which has no new rows.  -1 for an invalid
+ * context. */
+int64_t skm_assign_new_index_rows(const skm_ctx *c);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc): skm_assign_new for

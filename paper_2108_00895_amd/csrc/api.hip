@@ -664,6 +664,10 @@ skm_status build_index(skm_ctx *c, const int32_t *ids_dev = nullptr,
   hipStream_t s = c->stream;
   const int32_t k = c->k;
   HIP_TRY(c, hipEventRecord(c->ev[6], s));
+  {
+    std::lock_guard<std::mutex> lock(c->best_mu);
+    c->idx_best_ready = false;
+  }
   c->idx_h_cnt.resize(k, 0);
   c->idx_h_dirty.resize(k, 0);
   const bool can_delta = ids && ids_dev && c->index_ready && c->idx_cap_entries > 0 &&
@@ -810,7 +814,7 @@ hipError_t launch_new_rows(skm_ctx *c, const NewRows &b, int64_t n, hipStream_t 
   sa.counters = b.counters;
   sa.stat = b.stat;
   sa.no_exact = 0;
-  sa.mode = nullptr;
+  sa.mode = b.mode;
   hipError_t e = launch_fill_i32(b.counters, 0, 8, s);
   if (e == hipSuccess) e = launch_fill_i32(reinterpret_cast<int32_t *>(b.stat), 0, 16, s);
   if (e == hipSuccess) e = launch_score(sa, b.part, c->n_cu, c->prec, s, c->score_wpc);
@@ -1077,6 +1081,7 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
     A_(c->idx_dids, k);
     A_(c->idx_dbits, (k + 31) / 32);
     A_(c->idx_toff2, c->D + 1);
+    A_(c->idx_best, c->D);
     A_(c->idx_rows, N);
     A_(c->idx_cand, N * (int64_t)c->idx_cap);
     A_(c->idx_ncand, N);
@@ -1224,13 +1229,16 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
   // row scores the full copy.
   const double ncc_cost = (1.0 - c->full_frac) * (double)c->last_changed / (double)c->k + c->full_frac;
   bool ncc = (c->cfg.flags & SKM_NCC) && c->have_prev && ncc_cost <= kNccMaxCost;
-  if (ncc && c->cfg.ncc_adaptive && c->ms_full_score >= 0.f) {
-    // the scoring NCC saves, against what building its compacted copy costs
-    // (measured at its last use, else estimated from the bytes it moves)
-    const double prep = c->ms_ncc_prep >= 0.f
-                            ? (double)c->ms_ncc_prep
-                            : 3.0 * (double)c->D * c->last_changed * c->esize / 2e9;
-    if ((1.0 - ncc_cost) * (double)c->ms_full_score <= prep) ncc = false;
+  if (ncc && c->cfg.ncc_adaptive && c->ms_full_assign >= 0.f) {
+    // predicted Sec. 3.1 assignment: the share ncc_cost of the last full
+    // pass's scoring plus its own fixed cost (the compacted copy and lists,
+    // the row lists, the extra launches and waits), measured at its last use
+    // as its assignment time beyond the scaled scoring, else estimated from
+    // the bytes the compacted copy moves; against the last full assignment
+    const double fixed = c->ms_ncc_fixed >= 0.f
+                             ? (double)c->ms_ncc_fixed
+                             : 3.0 * (double)c->D * c->last_changed * c->esize / 2e9;
+    if (fixed + ncc_cost * (double)c->ms_full_score >= (double)c->ms_full_assign) ncc = false;
   }
   int32_t n_ch = c->k;
   HIP_TRY(c, hipEventRecord(c->ev[0], s));
@@ -1240,7 +1248,6 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
     HIP_TRY(c, launch_compact_changed(c->changed, c->k, c->ch_ids, c->ids_count, s));
     HIP_TRY(c, launch_gather_tile(c->tile, c->D, c->esize, c->ch_ids, n_ch, c->tile_ch, s));
     ST_TRY(build_tail(c, 1, c->tile_ch, n_ch, nullptr));
-    HIP_TRY(c, hipEventRecord(c->ev[8], s));
     a.a_prev = c->a_prev;
     a.changed = c->changed;
     a.tile_ch = c->tile_ch;
@@ -1332,10 +1339,15 @@ skm_status skm_assign(skm_ctx *c, skm_iter_stats *st_out) {
   HIP_TRY(c, hipMemcpyAsync(cnt, c->counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipMemcpyAsync(stv, c->stat, sizeof(stv), hipMemcpyDeviceToHost, s));
   HIP_TRY(c, hipStreamSynchronize(s));
-  if (ncc)
-    c->ms_ncc_prep = elapsed(c->ev[0], c->ev[8]);
-  else
-    c->ms_full_score = elapsed(c->ev[5], c->ev[1]);
+  {
+    const float ms_assign = elapsed(c->ev[0], c->ev[2]);
+    if (!ncc) {
+      c->ms_full_score = elapsed(c->ev[5], c->ev[1]);
+      c->ms_full_assign = ms_assign;
+    } else if (c->ms_full_score >= 0.f) {
+      c->ms_ncc_fixed = std::max(0.f, ms_assign - (float)(ncc_cost * c->ms_full_score));
+    }
+  }
   c->assigned = true;
   c->last_moved = c->have_prev ? (int64_t)stv[4] : c->N;
   if (use_index && !c->cfg.index_always) {
@@ -1758,14 +1770,70 @@ skm_status skm_assign_new(skm_ctx *c, const skm_csr *docs, int32_t *out_assign, 
   }
   NewRows nr{r.indptr, r.indices, r.values, r.xl1, part, a, lo, hi, flag_rows, flag_L, flag_mode,
              counters, stat, score};
-  hipError_t e = launch_new_rows(c, nr, n, s);
+  hipError_t e = hipSuccess;
+  unsigned long long *istat = nullptr;
+  if ((c->cfg.flags & SKM_INDEX) && c->index_ready) {
+    // Sec. 3.2 for rows without a previous assignment: the baseline is the
+    // certified score of a probe centroid (the best of the centroids largest
+    // at the row's largest values); the true maximum scores at least as
+    // much, so by Lemma 3.1 it is among the index's candidates at the level
+    // that baseline selects.  Rows the index settles skip the scoring pass.
+    int32_t *probe = nullptr, *cand = nullptr, *ncand = nullptr, *level = nullptr;
+    uint8_t *mode = nullptr;
+    if ((st = talloc(&probe, n * 4)) != SKM_OK || (st = talloc(&ncand, n * 4)) != SKM_OK ||
+        (st = talloc(&level, n * 4)) != SKM_OK || (st = talloc(&mode, n)) != SKM_OK ||
+        (st = talloc(&cand, n * 4 * (int64_t)c->idx_cap)) != SKM_OK ||
+        (st = talloc(&istat, 128)) != SKM_OK) {
+      release();
+      return st;
+    }
+    IndexArgs x = index_args(c);
+    {
+      std::lock_guard<std::mutex> lock(c->best_mu);
+      if (!c->idx_best_ready) {
+        e = index_best_centroid(x, c->idx_dirty, c->idx_sstart, c->idx_key0, c->idx_best, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);   // other streams read it next
+        c->idx_best_ready = e == hipSuccess;
+      }
+    }
+    if (e == hipSuccess) e = launch_fill_u8(mode, 0, n, s);
+    if (e == hipSuccess) e = launch_fill_i32(reinterpret_cast<int32_t *>(istat), 0, 32, s);
+    if (e == hipSuccess)
+      e = index_probe(r.indptr, r.indices, r.values, n, c->idx_best, c->master, c->D, probe, s);
+    x.indptr = r.indptr;
+    x.indices = r.indices;
+    x.values = r.values;
+    x.xl2 = r.xl2;
+    x.rows = nullptr;
+    x.a_prev = probe;
+    x.changed = nullptr;
+    x.n_ch = c->k;
+    x.cand = cand;
+    x.ncand = ncand;
+    x.level = level;
+    x.mode = mode;
+    x.stat = istat;
+    x.base_out = nullptr;
+    if (e == hipSuccess) e = index_query(x, n, s);
+    if (e == hipSuccess) e = index_score(x, n, a, lo, hi, s);
+    nr.mode = mode;
+  }
+  if (e == hipSuccess) e = launch_new_rows(c, nr, n, s);
+  unsigned long long ist[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (e == hipSuccess && istat) e = hipMemcpyAsync(ist, istat, sizeof(ist), hipMemcpyDeviceToHost, s);
   const hipMemcpyKind kind = docs->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   if (e == hipSuccess) e = hipMemcpyAsync(out_assign, a, n * 4, kind, s);
   if (e == hipSuccess) e = hipMemcpyAsync(out_score, score, n * 8, kind, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   release();
   if (e != hipSuccess) return device_fail(c, "skm_assign_new", e);
+  c->new_index_rows = (int64_t)ist[2];
   return SKM_OK;
+}
+
+int64_t skm_assign_new_index_rows(const skm_ctx *c) {
+  if (check_ctx(c) != SKM_OK) return -1;
+  return c->new_index_rows;
 }
 
 skm_status skm_get_assignments(const skm_ctx *c, int32_t *out, int32_t on_device) {

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -128,6 +130,7 @@ struct NewRows {
   int32_t *counters;
   unsigned long long *stat;
   double *score;
+  const uint8_t *mode = nullptr;   // [n] 2 = row already assigned (index path), or nullptr
 };
 
 // Device pieces of the Sec. 3.2 index.
@@ -317,6 +320,11 @@ struct skm_ctx {
   std::vector<uint8_t> idx_h_dirty;   // host copy of idx_dirty
   std::vector<int32_t> idx_h_dids;    // host copy of idx_dids
   int32_t idx_last_build = 0;    // 0 none, 1 full, 2 changed centroids only
+  int32_t *idx_best = nullptr;   // [D] centroid largest at each term (new rows' probes)
+  bool idx_best_ready = false;   // idx_best is that of the current index (under best_mu)
+  std::mutex best_mu;            // concurrent skm_assign_new calls build idx_best once
+  std::atomic<int64_t> new_index_rows{0};  // rows the index assigned in the last
+                                           // skm_assign_new to finish
   int32_t *idx_rows = nullptr, *idx_cand = nullptr, *idx_ncand = nullptr, *idx_level = nullptr;
   int32_t idx_cap = 128;
   double idx_guard = 0.25;
@@ -378,7 +386,8 @@ struct skm_ctx {
 
   hipEvent_t ev[10] = {};
   float ms_full_score = -1.f;  // device time of the last scoring pass over every centroid
-  float ms_ncc_prep = -1.f;    // device time of the last Sec. 3.1 preparation (compacted copy)
+  float ms_full_assign = -1.f; // device time of the last assignment without Sec. 3.1
+  float ms_ncc_fixed = -1.f;   // last Sec. 3.1 assignment's time beyond its scaled scoring
 };
 
 namespace skm {
@@ -474,6 +483,13 @@ hipError_t index_rows(const int32_t *a_prev, const uint8_t *changed, int64_t n, 
                       int32_t *count, int32_t *work, hipStream_t s, int32_t keep = 0,
                       const uint8_t *mode = nullptr);
 hipError_t index_query(const IndexArgs &x, int64_t n_slots, hipStream_t s);
+// best[t]: the centroid largest at term t (-1: none), from the built index.
+hipError_t index_best_centroid(const IndexArgs &x, const uint8_t *dirty, const int64_t *sstart,
+                               const uint64_t *key, int32_t *best, hipStream_t s);
+// probe[i]: a new row's probe centroid (baseline of its index query).
+hipError_t index_probe(const int64_t *indptr, const int32_t *indices, const float *values,
+                       int64_t n, const int32_t *best, const double *master, int64_t D,
+                       int32_t *probe, hipStream_t s);
 hipError_t index_score(const IndexArgs &x, int64_t n_slots, int32_t *a_out, double *lo_out,
                        double *hi_out, hipStream_t s);
 

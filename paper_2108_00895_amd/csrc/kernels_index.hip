@@ -527,6 +527,98 @@ __global__ __launch_bounds__(256) void k_index_score(IndexArgs x, int64_t n_slot
   }
 }
 
+// Per term t, the centroid with the largest value at t (lowest index among
+// equal values; -1 when no centroid has t), from the index entries: G (the
+// centroids not rebuilt since the last full build) and G2.  One wavefront per
+// term.
+__global__ __launch_bounds__(256) void k_best_centroid(const int64_t *toff, const uint2 *G,
+                                                       const int64_t *toff2, const uint2 *G2,
+                                                       const uint8_t *dirty, int32_t n_dirty,
+                                                       const int64_t *sstart, const uint64_t *key,
+                                                       int64_t D, int32_t *best) {
+  const int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= D) return;
+  const int lane = lane_id();
+  double bv = -INFINITY;
+  int bj = 0x7FFFFFFF;
+  for (int64_t g = toff[t] + lane; g < toff[t + 1]; g += kWave) {
+    const uint2 ent = G[g];
+    if (n_dirty > 0 && dirty[ent.x]) continue;
+    const double v = __longlong_as_double((long long)~key[sstart[ent.x] + ent.y]);
+    if (better_d(v, (int)ent.x, bv, bj)) {
+      bv = v;
+      bj = (int)ent.x;
+    }
+  }
+  if (n_dirty > 0) {
+    for (int64_t g = toff2[t] + lane; g < toff2[t + 1]; g += kWave) {
+      const uint2 ent = G2[g];
+      const double v = __longlong_as_double((long long)~key[sstart[ent.x] + ent.y]);
+      if (better_d(v, (int)ent.x, bv, bj)) {
+        bv = v;
+        bj = (int)ent.x;
+      }
+    }
+  }
+  wave_best_d(bv, bj);
+  if (lane == 0) best[t] = bj == 0x7FFFFFFF ? -1 : bj;
+}
+
+// Probe centroid of each new row (baseline of the index query): among the
+// centroids that are largest at the row's three largest values' terms, the
+// one with the highest FP64 score (lowest index among equal scores); 0 when
+// none of those terms is in any centroid.  One wavefront per row.
+__global__ __launch_bounds__(256) void k_probe(const int64_t *indptr, const int32_t *indices,
+                                               const float *values, int64_t n, const int32_t *best,
+                                               const double *master, int64_t D, int32_t *probe) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const int lane = lane_id();
+  const int64_t b = indptr[row], e = indptr[row + 1];
+  int cand[3] = {-1, -1, -1};
+  int64_t taken[3] = {-1, -1, -1};
+  for (int r = 0; r < 3; ++r) {
+    // the largest value not yet taken (lowest position among equal values)
+    float bv = -INFINITY;
+    int64_t bq = INT64_MAX;
+    for (int64_t q = b + lane; q < e; q += kWave) {
+      if (q == taken[0] || q == taken[1]) continue;
+      const float v = values[q];
+      if (v > bv || (v == bv && q < bq)) {
+        bv = v;
+        bq = q;
+      }
+    }
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) {
+      const float ov = __shfl_xor(bv, m, kWave);
+      const int64_t oq = __shfl_xor(bq, m, kWave);
+      if (ov > bv || (ov == bv && oq < bq)) {
+        bv = ov;
+        bq = oq;
+      }
+    }
+    if (bq == INT64_MAX) break;
+    taken[r] = bq;
+    cand[r] = best[indices[bq]];
+  }
+  double bs = -INFINITY;
+  int bj = 0x7FFFFFFF;
+  for (int r = 0; r < 3; ++r) {
+    const int j = cand[r];
+    if (j < 0 || (r > 0 && j == cand[0]) || (r > 1 && j == cand[1])) continue;
+    double t = 0.0;
+    for (int64_t q = b + lane; q < e; q += kWave)
+      t = fma((double)values[q], master[(int64_t)j * D + indices[q]], t);
+    t = wave_sum_d(t);
+    if (better_d(t, j, bs, bj)) {
+      bs = t;
+      bj = j;
+    }
+  }
+  if (lane == 0) probe[row] = bj == 0x7FFFFFFF ? 0 : bj;
+}
+
 // Rows whose previous centroid changed, in ascending order (index path).
 // Stable compaction of the rows whose previous centroid is flagged in
 // `changed` (keep = 0) or not flagged (keep = 1), all rows when changed ==
@@ -707,6 +799,22 @@ hipError_t index_query(const IndexArgs &x, int64_t n_slots, hipStream_t s) {
   if (n_slots <= 0) return hipSuccess;
   const size_t lds = index_lds_bytes(x.k);
   hipLaunchKernelGGL(k_index_query, dim3((unsigned)n_slots), dim3(256), lds, s, x);
+  return hipGetLastError();
+}
+
+hipError_t index_best_centroid(const IndexArgs &x, const uint8_t *dirty, const int64_t *sstart,
+                               const uint64_t *key, int32_t *best, hipStream_t s) {
+  hipLaunchKernelGGL(k_best_centroid, dim3((unsigned)((x.D + 3) / 4)), dim3(256), 0, s, x.toff, x.G,
+                     x.toff2, x.G2, dirty, x.n_dirty, sstart, key, x.D, best);
+  return hipGetLastError();
+}
+
+hipError_t index_probe(const int64_t *indptr, const int32_t *indices, const float *values,
+                       int64_t n, const int32_t *best, const double *master, int64_t D,
+                       int32_t *probe, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_probe, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, indptr, indices,
+                     values, n, best, master, D, probe);
   return hipGetLastError();
 }
 

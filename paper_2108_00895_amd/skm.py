@@ -35,6 +35,7 @@ EXPORTED = [
     "skm_server_cancel", "skm_context_bytes", "skm_tune_lambda", "skm_debug_fail_after",
     "skm_hbm_bytes", "skm_last_error", "skm_destroy", "skm_index_threshold",
     "skm_assign_new_static", "skm_static_scratch_bytes", "skm_static_max_rows",
+    "skm_assign_new_index_rows",
 ]
 
 
@@ -204,6 +205,8 @@ def load():
     lib.skm_error_bound_head.restype = ctypes.c_double
     lib.skm_error_bound_split.argtypes = [vp, ctypes.c_double, ctypes.c_double, i64, ctypes.c_double]
     lib.skm_error_bound_split.restype = ctypes.c_double
+    lib.skm_assign_new_index_rows.argtypes = [vp]
+    lib.skm_assign_new_index_rows.restype = i64
     lib.skm_get_index.argtypes = [vp, i32, vp, vp, P(i64)]
     lib.skm_get_index.restype = st
     lib.skm_index_query.argtypes = [vp, P(Csr), i32, vp, vp, i64]
@@ -438,6 +441,10 @@ class Context:
         _check(load().skm_assign_new(self._h, ctypes.byref(c), a.ctypes.data, s.ctypes.data,
                                      stream))
         return a, s
+
+    def assign_new_index_rows(self):
+        """Rows of the last assign_new that the index assigned."""
+        return int(load().skm_assign_new_index_rows(self._h))
 
     def assign_new_static(self, csr, out_assign, out_score, stream=None):
         """skm_assign_new_static: device rows (torch tensors) in, answers written

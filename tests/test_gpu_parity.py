@@ -542,6 +542,41 @@ def test_incremental_index_equals_oracle():
     ctx.close()
 
 
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_assign_new_with_index_probe_equals_oracle(prec):
+    """New rows on a context with the index: each row's baseline is a probe
+    centroid's certified score and the index settles rows of a
+    topic-structured request (at k = 48 its cost guard sends most rows to the
+    dense scan, which is cheap there); the answers equal the oracle's (exact
+    argmax, lowest index on ties) and those of a context without the index,
+    for host and device inputs."""
+    say("case: assign_new index probe", prec)
+    full, tc = _topic(5500, seed=13)
+    csr = synth.subset(*full, np.arange(4000))
+    new = synth.subset(*full, np.arange(4000, 5500))   # held-out rows of the same topics
+    k = 48
+    rows = synth.seed_rows(4000, k, 6)
+    ctx = Context(to_device(csr), tc.n_terms, k, init_rows=rows, precision=prec, ncc=True,
+                  index=True, stop_rule="fixed", max_iter=4, index_always=True)
+    ctx.iterate()
+    C = ctx.centroids()
+    a_ref, s1, s2 = oracle.assign(new, C)
+    a, s = ctx.assign_new(new)
+    n_idx = ctx.assign_new_index_rows()
+    say("  rows assigned by the index:", n_idx, "of", len(a))
+    assert_assign_equal(a, a_ref, s1, s2, "assign_new with index " + prec)
+    np.testing.assert_allclose(s, s1, rtol=1e-12)
+    assert n_idx > 0
+    ad, sd = ctx.assign_new(to_device(new))
+    assert np.array_equal(ad.cpu().numpy(), a)
+    plain = Context(csr, tc.n_terms, k, init_centroids=C, precision=prec)
+    ap, sp = plain.assign_new(new)
+    assert np.array_equal(ap, a)
+    assert plain.assign_new_index_rows() == 0
+    plain.close()
+    ctx.close()
+
+
 def test_index_query_equals_oracle():
     from oracle import index as oix
 
