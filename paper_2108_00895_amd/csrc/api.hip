@@ -222,7 +222,7 @@ skm_status build_tail(skm_ctx *c, int which, const uint8_t *tile, int32_t ncols,
     std::vector<uint32_t> tot(n);
     HIP_TRY(c, hipMemcpyAsync(T.chunks, list.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
     HIP_TRY(c, tail_count(tile, c->D, ncols, c->prec, T.chunks, n, T.cnt, T.tail, T.off, T.totals,
-                          s));
+                          T.bsum, s));
     HIP_TRY(c, hipMemcpyAsync(tot.data(), T.totals, sizeof(uint32_t) * n, hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
     for (int32_t q = 0; q < n; ++q) T.h_total[list[q]] = tot[q];
@@ -897,9 +897,10 @@ size_t skm_context_bytes(const skm_csr *docs, const skm_config *cfg) {
   b += 16 * k * D + D * ld * esize * (ncc ? 2 : 1);            // master, sums, codes
   b += 4 * ld + 48 * k + 8 * (k + 1);                          // scales, per-centroid state
   b += N * (4 + 4 + 8 * 4 + 4 + 8 + 1 + 4);                    // per-row state, members
-  b += 4 * std::ceil(N / 8192) * k + sizeof(Partial) * nch * N;  // histogram, partials
+  b += 4 * std::ceil(N / (double)bucket_rows(docs->n_rows, cfg->k)) * k +
+       sizeof(Partial) * nch * N;                              // histogram, partials
   if (!(cfg->flags & SKM_DENSE_ONLY))                          // list offsets, flags, counts
-    b += (ncc ? 2 : 1) * nch * (9 * D + 16);
+    b += (ncc ? 2 : 1) * nch * (9 * D + D / 1024 + 32);
   if (index) {
     const double nb = std::ceil(k / 64);
     b += N * (1 + 4 + 4 * 128 + 4 + 4) + 72 * (k + 1) + D * (12 * nb + 20);
@@ -968,7 +969,8 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
   c->uq = unit_roundoff(c->prec);
   c->abs_coef = abs_coefficient(c->prec);
   c->ld = round_up(c->k, kChunk);
-  c->nblk = (c->N + 8191) / 8192;
+  c->bucket_rows = bucket_rows(c->N, c->k);
+  c->nblk = (c->N + c->bucket_rows - 1) / c->bucket_rows;
 
   auto cleanup = [&](skm_status st) {
     skm_destroy(c);
@@ -1056,6 +1058,7 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
     A_(c->tails[w].base, nch + 1);
     A_(c->tails[w].totals, nch);
     A_(c->tails[w].chunks, nch);
+    A_(c->tails[w].bsum, nch * tail_scan_blocks(c->D));
   }
   if (c->cfg.flags & SKM_NCC) A_(c->tile_ch, c->D * c->ld * c->esize);
   if (c->cfg.flags & SKM_INDEX) {
@@ -1644,7 +1647,8 @@ skm_status skm_update(skm_ctx *c, skm_iter_stats *st_out) {
   int32_t n_ids = 0;
   HIP_TRY(c, launch_compact_changed(c->changed, c->k, c->ch_ids, c->ids_count, s));
   HIP_TRY(c, hipMemcpyAsync(&n_ids, c->ids_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  HIP_TRY(c, launch_bucket(c->a, c->N, c->k, c->nblk, c->hist, c->counts, c->offsets, c->members, s));
+  HIP_TRY(c, launch_bucket(c->a, c->N, c->k, c->bucket_rows, c->hist, c->counts, c->offsets,
+                           c->members, s));
   HIP_TRY(c, hipStreamSynchronize(s));
   std::vector<int32_t> ids, chunks;
   ST_TRY(sum_changed(c, n_ids, ids));

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <atomic>
 #include <mutex>
 #include <string>
@@ -284,6 +285,7 @@ struct skm_ctx {
     uint8_t *tail = nullptr;     // [nch][D] 1 = list term in chunk cc
     uint32_t *cnt = nullptr, *off = nullptr, *ent = nullptr;
     uint32_t *totals = nullptr;  // [nch] entries per listed chunk (last build)
+    uint32_t *bsum = nullptr;    // [nch][tail_scan_blocks(D)] scan scratch
     int32_t *chunks = nullptr;   // [nch] chunk list of the last build
     uint64_t *base = nullptr;    // [nch + 1] = cc * stride
     int64_t stride = 0;          // entries reserved per chunk
@@ -374,7 +376,8 @@ struct skm_ctx {
   double *work = nullptr;        // [work_slots][D] partial sums
   int64_t work_slots = 0;
   int n_cu = 256;                // compute units (the persistent scoring grid is sized from it)
-  int64_t nblk = 0;
+  int64_t nblk = 0;             // blocks of the update's counting sort
+  int64_t bucket_rows = 8192;   // rows per block (bucket_rows())
 
   // state
   int32_t iter = 0;            // completed updates
@@ -440,7 +443,8 @@ skm_status noalloc_setup(int device);
 // entries, chunk cc's from entry cc * stride.
 hipError_t tail_count(const uint8_t *tile, int64_t D, int32_t ncols, int prec,
                       const int32_t *chunks, int32_t n_list, uint32_t *cnt, uint8_t *tail,
-                      uint32_t *off, uint32_t *totals, hipStream_t s);
+                      uint32_t *off, uint32_t *totals, uint32_t *bsum, hipStream_t s);
+int64_t tail_scan_blocks(int64_t D);   // bsum entries per listed chunk
 hipError_t tail_fill(const uint8_t *tile, int64_t D, int32_t ncols, int prec,
                      const int32_t *chunks, int32_t n_list, const uint8_t *tail,
                      const uint32_t *off, int64_t stride, uint32_t *ent, hipStream_t s);
@@ -519,8 +523,16 @@ hipError_t launch_gather_tile(const uint8_t *tile, int64_t D, int esize, const i
                               int32_t n, uint8_t *out, hipStream_t s);
 hipError_t launch_centroid_columns(const double *master, int32_t k, int64_t D, const int32_t *terms,
                                    int32_t n, double *out, hipStream_t s);
-hipError_t launch_bucket(const int32_t *a, int64_t n, int32_t k, int64_t nblk, int32_t *hist,
+hipError_t launch_bucket(const int32_t *a, int64_t n, int32_t k, int64_t blk, int32_t *hist,
                          int32_t *counts, int64_t *offsets, int32_t *members, hipStream_t s);
+// Rows per block of the update's counting sort: blocks are walked by one
+// wavefront each, so more of them help, but the per-(block, cluster) counts
+// cost blocks x k: about 5e6 counts, 1,024 to 8,192 rows a block.
+inline int64_t bucket_rows(int64_t N, int64_t k) {
+  const int64_t target = std::min<int64_t>(2048, std::max<int64_t>(128, 5000000 / std::max<int64_t>(k, 1)));
+  const int64_t blk = ((N + target - 1) / target + 255) / 256 * 256;
+  return std::min<int64_t>(8192, std::max<int64_t>(1024, blk));
+}
 // Member sums of the tasks; terms with hot_slot[t] >= 0 (n_hot <= kSumHot of
 // them, hot_terms[slot] = t) are summed in LDS.  short_rows: the corpus has
 // short rows, summed several rows per step (when D < 2^24).

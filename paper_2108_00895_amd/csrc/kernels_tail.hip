@@ -75,49 +75,73 @@ __global__ __launch_bounds__(256) void k_tail_count(const uint8_t *tile, int64_t
   }
 }
 
-// Exclusive scan of one listed chunk's counts over terms: off[cc][t], and
-// off[cc][D] = the chunk's total.  One workgroup per chunk, 4096 terms per
-// step (four consecutive per thread), wave scans combined through LDS.
-__global__ __launch_bounds__(1024) void k_tail_scan(const uint32_t *cnt, int64_t D,
-                                                    const int32_t *chunks, uint32_t *off,
-                                                    uint32_t *totals) {
-  __shared__ uint32_t wsum[16];
-  const int cc = chunks[blockIdx.x];
+// Exclusive scan of each listed chunk's counts over terms: off[cc][t], and
+// off[cc][D] = the chunk's total (also in totals[i] for the i-th listed
+// chunk).  Three launches spread over the GPU: sums of blocks of kScanTerms
+// terms, a scan of each chunk's block sums, and the writes of each block.
+constexpr int kScanTerms = 4096;   // terms per block (256 threads x 16)
+
+__global__ __launch_bounds__(256) void k_tail_bsum(const uint32_t *cnt, int64_t D,
+                                                   const int32_t *chunks, int64_t nb,
+                                                   uint32_t *bsum) {
+  __shared__ uint32_t sh[256];
+  const int cc = chunks[blockIdx.y];
+  const int64_t t0 = (int64_t)blockIdx.x * kScanTerms;
   const uint32_t *c = cnt + (int64_t)cc * D;
-  uint32_t *o = off + (int64_t)cc * (D + 1);
-  const int t = threadIdx.x, lane = lane_id(), wave = t >> 6;
-  uint32_t carry = 0;
-  for (int64_t i0 = 0; i0 < D; i0 += 4096) {
-    const int64_t i = i0 + 4 * t;
-    uint32_t v[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = i + q < D ? c[i + q] : 0u;
-    const uint32_t s = v[0] + v[1] + v[2] + v[3];
-    uint32_t incl = s;
-#pragma unroll
-    for (int m = 1; m < kWave; m <<= 1) {
-      const uint32_t y = __shfl_up(incl, m, kWave);
-      if (lane >= m) incl += y;
-    }
-    if (lane == kWave - 1) wsum[wave] = incl;
-    __syncthreads();
-    uint32_t before = 0, step = 0;
-    for (int w = 0; w < 16; ++w) {
-      if (w < wave) before += wsum[w];
-      step += wsum[w];
-    }
-    uint32_t pos = carry + before + incl - s;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (i + q < D) o[i + q] = pos;
-      pos += v[q];
-    }
-    carry += step;
+  uint32_t v = 0;
+  for (int64_t t = t0 + threadIdx.x; t < min<int64_t>(D, t0 + kScanTerms); t += 256) v += c[t];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
     __syncthreads();
   }
-  if (t == 0) {
-    o[D] = carry;
-    totals[blockIdx.x] = carry;
+  if (threadIdx.x == 0) bsum[(int64_t)blockIdx.y * nb + blockIdx.x] = sh[0];
+}
+
+// Block sums -> exclusive block offsets in place, per listed chunk (a
+// handful of blocks: one thread walks them).
+__global__ void k_tail_bscan(uint32_t *bsum, int64_t nb, int32_t n_list, const int32_t *chunks,
+                             int64_t D, uint32_t *off, uint32_t *totals) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_list) return;
+  uint32_t run = 0;
+  for (int64_t b = 0; b < nb; ++b) {
+    const uint32_t v = bsum[(int64_t)i * nb + b];
+    bsum[(int64_t)i * nb + b] = run;
+    run += v;
+  }
+  off[(int64_t)chunks[i] * (D + 1) + D] = run;
+  totals[i] = run;
+}
+
+__global__ __launch_bounds__(256) void k_tail_write(const uint32_t *cnt, int64_t D,
+                                                    const int32_t *chunks, int64_t nb,
+                                                    const uint32_t *bsum, uint32_t *off) {
+  __shared__ uint32_t sh[256];
+  const int cc = chunks[blockIdx.y];
+  const int64_t t0 = (int64_t)blockIdx.x * kScanTerms + (int64_t)threadIdx.x * 16;
+  const uint32_t *c = cnt + (int64_t)cc * D;
+  uint32_t v[16], s = 0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    v[q] = t0 + q < D ? c[t0 + q] : 0u;
+    s += v[q];
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const uint32_t y = (int)threadIdx.x >= o ? sh[threadIdx.x - o] : 0u;
+    __syncthreads();
+    sh[threadIdx.x] += y;
+    __syncthreads();
+  }
+  uint32_t pos = bsum[(int64_t)blockIdx.y * nb + blockIdx.x] + sh[threadIdx.x] - s;
+  uint32_t *o = off + (int64_t)cc * (D + 1);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    if (t0 + q < D) o[t0 + q] = pos;
+    pos += v[q];
   }
 }
 
@@ -170,7 +194,7 @@ __global__ void k_tail_bases(uint64_t *base, int nch, int64_t stride) {
 
 hipError_t tail_count(const uint8_t *tile, int64_t D, int32_t ncols, int prec,
                       const int32_t *chunks, int32_t n_list, uint32_t *cnt, uint8_t *tail,
-                      uint32_t *off, uint32_t *totals, hipStream_t s) {
+                      uint32_t *off, uint32_t *totals, uint32_t *bsum, hipStream_t s) {
   if (n_list <= 0 || D <= 0) return hipSuccess;
   const dim3 g((unsigned)((D + 3) / 4), (unsigned)n_list), b(256);
   switch (prec) {
@@ -185,10 +209,17 @@ hipError_t tail_count(const uint8_t *tile, int64_t D, int32_t ncols, int prec,
       break;
     default: return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL(k_tail_scan, dim3((unsigned)n_list), dim3(1024), 0, s, cnt, D, chunks, off,
-                     totals);
+  const int64_t nb = tail_scan_blocks(D);
+  hipLaunchKernelGGL(k_tail_bsum, dim3((unsigned)nb, (unsigned)n_list), dim3(256), 0, s, cnt, D,
+                     chunks, nb, bsum);
+  hipLaunchKernelGGL(k_tail_bscan, dim3((unsigned)((n_list + 63) / 64)), dim3(64), 0, s, bsum, nb,
+                     n_list, chunks, D, off, totals);
+  hipLaunchKernelGGL(k_tail_write, dim3((unsigned)nb, (unsigned)n_list), dim3(256), 0, s, cnt, D,
+                     chunks, nb, bsum, off);
   return hipGetLastError();
 }
+
+int64_t tail_scan_blocks(int64_t D) { return (D + kScanTerms - 1) / kScanTerms; }
 
 hipError_t tail_fill(const uint8_t *tile, int64_t D, int32_t ncols, int prec,
                      const int32_t *chunks, int32_t n_list, const uint8_t *tail,

@@ -11,7 +11,6 @@
 namespace skm {
 namespace {
 
-constexpr int64_t kBucketBlock = 8192;   // rows per counting-sort block
 
 __device__ inline int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 __device__ inline int64_t gstride() { return (int64_t)gridDim.x * blockDim.x; }
@@ -280,9 +279,9 @@ __global__ __launch_bounds__(256) void k_centroid_columns(const double *master, 
 
 // ---- stable counting sort of rows by cluster
 
-__global__ void k_block_hist(const int32_t *a, int64_t n, int32_t k, int32_t *hist) {
+__global__ void k_block_hist(const int32_t *a, int64_t n, int32_t k, int64_t blk, int32_t *hist) {
   const int64_t b = blockIdx.x;
-  const int64_t lo = b * kBucketBlock, hi = min(n, lo + kBucketBlock);
+  const int64_t lo = b * blk, hi = min(n, lo + blk);
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) atomicAdd(&hist[b * k + a[i]], 1);
 }
 
@@ -327,10 +326,10 @@ __global__ __launch_bounds__(1024) void k_scan_counts(const int32_t *counts, int
 // the 64-row batch by ballots, running per-(block, cluster) counter by atomics
 // that only this wavefront touches.
 __global__ __launch_bounds__(64) void k_block_scatter(const int32_t *a, int64_t n, int32_t k,
-                                                      int32_t *hist, const int64_t *offsets,
-                                                      int32_t *members) {
+                                                      int64_t blk, int32_t *hist,
+                                                      const int64_t *offsets, int32_t *members) {
   const int64_t b = blockIdx.x;
-  const int64_t lo = b * kBucketBlock, hi = min(n, lo + kBucketBlock);
+  const int64_t lo = b * blk, hi = min(n, lo + blk);
   const int lane = lane_id();
   for (int64_t base = lo; base < hi; base += kWave) {
     const int64_t i = base + lane;
@@ -813,12 +812,13 @@ hipError_t launch_centroid_columns(const double *master, int32_t k, int64_t D, c
   return hipGetLastError();
 }
 
-hipError_t launch_bucket(const int32_t *a, int64_t n, int32_t k, int64_t nblk, int32_t *hist,
+hipError_t launch_bucket(const int32_t *a, int64_t n, int32_t k, int64_t blk, int32_t *hist,
                          int32_t *counts, int64_t *offsets, int32_t *members, hipStream_t s) {
+  const int64_t nblk = (n + blk - 1) / blk;
   hipError_t err = launch_fill_i32(hist, 0, nblk * k, s);
   if (err != hipSuccess) return err;
   if (n > 0) {
-    hipLaunchKernelGGL(k_block_hist, dim3((unsigned)nblk), dim3(256), 0, s, a, n, k, hist);
+    hipLaunchKernelGGL(k_block_hist, dim3((unsigned)nblk), dim3(256), 0, s, a, n, k, blk, hist);
     if ((err = hipGetLastError()) != hipSuccess) return err;
   }
   hipLaunchKernelGGL(k_block_scan, dim3((unsigned)((k + 255) / 256)), dim3(256), 0, s, hist, nblk, k,
@@ -827,8 +827,8 @@ hipError_t launch_bucket(const int32_t *a, int64_t n, int32_t k, int64_t nblk, i
   hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, s, counts, k, offsets);
   if ((err = hipGetLastError()) != hipSuccess) return err;
   if (n > 0) {
-    hipLaunchKernelGGL(k_block_scatter, dim3((unsigned)nblk), dim3(64), 0, s, a, n, k, hist, offsets,
-                       members);
+    hipLaunchKernelGGL(k_block_scatter, dim3((unsigned)nblk), dim3(64), 0, s, a, n, k, blk, hist,
+                       offsets, members);
     err = hipGetLastError();
   }
   return err;
