@@ -261,11 +261,12 @@ TailView tail_view(const skm_ctx *c, int which) {
 // Scoring copies of the centroids flagged in `changed` (all when nullptr),
 // and the full copy's tail lists (of the chunks in `chunks` when given).
 skm_status rebuild_tiles(skm_ctx *c, const uint8_t *changed,
-                         const std::vector<int32_t> *chunks) {
+                         const std::vector<int32_t> *chunks, const uint8_t *qmask = nullptr) {
+  // qmask: the changed centroids whose codes k_renorm has not written
+  const uint8_t *q = qmask ? qmask : changed;
   if (c->prec == SKM_FP8_E4M3)
-    HIP_TRY(c, launch_fp8_scales(c->master, c->k, c->D, changed, c->scale, c->stream));
-  HIP_TRY(c, launch_quantize(c->master, c->k, c->D, changed, c->scale, c->prec, c->tile,
-                             c->stream));
+    HIP_TRY(c, launch_fp8_scales(c->master, c->k, c->D, q, c->scale, c->stream));
+  HIP_TRY(c, launch_quantize(c->master, c->k, c->D, q, c->scale, c->prec, c->tile, c->stream));
   ST_TRY(build_tail(c, 0, c->tile, c->k, changed ? chunks : nullptr));
   if (c->head_H > 0)
     HIP_TRY(c, launch_head_codes(c->tile, c->master, c->scale, c->D, c->k, c->prec, c->head_terms,
@@ -563,10 +564,15 @@ skm_status sum_changed(skm_ctx *c, int32_t n_ids, std::vector<int32_t> &ids) {
     if (!groups.empty())
       HIP_TRY(c, hipMemcpyAsync(c->groups, groups.data(), sizeof(int4) * groups.size(),
                                 hipMemcpyHostToDevice, s));
+    SumSupport sp;
+    sp.W = c->sup_W;
+    sp.nb = c->sup_nb;
+    sp.s_dirty = c->sup_sdirty;
     HIP_TRY(c, launch_sum_tasks(c->indptr, c->indices, c->values, c->members, c->tasks, c->task_r0,
                                 (int32_t)tasks.size(), c->D, c->S, c->work, c->sum_hot_slot,
-                                c->sum_hot_terms, c->n_sum_hot, s, short_rows(c->N, c->Z)));
-    HIP_TRY(c, launch_combine(c->groups, (int32_t)groups.size(), c->D, c->work, c->S, s));
+                                c->sum_hot_terms, c->n_sum_hot, s, short_rows(c->N, c->Z), sp));
+    HIP_TRY(c, launch_combine(c->groups, (int32_t)groups.size(), c->D, c->work, c->S, c->sup_nb,
+                              c->sup_W, s));
     // the host vectors are reused next round: wait for the copies to finish
     HIP_TRY(c, hipStreamSynchronize(s));
   }
@@ -895,6 +901,7 @@ size_t skm_context_bytes(const skm_csr *docs, const skm_config *cfg) {
   if (!borrow) b += 8 * (N + 1) + 8 * Z;                      // rows
   b += 16 * N;                                                 // norms
   b += 16 * k * D + D * ld * esize * (ncc ? 2 : 1);            // master, sums, codes
+  b += 8 * k * std::ceil(D / 32) + 3 * k;                      // support bitmaps
   b += 4 * ld + 48 * k + 8 * (k + 1);                          // scales, per-centroid state
   b += N * (4 + 4 + 8 * 4 + 4 + 8 + 1 + 4);                    // per-row state, members
   b += 4 * std::ceil(N / (double)bucket_rows(docs->n_rows, cfg->k)) * k +
@@ -1022,6 +1029,12 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
     if (_s != SKM_OK) return cleanup(_s);         \
   } while (0)
   A_(c->master, kD);
+  c->sup_W = (c->D + 31) / 32;
+  A_(c->sup_nb, k * c->sup_W);
+  A_(c->sup_mb, k * c->sup_W);
+  A_(c->sup_mvalid, k);
+  A_(c->sup_sdirty, k);
+  A_(c->sup_qmask, k);
   A_(c->S, kD);
   A_(c->tile, c->D * c->ld * c->esize);
   A_(c->scale, c->ld);
@@ -1107,6 +1120,8 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
 
   hipStream_t s = c->stream;
   if (launch_fill_u8(c->tile, 0, c->D * c->ld * c->esize, s) != hipSuccess ||
+      launch_fill_u8(c->sup_mvalid, 0, k, s) != hipSuccess ||
+      launch_fill_u8(c->sup_sdirty, 1, k, s) != hipSuccess ||
       launch_fill_f64(c->snorm, 0.0, k, s) != hipSuccess ||
       launch_fill_u8(c->changed, 1, k, s) != hipSuccess)
     return cleanup(device_fail(c, "fill", hipGetLastError()));
@@ -1654,10 +1669,20 @@ skm_status skm_update(skm_ctx *c, skm_iter_stats *st_out) {
   ST_TRY(sum_changed(c, n_ids, ids));
   for (int32_t j : ids)   // ascending ids: ascending chunks
     if (chunks.empty() || chunks.back() != j / kChunk) chunks.push_back(j / kChunk);
+  RenormSupport rs;
+  rs.W = c->sup_W;
+  rs.nb = c->sup_nb;
+  rs.mb = c->sup_mb;
+  rs.mvalid = c->sup_mvalid;
+  rs.s_dirty = c->sup_sdirty;
+  rs.qmask = c->sup_qmask;
+  rs.tile = c->tile;
+  rs.scale = c->scale;
+  HIP_TRY(c, launch_fill_u8(c->sup_qmask, 0, c->k, s));
   HIP_TRY(c, launch_renorm(c->S, c->counts, c->ch_ids, n_ids, c->D, c->master, c->snorm, c->shift,
-                           c->dot_old, s));
+                           c->dot_old, rs, c->prec, s));
   HIP_TRY(c, launch_reduce_stats(c->changed, c->snorm, c->shift, c->dot_old, c->k, c->red, s));
-  ST_TRY(rebuild_tiles(c, c->changed, &chunks));
+  ST_TRY(rebuild_tiles(c, c->changed, &chunks, c->sup_qmask));
   HIP_TRY(c, hipEventRecord(c->ev[4], s));
   c->ms_index_build = 0.f;
   c->idx_last_build = 0;
@@ -1911,6 +1936,7 @@ skm_status skm_set_centroids(skm_ctx *c, const double *centroids) {
   if (!centroids) return fail(SKM_E_INVALID, "centroids is NULL");
   HIP_TRY(c, hipMemcpyAsync(c->master, centroids, sizeof(double) * c->k * c->D,
                             hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, launch_fill_u8(c->sup_mvalid, 0, c->k, c->stream));   // supports unknown
   ST_TRY(rebuild_tiles(c, nullptr, nullptr));
   if (c->cfg.flags & SKM_INDEX) ST_TRY(build_index(c));
   HIP_TRY(c, launch_fill_u8(c->changed, 1, c->k, c->stream));

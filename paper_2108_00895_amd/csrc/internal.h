@@ -134,6 +134,27 @@ struct NewRows {
   const uint8_t *mode = nullptr;   // [n] 2 = row already assigned (index path), or nullptr
 };
 
+// Support bitmaps of the update (bit t of a cluster's row: entry t is
+// non-zero), so that clusters summed straight into their sum row are
+// renormalised and requantised over their non-zeros only
+// (kernels_update.hip).
+struct SumSupport {
+  int64_t W = 0;                     // 32-bit words per cluster row
+  uint32_t *nb = nullptr;            // [k][W] support of S_j built by this update's sums
+  const uint8_t *s_dirty = nullptr;  // [k] S_j may hold non-zeros (cleared before summing)
+};
+
+struct RenormSupport {
+  int64_t W = 0;
+  const uint32_t *nb = nullptr;      // [k][W] support of S_j (this update), nullptr = none
+  uint32_t *mb = nullptr;            // [k][W] support of the master row c_j
+  uint8_t *mvalid = nullptr;         // [k] mb_j is exact
+  uint8_t *s_dirty = nullptr;        // [k] S_j may hold non-zeros
+  uint8_t *qmask = nullptr;          // [k] out: changed, left to k_quantize
+  uint8_t *tile = nullptr;           // scoring copy (written for the sparse path)
+  float *scale = nullptr;            // FP8 scales (written for the sparse path)
+};
+
 // Device pieces of the Sec. 3.2 index.
 struct IndexBuild {
   const double *master;
@@ -377,6 +398,10 @@ struct skm_ctx {
   int64_t work_slots = 0;
   int n_cu = 256;                // compute units (the persistent scoring grid is sized from it)
   int64_t nblk = 0;             // blocks of the update's counting sort
+  // support bitmaps of the update (RenormSupport)
+  int64_t sup_W = 0;             // 32-bit words per cluster row
+  uint32_t *sup_nb = nullptr, *sup_mb = nullptr;          // [k][sup_W]
+  uint8_t *sup_mvalid = nullptr, *sup_sdirty = nullptr, *sup_qmask = nullptr;  // [k]
   int64_t bucket_rows = 8192;   // rows per block (bucket_rows())
 
   // state
@@ -540,12 +565,13 @@ hipError_t launch_sum_tasks(const int64_t *indptr, const int32_t *indices, const
                             const int32_t *members, const int4 *tasks, const int64_t *task_r0,
                             int32_t n_tasks, int64_t D, double *S, double *work,
                             const int32_t *hot_slot, const int32_t *hot_terms, int32_t n_hot,
-                            hipStream_t s, bool short_rows);
+                            hipStream_t s, bool short_rows, SumSupport sp);
 hipError_t launch_combine(const int4 *groups, int32_t n_groups, int64_t D, const double *work,
-                          double *S, hipStream_t s);
-hipError_t launch_renorm(const double *S, const int32_t *counts, const int32_t *ids, int32_t n_ids,
+                          double *S, uint32_t *nb, int64_t W, hipStream_t s);
+// Renormalisation of the n_ids listed clusters (see k_renorm).
+hipError_t launch_renorm(double *S, const int32_t *counts, const int32_t *ids, int32_t n_ids,
                          int64_t D, double *master, double *snorm, double *shift, double *dot_old,
-                         hipStream_t s);
+                         const RenormSupport &rs, int prec, hipStream_t s);
 hipError_t launch_reduce_stats(const uint8_t *changed, const double *snorm, const double *shift,
                                const double *dot_old, int32_t k, double *out, hipStream_t s);
 

@@ -355,6 +355,41 @@ __global__ __launch_bounds__(64) void k_block_scatter(const int32_t *a, int64_t 
   }
 }
 
+// A sum task's destination row: workspace rows and sum rows that may hold
+// values (s_dirty) are cleared; a sum row kept clear since its last use is
+// not (its values were zeroed by the renormalisation that read them).  For a
+// task summing straight into S_j the support bitmap of S_j (bit t: S_j[t] !=
+// 0) is cleared here and set as terms are first added.
+__device__ inline void prepare_dst(double *dst, int64_t D, uint32_t *bits, const SumSupport &sp,
+                                   const int4 &tk) {
+  const int tid = threadIdx.x;
+  const bool clear = tk.z >= 0 || !sp.s_dirty || sp.s_dirty[tk.x];
+  if (clear) {
+    if (D % 2 == 0) {
+      v2d *d2 = reinterpret_cast<v2d *>(dst);
+      const v2d z = {0.0, 0.0};
+      for (int64_t t = tid; t < D / 2; t += 256) __builtin_nontemporal_store(z, d2 + t);
+    } else {
+      for (int64_t t = tid; t < D; t += 256) dst[t] = 0.0;
+    }
+  }
+  if (bits)
+    for (int64_t w = tid; w < sp.W; w += 256) bits[w] = 0u;
+}
+
+// dst[t] += v; the first add to an entry (values are positive, so the entry
+// was 0.0) sets its support bit.
+__device__ inline void add_tracked(double *dst, uint32_t *bits, int32_t t, double v) {
+  const double old = dst[t];
+  dst[t] = old + v;
+  if (bits && old == 0.0) atomicOr(&bits[t >> 5], 1u << (t & 31));
+}
+
+__device__ inline void store_tracked(double *dst, uint32_t *bits, int32_t t, double v) {
+  dst[t] = v;
+  if (bits && v != 0.0) atomicOr(&bits[t >> 5], 1u << (t & 31));
+}
+
 // Segmented member sums: task = (cluster, member range [r0, r1), destination).
 // A cluster with more members than one segment is split into fixed segments
 // whose sums go to partial rows of a workspace (dest >= 0) and are added in
@@ -370,18 +405,14 @@ __global__ __launch_bounds__(256) void k_sum_tasks(const int64_t *indptr, const 
                                                    const int4 *tasks, const int64_t *task_r0,
                                                    int64_t D, double *S, double *work,
                                                    const int32_t *hot_slot,
-                                                   const int32_t *hot_terms, int32_t n_hot) {
+                                                   const int32_t *hot_terms, int32_t n_hot,
+                                                   SumSupport sp) {
   __shared__ double hot[kSumHot];
   const int4 tk = tasks[blockIdx.x];   // x = cluster, y = count, z = dest slot (-1: S_j)
   double *dst = tk.z < 0 ? S + (int64_t)tk.x * D : work + (int64_t)tk.z * D;
+  uint32_t *bits = (sp.nb && tk.z < 0) ? sp.nb + (int64_t)tk.x * sp.W : nullptr;
   const int tid = threadIdx.x;
-  if (D % 2 == 0) {
-    v2d *d2 = reinterpret_cast<v2d *>(dst);
-    const v2d z = {0.0, 0.0};
-    for (int64_t t = tid; t < D / 2; t += 256) __builtin_nontemporal_store(z, d2 + t);
-  } else {
-    for (int64_t t = tid; t < D; t += 256) dst[t] = 0.0;
-  }
+  prepare_dst(dst, D, bits, sp, tk);
   for (int h = tid; h < n_hot; h += 256) hot[h] = 0.0;
   // Member row ranges are staged in LDS 256 rows at a time, and each thread's
   // first entry of the next row is loaded before the current row's adds, so
@@ -420,7 +451,7 @@ __global__ __launch_bounds__(256) void k_sum_tasks(const int64_t *indptr, const 
         if (h0 >= 0) {
           hot[h0] += v0;
         } else {
-          dst[t0] += v0;
+          add_tracked(dst, bits, t0, v0);
         }
       }
       for (int64_t p = b + 256 + tid; p < e; p += 256) {   // rows longer than 256 entries
@@ -430,14 +461,14 @@ __global__ __launch_bounds__(256) void k_sum_tasks(const int64_t *indptr, const 
         if (h >= 0) {
           hot[h] += v;
         } else {
-          dst[t] += v;
+          add_tracked(dst, bits, t, v);
         }
       }
       __syncthreads();
     }
   }
   __syncthreads();
-  for (int h = tid; h < n_hot; h += 256) dst[hot_terms[h]] = hot[h];
+  for (int h = tid; h < n_hot; h += 256) store_tracked(dst, bits, hot_terms[h], hot[h]);
 }
 
 // The same sums for corpora of short rows (a few dozen terms or fewer).  A
@@ -456,7 +487,8 @@ __global__ __launch_bounds__(256) void k_sum_tasks_short(const int64_t *indptr,
                                                          const int4 *tasks, const int64_t *task_r0,
                                                          int64_t D, double *S, double *work,
                                                          const int32_t *hot_slot,
-                                                         const int32_t *hot_terms, int32_t n_hot) {
+                                                         const int32_t *hot_terms, int32_t n_hot,
+                                                         SumSupport sp) {
   __shared__ double hot[kSumHot];
   __shared__ int64_t rb[256];
   __shared__ int32_t plen[257];          // inclusive prefix of the group's row lengths
@@ -464,21 +496,16 @@ __global__ __launch_bounds__(256) void k_sum_tasks_short(const int64_t *indptr,
   __shared__ double val[256];
   const int4 tk = tasks[blockIdx.x];   // x = cluster, y = count, z = dest slot (-1: S_j)
   double *dst = tk.z < 0 ? S + (int64_t)tk.x * D : work + (int64_t)tk.z * D;
+  uint32_t *bits = (sp.nb && tk.z < 0) ? sp.nb + (int64_t)tk.x * sp.W : nullptr;
   const int tid = threadIdx.x;
-  if (D % 2 == 0) {
-    v2d *d2 = reinterpret_cast<v2d *>(dst);
-    const v2d z = {0.0, 0.0};
-    for (int64_t t = tid; t < D / 2; t += 256) __builtin_nontemporal_store(z, d2 + t);
-  } else {
-    for (int64_t t = tid; t < D; t += 256) dst[t] = 0.0;
-  }
+  prepare_dst(dst, D, bits, sp, tk);
   for (int h = tid; h < n_hot; h += 256) hot[h] = 0.0;
   auto add = [&](int32_t t, double v) {
     const int32_t h = hot_slot ? hot_slot[t] : -1;
     if (h >= 0) {
       hot[h] += v;
     } else {
-      dst[t] += v;
+      add_tracked(dst, bits, t, v);
     }
   };
   const int64_t r0 = task_r0[blockIdx.x], r1 = r0 + tk.y;
@@ -554,109 +581,182 @@ __global__ __launch_bounds__(256) void k_sum_tasks_short(const int64_t *indptr,
     }
   }
   __syncthreads();
-  for (int h = tid; h < n_hot; h += 256) dst[hot_terms[h]] = hot[h];
+  for (int h = tid; h < n_hot; h += 256) store_tracked(dst, bits, hot_terms[h], hot[h]);
 }
 
-// S_j = sum of its segment partials, in segment order.  Block (group, term block).
+// S_j = sum of its segment partials, in segment order, and its support bits
+// (a wavefront's 64 consecutive terms by ballot).  Block (group, term block).
 __global__ __launch_bounds__(256) void k_combine(const int4 *groups, int64_t D, int64_t tblk,
-                                                 const double *work, double *S) {
+                                                 const double *work, double *S, uint32_t *nb,
+                                                 int64_t W) {
   const int4 g = groups[blockIdx.x / tblk];   // x = cluster, y = first slot, z = segments
   const int64_t t0 = (blockIdx.x % tblk) * 4096;
-  for (int64_t t = t0 + threadIdx.x; t < min(D, t0 + 4096); t += 256) {
-    const double *w = work + (int64_t)g.y * D + t;
+  for (int64_t tw = t0 + (threadIdx.x & ~63); tw < min(D, t0 + 4096); tw += 256) {
+    const int64_t t = tw + lane_id();
     double s = 0.0;
-    int p = 0;
-    for (; p + 4 <= g.z; p += 4) {   // four loads in flight, added in segment order
-      const double w0 = __builtin_nontemporal_load(w + (int64_t)p * D);
-      const double w1 = __builtin_nontemporal_load(w + (int64_t)(p + 1) * D);
-      const double w2 = __builtin_nontemporal_load(w + (int64_t)(p + 2) * D);
-      const double w3 = __builtin_nontemporal_load(w + (int64_t)(p + 3) * D);
-      s += w0;
-      s += w1;
-      s += w2;
-      s += w3;
+    if (t < D) {
+      const double *w = work + (int64_t)g.y * D + t;
+      int p = 0;
+      for (; p + 4 <= g.z; p += 4) {   // four loads in flight, added in segment order
+        const double w0 = __builtin_nontemporal_load(w + (int64_t)p * D);
+        const double w1 = __builtin_nontemporal_load(w + (int64_t)(p + 1) * D);
+        const double w2 = __builtin_nontemporal_load(w + (int64_t)(p + 2) * D);
+        const double w3 = __builtin_nontemporal_load(w + (int64_t)(p + 3) * D);
+        s += w0;
+        s += w1;
+        s += w2;
+        s += w3;
+      }
+      for (; p < g.z; ++p) s += __builtin_nontemporal_load(w + (int64_t)p * D);
+      __builtin_nontemporal_store(s, S + (int64_t)g.x * D + t);
     }
-    for (; p < g.z; ++p) s += __builtin_nontemporal_load(w + (int64_t)p * D);
-    __builtin_nontemporal_store(s, S + (int64_t)g.x * D + t);
+    if (nb) {
+      const uint64_t m = __ballot(s != 0.0);
+      if (lane_id() == 0) {
+        nb[(int64_t)g.x * W + (tw >> 5)] = (uint32_t)m;
+        if ((tw >> 5) + 1 < W) nb[(int64_t)g.x * W + (tw >> 5) + 1] = (uint32_t)(m >> 32);
+      }
+    }
   }
+}
+
+__device__ inline double block_max_256(double v, double *sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) sh[t] = fmax(sh[t], sh[t + w]);
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
 }
 
 // c_j = S_j / ||S_j|| (empty clusters keep c_j), with the per-cluster shift
-// ||c_j(new) - c_j(old)||^2 and S_j . c_j(old).  One workgroup per cluster;
-// 16-byte loads, four in flight per thread (rows start 16-byte aligned when D
-// is even; odd D takes the scalar loop).
-__global__ __launch_bounds__(256) void k_renorm(const double *S, const int32_t *counts,
+// ||c_j(new) - c_j(old)||^2 and S_j . c_j(old).  One workgroup per cluster.
+// When the support bitmaps of S_j (this update's sums) and of c_j are known,
+// only their non-zeros are visited: the norm over S_j's, then over the union
+// the new master entries, the shift, S_j . c_j(old), the scoring codes (FP8:
+// the scale from S_j's largest entry first), and S_j's entries are zeroed
+// for its next use.  Otherwise (the first update, or after the centroids were
+// replaced) every entry is visited in the same order, the master's support
+// bitmap is built, and k_quantize encodes the row.
+template <int P>
+__global__ __launch_bounds__(256) void k_renorm(double *S, const int32_t *counts,
                                                 const int32_t *ids, int64_t D, double *master,
-                                                double *snorm, double *shift, double *dot_old) {
+                                                double *snorm, double *shift, double *dot_old,
+                                                RenormSupport rs) {
   __shared__ double sh[256];
   const int32_t j = ids[blockIdx.x];
-  const double *Sj = S + (int64_t)j * D;
+  double *Sj = S + (int64_t)j * D;
   double *Mj = master + (int64_t)j * D;
+  const int tid = threadIdx.x;
   if (counts[j] == 0) {
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
       snorm[j] = 0.0;
       shift[j] = 0.0;
       dot_old[j] = 0.0;
+      if (rs.qmask) rs.qmask[j] = 0;   // c_j is kept, so are its codes
     }
     return;
   }
-  const int tid = threadIdx.x;
-  const int64_t D2 = (D % 2 == 0) ? D / 2 : 0;
-  const v2d *S2 = reinterpret_cast<const v2d *>(Sj);
-  v2d *M2 = reinterpret_cast<v2d *>(Mj);
+  if (rs.nb && rs.mvalid[j]) {
+    const uint32_t *nbj = rs.nb + (int64_t)j * rs.W;
+    uint32_t *mbj = rs.mb + (int64_t)j * rs.W;
+    double ss = 0.0, smax = 0.0;
+    for (int64_t w = tid; w < rs.W; w += 256) {
+      uint32_t m = nbj[w];
+      while (m) {
+        const int64_t t = w * 32 + __builtin_ctz(m);
+        m &= m - 1;
+        const double v = Sj[t];
+        ss += v * v;
+        smax = fmax(smax, v);
+      }
+    }
+    const double nrm = sqrt(block_sum_256(ss, sh));
+    int e = 0;
+    if (P == SKM_FP8_E4M3) {
+      // the scale of the new row: its largest value is the largest S_j over the norm
+      smax = block_max_256(smax, sh);
+      e = e4m3_scale_exp(smax / nrm);
+      if (tid == 0) rs.scale[j] = ldexpf(1.0f, e);
+    }
+    using T = typename CodeOf<P>::T;
+    T *codes = reinterpret_cast<T *>(rs.tile);
+    double sh2 = 0.0, dot = 0.0;
+    for (int64_t w = tid; w < rs.W; w += 256) {
+      const uint32_t nw = nbj[w];
+      uint32_t m = nw | mbj[w];
+      while (m) {
+        const int b = __builtin_ctz(m);
+        m &= m - 1;
+        const int64_t t = w * 32 + b;
+        const bool in = (nw >> b) & 1u;
+        const double sv = in ? Sj[t] : 0.0;
+        const double o = Mj[t];
+        const double c = in ? sv / nrm : 0.0;
+        const double d = c - o;
+        sh2 += d * d;
+        dot += sv * o;
+        Mj[t] = c;
+        codes[tile_index(t, j, D)] = encode_code<P>(c, e);
+        if (in) Sj[t] = 0.0;
+      }
+      mbj[w] = nw;
+    }
+    sh2 = block_sum_256(sh2, sh);
+    dot = block_sum_256(dot, sh);
+    if (tid == 0) {
+      snorm[j] = nrm;
+      shift[j] = sh2;
+      dot_old[j] = dot;
+      rs.s_dirty[j] = 0;
+      rs.qmask[j] = 0;
+    }
+    return;
+  }
+  // Dense rows, visited in the sparse path's order (thread tid takes words
+  // tid, tid + 256, ..., the 32 terms of a word ascending): the zeros add
+  // exact zeros, so both paths give the same bits for the same S_j.
+  const int64_t W = (D + 31) / 32;
   double ss = 0.0;
-  int64_t i = tid;
-  for (; i + 768 < D2; i += 1024) {
-    const v2d a0 = __builtin_nontemporal_load(S2 + i);
-    const v2d a1 = __builtin_nontemporal_load(S2 + i + 256);
-    const v2d a2 = __builtin_nontemporal_load(S2 + i + 512);
-    const v2d a3 = __builtin_nontemporal_load(S2 + i + 768);
-    ss += a0.x * a0.x + a0.y * a0.y + a1.x * a1.x + a1.y * a1.y;
-    ss += a2.x * a2.x + a2.y * a2.y + a3.x * a3.x + a3.y * a3.y;
+  for (int64_t w = tid; w < W; w += 256) {
+    const int64_t t0 = w * 32, n = min<int64_t>(32, D - t0);
+    for (int64_t b = 0; b < n; ++b) {
+      const double v = Sj[t0 + b];
+      ss += v * v;
+    }
   }
-  for (; i < D2; i += 256) {
-    const v2d a0 = __builtin_nontemporal_load(S2 + i);
-    ss += a0.x * a0.x + a0.y * a0.y;
-  }
-  for (int64_t t = 2 * D2 + tid; t < D; t += 256) ss += Sj[t] * Sj[t];
   const double nrm = sqrt(block_sum_256(ss, sh));
   double sh2 = 0.0, dot = 0.0;
-  auto one = [&](double s, double o) -> double {
-    const double c = s / nrm;
-    const double d = c - o;
-    sh2 += d * d;
-    dot += s * o;
-    return c;
-  };
-  i = tid;
-  for (; i + 256 < D2; i += 512) {
-    const v2d a0 = __builtin_nontemporal_load(S2 + i);
-    const v2d a1 = __builtin_nontemporal_load(S2 + i + 256);
-    const v2d o0 = __builtin_nontemporal_load(M2 + i);
-    const v2d o1 = __builtin_nontemporal_load(M2 + i + 256);
-    v2d c0, c1;
-    c0.x = one(a0.x, o0.x);
-    c0.y = one(a0.y, o0.y);
-    c1.x = one(a1.x, o1.x);
-    c1.y = one(a1.y, o1.y);
-    __builtin_nontemporal_store(c0, M2 + i);
-    __builtin_nontemporal_store(c1, M2 + i + 256);
+  uint32_t *mbj = rs.mb ? rs.mb + (int64_t)j * rs.W : nullptr;
+  for (int64_t w = tid; w < W; w += 256) {
+    const int64_t t0 = w * 32, n = min<int64_t>(32, D - t0);
+    uint32_t m = 0;
+    for (int64_t b = 0; b < n; ++b) {
+      const double sv = Sj[t0 + b], o = Mj[t0 + b];
+      const double c = sv / nrm;
+      const double d = c - o;
+      sh2 += d * d;
+      dot += sv * o;
+      Mj[t0 + b] = c;
+      m |= (c != 0.0 ? 1u : 0u) << b;
+    }
+    if (mbj) mbj[w] = m;
   }
-  for (; i < D2; i += 256) {
-    const v2d a0 = __builtin_nontemporal_load(S2 + i);
-    const v2d o0 = __builtin_nontemporal_load(M2 + i);
-    v2d c0;
-    c0.x = one(a0.x, o0.x);
-    c0.y = one(a0.y, o0.y);
-    __builtin_nontemporal_store(c0, M2 + i);
-  }
-  for (int64_t t = 2 * D2 + tid; t < D; t += 256) Mj[t] = one(Sj[t], Mj[t]);
   sh2 = block_sum_256(sh2, sh);
   dot = block_sum_256(dot, sh);
   if (tid == 0) {
     snorm[j] = nrm;
     shift[j] = sh2;
     dot_old[j] = dot;
+    if (rs.mb) {
+      rs.mvalid[j] = 1;
+      rs.s_dirty[j] = 1;
+      rs.qmask[j] = 1;
+    }
   }
 }
 
@@ -838,36 +938,49 @@ hipError_t launch_sum_tasks(const int64_t *indptr, const int32_t *indices, const
                             const int32_t *members, const int4 *tasks, const int64_t *task_r0,
                             int32_t n_tasks, int64_t D, double *S, double *work,
                             const int32_t *hot_slot, const int32_t *hot_terms, int32_t n_hot,
-                            hipStream_t s, bool short_rows) {
+                            hipStream_t s, bool short_rows, SumSupport sp) {
   if (n_tasks <= 0) return hipSuccess;
   if (n_hot > kSumHot || (n_hot > 0 && (!hot_slot || !hot_terms))) return hipErrorInvalidValue;
   if (short_rows && D < (int64_t(1) << 24)) {
     hipLaunchKernelGGL(k_sum_tasks_short, dim3((unsigned)n_tasks), dim3(256), 0, s, indptr, indices,
                        values, members, tasks, task_r0, D, S, work,
-                       n_hot > 0 ? hot_slot : nullptr, hot_terms, n_hot);
+                       n_hot > 0 ? hot_slot : nullptr, hot_terms, n_hot, sp);
   } else {
     hipLaunchKernelGGL(k_sum_tasks, dim3((unsigned)n_tasks), dim3(256), 0, s, indptr, indices,
                        values, members, tasks, task_r0, D, S, work,
-                       n_hot > 0 ? hot_slot : nullptr, hot_terms, n_hot);
+                       n_hot > 0 ? hot_slot : nullptr, hot_terms, n_hot, sp);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_combine(const int4 *groups, int32_t n_groups, int64_t D, const double *work,
-                          double *S, hipStream_t s) {
+                          double *S, uint32_t *nb, int64_t W, hipStream_t s) {
   if (n_groups <= 0) return hipSuccess;
   const int64_t tblk = (D + 4095) / 4096;
   hipLaunchKernelGGL(k_combine, dim3((unsigned)(n_groups * tblk)), dim3(256), 0, s, groups, D, tblk,
-                     work, S);
+                     work, S, nb, W);
   return hipGetLastError();
 }
 
-hipError_t launch_renorm(const double *S, const int32_t *counts, const int32_t *ids, int32_t n_ids,
+hipError_t launch_renorm(double *S, const int32_t *counts, const int32_t *ids, int32_t n_ids,
                          int64_t D, double *master, double *snorm, double *shift, double *dot_old,
-                         hipStream_t s) {
+                         const RenormSupport &rs, int prec, hipStream_t s) {
   if (n_ids <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_renorm, dim3((unsigned)n_ids), dim3(256), 0, s, S, counts, ids, D, master,
-                     snorm, shift, dot_old);
+  switch (prec) {
+    case SKM_FP32:
+      hipLaunchKernelGGL(k_renorm<SKM_FP32>, dim3((unsigned)n_ids), dim3(256), 0, s, S, counts, ids,
+                         D, master, snorm, shift, dot_old, rs);
+      break;
+    case SKM_BF16:
+      hipLaunchKernelGGL(k_renorm<SKM_BF16>, dim3((unsigned)n_ids), dim3(256), 0, s, S, counts, ids,
+                         D, master, snorm, shift, dot_old, rs);
+      break;
+    case SKM_FP8_E4M3:
+      hipLaunchKernelGGL(k_renorm<SKM_FP8_E4M3>, dim3((unsigned)n_ids), dim3(256), 0, s, S, counts,
+                         ids, D, master, snorm, shift, dot_old, rs);
+      break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
