@@ -567,7 +567,6 @@ skm_status sum_changed(skm_ctx *c, int32_t n_ids, std::vector<int32_t> &ids) {
     SumSupport sp;
     sp.W = c->sup_W;
     sp.nb = c->sup_nb;
-    sp.s_dirty = c->sup_sdirty;
     HIP_TRY(c, launch_sum_tasks(c->indptr, c->indices, c->values, c->members, c->tasks, c->task_r0,
                                 (int32_t)tasks.size(), c->D, c->S, c->work, c->sum_hot_slot,
                                 c->sum_hot_terms, c->n_sum_hot, s, short_rows(c->N, c->Z), sp));
@@ -901,7 +900,7 @@ size_t skm_context_bytes(const skm_csr *docs, const skm_config *cfg) {
   if (!borrow) b += 8 * (N + 1) + 8 * Z;                      // rows
   b += 16 * N;                                                 // norms
   b += 16 * k * D + D * ld * esize * (ncc ? 2 : 1);            // master, sums, codes
-  b += 8 * k * std::ceil(D / 32) + 3 * k;                      // support bitmaps
+  b += 8 * k * std::ceil(D / 32) + 2 * k;                      // support bitmaps
   b += 4 * ld + 48 * k + 8 * (k + 1);                          // scales, per-centroid state
   b += N * (4 + 4 + 8 * 4 + 4 + 8 + 1 + 4);                    // per-row state, members
   b += 4 * std::ceil(N / (double)bucket_rows(docs->n_rows, cfg->k)) * k +
@@ -1033,7 +1032,6 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
   A_(c->sup_nb, k * c->sup_W);
   A_(c->sup_mb, k * c->sup_W);
   A_(c->sup_mvalid, k);
-  A_(c->sup_sdirty, k);
   A_(c->sup_qmask, k);
   A_(c->S, kD);
   A_(c->tile, c->D * c->ld * c->esize);
@@ -1121,7 +1119,7 @@ skm_status skm_init(const skm_csr *docs, const skm_config *cfg, skm_ctx **out) {
   hipStream_t s = c->stream;
   if (launch_fill_u8(c->tile, 0, c->D * c->ld * c->esize, s) != hipSuccess ||
       launch_fill_u8(c->sup_mvalid, 0, k, s) != hipSuccess ||
-      launch_fill_u8(c->sup_sdirty, 1, k, s) != hipSuccess ||
+      launch_fill_f64(c->S, 0.0, kD, s) != hipSuccess ||
       launch_fill_f64(c->snorm, 0.0, k, s) != hipSuccess ||
       launch_fill_u8(c->changed, 1, k, s) != hipSuccess)
     return cleanup(device_fail(c, "fill", hipGetLastError()));
@@ -1674,7 +1672,6 @@ skm_status skm_update(skm_ctx *c, skm_iter_stats *st_out) {
   rs.nb = c->sup_nb;
   rs.mb = c->sup_mb;
   rs.mvalid = c->sup_mvalid;
-  rs.s_dirty = c->sup_sdirty;
   rs.qmask = c->sup_qmask;
   rs.tile = c->tile;
   rs.scale = c->scale;

@@ -141,15 +141,13 @@ struct NewRows {
 struct SumSupport {
   int64_t W = 0;                     // 32-bit words per cluster row
   uint32_t *nb = nullptr;            // [k][W] support of S_j built by this update's sums
-  const uint8_t *s_dirty = nullptr;  // [k] S_j may hold non-zeros (cleared before summing)
 };
 
 struct RenormSupport {
   int64_t W = 0;
-  const uint32_t *nb = nullptr;      // [k][W] support of S_j (this update), nullptr = none
+  const uint32_t *nb = nullptr;      // [k][W] support of S_j (this update)
   uint32_t *mb = nullptr;            // [k][W] support of the master row c_j
   uint8_t *mvalid = nullptr;         // [k] mb_j is exact
-  uint8_t *s_dirty = nullptr;        // [k] S_j may hold non-zeros
   uint8_t *qmask = nullptr;          // [k] out: changed, left to k_quantize
   uint8_t *tile = nullptr;           // scoring copy (written for the sparse path)
   float *scale = nullptr;            // FP8 scales (written for the sparse path)
@@ -401,7 +399,7 @@ struct skm_ctx {
   // support bitmaps of the update (RenormSupport)
   int64_t sup_W = 0;             // 32-bit words per cluster row
   uint32_t *sup_nb = nullptr, *sup_mb = nullptr;          // [k][sup_W]
-  uint8_t *sup_mvalid = nullptr, *sup_sdirty = nullptr, *sup_qmask = nullptr;  // [k]
+  uint8_t *sup_mvalid = nullptr, *sup_qmask = nullptr;  // [k]
   int64_t bucket_rows = 8192;   // rows per block (bucket_rows())
 
   // state

@@ -355,16 +355,14 @@ __global__ __launch_bounds__(64) void k_block_scatter(const int32_t *a, int64_t 
   }
 }
 
-// A sum task's destination row: workspace rows and sum rows that may hold
-// values (s_dirty) are cleared; a sum row kept clear since its last use is
-// not (its values were zeroed by the renormalisation that read them).  For a
-// task summing straight into S_j the support bitmap of S_j (bit t: S_j[t] !=
-// 0) is cleared here and set as terms are first added.
+// A sum task's destination row: workspace rows are cleared; sum rows S_j are
+// all zero already (zeroed at set-up and by the renormalisation that read
+// them).  For a task summing straight into S_j the support bitmap of S_j (bit
+// t: S_j[t] != 0) is cleared here and set as terms are first added.
 __device__ inline void prepare_dst(double *dst, int64_t D, uint32_t *bits, const SumSupport &sp,
                                    const int4 &tk) {
   const int tid = threadIdx.x;
-  const bool clear = tk.z >= 0 || !sp.s_dirty || sp.s_dirty[tk.x];
-  if (clear) {
+  if (tk.z >= 0) {
     if (D % 2 == 0) {
       v2d *d2 = reinterpret_cast<v2d *>(dst);
       const v2d z = {0.0, 0.0};
@@ -634,14 +632,18 @@ __device__ inline double block_max_256(double v, double *sh) {
 }
 
 // c_j = S_j / ||S_j|| (empty clusters keep c_j), with the per-cluster shift
-// ||c_j(new) - c_j(old)||^2 and S_j . c_j(old).  One workgroup per cluster.
-// When the support bitmaps of S_j (this update's sums) and of c_j are known,
-// only their non-zeros are visited: the norm over S_j's, then over the union
-// the new master entries, the shift, S_j . c_j(old), the scoring codes (FP8:
-// the scale from S_j's largest entry first), and S_j's entries are zeroed
-// for its next use.  Otherwise (the first update, or after the centroids were
-// replaced) every entry is visited in the same order, the master's support
-// bitmap is built, and k_quantize encodes the row.
+// ||c_j(new) - c_j(old)||^2 and S_j . c_j(old); S_j is left all zero for its
+// next sums.  One workgroup per cluster.  The norm is summed over S_j's
+// non-zeros as its support bitmap lists them (thread tid takes words tid, tid
+// + 256, ..., the set bits of a word ascending, eight loads in flight), so it
+// does not depend on which of the two paths below writes the row:
+//   - sparse (the master row's support is known and S_j holds fewer than
+//     D / 2 non-zeros): only the union of both supports is visited; the new
+//     master entries, the shift, S_j . c_j(old) and the scoring codes (FP8:
+//     the scale from S_j's largest entry) are written there;
+//   - dense: the rows are streamed (a wavefront per 64 consecutive terms),
+//     the master's support bitmap built by ballots, and k_quantize encodes
+//     the row (qmask).
 template <int P>
 __global__ __launch_bounds__(256) void k_renorm(double *S, const int32_t *counts,
                                                 const int32_t *ids, int64_t D, double *master,
@@ -657,28 +659,44 @@ __global__ __launch_bounds__(256) void k_renorm(double *S, const int32_t *counts
       snorm[j] = 0.0;
       shift[j] = 0.0;
       dot_old[j] = 0.0;
-      if (rs.qmask) rs.qmask[j] = 0;   // c_j is kept, so are its codes
+      rs.qmask[j] = 0;   // c_j is kept, so are its codes
     }
     return;
   }
-  if (rs.nb && rs.mvalid[j]) {
-    const uint32_t *nbj = rs.nb + (int64_t)j * rs.W;
-    uint32_t *mbj = rs.mb + (int64_t)j * rs.W;
-    double ss = 0.0, smax = 0.0;
-    for (int64_t w = tid; w < rs.W; w += 256) {
-      uint32_t m = nbj[w];
-      while (m) {
-        const int64_t t = w * 32 + __builtin_ctz(m);
-        m &= m - 1;
-        const double v = Sj[t];
-        ss += v * v;
-        smax = fmax(smax, v);
+  const uint32_t *nbj = rs.nb + (int64_t)j * rs.W;
+  double ss = 0.0, smax = 0.0;
+  int64_t cnt = 0;
+  for (int64_t w = tid; w < rs.W; w += 256) {
+    uint32_t m = nbj[w];
+    cnt += __popc(m);
+    while (m) {
+      int64_t t[8];
+      int nt = 0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        t[u] = m ? w * 32 + __builtin_ctz(m) : -1;
+        nt += m ? 1 : 0;
+        m &= m ? m - 1 : 0u;
       }
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = u < nt ? Sj[t[u]] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (u < nt) {
+          ss += v[u] * v[u];
+          smax = fmax(smax, v[u]);
+        }
     }
-    const double nrm = sqrt(block_sum_256(ss, sh));
+  }
+  const double nrm = sqrt(block_sum_256(ss, sh));
+  const double total = block_sum_256((double)cnt, sh);
+  const bool sparse = rs.mvalid[j] && total * 2.0 < (double)D;
+  if (sparse) {
+    uint32_t *mbj = rs.mb + (int64_t)j * rs.W;
     int e = 0;
     if (P == SKM_FP8_E4M3) {
-      // the scale of the new row: its largest value is the largest S_j over the norm
+      // the new row's largest value is S_j's largest over the norm
       smax = block_max_256(smax, sh);
       e = e4m3_scale_exp(smax / nrm);
       if (tid == 0) rs.scale[j] = ldexpf(1.0f, e);
@@ -690,19 +708,33 @@ __global__ __launch_bounds__(256) void k_renorm(double *S, const int32_t *counts
       const uint32_t nw = nbj[w];
       uint32_t m = nw | mbj[w];
       while (m) {
-        const int b = __builtin_ctz(m);
-        m &= m - 1;
-        const int64_t t = w * 32 + b;
-        const bool in = (nw >> b) & 1u;
-        const double sv = in ? Sj[t] : 0.0;
-        const double o = Mj[t];
-        const double c = in ? sv / nrm : 0.0;
-        const double d = c - o;
-        sh2 += d * d;
-        dot += sv * o;
-        Mj[t] = c;
-        codes[tile_index(t, j, D)] = encode_code<P>(c, e);
-        if (in) Sj[t] = 0.0;
+        int64_t t[4];
+        int nt = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          t[u] = m ? w * 32 + __builtin_ctz(m) : -1;
+          nt += m ? 1 : 0;
+          m &= m ? m - 1 : 0u;
+        }
+        double sv[4], o[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const bool in = u < nt && ((nw >> (t[u] & 31)) & 1u);
+          sv[u] = in ? Sj[t[u]] : 0.0;
+          o[u] = u < nt ? Mj[t[u]] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (u >= nt) continue;
+          const bool in = (nw >> (t[u] & 31)) & 1u;
+          const double c = in ? sv[u] / nrm : 0.0;
+          const double d = c - o[u];
+          sh2 += d * d;
+          dot += sv[u] * o[u];
+          Mj[t[u]] = c;
+          codes[tile_index(t[u], j, D)] = encode_code<P>(c, e);
+          if (in) Sj[t[u]] = 0.0;
+        }
       }
       mbj[w] = nw;
     }
@@ -712,39 +744,31 @@ __global__ __launch_bounds__(256) void k_renorm(double *S, const int32_t *counts
       snorm[j] = nrm;
       shift[j] = sh2;
       dot_old[j] = dot;
-      rs.s_dirty[j] = 0;
       rs.qmask[j] = 0;
     }
     return;
   }
-  // Dense rows, visited in the sparse path's order (thread tid takes words
-  // tid, tid + 256, ..., the 32 terms of a word ascending): the zeros add
-  // exact zeros, so both paths give the same bits for the same S_j.
-  const int64_t W = (D + 31) / 32;
-  double ss = 0.0;
-  for (int64_t w = tid; w < W; w += 256) {
-    const int64_t t0 = w * 32, n = min<int64_t>(32, D - t0);
-    for (int64_t b = 0; b < n; ++b) {
-      const double v = Sj[t0 + b];
-      ss += v * v;
-    }
-  }
-  const double nrm = sqrt(block_sum_256(ss, sh));
   double sh2 = 0.0, dot = 0.0;
-  uint32_t *mbj = rs.mb ? rs.mb + (int64_t)j * rs.W : nullptr;
-  for (int64_t w = tid; w < W; w += 256) {
-    const int64_t t0 = w * 32, n = min<int64_t>(32, D - t0);
-    uint32_t m = 0;
-    for (int64_t b = 0; b < n; ++b) {
-      const double sv = Sj[t0 + b], o = Mj[t0 + b];
-      const double c = sv / nrm;
+  uint32_t *mbj = rs.mb + (int64_t)j * rs.W;
+  const int lane = lane_id();
+  for (int64_t t0 = (int64_t)(tid & ~63); t0 < D; t0 += 256) {
+    const int64_t t = t0 + lane;
+    double c = 0.0;
+    if (t < D) {
+      const double sv = __builtin_nontemporal_load(Sj + t);
+      const double o = __builtin_nontemporal_load(Mj + t);
+      c = sv / nrm;
       const double d = c - o;
       sh2 += d * d;
       dot += sv * o;
-      Mj[t0 + b] = c;
-      m |= (c != 0.0 ? 1u : 0u) << b;
+      __builtin_nontemporal_store(c, Mj + t);
+      if (sv != 0.0) Sj[t] = 0.0;
     }
-    if (mbj) mbj[w] = m;
+    const uint64_t m = __ballot(c != 0.0);
+    if (lane == 0) {
+      mbj[t0 >> 5] = (uint32_t)m;
+      if ((t0 >> 5) + 1 < rs.W) mbj[(t0 >> 5) + 1] = (uint32_t)(m >> 32);
+    }
   }
   sh2 = block_sum_256(sh2, sh);
   dot = block_sum_256(dot, sh);
@@ -752,11 +776,8 @@ __global__ __launch_bounds__(256) void k_renorm(double *S, const int32_t *counts
     snorm[j] = nrm;
     shift[j] = sh2;
     dot_old[j] = dot;
-    if (rs.mb) {
-      rs.mvalid[j] = 1;
-      rs.s_dirty[j] = 1;
-      rs.qmask[j] = 1;
-    }
+    rs.mvalid[j] = 1;
+    rs.qmask[j] = 1;
   }
 }
 
