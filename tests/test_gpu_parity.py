@@ -401,6 +401,39 @@ def test_deterministic_runs(mid):
     assert np.array_equal(out[0][1].view(np.uint64), out[1][1].view(np.uint64))
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+def test_sparse_and_dense_update_give_the_same_bits(mid, prec):
+    """An update renormalises a cluster either over the non-zeros of its sum
+    and master rows (support bitmaps known) or over the dense rows (the
+    first update, or after the centroids were replaced); both must write the
+    same FP64 centroids.  A run continued from its own centroids after three
+    updates (sparse path) and a fresh context started from those centroids
+    (dense first update) end with the same assignment and bitwise equal
+    centroids and scoring codes."""
+    csr, c, rows = mid
+    say("case: sparse vs dense update", prec)
+    k = len(rows)
+    a = Context(to_device(csr), c.n_terms, k, init_rows=rows, precision=prec, ncc=True,
+                stop_rule="fixed", max_iter=3)
+    a.iterate(3)
+    C3 = a.centroids()
+    for _ in range(3):
+        a.assign()
+        a.update()
+    b = Context(to_device(csr), c.n_terms, k, init_centroids=C3, precision=prec, ncc=True,
+                stop_rule="fixed", max_iter=3)
+    for _ in range(3):
+        b.assign()
+        b.update()
+    assert np.array_equal(a.assignments(), b.assignments())
+    assert np.array_equal(a.centroids().view(np.uint64), b.centroids().view(np.uint64))
+    ca, sa = a.tile()
+    cb, sb = b.tile()
+    assert np.array_equal(ca, cb) and np.array_equal(sa, sb)
+    a.close()
+    b.close()
+
+
 def test_error_paths():
     say("case: errors")
     csr, c = corpus(100, 300, nnz_mean=10.0, nnz_max=30, seed=4)
