@@ -706,7 +706,6 @@ skm_status build_index(skm_ctx *c, const int32_t *ids_dev = nullptr,
         ST_TRY(index_segments_of(c, ids_dev, ids));
         c->idx_used_e += tot[0];
         c->idx_used_q += tot[1];
-        c->idx_entries = live;
         std::sort(c->idx_h_dids.begin(), c->idx_h_dids.end());
         const int32_t nd = (int32_t)c->idx_h_dids.size();
         HIP_TRY(c, hipMemcpyAsync(c->idx_dids, c->idx_h_dids.data(), sizeof(int32_t) * nd,
@@ -742,7 +741,6 @@ skm_status build_index(skm_ctx *c, const int32_t *ids_dev = nullptr,
     c->idx_h_dids.clear();
     c->idx_used_e = total;
     c->idx_used_q = tot[1];
-    c->idx_entries = total;
     c->idx_g_entries = total;
     c->idx_last_build = 1;
   }

@@ -316,7 +316,6 @@ struct skm_ctx {
   // Sec. 3.2 index (built when SKM_INDEX is set)
   bool index_ready = false;
   int64_t idx_cap_entries = 0;   // capacity of the entry-sized buffers
-  int64_t idx_entries = 0;       // live entries (all centroids)
   int64_t idx_g_entries = 0;     // entries of G (last full build)
   int64_t idx_used_e = 0, idx_used_q = 0;  // entry / prefix-sum slots in use
   int32_t *idx_cnt = nullptr;    // [k] entries per centroid
