@@ -1587,18 +1587,17 @@ skm_status skm_autotune(skm_ctx *c, skm_tune_report *report) {
   const int64_t rows0 = c->head_rows;
   double warm = 0;
   ST_TRY(pass(chunks0, rows0, c->score_wpc, &warm));   // first-use costs, not recorded
-  // stage 1: workgroups per CU of the sparse kernel around the occupancy limit
+  // stage 1: workgroups per CU of the sparse kernel, from one above the
+  // occupancy limit down to four below it (fewer rows in flight can keep more
+  // of a chunk's code rows in L2)
   const int occ = score_occupancy(c->prec);
-  std::vector<int32_t> wpcs;
-  for (int32_t w : {occ, occ - 1, occ + 1, 8})
-    if (w >= 2 && w <= 8 && std::find(wpcs.begin(), wpcs.end(), w) == wpcs.end()) wpcs.push_back(w);
-  for (int32_t w : wpcs) ST_TRY(trial(chunks0, rows0, w));
-  // a candidate displaces the incumbent (the default shape, tried first) only
-  // when it is at least 5 % faster: closer timings are within run-to-run noise
+  for (int32_t w = std::min(occ + 1, 8); w >= std::max(occ - 4, 2); --w)
+    ST_TRY(trial(chunks0, rows0, w));
+  // the fastest trial (equal times: the earlier one)
   auto best_of = [&]() {
     int32_t b = 0;
     for (int32_t i = 1; i < rep.n_trials; ++i)
-      if (rep.trials[i].ms < 0.95 * rep.trials[b].ms) b = i;
+      if (rep.trials[i].ms < rep.trials[b].ms) b = i;
     return b;
   };
   const int32_t wbest = rep.trials[best_of()].workgroups_per_cu;

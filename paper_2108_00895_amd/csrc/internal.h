@@ -22,9 +22,12 @@ constexpr int kSumHot = 2048;
 
 // Lists of non-zero codes of the tail terms of one scoring copy (see
 // kernels_tail.hip).  tail == nullptr: every term takes the dense path.
+// Bit 31 of a list offset word: the term is a list (rare) term of the chunk.
+constexpr uint32_t kListFlag = 0x80000000u;
 struct TailView {
   const uint8_t *tail;    // [nch][D] 1 = list term of chunk cc
-  const uint32_t *off;    // [nch][D + 1] entry offsets within chunk cc's entries
+  const uint32_t *off;    // [nch][D + 1] entry offsets within chunk cc's entries,
+                          // kListFlag set on list terms (not on off[cc][D])
   const uint64_t *base;   // [nch + 1] first entry of chunk cc
   const uint32_t *ent;    // entries (BF16 / FP8: (col << 16) | code; FP32: (col, bits))
 };

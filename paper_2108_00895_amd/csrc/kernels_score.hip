@@ -123,7 +123,9 @@ __device__ inline int32_t uniform32(int32_t v) { return __builtin_amdgcn_readfir
 // Head terms: one slab-row load per term (8 loads in flight per lane) and
 // eight FMAs into registers.  Tail terms of the chunk: the term's list of
 // non-zero codes in this chunk, lanes over entries, products added into the
-// wave's 512-float LDS accumulator lacc, folded into acc at the end.  The
+// wave's 512-float LDS accumulator lacc, folded into acc at the end.  A term's
+// list word (entry offset, kListFlag = a tail term of this chunk) gives both
+// the choice and the list, so the list walk waits for no further load.  The
 // order of the sum differs from the term order; the error bound allows any
 // order (at most two roundings per term plus the final merge).  Lanes whose
 // columns all lie at or past nvalid (a ragged or narrow compacted chunk) issue
@@ -144,23 +146,26 @@ __device__ inline void score_chunk(int64_t b, int64_t e, const int32_t *__restri
       const_cast<uint8_t *>(slab), 0, (int)(D * kChunk * C::kBytes), 0x00020000);
   const int voff = lane * kColsPerLane * C::kBytes;
   constexpr int rowbytes = kChunk * C::kBytes;
-  const uint8_t *ttail = tv.tail ? tv.tail + cc * D : nullptr;
-  const uint32_t *toff = tv.tail ? tv.off + cc * (D + 1) : nullptr;
-  const uint32_t *tent = tv.tail ? tv.ent + (int64_t)tv.base[cc] * C::kEntWords : nullptr;
+  const uint32_t *toff = tv.off ? tv.off + cc * (D + 1) : nullptr;
+  const uint32_t *tent = tv.off ? tv.ent + (int64_t)tv.base[cc] * C::kEntWords : nullptr;
   bool used_lds = false;
   for (int64_t q0 = b; q0 < e; q0 += kWave) {
     const int cnt = (int)((e - q0) < kWave ? (e - q0) : kWave);
     int my_t = 0;
     float my_x = 0.f;
-    bool my_tail = false;
+    uint32_t w0 = 0, w1 = 0;
     if (lane < cnt) {
       // streamed once per (row, chunk): non-temporal, to leave L2 to the codes
       my_t = __builtin_nontemporal_load(indices + q0 + lane);
       my_x = __builtin_nontemporal_load(values + q0 + lane);
-      my_tail = ttail && ttail[my_t];
+      if (toff) {
+        w0 = toff[my_t];
+        w1 = toff[my_t + 1];
+      }
     }
+    const bool my_tail = (w0 & kListFlag) != 0u;
     uint64_t dmask = __ballot(lane < cnt && !my_tail);
-    uint64_t tmask = __ballot(my_tail);
+    const uint64_t tmask = __ballot(my_tail);
     while (__popcll(dmask) >= 8) {
       int u[8];
 #pragma unroll
@@ -198,11 +203,8 @@ __device__ inline void score_chunk(int64_t b, int64_t e, const int32_t *__restri
       // of its term; the lists are flattened and each lane takes one entry
       // per step, finding its owner by a binary search over the prefix sums.
       used_lds = true;
-      uint32_t o0 = 0, len = 0;
-      if (my_tail) {
-        o0 = toff[my_t];
-        len = toff[my_t + 1] - o0;
-      }
+      const uint32_t o0 = w0 & ~kListFlag;
+      const uint32_t len = my_tail ? (w1 & ~kListFlag) - o0 : 0u;
       uint32_t incl = len;
 #pragma unroll
       for (int m = 1; m < kWave; m <<= 1) {
@@ -308,10 +310,12 @@ __device__ inline void part_bound(const ScoreArgs &a, int64_t row, int64_t n, do
 // persistent and walks items chunk-major (item = chunk * n_rows + row), so all
 // wavefronts sweep the same 512-centroid slice of the codes at the same time
 // and its hot term rows stay in L2 / the Infinity Cache instead of being
-// re-fetched from HBM for every row.
+// re-fetched from HBM for every row.  BF16 / FP8: built for the register
+// budget of eight waves per SIMD (the eight loads in flight still fit); FP32
+// would spill there.
 template <int P>
-__global__ __launch_bounds__(256) void k_score_part(ScoreArgs a, Partial *__restrict__ part,
-                                                    int64_t n_items) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == SKM_FP32 ? 1 : 8)))
+void k_score_part(ScoreArgs a, Partial *__restrict__ part, int64_t n_items) {
   __shared__ float lacc_all[4][kChunk];
   const int wave = uniform32(threadIdx.x >> 6);
   const int lane = lane_id();

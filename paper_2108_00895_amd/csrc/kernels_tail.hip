@@ -75,10 +75,11 @@ __global__ __launch_bounds__(256) void k_tail_count(const uint8_t *tile, int64_t
   }
 }
 
-// Exclusive scan of each listed chunk's counts over terms: off[cc][t], and
-// off[cc][D] = the chunk's total (also in totals[i] for the i-th listed
-// chunk).  Three launches spread over the GPU: sums of blocks of kScanTerms
-// terms, a scan of each chunk's block sums, and the writes of each block.
+// Exclusive scan of each listed chunk's counts over terms: off[cc][t], with
+// kListFlag set on the chunk's list terms, and off[cc][D] = the chunk's total
+// (also in totals[i] for the i-th listed chunk).  Three launches spread over
+// the GPU: sums of blocks of kScanTerms terms, a scan of each chunk's block
+// sums, and the writes of each block.
 constexpr int kScanTerms = 4096;   // terms per block (256 threads x 16)
 
 __global__ __launch_bounds__(256) void k_tail_bsum(const uint32_t *cnt, int64_t D,
@@ -115,8 +116,8 @@ __global__ void k_tail_bscan(uint32_t *bsum, int64_t nb, int32_t n_list, const i
   totals[i] = run;
 }
 
-__global__ __launch_bounds__(256) void k_tail_write(const uint32_t *cnt, int64_t D,
-                                                    const int32_t *chunks, int64_t nb,
+__global__ __launch_bounds__(256) void k_tail_write(const uint32_t *cnt, const uint8_t *tail,
+                                                    int64_t D, const int32_t *chunks, int64_t nb,
                                                     const uint32_t *bsum, uint32_t *off) {
   __shared__ uint32_t sh[256];
   const int cc = chunks[blockIdx.y];
@@ -138,9 +139,10 @@ __global__ __launch_bounds__(256) void k_tail_write(const uint32_t *cnt, int64_t
   }
   uint32_t pos = bsum[(int64_t)blockIdx.y * nb + blockIdx.x] + sh[threadIdx.x] - s;
   uint32_t *o = off + (int64_t)cc * (D + 1);
+  const uint8_t *fl = tail + (int64_t)cc * D;
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
-    if (t0 + q < D) o[t0 + q] = pos;
+    if (t0 + q < D) o[t0 + q] = pos | (fl[t0 + q] ? kListFlag : 0u);
     pos += v[q];
   }
 }
@@ -168,7 +170,7 @@ __global__ __launch_bounds__(256) void k_tail_fill(const uint8_t *tile, int64_t 
     const int y = __shfl_up(incl, s, kWave);
     if (lane >= s) incl += y;
   }
-  uint64_t pos = (uint64_t)cc * (uint64_t)stride + off[(int64_t)cc * (D + 1) + t] +
+  uint64_t pos = (uint64_t)cc * (uint64_t)stride + (off[(int64_t)cc * (D + 1) + t] & ~kListFlag) +
                  (uint64_t)(incl - c);
 #pragma unroll
   for (int v = 0; v < 8; ++v) {
@@ -214,8 +216,8 @@ hipError_t tail_count(const uint8_t *tile, int64_t D, int32_t ncols, int prec,
                      chunks, nb, bsum);
   hipLaunchKernelGGL(k_tail_bscan, dim3((unsigned)((n_list + 63) / 64)), dim3(64), 0, s, bsum, nb,
                      n_list, chunks, D, off, totals);
-  hipLaunchKernelGGL(k_tail_write, dim3((unsigned)nb, (unsigned)n_list), dim3(256), 0, s, cnt, D,
-                     chunks, nb, bsum, off);
+  hipLaunchKernelGGL(k_tail_write, dim3((unsigned)nb, (unsigned)n_list), dim3(256), 0, s, cnt, tail,
+                     D, chunks, nb, bsum, off);
   return hipGetLastError();
 }
 
