@@ -86,10 +86,14 @@ def test_profile_summary_scales_and_windows(tmp_path):
     other = dict(shape, workgroups_per_cu=5)
     assert bench.measured_traffic("k_score_part<bf16>", "wl", other, 1.0, 3, 2, path=out) is None
     assert bench.measured_traffic("k_score_part<bf16>", "x", shape, 1.0, 3, 2, path=out) is None
+    # the shape the record was taken at, for the bench to prefer among equal trials
+    assert bench.profiled_shape("k_score_part<bf16>", "wl", path=out) == shape
+    assert bench.profiled_shape("k_score_part<bf16>", "x", path=out) is None
     rec2 = json.load(open(out))
     rec2["k_score_part<bf16>@wl"]["src_sha"] = "0" * 16
     json.dump(rec2, open(out, "w"))
     assert bench.measured_traffic("k_score_part<bf16>", "wl", shape, 1.0, 3, 2, path=out) is None
+    assert bench.profiled_shape("k_score_part<bf16>", "wl", path=out) is None
 
 
 def test_committed_record_is_well_formed():
