@@ -1206,16 +1206,26 @@ skm_status head_pass(skm_ctx *c, ScoreArgs &a, hipStream_t s, const uint16_t *ch
   a.head_H = c->head_H;
   a.row_list = rows;
   const int32_t nch = (int32_t)((ncols + kChunk - 1) / kChunk);
-  a.hs_ld = (int64_t)c->head_chunks * kChunk;
-  for (int64_t r0 = 0; r0 < n_rows; r0 += c->head_rows) {
-    const int64_t nb = std::min<int64_t>(c->head_rows, n_rows - r0);
-    for (int32_t g0 = 0; g0 < nch; g0 += c->head_chunks) {
-      const int32_t gc = std::min<int32_t>(c->head_chunks, nch - g0);
+  // fewer rows than a batch (the rows of changed clusters late in a run): as
+  // many chunks per batch as the head-score buffer holds, so that each sparse
+  // launch still has many items to spread over the GPU
+  const int64_t rb = std::max<int64_t>(1, std::min<int64_t>(c->head_rows, n_rows));
+  const int32_t g = (int32_t)std::max<int64_t>(
+      c->head_chunks, std::min<int64_t>(nch, c->hs_cap / (rb * kChunk)));
+  a.hs_ld = (int64_t)g * kChunk;
+  for (int64_t r0 = 0; r0 < n_rows; r0 += rb) {
+    const int64_t nb = std::min<int64_t>(rb, n_rows - r0);
+    for (int32_t g0 = 0; g0 < nch; g0 += g) {
+      const int32_t gc = std::min<int32_t>(g, nch - g0);
+      // the product stops at the first 256-column tile boundary past the last
+      // live column (a compacted copy of few changed centroids)
+      const int64_t gcols =
+          std::min<int64_t>((int64_t)gc * kChunk, round_up(ncols - (int64_t)g0 * kChunk, 256));
       ST_TRY(mark(c, c->head_t, s));
       HIP_TRY(c, launch_head_gemm(c->xh, c->head_H, r0, nb, rows, chead, (int64_t)g0 * kChunk,
-                                  (int64_t)gc * kChunk, c->hs, a.hs_ld, s));
+                                  gcols, c->hs, a.hs_ld, s));
       ST_TRY(mark(c, c->head_t, s));
-      c->head_pairs += (double)nb * (double)gc * kChunk;
+      c->head_pairs += (double)nb * (double)gcols;
       a.row0 = r0;
       a.nb = nb;
       a.c_first = g0;
