@@ -7,7 +7,9 @@ two regimes of Sec. 3.1 have each carried one assignment step:
     centroid score the compacted changed centroids through the head product
     and the sparse kernel);
   * "narrow": NCC on, at most 64 changed centroids (those rows are scored by
-    the narrow kernel straight from the compacted codes).
+    the narrow kernel straight from the compacted codes);
+  * "short" (BF16 run): NCC on, 65 to 256 changed centroids (the head
+    product over the compacted copy stops at its first 256-column tile).
 At each, with the centroids C the step used and the previous assignment a':
   * a seeded sample of rows: the assignment is the lowest-index argmax of the
     FP64 dot products with C's columns at the row's terms (rows whose top-two
@@ -28,8 +30,9 @@ from gpu_common import TIE, say, to_device
 pytestmark = pytest.mark.gpu
 
 CASES = {
-    "bf16-2m": (synth.PRUNED_BF16_2M.corpus, 10_000, "bf16", 60),
-    "fp8-1m": (synth.scaled(synth.FP8_8M.corpus, 1_000_000), 20_000, "fp8", 80),
+    "bf16-2m": (synth.PRUNED_BF16_2M.corpus, 10_000, "bf16", 60, {"head", "narrow", "short"}),
+    "fp8-1m": (synth.scaled(synth.FP8_8M.corpus, 1_000_000), 20_000, "fp8", 80,
+               {"head", "narrow"}),
 }
 
 
@@ -44,6 +47,8 @@ def _regime(st):
         return "head"
     if st["changed_centroids"] <= 64:
         return "narrow"
+    if st["changed_centroids"] <= 256:
+        return "short"
     return None
 
 
@@ -74,7 +79,7 @@ def _check_step(ctx, csr, c, k, a_prev, a, rng, n_rows=600, n_band_rows=60):
 
 @pytest.mark.parametrize("name", list(CASES))
 def test_late_ncc_regimes(name):
-    corp, k, prec, cap = CASES[name]
+    corp, k, prec, cap, want = CASES[name]
     say("case: late iterations", name)
     csr = synth.generate(corp)
     rows = synth.seed_rows(corp.n_docs, k, corp.seed)
@@ -86,7 +91,7 @@ def test_late_ncc_regimes(name):
     for it in range(cap):
         st = ctx.assign()
         reg = _regime(st)
-        if reg and reg not in seen:
+        if reg in want and reg not in seen:
             a = ctx.assignments()
             say(f"  iteration {it}: regime {reg}, changed {st['changed_centroids']}, ncc rows "
                 f"{st['ncc_rows']}, flagged {st['flagged']}")
@@ -94,9 +99,9 @@ def test_late_ncc_regimes(name):
             say(f"  argmax property holds (ties {n_tie}); {n_band} band centroids equal the "
                 f"oracle's member sums")
             seen[reg] = it
-        if len(seen) == 2:
+        if set(seen) == want:
             break
         ctx.update()
         a_prev = ctx.assignments()
     ctx.close()
-    assert set(seen) == {"head", "narrow"}, seen
+    assert set(seen) == want, seen
