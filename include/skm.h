@@ -390,10 +390,10 @@ int32_t skm_head_terms(const skm_ctx *c);
 
 /* Autotuner: times one full scoring pass (low precision, all centroids, no
  * exact tier) of the context's own rows for candidate shapes of the work —
- * the workgroups per CU of the persistent sparse scoring grid around its
- * occupancy limit, then the head batch shape (rows x 512-centroid chunks
- * filling the head-score buffer) — and keeps the fastest for the following
- * assignment steps.  Results are unaffected (the shape only changes the
+ * the workgroups per CU of the persistent sparse scoring grid, from one above
+ * its occupancy limit down to four below it, then the head batch shape (rows
+ * x 512-centroid chunks filling the head-score buffer) — and keeps the
+ * fastest trial for the following assignment steps.  Results are unaffected (the shape only changes the
  * schedule).  Call it with no assignment pending (before skm_assign or after
  * skm_update); SKM_E_STATE otherwise.  report (may be NULL) receives every
  * trial. */
